@@ -1,0 +1,479 @@
+"""Pins of the FP64 reference against what the paper and mathematics fix.
+
+Each test checks the reference against something other than itself: hand-
+worked values of eq. 1 / eq. 2 (tests/golden), brute force on tiny inputs,
+textbook special cases (Kadane's maximum subarray), closed forms of the master
+problem, an independent exact line search, library conversions for the
+reduced-precision formats, and the invariants of column generation.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    out = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                out.append([float(v) for v in line.split()])
+    return out
+
+
+# ---------------------------------------------------------------- eq. 1 / eq. 2
+
+def test_eq1_penalty_golden():
+    for a, b, T, z, F, dF in _rows("eq1_penalty.txt"):
+        Fo, dFo = O.penalty(np.array([z]), np.array([a]), np.array([b]), np.array([T]))
+        assert Fo == F
+        assert dFo[0] == dF
+
+
+def test_eq1_zero_dose_cost():
+    # y = 0 gives z = 0 and F = sum_j alpha_j T_j^2 (eq. 1 with z_j = 0 <= T_j)
+    rng = np.random.default_rng(1)
+    a, b, T = rng.random(50), rng.random(50), rng.random(50) * 70
+    F, _ = O.penalty(np.zeros(50), a, b, T)
+    assert F == pytest.approx(float(np.sum(a * T * T)), rel=1e-14)
+
+
+def test_eq2_smoothing_golden():
+    for circ, y1, y2, y3, t1, t2, t3, G, g1, g2, g3 in _rows("eq2_smoothing.txt"):
+        Go, dGo = O.smoothing(np.array([y1, y2, y3]), np.array([t1, t2, t3]), int(circ))
+        assert Go == pytest.approx(G, rel=1e-15)
+        np.testing.assert_allclose(dGo, [g1, g2, g3], rtol=1e-14)
+
+
+def test_eq2_gradient_and_curvature_fd():
+    rng = np.random.default_rng(2)
+    th = np.sort(rng.choice(360, 7, replace=False)).astype(float)
+    for circ in (0, 1):
+        y, d = rng.random(7), rng.standard_normal(7)
+        G0, dG = O.smoothing(y, th, circ)
+        h = 1e-4
+        Gp, _ = O.smoothing(y + h * d, th, circ)
+        Gm, _ = O.smoothing(y - h * d, th, circ)
+        assert (Gp - Gm) / (2 * h) == pytest.approx(float(dG @ d), rel=1e-8)
+        # G is quadratic: second difference is exact up to rounding
+        assert (Gp - 2 * G0 + Gm) / h ** 2 == pytest.approx(O.smoothing_curvature(d, th, circ), rel=1e-5)
+
+
+# ---------------------------------------------------------------- dose model
+
+def test_dose_bruteforce_small_integers():
+    """z_j = sum_k y_k sum_{i in A_k} D_ij (Sec. 2.1), by explicit loops, exact on integers."""
+    rng = np.random.default_rng(3)
+    N, R, C, nv = 4, 3, 5, 17
+    nb = N * R * C
+    Dd = rng.integers(0, 4, size=(nb, nv)) * (rng.random((nb, nv)) < 0.4)
+    y = rng.integers(0, 5, size=N).astype(float)
+    occ = np.array([1, 0, 1, 1], dtype=np.uint8)
+    l = rng.integers(0, C + 1, size=N * R)
+    r = np.maximum(l, rng.integers(0, C + 1, size=N * R))
+    z_ref = np.zeros(nv)
+    for k in range(N):
+        if not occ[k]:
+            continue
+        for rho in range(R):
+            for c in range(l[k * R + rho], r[k * R + rho]):
+                i = (k * R + rho) * C + c
+                for j in range(nv):
+                    z_ref[j] += y[k] * Dd[i, j]
+    D = sp.csr_matrix(Dd.astype(float))
+    z = O.dose(D, O.fluence(y, l, r, occ, R, C))
+    assert np.array_equal(z, z_ref)
+
+
+def test_dose_adjoint_identity():
+    rng = np.random.default_rng(4)
+    N, R, C, nv = 5, 4, 6, 200
+    nb = N * R * C
+    D = sp.random(nb, nv, density=0.1, random_state=5, format="csr")
+    y = rng.random(N)
+    occ = (rng.random(N) < 0.7).astype(np.uint8)
+    l = rng.integers(0, C + 1, N * R)
+    r = np.maximum(l, rng.integers(0, C + 1, N * R))
+    w = rng.standard_normal(nv)
+    lhs = float(O.dose(D, O.fluence(y, l, r, occ, R, C)) @ w)
+    rhs = float(y @ O.beam_sums(D @ w, l, r, occ, R, C))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_dose_voxel_permutation_invariance():
+    rng = np.random.default_rng(6)
+    nb, nv = 30, 40
+    D = sp.random(nb, nv, density=0.2, random_state=7, format="csr")
+    x = rng.random(nb)
+    perm = rng.permutation(nv)
+    z = O.dose(D, x)
+    zp = O.dose(D[:, perm], x)
+    np.testing.assert_allclose(zp, z[perm], rtol=1e-15)
+
+
+def test_objective_gradient_fd():
+    rng = np.random.default_rng(8)
+    N, R, C, nv = 6, 2, 4, 60
+    nb = N * R * C
+    D = sp.random(nb, nv, density=0.3, random_state=9, format="csr")
+    alpha = (rng.random(nv) < 0.5) * rng.random(nv)
+    beta = rng.random(nv)
+    T = rng.random(nv) * 2
+    th = np.arange(N) * 60.0
+    occ = np.array([1, 1, 0, 1, 1, 1], dtype=np.uint8)
+    l = rng.integers(0, 2, N * R)
+    r = rng.integers(2, C + 1, N * R)
+    y = rng.random(N) * 3 * occ
+    F, gG, z, dF, g, grad = O.objective(D, (alpha, beta, T), y, l, r, occ, 0.3, th, 1, R, C)
+    for k in np.flatnonzero(occ):
+        h = 1e-6
+        e = np.zeros(N)
+        e[k] = h
+        fp = sum(O.objective(D, (alpha, beta, T), y + e, l, r, occ, 0.3, th, 1, R, C)[:2])
+        fm = sum(O.objective(D, (alpha, beta, T), y - e, l, r, occ, 0.3, th, 1, R, C)[:2])
+        assert (fp - fm) / (2 * h) == pytest.approx(grad[k], rel=1e-5, abs=1e-7)
+
+
+# ---------------------------------------------------------------- pricing
+
+def _brute_row(g, Llo, Lhi, Rlo, Rhi):
+    best = None
+    for l in range(Llo, Lhi + 1):
+        for r in range(max(l, Rlo), Rhi + 1):
+            S = sum(g[l:r])
+            key = (S, r - l, l)
+            if best is None or key < best[0]:
+                best = (key, l, r)
+    return best
+
+
+def test_price_row_exhaustive_small_integer_rows():
+    """Every row with g_c in {-2..2} for C <= 5, every window: exact ties included."""
+    for C in range(1, 6):
+        for g in itertools.product(range(-2, 3), repeat=C):
+            g = np.array(g, dtype=float)
+            for Llo, Lhi, Rlo, Rhi in ((0, C, 0, C), (1, min(2, C), 1, C), (0, 1, max(0, C - 1), C)):
+                if Llo > Lhi or Rlo > Rhi:
+                    continue
+                S, l, r = O.price_row(g, Llo, Lhi, Rlo, Rhi)
+                br = _brute_row(list(g), Llo, Lhi, Rlo, Rhi)
+                assert (S, l, r) == (br[0][0], br[1], br[2]), (g, Llo, Lhi, Rlo, Rhi)
+
+
+def test_price_row_random_bounds_vs_bruteforce():
+    rng = np.random.default_rng(10)
+    for _ in range(3000):
+        C = int(rng.integers(1, 13))
+        g = rng.integers(-5, 6, C).astype(float)
+        a, b = sorted(rng.integers(0, C + 1, 2))
+        c, d = sorted(rng.integers(0, C + 1, 2))
+        if a > d:
+            continue
+        S, l, r = O.price_row(g, a, b, c, d)
+        br = _brute_row(list(g), a, b, c, d)
+        assert (S, l, r) == (br[0][0], br[1], br[2])
+
+
+def _kadane(v):
+    best = cur = 0.0
+    for x in v:
+        cur = max(0.0, cur + x)
+        best = max(best, cur)
+    return best
+
+
+def test_price_row_unconstrained_is_kadane():
+    rng = np.random.default_rng(11)
+    for _ in range(2000):
+        C = int(rng.integers(1, 40))
+        g = rng.integers(-9, 10, C).astype(float)
+        S, l, r = O.price_row(g, 0, C, 0, C)
+        assert -S == _kadane(-g)
+        assert S == g[l:r].sum()
+
+
+def test_row_margin_bruteforce():
+    rng = np.random.default_rng(12)
+    for _ in range(300):
+        C = int(rng.integers(1, 9))
+        g = rng.integers(-3, 4, C).astype(float)
+        S, l, r = O.price_row(g, 0, C, 0, C)
+        vals = sorted({sum(g[a:b]) for a in range(C + 1) for b in range(a, C + 1)})
+        higher = [v for v in vals if v != S]
+        m = O.row_margin(g, 0, C, 0, C, S)
+        assert m == (min(higher) - S if higher else math.inf)
+
+
+def test_first_pricing_opens_negative_span():
+    """At z = 0 every price is <= 0; each row opens from its first to its last
+    strictly negative beamlet (the unique shortest minimiser)."""
+    rng = np.random.default_rng(13)
+    N, R, C = 5, 6, 9
+    g = -1.0 * (rng.random(N * R * C) < 0.4) * rng.random(N * R * C)
+    pr = O.price(g, np.zeros(N), np.zeros(N * R, int), np.zeros(N * R, int), np.zeros(N, np.uint8),
+                 np.arange(N) * 72.0, 0.1, R, C, 2, 1)
+    gk = g.reshape(N, R, C)[pr.beam]
+    for rho in range(R):
+        neg = np.flatnonzero(gk[rho] < 0)
+        if neg.size:
+            assert (pr.l[rho], pr.r[rho]) == (neg[0], neg[-1] + 1)
+        else:
+            assert (pr.l[rho], pr.r[rho]) == (0, 0)
+    sums = g.reshape(N, R * C).sum(axis=1)
+    assert pr.beam == int(np.argmin(sums))
+
+
+def test_leaf_bounds_deliverable_against_all_occupied():
+    """A priced aperture is within delta*(distance) of every occupied beam's leaves."""
+    rng = np.random.default_rng(14)
+    N, R, C, delta = 12, 3, 10, 1
+    for circ in (0, 1):
+        occ = np.zeros(N, np.uint8)
+        l = np.zeros(N * R, int)
+        r = np.zeros(N * R, int)
+        for _ in range(N):
+            g = rng.standard_normal(N * R * C)
+            pr = O.price(g, np.zeros(N), l, r, occ, np.arange(N) * 30.0, 0.0, R, C, delta, circ)
+            k = pr.beam
+            for a in np.flatnonzero(occ):
+                dist = abs(a - k) if not circ else min(abs(a - k), N - abs(a - k))
+                assert np.all(np.abs(pr.l - l[a * R:(a + 1) * R]) <= delta * dist)
+                assert np.all(np.abs(pr.r - r[a * R:(a + 1) * R]) <= delta * dist)
+            assert np.all(pr.l <= pr.r)
+            occ[k] = 1
+            l[k * R:(k + 1) * R], r[k * R:(k + 1) * R] = pr.l, pr.r
+
+
+def test_beam_price_includes_smoothing_derivative():
+    # single-row, single-column beams; price = g + gamma dG/dy_k at y_k = 0
+    N, R, C = 4, 1, 1
+    th = np.array([0.0, 90.0, 180.0, 270.0])
+    y = np.array([2.0, 0.0, 0.0, 1.0])
+    occ = np.array([1, 0, 0, 1], np.uint8)
+    g = np.array([0.0, -1.0, -0.5, 0.0])
+    pr = O.price(g, y, np.zeros(4, int), np.ones(4, int), occ, th, 0.5, R, C, -1, 1)
+    # beam 1: neighbours y0=2 (gap 90), y2=0 -> -2*0.5*(2/90); beam 2: y3=1 -> -2*0.5*(1/90)
+    p1 = -1.0 - 2 * 0.5 * 2 / 90
+    p2 = -0.5 - 2 * 0.5 * 1 / 90
+    np.testing.assert_allclose(pr.beam_prices[[1, 2]], [p1, p2], rtol=1e-15)
+    assert pr.beam == 1 and pr.margin == pytest.approx(p2 - p1)
+
+
+# ---------------------------------------------------------------- line search / master
+
+def _exact_min_piecewise(z, dz, a, b, T, s0, c, tmax):
+    """Independent exact minimiser: split [0, tmax] at every threshold crossing;
+    on each piece phi is quadratic, minimise it there in closed form."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        bp = (T - z) / dz
+    bp = np.sort(bp[np.isfinite(bp) & (bp > 0) & (bp < tmax)])
+    edges = np.concatenate([[0.0], bp, [tmax]])
+
+    def phi(t):
+        F, _ = O.penalty(z + t * dz, a, b, T)
+        return F + s0 * t + 0.5 * c * t * t
+
+    best_t, best_v = 0.0, phi(0.0)
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        mid = 0.5 * (lo + hi)
+        zm = z + mid * dz
+        w = np.where(zm < T, a, b)                 # regime on this piece
+        q2 = float(np.sum(w * dz * dz)) + 0.5 * c  # phi = q2 t^2 + q1 t + const
+        q1 = float(np.sum(2 * w * dz * (z - T))) + s0
+        cands = [lo, hi]
+        if q2 > 0:
+            cands.append(min(max(-q1 / (2 * q2), lo), hi))
+        for t in cands:
+            v = phi(t)
+            if v < best_v:
+                best_t, best_v = t, v
+    return best_t, best_v
+
+
+def test_line_search_exact_vs_piecewise():
+    rng = np.random.default_rng(15)
+    for trial in range(60):
+        n = 40
+        z = rng.random(n) * 10
+        dz = rng.standard_normal(n) * 3
+        a = rng.random(n) * (rng.random(n) < 0.6)
+        b = rng.random(n)
+        T = rng.random(n) * 10
+        s0 = rng.standard_normal() * 0.1
+        c = rng.random() * 0.1
+        tmax = 1.0 if trial % 2 else math.inf
+        t, _ = O.line_search(z, dz, a, b, T, s0, c, tmax)
+        tt, vv = _exact_min_piecewise(z, dz, a, b, T, s0, c, 1e6 if math.isinf(tmax) else tmax)
+        F, _ = O.penalty(z + t * dz, a, b, T)
+        v = F + s0 * t + 0.5 * c * t * t
+        assert v <= vv + 1e-10 * max(1.0, abs(vv))
+        assert t == pytest.approx(tt, rel=1e-7, abs=1e-9) or abs(v - vv) <= 1e-12 * max(1, abs(vv))
+
+
+def _single_beam_problem(Dval, alpha, T, gamma):
+    N, R, C = 3, 1, 1
+    D = sp.csr_matrix(np.array([[Dval], [0.0], [0.0]]))
+    th = np.array([0.0, 120.0, 240.0])
+    return D, th, N, R, C
+
+
+def test_master_one_beam_one_voxel_closed_form():
+    """f = alpha (T - yD)^2 + gamma y^2 (1/dth- + 1/dth+)  =>  y* = alpha D T / (alpha D^2 + gamma (...))."""
+    for Dval, alpha, T, gamma in ((0.7, 1.0, 60.0, 0.1), (2.0, 3.0, 10.0, 5.0), (0.3, 0.5, 78.0, 0.0)):
+        D, th, N, R, C = _single_beam_problem(Dval, alpha, T, gamma)
+        occ = np.array([1, 0, 0], np.uint8)
+        m = O.master(D, np.array([alpha]), np.array([1.0]), np.array([T]), th, gamma, 1, R, C,
+                     np.zeros(3, int), np.ones(3, int), occ, np.zeros(3), O.MasterOpts(tol_rel=1e-12))
+        y_star = alpha * Dval * T / (alpha * Dval ** 2 + gamma * (1 / 120 + 1 / 120))
+        assert m.y[0] == pytest.approx(y_star, rel=1e-10)
+        assert m.converged
+
+
+def _enumerate_kkt(Dd, alpha, beta, T, th, gamma, circ, occ):
+    """Exact solution of a tiny master problem by enumerating active sets and
+    voxel regimes; each candidate is a linear system."""
+    N, nv = Dd.shape
+    best = None
+    occ_idx = [k for k in range(N) if occ[k]]
+    pairs = O.smoothing_pairs(th, circ)
+    H_G = np.zeros((N, N))
+    for a_, b_, w in pairs:
+        H_G[a_, a_] += 2 / w
+        H_G[b_, b_] += 2 / w
+        H_G[a_, b_] -= 2 / w
+        H_G[b_, a_] -= 2 / w
+    for mask in itertools.product((0, 1), repeat=len(occ_idx)):
+        S = [k for k, m in zip(occ_idx, mask) if m]
+        for reg in itertools.product((0, 1), repeat=nv):
+            w = np.where(np.array(reg) == 1, beta, alpha)   # 1: over-dose regime
+            # f = sum_j w_j (z_j - T_j)^2 + gamma/2 y^T H_G y, z = Dd^T y
+            H = 2 * (Dd * w) @ Dd.T + gamma * H_G
+            rhs = 2 * (Dd * w) @ T
+            y = np.zeros(N)
+            if S:
+                HS = H[np.ix_(S, S)]
+                try:
+                    y[S] = np.linalg.solve(HS, rhs[S])
+                except np.linalg.LinAlgError:
+                    continue
+            if np.any(y < -1e-12):
+                continue
+            y = np.maximum(y, 0)
+            z = Dd.T @ y
+            F, dF = O.penalty(z, alpha, beta, T)
+            G, dG = O.smoothing(y, th, circ)
+            grad = Dd @ dF + gamma * dG
+            if any(grad[k] < -1e-9 for k in occ_idx if k not in S):
+                continue
+            f = F + gamma * G
+            if best is None or f < best[0]:
+                best = (f, y)
+    return best
+
+
+def test_master_small_problems_vs_enumeration():
+    rng = np.random.default_rng(16)
+    for trial in range(25):
+        N, nv = 4, 5
+        Dd = rng.random((N, nv)) * (rng.random((N, nv)) < 0.8)
+        alpha = np.where(rng.random(nv) < 0.5, rng.random(nv) + 0.1, 0.0)
+        beta = rng.random(nv) + 0.1
+        T = rng.random(nv) * 5
+        th = np.array([0.0, 80.0, 170.0, 260.0])
+        gamma = 0.05 * trial
+        occ = np.array([1, 1, 0, 1], np.uint8) if trial % 3 else np.ones(4, np.uint8)
+        best = _enumerate_kkt(Dd, alpha, beta, T, th, gamma, 1, occ)
+        D = sp.csr_matrix(Dd)
+        m = O.master(D, alpha, beta, T, th, gamma, 1, 1, 1, np.zeros(N, int), np.ones(N, int), occ,
+                     np.zeros(N), O.MasterOpts(tol_rel=1e-12, max_iter=2000))
+        f = m.F + m.gG
+        assert f == pytest.approx(best[0], rel=1e-9, abs=1e-12)
+
+
+def test_master_kkt_and_monotone_on_generated_case():
+    import casegen
+    c = casegen.make_case(casegen.tiny_case(n_beams=6, n_rows=3, n_cols=5))
+    D = O.dose_matrix(c.row_ptr, c.col, c.val, c.n_voxels)
+    N, R, C = c.n_beams, c.n_rows, c.n_cols
+    occ = np.array([1, 0, 1, 1, 0, 1], np.uint8)
+    l = np.tile([0, 1, 0], N)
+    r = np.tile([5, 4, 3], N)
+    m = O.master(D, c.alpha, c.beta, c.T, c.theta_deg, c.gamma, 1, R, C, l, r, occ, np.zeros(N),
+                 O.MasterOpts(tol_rel=1e-9, max_iter=1000))
+    assert m.converged
+    F, gG, z, dF, g, grad = O.objective(D, (c.alpha, c.beta, c.T), m.y, l, r, occ, c.gamma,
+                                        c.theta_deg, 1, R, C)
+    kkt = np.abs(np.minimum(m.y, grad))[occ == 1].max()
+    assert kkt <= 1e-9 * m.kkt_ref * 1.0001
+    assert np.all(m.y[occ == 0] == 0)
+
+
+# ---------------------------------------------------------------- column generation
+
+def test_column_generation_invariants():
+    import casegen
+    for delta, circ in ((2, 1), (1, 0), (-1, 1)):
+        c = casegen.make_case(casegen.tiny_case(n_beams=8, n_rows=4, n_cols=6, circular=circ,
+                                                max_leaf_step=delta))
+        D = O.dose_matrix(c.row_ptr, c.col, c.val, c.n_voxels)
+        N, R, C = c.n_beams, c.n_rows, c.n_cols
+        res = O.solve(D, c.alpha, c.beta, c.T, c.theta_deg, c.gamma, circ, R, C, delta)
+        assert sorted(res.order) == list(range(N))                # one aperture per beam
+        costs = res.costs
+        assert costs[0] == pytest.approx(float(np.sum(c.alpha.astype(float) * c.T.astype(float) ** 2)))
+        for a, b in zip(costs[:-1], costs[1:]):
+            assert b <= a * (1 + 1e-12)                           # cost never increases
+        lk, rk = res.l.reshape(N, R), res.r.reshape(N, R)
+        assert np.all(lk <= rk) and np.all(lk >= 0) and np.all(rk <= C)
+        if delta >= 0:
+            pairs = [(k, k + 1) for k in range(N - 1)] + ([(N - 1, 0)] if circ else [])
+            for a, b in pairs:
+                assert np.all(np.abs(lk[a] - lk[b]) <= delta)
+                assert np.all(np.abs(rk[a] - rk[b]) <= delta)
+        assert np.all(res.y >= 0)
+
+
+# ---------------------------------------------------------------- reduced precision
+
+def test_bf16_fp16_rounding_match_library():
+    import torch
+    rng = np.random.default_rng(17)
+    v = (rng.random(100000) * 2).astype(np.float32)
+    v[:10] = [0.0, 1.0, 1.00390625, 1.005859375, 0.5, 3.0, 1e-3, 0.99609375, 1.0078125, 2.0]
+    np.testing.assert_array_equal(O.bf16_round(v), torch.from_numpy(v).to(torch.bfloat16).float().numpy())
+    np.testing.assert_array_equal(O.fp16_round(v), torch.from_numpy(v).half().float().numpy())
+
+
+def test_e4m3_table_and_encoder_match_library():
+    import torch
+    codes = torch.arange(256, dtype=torch.uint8)
+    lib = codes.view(torch.float8_e4m3fn).float().numpy().astype(np.float64)
+    mine = O.e4m3_values()
+    same = (lib == mine) | (np.isnan(lib) & np.isnan(mine))
+    assert same.all()
+    rng = np.random.default_rng(18)
+    v = np.concatenate([rng.random(200000) * 448.0, mine[:127]])
+    lib_codes = torch.from_numpy(v.astype(np.float32)).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    assert np.array_equal(O.e4m3_encode(v.astype(np.float32).astype(np.float64)), lib_codes)
+
+
+def test_fp8_quantisation_error_bound():
+    import casegen
+    c = casegen.make_case(casegen.tiny_case())
+    scale, q = O.fp8_quantise(c.row_ptr, c.val)
+    dq = O.fp8_dequantise(c.row_ptr, scale, q)
+    rel = np.abs(dq - c.val) / c.val
+    assert rel.max() <= 2.0 ** -4 + 1e-12          # 3 mantissa bits: half-ulp <= 2^-4 relative
+    D = O.dose_matrix(c.row_ptr, c.col, c.val, c.n_voxels)
+    Dh = O.dose_matrix(c.row_ptr, c.col, dq, c.n_voxels)
+    x = np.random.default_rng(19).random(D.shape[0])
+    B = O.quantisation_bound(D, Dh, x)
+    assert np.all(np.abs(O.dose(Dh, x) - O.dose(D, x)) <= B * (1 + 1e-12) + 1e-300)
