@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Benchmark of the VMAT column-generation hot path on one MI355X.
+
+A step is one full plan (column generation until every beam has an aperture:
+pricing, master solves with their dose products, adjoints and line searches)
+on the prostate-shaped case: 180 beams at 2 deg, 40x40 beamlets at 5 mm
+(288,000 beamlets), 128x128x64 voxels at 2.5 mm, about 1.09e8 non-zeros of D.
+
+value = algorithmic bytes of all D.x (forward) and D^T.r (adjoint) products
+run during the timed plans / wall time of those plans (GB/s).  The roofline
+object reports the dominant product kernel alone, timed with HIP events on the
+stream it runs on, against the 8 TB/s HBM peak.  The CPU baseline is the FP64
+reference running the first column-generation iterations of the same plan.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "D·x + Dᵀr HBM GB/s vs peak; plan s; bf16/fp8-D vs fp32 at stated dose error"
+
+
+def product_bytes(case, vb_fwd, vb_adj, n_quads_fwd, n_quads_adj):
+    """Algorithmic bytes per product of the quad-CSR layouts.
+
+    forward (voxel rows):  4 quads x (value bytes + 4 index bytes) + row pointers
+                           (4 B/voxel) + x gather (8 B/beamlet, once) + z write (8 B/voxel)
+    adjoint (beamlet rows): same for the beamlet rows + w gather (4 B/voxel, once)
+                           + g write (8 B/beamlet)
+    """
+    nv, nb = case.n_voxels, case.n_beamlets
+    fwd = 4 * n_quads_fwd * (vb_fwd + 4) + 4 * (nv + 1) + 8 * nb + 8 * nv
+    adj = 4 * n_quads_adj * (vb_adj + 4) + 4 * (nb + 1) + 4 * nv + 8 * nb
+    return fwd, adj
+
+
+def time_kernel(fn, reps, torch):
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps  # ms
+
+
+def cpu_baseline(case, n_iter):
+    """The FP64 reference, unmodified, on the first column-generation iterations
+    of the same plan.  Returns (bytes-weighted product counts, seconds, result)."""
+    import oracle as O
+    D = O.dose_matrix(case.row_ptr, case.col, case.val, case.n_voxels)
+    t0 = time.perf_counter()
+    res = O.solve(D, case.alpha, case.beta, case.T, case.theta_deg, case.gamma, case.circular,
+                  case.n_rows, case.n_cols, case.max_leaf_step, max_cg_iter=n_iter, with_margins=False)
+    dt = time.perf_counter() - t0
+    n_it = len(res.order)
+    # one adjoint for the empty plan; per master solve one fresh forward + adjoint,
+    # then one of each per master iteration
+    nf = n_it + sum(res.master_iters)
+    na = 1 + n_it + sum(res.master_iters)
+    return nf, na, n_it, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="prostate180")
+    ap.add_argument("--d-store", default="f32", choices=["f32", "bf16", "f16", "fp8"])
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the hot path is measured at one GPU's share; "
+              "the multi-GPU sharding is a design (voxel-slab split) without a runnable path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import casegen
+    import paper_1005_4396_amd as P
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    case = casegen.make_case(casegen.preset(args.workload))
+    log(f"[bench] case {args.workload}: nb={case.n_beamlets} nv={case.n_voxels} nnz={case.nnz} "
+        f"gen {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    prob = P.Problem.from_case(case, d_store=args.d_store)
+    log(f"[bench] handle built in {time.perf_counter() - t0:.1f}s, device bytes {prob.device_bytes() / 1e9:.2f} GB")
+
+    def one_plan():
+        l, r, occ, y = prob.empty_plan()
+        rep, tr = prob.solve(l, r, occ, y, want_trace=True)
+        return rep, tr
+
+    for w in range(args.warmup):
+        rep, tr = one_plan()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w}: cg={rep.cg_iters} master_iters={rep.master_iters} fwd={rep.n_forward} "
+            f"adj={rep.n_adjoint} cost={rep.F + rep.gG:.6g}")
+
+    torch.cuda.synchronize()
+    reps = []
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        rep, tr = one_plan()
+        reps.append(rep)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = wall * 1e3 / args.steps
+
+    # algorithmic bytes of the products run during the timed plans
+    vb = {"f32": 4, "bf16": 2, "f16": 2, "fp8": 1}[args.d_store]
+    fwd_b, adj_b = product_bytes(case, vb, vb, *layout_quads(case))
+    n_fwd = sum(r.n_forward for r in reps)
+    n_adj = sum(r.n_adjoint for r in reps)
+    total_bytes = n_fwd * fwd_b + n_adj * adj_b
+    value = total_bytes / wall / 1e9
+    log(f"[bench] {args.steps} plans in {wall:.2f}s: {ms_per_step:.1f} ms/plan, fwd={n_fwd} adj={n_adj}")
+
+    # per-kernel timing of the two products (HIP events on torch's current stream)
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.random(case.n_beamlets)).cuda()
+    w = torch.from_numpy(rng.standard_normal(case.n_voxels).astype(np.float32)).cuda()
+    zbuf = torch.empty(case.n_voxels, dtype=torch.float64, device="cuda")
+    gbuf = torch.empty(case.n_beamlets, dtype=torch.float64, device="cuda")
+    fwd_ms = time_kernel(lambda: prob.forward(x, zbuf), args.kernel_reps, torch)
+    adj_ms = time_kernel(lambda: prob.adjoint(w, gbuf), args.kernel_reps, torch)
+    fwd_gbs = fwd_b / fwd_ms / 1e6
+    adj_gbs = adj_b / adj_ms / 1e6
+    dom = "forward" if fwd_ms * n_fwd >= adj_ms * n_adj else "adjoint"
+    dom_gbs, dom_bytes = (fwd_gbs, fwd_b) if dom == "forward" else (adj_gbs, adj_b)
+    log(f"[bench] forward {fwd_ms:.4f} ms ({fwd_gbs:.0f} GB/s), adjoint {adj_ms:.4f} ms ({adj_gbs:.0f} GB/s)")
+
+    # device copy ceiling (context)
+    big = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    big2 = torch.empty_like(big)
+    cp_ms = time_kernel(lambda: big2.copy_(big), 20, torch)
+    copy_gbs = 2 * big.numel() * 4 / cp_ms / 1e6
+    del big, big2
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_beams": case.n_beams, "beamlets": case.n_beamlets,
+                   "voxels": case.n_voxels, "nnz": case.nnz, "d_store": args.d_store,
+                   "step": "one full column-generation plan"},
+        "plan_s": round(ms_per_step / 1e3, 4),
+        "plan": {"cg_iters": reps[-1].cg_iters, "master_iters": reps[-1].master_iters,
+                 "n_forward": reps[-1].n_forward, "n_adjoint": reps[-1].n_adjoint,
+                 "n_ls_evals": reps[-1].n_ls_evals, "cost": reps[-1].F + reps[-1].gG},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(dom_gbs, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(dom_gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                     "bytes_per_launch": dom_bytes},
+        "products": {"forward_ms": round(fwd_ms, 5), "forward_GBs": round(fwd_gbs, 1), "forward_bytes": fwd_b,
+                     "adjoint_ms": round(adj_ms, 5), "adjoint_GBs": round(adj_gbs, 1), "adjoint_bytes": adj_b,
+                     "device_copy_GBs": round(copy_gbs, 1)},
+    }
+
+    if not args.no_precision and args.d_store == "f32":
+        out["precision"] = precision_study(case, prob, torch, P, args.kernel_reps, log)
+
+    if not args.no_cpu_baseline:
+        nf, na, n_it, dt = cpu_baseline(case, args.cpu_iters)
+        cpu_bytes = nf * fwd_b + na * adj_b
+        out["cpu_baseline"] = {"value": round(cpu_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"first {n_it} column-generation iterations of the same plan "
+                                         f"({nf} forward + {na} adjoint products, {dt:.1f} s)"}
+        log(f"[bench] cpu baseline {out['cpu_baseline']}")
+
+    prob.close()
+    print(json.dumps(out), flush=True)
+
+
+def layout_quads(case):
+    """Quads (rows padded to a multiple of 4 entries) of the voxel-major and the
+    beamlet-major layouts of D."""
+    bm = int(np.sum((np.diff(case.row_ptr) + 3) // 4))
+    cnt = np.bincount(case.col, minlength=case.n_voxels)
+    vm = int(np.sum((cnt + 3) // 4))
+    return vm, bm
+
+
+def precision_study(case, prob32, torch, P, reps, log):
+    """Forward/adjoint speed of BF16 and FP8 storage against FP32 on this GPU, at the
+    dose error each gives against the FP64 reference for one full-open plan."""
+    import oracle as O
+    D = O.dose_matrix(case.row_ptr, case.col, case.val, case.n_voxels)
+    rng = np.random.default_rng(7)
+    N, R, C = case.n_beams, case.n_rows, case.n_cols
+    occ = np.ones(N, np.uint8)
+    l = np.zeros(N * R, np.int32)
+    r = np.full(N * R, C, np.int32)
+    y = rng.random(N) + 0.5
+    zo = O.dose(D, O.fluence(y, l, r, occ, R, C))
+    T = lambda a, dt: torch.as_tensor(a, dtype=dt, device="cuda")  # noqa: E731
+    yt, lt, rt, ot = T(y, torch.float64), T(l, torch.int32), T(r, torch.int32), T(occ, torch.uint8)
+    x = torch.from_numpy(rng.random(case.n_beamlets)).cuda()
+    w = torch.from_numpy(rng.standard_normal(case.n_voxels).astype(np.float32)).cuda()
+    zb = torch.empty(case.n_voxels, dtype=torch.float64, device="cuda")
+    gb = torch.empty(case.n_beamlets, dtype=torch.float64, device="cuda")
+    res = {}
+    for fmt in ("f32", "bf16", "fp8"):
+        prob = prob32 if fmt == "f32" else P.Problem.from_case(case, d_store=fmt)
+        zg = prob.dose(yt, lt, rt, ot).cpu().numpy().astype(np.float64)
+        err_l2 = float(np.linalg.norm(zg - zo) / np.linalg.norm(zo))
+        err_inf = float(np.abs(zg - zo).max() / np.abs(zo).max())
+        f_ms = time_kernel(lambda: prob.forward(x, zb), reps, torch)
+        a_ms = time_kernel(lambda: prob.adjoint(w, gb), reps, torch)
+        res[fmt] = {"forward_ms": round(f_ms, 5), "adjoint_ms": round(a_ms, 5), "dose_rel_l2": err_l2,
+                    "dose_rel_inf": err_inf}
+        log(f"[bench] {fmt}: fwd {f_ms:.4f} ms adj {a_ms:.4f} ms dose err l2 {err_l2:.2e} inf {err_inf:.2e}")
+        if prob is not prob32:
+            prob.close()
+    for fmt in ("bf16", "fp8"):
+        res[fmt]["speedup_vs_f32"] = round((res["f32"]["forward_ms"] + res["f32"]["adjoint_ms"]) /
+                                           (res[fmt]["forward_ms"] + res[fmt]["adjoint_ms"]), 3)
+    return res
+
+
+if __name__ == "__main__":
+    main()

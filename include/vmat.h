@@ -1,0 +1,204 @@
+/*
+ * vmat.h - C ABI of the MI355X (gfx950) column-generation VMAT hot path.
+ *
+ * The problem is the paper's model (Sec. 2.1, eq. 1-3):
+ *   N beams sorted by angle theta_k in [0, 360) degrees; beam k has R leaf rows
+ *   of C beamlets; beamlet i = (k*R + rho)*C + c, nb = N*R*C.
+ *   D (nb x nv, row = beamlet, column = voxel) holds the dose-deposition
+ *   coefficients D_ij >= 0.  An aperture A_k is one open interval
+ *   [l_{k,rho}, r_{k,rho}) of columns per leaf row (l == r: closed row) and
+ *   exists only when occ[k] != 0; y_k >= 0 is its intensity.
+ *   Dose:      z_j = sum_k y_k sum_{i in A_k} D_ij                    (eq. 3)
+ *   Penalty:   F(z) = sum_j a_j max(0,T_j-z_j)^2 + b_j max(0,z_j-T_j)^2 (eq. 1)
+ *   Smoothing: G(y) = sum_k (y_{k+1}-y_k)^2 / (theta_{k+1}-theta_k)    (eq. 2)
+ *              plus the pair (N,1) with gap theta_1+360-theta_N when circular.
+ *   Model:     min F(z) + gamma G(y), y >= 0                           (eq. 3)
+ *
+ * Conventions for every call
+ *   - "DEVICE" pointers are HIP device memory of the current device; "HOST"
+ *     pointers are ordinary host memory.  The caller owns every pointer it
+ *     passes; the library keeps none of them after the call returns.
+ *   - Work is ordered on the given stream.  vmat_dose, vmat_grad, vmat_price
+ *     and the *_fluence calls are asynchronous; vmat_create, vmat_master and
+ *     vmat_solve synchronise the stream before they return.
+ *   - Every call returns a vmat_status and never aborts.  Arguments are
+ *     checked before any launch, so VMAT_ERR_INVALID_ARG leaves outputs
+ *     untouched.  vmat_last_error() gives a text for the last failure on the
+ *     calling thread.
+ *   - A handle is not thread-safe; distinct handles are independent.  All
+ *     device memory a handle needs is allocated by vmat_create and released
+ *     by vmat_destroy; no other call allocates.
+ */
+#ifndef VMAT_H
+#define VMAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vmat_status;
+enum {
+    VMAT_OK = 0,
+    VMAT_ERR_INVALID_ARG = 1,   /* bad pointer, size or value; nothing was launched   */
+    VMAT_ERR_DEVICE = 2,        /* a HIP call failed; text in vmat_last_error()       */
+    VMAT_ERR_ALLOC = 3,         /* device allocation in vmat_create failed            */
+    VMAT_ERR_NOT_CONVERGED = 4, /* master hit its iteration cap; outputs are valid    */
+    VMAT_ERR_UNSUPPORTED = 5    /* option not available (e.g. n_cols > 64)            */
+};
+
+/* Storage of the library's device copies of D.  Accumulation is FP64 for every
+ * format; the reduced formats are the only approximation.                      */
+typedef enum {
+    VMAT_F32 = 0,       /* D as given                                            */
+    VMAT_F16 = 1,       /* IEEE half, round to nearest even                      */
+    VMAT_BF16 = 2,      /* bfloat16, round to nearest even                       */
+    VMAT_FP8_E4M3 = 3   /* OCP FP8 E4M3 with a per-beamlet FP32 scale            */
+                        /* s_i = max_j D_ij / 448, code = RNE(D_ij / s_i)          */
+} vmat_dtype;
+
+typedef struct vmat_ctx* vmat_handle;
+
+typedef struct vmat_problem {
+    int32_t n_beams;          /* N >= 1                                                  */
+    int32_t n_rows;           /* R >= 1 leaf rows per beam                               */
+    int32_t n_cols;           /* C, 1 <= C <= 64 beamlets per row                        */
+    int32_t d_store;          /* vmat_dtype                                              */
+    int64_t n_voxels;         /* nv >= 1, < 2^31                                          */
+    int64_t nnz;              /* non-zeros of D, < 2^33                                   */
+    const double* theta_deg;  /* HOST [N] strictly increasing, in [0, 360)                */
+    const int64_t* row_ptr;   /* DEVICE [nb+1] beamlet-major CSR; row_ptr[0]=0, [nb]=nnz */
+    const int32_t* col;       /* DEVICE [nnz] voxel index in [0,nv), ascending per row   */
+    const float* val;         /* DEVICE [nnz] D_ij, finite, >= 0                          */
+    const float* alpha;       /* DEVICE [nv] underdose weight, finite, >= 0  (eq. 1)       */
+    const float* beta;        /* DEVICE [nv] overdose weight, finite, >= 0   (eq. 1)       */
+    const float* T;           /* DEVICE [nv] threshold dose, finite          (eq. 1)       */
+    double gamma;             /* smoothing weight, finite, >= 0 (eq. 3; the paper: > 0)   */
+    int32_t circular;         /* 0: open chain of eq. 2; 1: add the wrap pair (N,1)       */
+    int32_t max_leaf_step;    /* delta: columns a leaf may move per beam index step when  */
+                              /* a new aperture is priced; < 0 means unconstrained        */
+} vmat_problem;
+
+/* Copies D, alpha, beta, T into the library's own device layouts (beamlet-major
+ * and voxel-major, in d_store precision) and validates them (one pass; invalid
+ * data gives VMAT_ERR_INVALID_ARG).  The caller may free its arrays afterwards. */
+vmat_status vmat_create(const vmat_problem* prob, hipStream_t stream, vmat_handle* out);
+vmat_status vmat_destroy(vmat_handle h);
+const char* vmat_last_error(void);
+/* Device bytes held by the handle (all layouts and work buffers). */
+vmat_status vmat_device_bytes(vmat_handle h, int64_t* bytes);
+
+/* Dose of a plan (Sec. 2.1; the constraint of eq. 3):
+ *   z_j = sum_k y_k sum_{i in A_k} D_ij, accumulated in FP64, stored as FP32.
+ * y: DEVICE double [N]; l, r: DEVICE int32 [N*R]; occ: DEVICE uint8 [N];
+ * z: DEVICE float [nv] (out).  Leaf pairs must satisfy 0 <= l <= r <= C for
+ * occupied beams (checked on the device; a violation makes the call return
+ * nothing useful, so check on the host when the data is untrusted).           */
+vmat_status vmat_dose(vmat_handle h, const double* y, const int32_t* l, const int32_t* r,
+                      const uint8_t* occ, float* z, hipStream_t stream);
+
+/* Cost and gradient of a plan (eq. 1-3; the KKT prices of Sec. 2.2):
+ *   cost[0] = F(z), cost[1] = gamma G(y)                 DEVICE double [2]
+ *   z    (nullable) DEVICE float  [nv] dose
+ *   dFdz (nullable) DEVICE float  [nv] F'(z_j) = 2b(z-T)+ - 2a(T-z)+
+ *   g    (nullable) DEVICE double [nb] beamlet prices g_i = sum_j D_ij F'(z_j)
+ *   dfdy (nullable) DEVICE double [N]  sum_{i in A_k} g_i + gamma dG/dy_k
+ * Inputs as for vmat_dose.                                                     */
+vmat_status vmat_grad(vmat_handle h, const double* y, const int32_t* l, const int32_t* r,
+                      const uint8_t* occ, double* cost, float* z, float* dFdz, double* g,
+                      double* dfdy, hipStream_t stream);
+
+/* Fluence-space forms (beamlet intensities x instead of apertures):
+ *   vmat_dose_fluence:  z = D^T x                   x: DEVICE double [nb]
+ *   vmat_grad_fluence:  cost[0] = F(D^T x); z, dFdz, g as in vmat_grad (nullable)
+ * These carry the derivative of the dose and cost with respect to x.          */
+vmat_status vmat_dose_fluence(vmat_handle h, const double* x, float* z, hipStream_t stream);
+vmat_status vmat_grad_fluence(vmat_handle h, const double* x, double* cost, float* z,
+                              float* dFdz, double* g, hipStream_t stream);
+
+/* Raw products, one kernel each (FP32/BF16/FP16 storage; FP8 adds a scaling pass):
+ *   vmat_forward:  z = D^T x      x: DEVICE double [nb],  z: DEVICE double [nv]
+ *   vmat_adjoint:  g = D w        w: DEVICE float  [nv],  g: DEVICE double [nb]
+ * FP64 accumulation; the forward is the dose of eq. 3 for beamlet
+ * intensities x, the adjoint gives the beamlet prices of Sec. 2.2 for w = F'(z). */
+vmat_status vmat_forward(vmat_handle h, const double* x, double* z, hipStream_t stream);
+vmat_status vmat_adjoint(vmat_handle h, const float* w, double* g, hipStream_t stream);
+
+/* Pricing (Sec. 2.2): the best deliverable aperture over the unoccupied beams.
+ * Per unoccupied beam and leaf row, one left-to-right pass minimises
+ * S(l,r) = sum_{c=l}^{r-1} g_c over leaf pairs within delta*(index distance)
+ * of the nearest occupied beam on each side (key (S, r-l, l); the best left
+ * end for a right end is the largest running prefix sum, ties to the later l).
+ * Beam price p_k = sum_rho S*_rho + gamma dG/dy_k at y_k = 0; the chosen beam
+ * is the smallest k with the least p_k.
+ *   g: DEVICE double [nb]; y, l, r, occ: current plan (DEVICE, as above)
+ *   out_beam:  DEVICE int32 [1 + 2R]: k* (-1 if all occupied), l*[R], r*[R]
+ *   out_price: DEVICE double [3]: p_k*, second-best p minus p_k* (inf if none),
+ *              least gap in any row of k* between S* and a different S value
+ *   beam_prices (nullable): DEVICE double [N], +inf for occupied beams          */
+vmat_status vmat_price(vmat_handle h, const double* g, const double* y, const int32_t* l,
+                       const int32_t* r, const uint8_t* occ, int32_t* out_beam,
+                       double* out_price, double* beam_prices, hipStream_t stream);
+
+typedef struct vmat_master_opts {
+    int32_t max_iter;       /* iteration cap (default 200)                              */
+    int32_t ls_max_steps;   /* Newton/bisection steps per line search (default 50)     */
+    double tol_rel;         /* stop when max_k |min(y_k, grad_k)| <= tol_rel * ref      */
+    double kkt_ref;         /* ref; <= 0: max_k |grad_k| at the start point             */
+} vmat_master_opts;
+
+typedef struct vmat_master_report {
+    int32_t iters, converged, n_forward, n_adjoint, n_ls_evals, reserved;
+    double F, gG, kkt, kkt_ref;
+} vmat_master_report;
+
+/* Master problem (Sec. 2.2): min F(z) + gamma G(y), y >= 0, over the intensities
+ * of the given apertures, by gradient projection: steepest descent on the free
+ * face after each face change, Polak-Ribiere(+) conjugate directions while the
+ * face holds, exact line search (safeguarded Newton) up to the first blocking
+ * bound.  y: DEVICE double [N], in: start point (unoccupied entries ignored),
+ * out: solution (0 for unoccupied beams).  opts (HOST, nullable: defaults),
+ * rep (HOST, nullable).  Returns VMAT_ERR_NOT_CONVERGED at the iteration cap.  */
+vmat_status vmat_master(vmat_handle h, const int32_t* l, const int32_t* r, const uint8_t* occ,
+                        double* y, const vmat_master_opts* opts, vmat_master_report* rep,
+                        hipStream_t stream);
+
+typedef struct vmat_solve_opts {
+    int32_t max_cg_iter;     /* apertures to add (<= 0 or > free beams: until all occupied) */
+    int32_t reserved;
+    vmat_master_opts master; /* master.kkt_ref <= 0: |p| of the first priced aperture       */
+} vmat_solve_opts;
+
+typedef struct vmat_solve_report {
+    int32_t cg_iters, master_iters, n_forward, n_adjoint, n_ls_evals, not_converged;
+    double F, gG, kkt_ref;
+} vmat_solve_report;
+
+/* Per-iteration record (HOST arrays, each nullable, length max iterations;
+ * cost has one more entry: cost[0] is the cost before the first aperture).     */
+typedef struct vmat_solve_trace {
+    int32_t* beam;
+    double* price;
+    double* margin;
+    double* row_margin;
+    double* cost;
+    int32_t* master_iters;
+} vmat_solve_trace;
+
+/* Column generation (abstract; Sec. 2.2): repeat pricing -> add the aperture
+ * (y = 0) -> master, until every beam has an aperture or max_cg_iter.
+ * l, r, occ, y: DEVICE, in: start state (occ all zero: empty plan; otherwise a
+ * resumed plan whose y is re-optimised first), out: final plan.
+ * z (nullable): DEVICE float [nv] final dose.  opts, rep, trace: HOST, nullable.
+ * Returns VMAT_OK even if some master solve hit its cap (rep->not_converged).   */
+vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, int32_t* l, int32_t* r,
+                       uint8_t* occ, double* y, float* z, vmat_solve_report* rep,
+                       vmat_solve_trace* trace, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VMAT_H */

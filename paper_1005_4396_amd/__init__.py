@@ -1,0 +1,7 @@
+"""MI355X (gfx950) HIP implementation of the column-generation VMAT hot path.
+
+``vmat`` is the Python binding of the C ABI (include/vmat.h); ``build`` compiles
+libvmat.so in-tree.
+"""
+from . import vmat  # noqa: F401
+from .vmat import Problem, VmatError, master_opts  # noqa: F401

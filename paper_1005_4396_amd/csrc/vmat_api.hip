@@ -1,0 +1,312 @@
+// C-ABI entry points: argument checks, then the kernel sequences of the dose,
+// gradient, pricing, master and column-generation calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "vmat_internal.h"
+#include "vmat_kernels.h"
+
+using namespace vmat;
+
+namespace {
+
+#define TRY(x)                          \
+    do {                                \
+        vmat_status s_ = (x);           \
+        if (s_ != VMAT_OK) return s_;   \
+    } while (0)
+
+vmat_status check_handle(vmat_handle h) {
+    set_error("");
+    if (!h) return fail(VMAT_ERR_INVALID_ARG, "null handle");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != h->device)
+        return fail(VMAT_ERR_INVALID_ARG, "the handle belongs to another device than the current one");
+    return VMAT_OK;
+}
+
+vmat_status check_plan(const double* y, const int32_t* l, const int32_t* r, const uint8_t* occ) {
+    if (!y || !l || !r || !occ) return fail(VMAT_ERR_INVALID_ARG, "null plan array (y, l, r or occ)");
+    return VMAT_OK;
+}
+
+__global__ void k_to_float(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+__global__ void k_scale_copy(int64_t n, const double* __restrict__ x, const float* __restrict__ s,
+                             double* __restrict__ o) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) o[i] = x[i] * (double)s[i];
+}
+
+vmat_status to_float(const double* a, float* b, int64_t n, hipStream_t st) {
+    if (n <= 0) return VMAT_OK;
+    k_to_float<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, a, b);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
+// x as the forward product needs it: the FP8 per-beamlet scale folded in.
+vmat_status forward_from_fluence(vmat_ctx* h, const double* x, hipStream_t st) {
+    const double* xs = x;
+    if (h->bm.scale) {
+        k_scale_copy<<<(unsigned)((h->nb + 255) / 256), 256, 0, st>>>(h->nb, x, h->bm.scale, h->x);
+        VMAT_LAUNCH_CHECK();
+        xs = h->x;
+    }
+    return launch_spmv(h, h->vm, xs, h->z, nullptr, st);
+}
+
+vmat_status forward_from_plan(vmat_ctx* h, const double* y, const int32_t* l, const int32_t* r,
+                              const uint8_t* occ, double* zout, const int32_t* skip, hipStream_t st) {
+    TRY(launch_fluence(h, y, l, r, occ, h->bm.scale, h->x, skip, st));
+    return launch_spmv(h, h->vm, h->x, zout, skip, st);
+}
+
+vmat_master_opts defaults(const vmat_master_opts* o) {
+    vmat_master_opts d;
+    d.max_iter = 200;
+    d.ls_max_steps = 50;
+    d.tol_rel = 1e-5;
+    d.kkt_ref = 0.0;
+    if (o) d = *o;
+    return d;
+}
+
+vmat_status check_opts(const vmat_master_opts& o) {
+    if (o.max_iter < 0 || o.ls_max_steps < 1 || !(o.tol_rel >= 0.0) || !std::isfinite(o.tol_rel) ||
+        !std::isfinite(o.kkt_ref))
+        return fail(VMAT_ERR_INVALID_ARG, "invalid master options");
+    return VMAT_OK;
+}
+
+vmat_status sync_state(vmat_ctx* h, hipStream_t st) {
+    VMAT_HIP(hipMemcpyAsync(h->ms_host, h->ms, sizeof(MasterState), hipMemcpyDeviceToHost, st));
+    VMAT_HIP(hipStreamSynchronize(st));
+    return VMAT_OK;
+}
+
+// One master solve (Sec. 2.2) on the device; the host only enqueues and reads
+// the done / line-search flags once per iteration.
+vmat_status run_master(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
+                       const vmat_master_opts& o, vmat_master_report* rep, hipStream_t st) {
+    const int32_t* done = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(h->ms) +
+                                                           offsetof(MasterState, done));
+    TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, st));
+    TRY(forward_from_plan(h, y, l, r, occ, h->z, nullptr, st));
+    TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
+    TRY(launch_spmv(h, h->bm, h->rz, h->g, nullptr, st));
+    TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, nullptr, st));
+    TRY(launch_master_grad(h, y, occ, 1, st));
+    for (;;) {
+        TRY(launch_master_dir(h, y, occ, st));
+        TRY(launch_fluence(h, h->md, l, r, occ, h->bm.scale, h->x, done, st));
+        TRY(launch_spmv(h, h->vm, h->x, h->dz, done, st));
+        for (int i = 0; i < 3; ++i) {
+            TRY(launch_ls_eval(h, st));
+            TRY(launch_ls_ctrl(h, st));
+        }
+        TRY(sync_state(h, st));
+        if (h->ms_host->done) break;
+        while (!h->ms_host->ls_done) {
+            for (int i = 0; i < 4; ++i) {
+                TRY(launch_ls_eval(h, st));
+                TRY(launch_ls_ctrl(h, st));
+            }
+            TRY(sync_state(h, st));
+        }
+        TRY(launch_master_step(h, y, st));
+        TRY(launch_update(h, st));
+        TRY(launch_spmv(h, h->bm, h->rz, h->g, done, st));
+        TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, done, st));
+        TRY(launch_master_grad(h, y, occ, 0, st));
+    }
+    const MasterState& s = *h->ms_host;
+    if (rep) {
+        rep->iters = s.it;
+        rep->converged = s.converged;
+        rep->n_forward = s.n_fwd;
+        rep->n_adjoint = s.n_adj;
+        rep->n_ls_evals = s.n_ls;
+        rep->reserved = 0;
+        rep->F = s.F;
+        rep->gG = s.gG;
+        rep->kkt = s.kkt;
+        rep->kkt_ref = s.kkt_ref;
+    }
+    return s.converged ? VMAT_OK : VMAT_ERR_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" vmat_status vmat_dose(vmat_handle h, const double* y, const int32_t* l, const int32_t* r,
+                                 const uint8_t* occ, float* z, hipStream_t st) {
+    TRY(check_handle(h));
+    TRY(check_plan(y, l, r, occ));
+    if (!z) return fail(VMAT_ERR_INVALID_ARG, "null z");
+    TRY(forward_from_plan(h, y, l, r, occ, h->z, nullptr, st));
+    return to_float(h->z, z, h->nv, st);
+}
+
+extern "C" vmat_status vmat_dose_fluence(vmat_handle h, const double* x, float* z, hipStream_t st) {
+    TRY(check_handle(h));
+    if (!x || !z) return fail(VMAT_ERR_INVALID_ARG, "null x or z");
+    TRY(forward_from_fluence(h, x, st));
+    return to_float(h->z, z, h->nv, st);
+}
+
+extern "C" vmat_status vmat_forward(vmat_handle h, const double* x, double* z, hipStream_t st) {
+    TRY(check_handle(h));
+    if (!x || !z) return fail(VMAT_ERR_INVALID_ARG, "null x or z");
+    const double* xs = x;
+    if (h->bm.scale) {
+        k_scale_copy<<<(unsigned)((h->nb + 255) / 256), 256, 0, st>>>(h->nb, x, h->bm.scale, h->x);
+        VMAT_LAUNCH_CHECK();
+        xs = h->x;
+    }
+    return launch_spmv(h, h->vm, xs, z, nullptr, st);
+}
+
+extern "C" vmat_status vmat_adjoint(vmat_handle h, const float* w, double* g, hipStream_t st) {
+    TRY(check_handle(h));
+    if (!w || !g) return fail(VMAT_ERR_INVALID_ARG, "null w or g");
+    return launch_spmv(h, h->bm, w, g, nullptr, st);
+}
+
+extern "C" vmat_status vmat_grad(vmat_handle h, const double* y, const int32_t* l, const int32_t* r,
+                                 const uint8_t* occ, double* cost, float* z, float* dFdz, double* g,
+                                 double* dfdy, hipStream_t st) {
+    TRY(check_handle(h));
+    TRY(check_plan(y, l, r, occ));
+    if (!cost) return fail(VMAT_ERR_INVALID_ARG, "null cost");
+    double* gout = g ? g : h->g;
+    TRY(forward_from_plan(h, y, l, r, occ, h->z, nullptr, st));
+    TRY(launch_penalty(h, h->z, z, dFdz, st));
+    TRY(launch_spmv(h, h->bm, h->rz, gout, nullptr, st));
+    TRY(launch_beam_sums(h, gout, l, r, occ, h->mgF, nullptr, st));
+    return launch_grad_finish(h, y, h->mgF, cost, dfdy, st);
+}
+
+extern "C" vmat_status vmat_grad_fluence(vmat_handle h, const double* x, double* cost, float* z, float* dFdz,
+                                         double* g, hipStream_t st) {
+    TRY(check_handle(h));
+    if (!x || !cost) return fail(VMAT_ERR_INVALID_ARG, "null x or cost");
+    TRY(forward_from_fluence(h, x, st));
+    TRY(launch_penalty(h, h->z, z, dFdz, st));
+    if (g) TRY(launch_spmv(h, h->bm, h->rz, g, nullptr, st));
+    return launch_cost_only(h, cost, st);
+}
+
+extern "C" vmat_status vmat_price(vmat_handle h, const double* g, const double* y, const int32_t* l,
+                                  const int32_t* r, const uint8_t* occ, int32_t* out_beam, double* out_price,
+                                  double* beam_prices, hipStream_t st) {
+    TRY(check_handle(h));
+    TRY(check_plan(y, l, r, occ));
+    if (!g || !out_beam || !out_price) return fail(VMAT_ERR_INVALID_ARG, "null g or output");
+    return launch_price(h, g, y, l, r, occ, out_beam, out_price, beam_prices, 0, 0, nullptr, nullptr, nullptr,
+                        nullptr, st);
+}
+
+extern "C" vmat_status vmat_master(vmat_handle h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
+                                   const vmat_master_opts* opts, vmat_master_report* rep, hipStream_t st) {
+    TRY(check_handle(h));
+    TRY(check_plan(y, l, r, occ));
+    const vmat_master_opts o = defaults(opts);
+    TRY(check_opts(o));
+    return run_master(h, l, r, occ, y, o, rep, st);
+}
+
+extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, int32_t* l, int32_t* r, uint8_t* occ,
+                                  double* y, float* z, vmat_solve_report* rep, vmat_solve_trace* trace,
+                                  hipStream_t st) {
+    TRY(check_handle(h));
+    TRY(check_plan(y, l, r, occ));
+    vmat_solve_opts so;
+    so.max_cg_iter = 0;
+    so.reserved = 0;
+    so.master = defaults(nullptr);
+    if (opts) so = *opts;
+    TRY(check_opts(so.master));
+    const int N = h->N;
+    std::vector<uint8_t> occ_h(N);
+    VMAT_HIP(hipMemcpyAsync(occ_h.data(), occ, N, hipMemcpyDeviceToHost, st));
+    VMAT_HIP(hipStreamSynchronize(st));
+    int n_occ = 0;
+    for (uint8_t o : occ_h) n_occ += o ? 1 : 0;
+    int iters = N - n_occ;
+    if (so.max_cg_iter > 0) iters = std::min(iters, so.max_cg_iter);
+
+    vmat_solve_report R = {};
+    std::vector<double> costs(iters + 1, 0.0);
+    std::vector<int32_t> miters(iters, 0);
+    double ref = so.master.kkt_ref;
+    vmat_master_report mr{};
+    if (n_occ > 0) {
+        vmat_master_opts mo = so.master;
+        vmat_status rc = run_master(h, l, r, occ, y, mo, &mr, st);
+        if (rc != VMAT_OK && rc != VMAT_ERR_NOT_CONVERGED) return rc;
+        if (rc == VMAT_ERR_NOT_CONVERGED) R.not_converged++;
+        R.master_iters += mr.iters; R.n_forward += mr.n_forward; R.n_adjoint += mr.n_adjoint;
+        R.n_ls_evals += mr.n_ls_evals;
+        if (!(ref > 0.0)) ref = mr.kkt_ref;
+        costs[0] = mr.F + mr.gG;
+    } else {
+        VMAT_HIP(hipMemsetAsync(h->z, 0, h->nv * sizeof(double), st));
+        TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
+        TRY(launch_spmv(h, h->bm, h->rz, h->g, nullptr, st));
+        TRY(launch_cost_only(h, h->cost2, st));
+        R.n_adjoint += 1;
+        double c0 = 0.0;
+        VMAT_HIP(hipMemcpyAsync(&c0, h->cost2, sizeof(double), hipMemcpyDeviceToHost, st));
+        VMAT_HIP(hipStreamSynchronize(st));
+        costs[0] = c0;
+    }
+    for (int t = 0; t < iters; ++t) {
+        TRY(launch_price(h, h->g, y, l, r, occ, h->pbeam, h->pscore, nullptr, 1, t, l, r, occ, y, st));
+        if (!(ref > 0.0)) {
+            double ps[3];
+            VMAT_HIP(hipMemcpyAsync(ps, h->pscore, sizeof(ps), hipMemcpyDeviceToHost, st));
+            VMAT_HIP(hipStreamSynchronize(st));
+            ref = ps[0] != 0.0 && std::isfinite(ps[0]) ? std::fabs(ps[0]) : 1.0;
+        }
+        vmat_master_opts mo = so.master;
+        mo.kkt_ref = ref;
+        vmat_status rc = run_master(h, l, r, occ, y, mo, &mr, st);
+        if (rc != VMAT_OK && rc != VMAT_ERR_NOT_CONVERGED) return rc;
+        if (rc == VMAT_ERR_NOT_CONVERGED) R.not_converged++;
+        R.master_iters += mr.iters; R.n_forward += mr.n_forward; R.n_adjoint += mr.n_adjoint;
+        R.n_ls_evals += mr.n_ls_evals;
+        costs[t + 1] = mr.F + mr.gG;
+        miters[t] = mr.iters;
+        R.cg_iters = t + 1;
+        R.F = mr.F;
+        R.gG = mr.gG;
+    }
+    if (iters == 0 && n_occ > 0) {
+        R.F = mr.F;
+        R.gG = mr.gG;
+    }
+    R.kkt_ref = ref;
+    if (z) TRY(to_float(h->z, z, h->nv, st));
+    if (trace) {
+        const int n = R.cg_iters;
+        if (trace->beam && n) VMAT_HIP(hipMemcpyAsync(trace->beam, h->tr.beam, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        if (trace->price && n) VMAT_HIP(hipMemcpyAsync(trace->price, h->tr.price, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (trace->margin && n) VMAT_HIP(hipMemcpyAsync(trace->margin, h->tr.margin, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (trace->row_margin && n)
+            VMAT_HIP(hipMemcpyAsync(trace->row_margin, h->tr.row_margin, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        VMAT_HIP(hipStreamSynchronize(st));
+        if (trace->cost) std::copy(costs.begin(), costs.begin() + n + 1, trace->cost);
+        if (trace->master_iters) std::copy(miters.begin(), miters.begin() + n, trace->master_iters);
+    }
+    VMAT_HIP(hipStreamSynchronize(st));
+    if (rep) *rep = R;
+    return VMAT_OK;
+}

@@ -1,0 +1,106 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "vmat.h"
+
+namespace vmat {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+vmat_status fail(vmat_status code, const std::string& msg);
+
+#define VMAT_HIP(call)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::vmat::fail(VMAT_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define VMAT_LAUNCH_CHECK() VMAT_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- layouts
+// A sparse matrix in "quad CSR": each row padded to a multiple of 4 entries so
+// that a lane reads 4 values and 4 column indices with one 16-byte (values:
+// 16/8/4-byte) load each.  Padding entries have value 0 and repeat a valid
+// column of the row (or column 0 for an empty row), so they are harmless.
+struct QuadCsr {
+    int64_t n_rows = 0;
+    int64_t n_quads = 0;        // padded entries / 4
+    uint32_t* qptr = nullptr;   // [n_rows+1] row start in quads
+    int32_t* col = nullptr;     // [4*n_quads]
+    void* val = nullptr;        // [4*n_quads] of the storage type
+    float* scale = nullptr;     // [n_rows] per-row scale (FP8 only), else null
+    int lanes_per_row = 16;     // lanes cooperating on one row (power of 2, <= 64)
+};
+
+// Scalars and small vectors of the master iteration, resident on the device.
+struct MasterState {
+    // line search
+    double t_max, t_eval, t, lo, hi, p0, h0, p, h, t_star, slope0, curv;
+    // master
+    double kkt, kkt_ref, tol, F, gG, beta_cg;
+    int32_t it, max_iter, done, converged;
+    int32_t ls_phase, ls_steps, ls_max, ls_done;
+    int32_t n_fwd, n_adj, n_ls, have_prev;
+    int32_t blocked, pad0, pad1, pad2;
+};
+
+// Per-iteration record of vmat_solve, resident on the device.
+struct SolveTraceDev {
+    int32_t* beam;       // [N]
+    double* price;       // [N]
+    double* margin;      // [N]
+    double* row_margin;  // [N]
+    double* cost;        // [N+1]
+    int32_t* miters;     // [N]
+};
+
+}  // namespace vmat
+
+struct vmat_ctx {
+    int32_t N, R, C;
+    int64_t nb, nv, nnz;
+    int32_t d_store;
+    double gamma;
+    int32_t circular, delta;
+    int device;
+
+    std::vector<double> theta;     // host copy
+    double* d_theta = nullptr;     // [N]
+
+    vmat::QuadCsr bm;              // beamlet-major (rows = beamlets): adjoint g = D r
+    vmat::QuadCsr vm;              // voxel-major (rows = voxels): forward z = D^T x
+    float4* abT = nullptr;         // [nv] (alpha, beta, T, 0)
+
+    // work buffers
+    double* x = nullptr;           // [nb] fluence
+    double* z = nullptr;           // [nv] dose (FP64)
+    double* dz = nullptr;          // [nv] dose of the search direction
+    float* rz = nullptr;           // [nv] F'(z) for the adjoint gather
+    double* g = nullptr;           // [nb] beamlet prices
+    double* part = nullptr;        // [n_part * 4] block partial sums
+    int n_part = 0;
+    // master vectors [N]
+    double *my = nullptr, *mgrad = nullptr, *mgrad_prev = nullptr, *md = nullptr, *md_prev = nullptr,
+           *mgF = nullptr;
+    uint8_t *mW = nullptr, *mW_prev = nullptr;
+    vmat::MasterState* ms = nullptr;      // device
+    vmat::MasterState* ms_host = nullptr; // pinned host mirror
+    // pricing
+    double* row_S = nullptr;       // [N*R]
+    int32_t* row_l = nullptr;      // [N*R]
+    int32_t* row_r = nullptr;      // [N*R]
+    double* row_m = nullptr;       // [N*R] row margins
+    double* bprice = nullptr;      // [N]
+    int32_t* pbeam = nullptr;      // [1 + 2R]
+    double* pscore = nullptr;      // [3]
+    double* cost2 = nullptr;       // [2]
+    vmat::SolveTraceDev tr{};
+    int64_t bytes = 0;
+};

@@ -1,0 +1,57 @@
+// Launch wrappers of the hot-path kernels (all asynchronous on `st`).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vmat_internal.h"
+
+namespace vmat {
+
+// x_i = v_k if beamlet i of beam k is exposed (occ_k, l <= c < r), else 0;
+// times the per-beamlet FP8 scale when `scale` is given.  Skipped when *skip.
+vmat_status launch_fluence(const vmat_ctx* h, const double* v, const int32_t* l, const int32_t* r,
+                           const uint8_t* occ, const float* scale, double* x, const int32_t* skip,
+                           hipStream_t st);
+
+// out_row = sum_e val_e x[col_e] (FP64 accumulation) for every row of A; the
+// per-row scale of A multiplies the result when present.  Skipped when *skip.
+vmat_status launch_spmv(const vmat_ctx* h, const QuadCsr& A, const double* x, double* out,
+                        const int32_t* skip, hipStream_t st);
+vmat_status launch_spmv(const vmat_ctx* h, const QuadCsr& A, const float* x, double* out,
+                        const int32_t* skip, hipStream_t st);
+
+// F'(z) into rz (FP32, for the adjoint gather), optional FP32 copies of z and
+// F'(z), and block partial sums of F(z) into part slot 0.
+vmat_status launch_penalty(const vmat_ctx* h, const double* z, float* z_out, float* dF_out, hipStream_t st);
+
+// sum_k-per-beam sums over apertures: out[k] = sum_{i in A_k} g_i.  Skipped when *skip.
+vmat_status launch_beam_sums(const vmat_ctx* h, const double* g, const int32_t* l, const int32_t* r,
+                             const uint8_t* occ, double* out, const int32_t* skip, hipStream_t st);
+
+// cost[0] = F (from partial slot 0), cost[1] = gamma G(y); dfdy = gF + gamma dG/dy.
+vmat_status launch_grad_finish(const vmat_ctx* h, const double* y, const double* gF, double* cost,
+                               double* dfdy, hipStream_t st);
+// cost[0] = F only (fluence form).
+vmat_status launch_cost_only(const vmat_ctx* h, double* cost, hipStream_t st);
+
+// ---- master iteration pieces (device-resident state in h->ms)
+vmat_status launch_master_begin(const vmat_ctx* h, double* y, const uint8_t* occ, int max_iter, int ls_max,
+                                double tol, double kkt_ref, hipStream_t st);
+vmat_status launch_master_grad(const vmat_ctx* h, const double* y, const uint8_t* occ, int first,
+                               hipStream_t st);
+vmat_status launch_master_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, hipStream_t st);
+vmat_status launch_ls_eval(const vmat_ctx* h, hipStream_t st);
+vmat_status launch_ls_ctrl(const vmat_ctx* h, hipStream_t st);
+vmat_status launch_master_step(const vmat_ctx* h, double* y, hipStream_t st);
+vmat_status launch_update(const vmat_ctx* h, hipStream_t st);
+
+// ---- pricing
+// apply != 0: also occupy the chosen beam in (l, r, occ, y), record the trace
+// entry `iter` and set the master's reference scale on the first call.
+vmat_status launch_price(const vmat_ctx* h, const double* g, const double* y, const int32_t* l,
+                         const int32_t* r, const uint8_t* occ, int32_t* out_beam, double* out_price,
+                         double* beam_prices, int apply, int iter, int32_t* lw, int32_t* rw, uint8_t* occw,
+                         double* yw, hipStream_t st);
+
+}  // namespace vmat

@@ -1,0 +1,216 @@
+// Pricing (Sec. 2.2): for every unoccupied beam and leaf row, the best leaf
+// pair in one left-to-right pass over the beamlet prices; then the beam price
+// and the chosen beam.
+//
+// One wavefront per (beam, row): lane c holds the prefix sum P[c] (summed in
+// column order, as a sequential pass would), lane r evaluates right end r
+// against the running best left end inside the leaf-speed window, and a
+// shuffle tree picks the least key (S, r-l, l).  C <= 64 columns fit one wave.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "vmat_internal.h"
+#include "vmat_kernels.h"
+
+namespace vmat {
+
+struct Cand {
+    double S;
+    int len, l, r;
+};
+
+__device__ __forceinline__ bool less_key(const Cand& a, const Cand& b) {
+    if (a.S != b.S) return a.S < b.S;
+    if (a.len != b.len) return a.len < b.len;
+    return a.l < b.l;
+}
+
+__global__ __launch_bounds__(256) void k_price_rows(int N, int R, int C, int delta, int circ,
+                                                    const double* __restrict__ g, const int32_t* __restrict__ l,
+                                                    const int32_t* __restrict__ r, const uint8_t* __restrict__ occ,
+                                                    double* __restrict__ rowS, int32_t* __restrict__ rowl,
+                                                    int32_t* __restrict__ rowr, double* __restrict__ rowm) {
+    __shared__ double P[4][65];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t kr = (int64_t)blockIdx.x * 4 + w;
+    const bool valid = kr < (int64_t)N * R;
+    const int k = valid ? (int)(kr / R) : 0;
+    const int rho = valid ? (int)(kr - (int64_t)k * R) : 0;
+    const bool active = valid && !occ[k];
+
+    // leaf windows from the nearest occupied beam on each side
+    int Llo = 0, Lhi = C, Rlo = 0, Rhi = C;
+    if (active && delta >= 0) {
+        for (int side = 0; side < 2; ++side) {
+            for (int dist = 1; dist < N; ++dist) {
+                int kk = side == 0 ? k - dist : k + dist;
+                if (kk < 0 || kk >= N) {
+                    if (!circ) break;
+                    kk = kk < 0 ? kk + N : kk - N;
+                }
+                if (occ[kk]) {
+                    const int reach = (int)min((int64_t)delta * dist, (int64_t)(1 << 20));
+                    const int64_t a = (int64_t)kk * R + rho;
+                    Llo = max(Llo, l[a] - reach);
+                    Lhi = min(Lhi, l[a] + reach);
+                    Rlo = max(Rlo, r[a] - reach);
+                    Rhi = min(Rhi, r[a] + reach);
+                    break;
+                }
+            }
+        }
+    }
+    // prefix sums P[0..C] in column order; lane t holds P[t] and P[t+64]
+    const double* gr = g + kr * C;
+    if (active) {
+        for (int pos = lane; pos <= C; pos += 64) {
+            double acc = 0.0;
+            for (int c = 0; c < pos; ++c) acc = acc + gr[c];
+            P[w][pos] = acc;
+        }
+    }
+    __syncthreads();
+
+    // lane t evaluates the right ends t and t+64 (C <= 64, so at most r = 64)
+    Cand best;
+    best.S = INFINITY;
+    best.len = 1 << 30;
+    best.l = -1;
+    best.r = -1;
+    for (int rr = lane; active && rr <= C; rr += 64) {
+        if (rr < Rlo || rr > Rhi) continue;
+        const int lmax = min(Lhi, rr);
+        double bp = -INFINITY;
+        int bl = -1;
+        for (int ll = Llo; ll <= lmax; ++ll) {
+            const double pl = P[w][ll];
+            if (pl >= bp) {
+                bp = pl;
+                bl = ll;
+            }
+        }
+        if (bl >= 0) {
+            Cand c;
+            c.S = P[w][rr] - bp;
+            c.len = rr - bl;
+            c.l = bl;
+            c.r = rr;
+            if (less_key(c, best)) best = c;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        Cand o;
+        o.S = __shfl_xor(best.S, off, 64);
+        o.len = __shfl_xor(best.len, off, 64);
+        o.l = __shfl_xor(best.l, off, 64);
+        o.r = __shfl_xor(best.r, off, 64);
+        if (less_key(o, best)) best = o;
+    }
+    // least gap between S* and any feasible pair with a different S
+    double gap = INFINITY;
+    for (int rr = lane; active && rr <= C; rr += 64) {
+        if (rr < Rlo || rr > Rhi) continue;
+        const int lmax = min(Lhi, rr);
+        for (int ll = Llo; ll <= lmax; ++ll) {
+            const double S = P[w][rr] - P[w][ll];
+            if (S != best.S) gap = fmin(gap, S - best.S);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) gap = fmin(gap, __shfl_xor(gap, off, 64));
+    if (valid && lane == 0) {
+        rowS[kr] = active ? best.S : INFINITY;
+        rowl[kr] = best.l;
+        rowr[kr] = best.r;
+        rowm[kr] = gap;
+    }
+}
+
+// Beam prices, the chosen beam, and (apply) the update of the plan state.
+__global__ __launch_bounds__(256) void k_price_beams(int N, int R, double gamma, int circ,
+                                                     const double* __restrict__ th, const double* __restrict__ y,
+                                                     const uint8_t* __restrict__ occ,
+                                                     const double* __restrict__ rowS, const int32_t* __restrict__ rowl,
+                                                     const int32_t* __restrict__ rowr, const double* __restrict__ rowm,
+                                                     double* __restrict__ bprice, int32_t* __restrict__ out_beam,
+                                                     double* __restrict__ out_price, double* __restrict__ user_bp,
+                                                     int apply, int iter, int32_t* __restrict__ lw,
+                                                     int32_t* __restrict__ rw, uint8_t* __restrict__ occw,
+                                                     double* __restrict__ yw, SolveTraceDev tr) {
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        double p = INFINITY;
+        if (!occ[k]) {
+            double tot = 0.0;
+            for (int rho = 0; rho < R; ++rho) tot = tot + rowS[(int64_t)k * R + rho];
+            // gamma dG/dy_k at y_k = 0 (eq. 2): -2 y_{k-1}/gap^- - 2 y_{k+1}/gap^+
+            double dG = 0.0;
+            const bool has_prev = k > 0 || (circ && N > 1);
+            const bool has_next = k < N - 1 || (circ && N > 1);
+            if (has_prev) {
+                const int a = k > 0 ? k - 1 : N - 1;
+                const double w = k > 0 ? th[k] - th[k - 1] : th[0] + 360.0 - th[N - 1];
+                dG += 2.0 * (0.0 - y[a]) / w;
+            }
+            if (has_next) {
+                const int b = k < N - 1 ? k + 1 : 0;
+                const double w = k < N - 1 ? th[k + 1] - th[k] : th[0] + 360.0 - th[N - 1];
+                dG -= 2.0 * (y[b] - 0.0) / w;
+            }
+            p = tot + gamma * dG;
+        }
+        bprice[k] = p;
+        if (user_bp) user_bp[k] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    int ks = -1;
+    double pb = INFINITY;
+    for (int k = 0; k < N; ++k)
+        if (!occ[k] && (ks < 0 || bprice[k] < pb)) {
+            ks = k;
+            pb = bprice[k];
+        }
+    double second = INFINITY;
+    for (int k = 0; k < N; ++k)
+        if (!occ[k] && k != ks) second = fmin(second, bprice[k]);
+    double rm = INFINITY;
+    if (ks >= 0)
+        for (int rho = 0; rho < R; ++rho) rm = fmin(rm, rowm[(int64_t)ks * R + rho]);
+    const double margin = ks >= 0 && isfinite(second) ? second - pb : INFINITY;
+    out_beam[0] = ks;
+    for (int rho = 0; rho < R; ++rho) {
+        out_beam[1 + rho] = ks >= 0 ? rowl[(int64_t)ks * R + rho] : 0;
+        out_beam[1 + R + rho] = ks >= 0 ? rowr[(int64_t)ks * R + rho] : 0;
+    }
+    out_price[0] = pb;
+    out_price[1] = margin;
+    out_price[2] = rm;
+    if (apply && ks >= 0) {
+        occw[ks] = 1;
+        yw[ks] = 0.0;
+        for (int rho = 0; rho < R; ++rho) {
+            lw[(int64_t)ks * R + rho] = rowl[(int64_t)ks * R + rho];
+            rw[(int64_t)ks * R + rho] = rowr[(int64_t)ks * R + rho];
+        }
+        tr.beam[iter] = ks;
+        tr.price[iter] = pb;
+        tr.margin[iter] = margin;
+        tr.row_margin[iter] = rm;
+    }
+}
+
+vmat_status launch_price(const vmat_ctx* h, const double* g, const double* y, const int32_t* l, const int32_t* r,
+                         const uint8_t* occ, int32_t* out_beam, double* out_price, double* beam_prices, int apply,
+                         int iter, int32_t* lw, int32_t* rw, uint8_t* occw, double* yw, hipStream_t st) {
+    const int64_t NR = (int64_t)h->N * h->R;
+    k_price_rows<<<(unsigned)((NR + 3) / 4), 256, 0, st>>>(h->N, h->R, h->C, h->delta, h->circular, g, l, r, occ,
+                                                           h->row_S, h->row_l, h->row_r, h->row_m);
+    VMAT_LAUNCH_CHECK();
+    k_price_beams<<<1, 256, 0, st>>>(h->N, h->R, h->gamma, h->circular, h->d_theta, y, occ, h->row_S, h->row_l,
+                                     h->row_r, h->row_m, h->bprice, out_beam, out_price, beam_prices, apply, iter,
+                                     lw, rw, occw, yw, h->tr);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
+}  // namespace vmat

@@ -1,0 +1,293 @@
+"""Python binding of libvmat.so (the C ABI in include/vmat.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch provides device memory (tensors) and the current stream.
+The module raises if the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvmat.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "vmat.h")
+
+VMAT_OK, VMAT_ERR_INVALID_ARG, VMAT_ERR_DEVICE, VMAT_ERR_ALLOC, VMAT_ERR_NOT_CONVERGED, VMAT_ERR_UNSUPPORTED = range(6)
+DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
+
+_lib = None
+
+
+class VmatError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vmat error {code}: {msg}")
+        self.code = code
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("n_beams", ctypes.c_int32), ("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32),
+        ("d_store", ctypes.c_int32),
+        ("n_voxels", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("theta_deg", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+        ("val", ctypes.c_void_p), ("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p), ("T", ctypes.c_void_p),
+        ("gamma", ctypes.c_double), ("circular", ctypes.c_int32), ("max_leaf_step", ctypes.c_int32),
+    ]
+
+
+class MasterOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("ls_max_steps", ctypes.c_int32),
+                ("tol_rel", ctypes.c_double), ("kkt_ref", ctypes.c_double)]
+
+
+class MasterReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("n_forward", ctypes.c_int32),
+                ("n_adjoint", ctypes.c_int32), ("n_ls_evals", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("F", ctypes.c_double), ("gG", ctypes.c_double), ("kkt", ctypes.c_double),
+                ("kkt_ref", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("max_cg_iter", ctypes.c_int32), ("reserved", ctypes.c_int32), ("master", MasterOpts)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("cg_iters", ctypes.c_int32), ("master_iters", ctypes.c_int32), ("n_forward", ctypes.c_int32),
+                ("n_adjoint", ctypes.c_int32), ("n_ls_evals", ctypes.c_int32), ("not_converged", ctypes.c_int32),
+                ("F", ctypes.c_double), ("gG", ctypes.c_double), ("kkt_ref", ctypes.c_double)]
+
+
+class SolveTrace(ctypes.Structure):
+    _fields_ = [("beam", ctypes.c_void_p), ("price", ctypes.c_void_p), ("margin", ctypes.c_void_p),
+                ("row_margin", ctypes.c_void_p), ("cost", ctypes.c_void_p), ("master_iters", ctypes.c_void_p)]
+
+
+def header_symbols():
+    """Names of the functions declared in include/vmat.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:vmat_status|const char\*)\s+(vmat_\w+)\s*\(", text, re.M)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python paper_1005_4396_amd/build.py`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "vmat_create": [ctypes.POINTER(_Problem), P, ctypes.POINTER(P)],
+            "vmat_destroy": [P],
+            "vmat_device_bytes": [P, ctypes.POINTER(I64)],
+            "vmat_dose": [P, P, P, P, P, P, P],
+            "vmat_dose_fluence": [P, P, P, P],
+            "vmat_forward": [P, P, P, P],
+            "vmat_adjoint": [P, P, P, P],
+            "vmat_grad": [P, P, P, P, P, P, P, P, P, P, P],
+            "vmat_grad_fluence": [P, P, P, P, P, P, P],
+            "vmat_price": [P, P, P, P, P, P, P, P, P, P],
+            "vmat_master": [P, P, P, P, P, ctypes.POINTER(MasterOpts), ctypes.POINTER(MasterReport), P],
+            "vmat_solve": [P, ctypes.POINTER(SolveOpts), P, P, P, P, P, ctypes.POINTER(SolveReport),
+                           ctypes.POINTER(SolveTrace), P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = I32
+        L.vmat_last_error.restype = ctypes.c_char_p
+        L.vmat_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().vmat_last_error().decode()
+
+
+def _check(code, allow=()):
+    if code != VMAT_OK and code not in allow:
+        raise VmatError(code, last_error())
+    return code
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def master_opts(max_iter=200, ls_max_steps=50, tol_rel=1e-5, kkt_ref=0.0) -> MasterOpts:
+    return MasterOpts(max_iter, ls_max_steps, tol_rel, kkt_ref)
+
+
+@dataclasses.dataclass
+class PriceOut:
+    beam: int
+    l: np.ndarray
+    r: np.ndarray
+    price: float
+    margin: float
+    row_margin: float
+    beam_prices: np.ndarray
+
+
+class Problem:
+    """A handle over one problem (D, voxel weights, beams) on the current GPU."""
+
+    def __init__(self, n_beams, n_rows, n_cols, n_voxels, theta_deg, row_ptr, col, val, alpha, beta, T,
+                 gamma, circular=1, max_leaf_step=2, d_store="f32"):
+        import torch
+        self.N, self.R, self.C, self.nv = int(n_beams), int(n_rows), int(n_cols), int(n_voxels)
+        self.nb = self.N * self.R * self.C
+        self.device = row_ptr.device
+        self._theta = np.ascontiguousarray(theta_deg, dtype=np.float64)
+        for t, dt in ((row_ptr, torch.int64), (col, torch.int32), (val, torch.float32),
+                      (alpha, torch.float32), (beta, torch.float32), (T, torch.float32)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("problem arrays must be contiguous CUDA tensors of the documented dtypes")
+        p = _Problem(self.N, self.R, self.C, DTYPES[d_store], self.nv, int(col.numel()),
+                     self._theta.ctypes.data, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr(),
+                     alpha.data_ptr(), beta.data_ptr(), T.data_ptr(), float(gamma), int(circular),
+                     int(max_leaf_step))
+        h = ctypes.c_void_p()
+        _check(lib().vmat_create(ctypes.byref(p), _stream(), ctypes.byref(h)))
+        self._h = h
+        self.d_store = d_store
+        self.gamma, self.circular, self.max_leaf_step = float(gamma), int(circular), int(max_leaf_step)
+
+    @classmethod
+    def from_case(cls, case, d_store="f32", device="cuda"):
+        import torch
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
+        rp, col, val = t(case.row_ptr), t(case.col), t(case.val)
+        a, b, T = t(case.alpha), t(case.beta), t(case.T)
+        prob = cls(case.n_beams, case.n_rows, case.n_cols, case.n_voxels, case.theta_deg, rp, col, val, a, b, T,
+                   case.gamma, case.circular, case.max_leaf_step, d_store)
+        torch.cuda.synchronize()
+        return prob
+
+    # ------------------------------------------------------------ lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vmat_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def device_bytes(self) -> int:
+        v = ctypes.c_int64()
+        _check(lib().vmat_device_bytes(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    # ------------------------------------------------------------ helpers
+    def empty_plan(self):
+        import torch
+        dev = self.device
+        return (torch.zeros(self.N * self.R, dtype=torch.int32, device=dev),
+                torch.zeros(self.N * self.R, dtype=torch.int32, device=dev),
+                torch.zeros(self.N, dtype=torch.uint8, device=dev),
+                torch.zeros(self.N, dtype=torch.float64, device=dev))
+
+    # ------------------------------------------------------------ calls
+    def dose(self, y, l, r, occ, z=None):
+        import torch
+        if z is None:
+            z = torch.empty(self.nv, dtype=torch.float32, device=self.device)
+        _check(lib().vmat_dose(self._h, _ptr(y), _ptr(l), _ptr(r), _ptr(occ), _ptr(z), _stream()))
+        return z
+
+    def dose_fluence(self, x, z=None):
+        import torch
+        if z is None:
+            z = torch.empty(self.nv, dtype=torch.float32, device=self.device)
+        _check(lib().vmat_dose_fluence(self._h, _ptr(x), _ptr(z), _stream()))
+        return z
+
+    def forward(self, x, z=None):
+        """z = D^T x (FP64 in, FP64 out), one kernel."""
+        import torch
+        if z is None:
+            z = torch.empty(self.nv, dtype=torch.float64, device=self.device)
+        _check(lib().vmat_forward(self._h, _ptr(x), _ptr(z), _stream()))
+        return z
+
+    def adjoint(self, w, g=None):
+        """g = D w (FP32 w, FP64 g), one kernel."""
+        import torch
+        if g is None:
+            g = torch.empty(self.nb, dtype=torch.float64, device=self.device)
+        _check(lib().vmat_adjoint(self._h, _ptr(w), _ptr(g), _stream()))
+        return g
+
+    def grad(self, y, l, r, occ, want=("z", "dF", "g", "dfdy")):
+        import torch
+        dev = self.device
+        cost = torch.empty(2, dtype=torch.float64, device=dev)
+        z = torch.empty(self.nv, dtype=torch.float32, device=dev) if "z" in want else None
+        dF = torch.empty(self.nv, dtype=torch.float32, device=dev) if "dF" in want else None
+        g = torch.empty(self.nb, dtype=torch.float64, device=dev) if "g" in want else None
+        dfdy = torch.empty(self.N, dtype=torch.float64, device=dev) if "dfdy" in want else None
+        _check(lib().vmat_grad(self._h, _ptr(y), _ptr(l), _ptr(r), _ptr(occ), _ptr(cost), _ptr(z), _ptr(dF),
+                               _ptr(g), _ptr(dfdy), _stream()))
+        return {"cost": cost, "z": z, "dF": dF, "g": g, "dfdy": dfdy}
+
+    def grad_fluence(self, x, want=("z", "dF", "g")):
+        import torch
+        dev = self.device
+        cost = torch.empty(2, dtype=torch.float64, device=dev)
+        z = torch.empty(self.nv, dtype=torch.float32, device=dev) if "z" in want else None
+        dF = torch.empty(self.nv, dtype=torch.float32, device=dev) if "dF" in want else None
+        g = torch.empty(self.nb, dtype=torch.float64, device=dev) if "g" in want else None
+        _check(lib().vmat_grad_fluence(self._h, _ptr(x), _ptr(cost), _ptr(z), _ptr(dF), _ptr(g), _stream()))
+        return {"cost": cost, "z": z, "dF": dF, "g": g}
+
+    def price(self, g, y, l, r, occ) -> PriceOut:
+        import torch
+        dev = self.device
+        ob = torch.empty(1 + 2 * self.R, dtype=torch.int32, device=dev)
+        op = torch.empty(3, dtype=torch.float64, device=dev)
+        bp = torch.empty(self.N, dtype=torch.float64, device=dev)
+        _check(lib().vmat_price(self._h, _ptr(g), _ptr(y), _ptr(l), _ptr(r), _ptr(occ), _ptr(ob), _ptr(op),
+                                _ptr(bp), _stream()))
+        ob, op, bp = ob.cpu().numpy(), op.cpu().numpy(), bp.cpu().numpy()
+        R = self.R
+        return PriceOut(int(ob[0]), ob[1:1 + R].copy(), ob[1 + R:].copy(), float(op[0]), float(op[1]),
+                        float(op[2]), bp)
+
+    def master(self, l, r, occ, y, opts: MasterOpts | None = None):
+        rep = MasterReport()
+        code = lib().vmat_master(self._h, _ptr(l), _ptr(r), _ptr(occ), _ptr(y),
+                                 ctypes.byref(opts) if opts is not None else None, ctypes.byref(rep), _stream())
+        _check(code, allow=(VMAT_ERR_NOT_CONVERGED,))
+        return rep
+
+    def solve(self, l, r, occ, y, opts: SolveOpts | None = None, z=None, want_trace=True):
+        rep = SolveReport()
+        n = self.N
+        tr_arrays = None
+        tr = None
+        if want_trace:
+            tr_arrays = {"beam": np.zeros(n, np.int32), "price": np.zeros(n), "margin": np.zeros(n),
+                         "row_margin": np.zeros(n), "cost": np.zeros(n + 1), "master_iters": np.zeros(n, np.int32)}
+            tr = SolveTrace(*(tr_arrays[k].ctypes.data for k in
+                              ("beam", "price", "margin", "row_margin", "cost", "master_iters")))
+        _check(lib().vmat_solve(self._h, ctypes.byref(opts) if opts is not None else None, _ptr(l), _ptr(r),
+                                _ptr(occ), _ptr(y), _ptr(z), ctypes.byref(rep),
+                                ctypes.byref(tr) if tr is not None else None, _stream()))
+        if tr_arrays is not None:
+            k = rep.cg_iters
+            tr_arrays = {key: (v[:k + 1] if key == "cost" else v[:k]) for key, v in tr_arrays.items()}
+        return rep, tr_arrays
