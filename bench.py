@@ -31,20 +31,6 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "D·x + Dᵀr HBM GB/s vs peak; plan s; bf16/fp8-D vs fp32 at stated dose error"
 
 
-def product_bytes(case, vb_fwd, vb_adj, n_quads_fwd, n_quads_adj):
-    """Algorithmic bytes per product of the quad-CSR layouts.
-
-    forward (voxel rows):  4 quads x (value bytes + 4 index bytes) + row pointers
-                           (4 B/voxel) + x gather (8 B/beamlet, once) + z write (8 B/voxel)
-    adjoint (beamlet rows): same for the beamlet rows + w gather (4 B/voxel, once)
-                           + g write (8 B/beamlet)
-    """
-    nv, nb = case.n_voxels, case.n_beamlets
-    fwd = 4 * n_quads_fwd * (vb_fwd + 4) + 4 * (nv + 1) + 8 * nb + 8 * nv
-    adj = 4 * n_quads_adj * (vb_adj + 4) + 4 * (nb + 1) + 4 * nv + 8 * nb
-    return fwd, adj
-
-
 def time_kernel(fn, reps, torch):
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     fn()
@@ -67,10 +53,9 @@ def cpu_baseline(case, n_iter):
                   case.n_rows, case.n_cols, case.max_leaf_step, max_cg_iter=n_iter, with_margins=False)
     dt = time.perf_counter() - t0
     n_it = len(res.order)
-    # one adjoint for the empty plan; per master solve one fresh forward + adjoint,
-    # then one of each per master iteration
-    nf = n_it + sum(res.master_iters)
-    na = 1 + n_it + sum(res.master_iters)
+    # one adjoint for the empty plan, then one forward + one adjoint per master iteration
+    nf = sum(res.master_iters)
+    na = 1 + sum(res.master_iters)
     return nf, na, n_it, dt
 
 
@@ -130,8 +115,8 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
 
     # algorithmic bytes of the products run during the timed plans
-    vb = {"f32": 4, "bf16": 2, "f16": 2, "fp8": 1}[args.d_store]
-    fwd_b, adj_b = product_bytes(case, vb, vb, *layout_quads(case))
+    lay = prob.layout()
+    fwd_b, adj_b = lay["fwd_bytes"], lay["adj_bytes"]
     n_fwd = sum(r.n_forward for r in reps)
     n_adj = sum(r.n_adjoint for r in reps)
     total_bytes = n_fwd * fwd_b + n_adj * adj_b
@@ -174,6 +159,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_beams": case.n_beams, "beamlets": case.n_beamlets,
                    "voxels": case.n_voxels, "nnz": case.nnz, "d_store": args.d_store,
+                   "layout": "tiled" if lay["tiled"] else "plain",
                    "step": "one full column-generation plan"},
         "plan_s": round(ms_per_step / 1e3, 4),
         "plan": {"cg_iters": reps[-1].cg_iters, "master_iters": reps[-1].master_iters,
@@ -184,7 +170,9 @@ def main():
                      "bytes_per_launch": dom_bytes},
         "products": {"forward_ms": round(fwd_ms, 5), "forward_GBs": round(fwd_gbs, 1), "forward_bytes": fwd_b,
                      "adjoint_ms": round(adj_ms, 5), "adjoint_GBs": round(adj_gbs, 1), "adjoint_bytes": adj_b,
-                     "device_copy_GBs": round(copy_gbs, 1)},
+                     "nnz_per_s_fwd": round(case.nnz / fwd_ms / 1e6, 1), "nnz_per_s_adj": round(case.nnz / adj_ms / 1e6, 1),
+                     "csr_fp32_equiv_GBs_fwd": round(8 * case.nnz / fwd_ms / 1e6, 1),
+                     "device_copy_GBs": round(copy_gbs, 1), "layout": lay},
     }
 
     if not args.no_precision and args.d_store == "f32":
@@ -201,15 +189,6 @@ def main():
 
     prob.close()
     print(json.dumps(out), flush=True)
-
-
-def layout_quads(case):
-    """Quads (rows padded to a multiple of 4 entries) of the voxel-major and the
-    beamlet-major layouts of D."""
-    bm = int(np.sum((np.diff(case.row_ptr) + 3) // 4))
-    cnt = np.bincount(case.col, minlength=case.n_voxels)
-    vm = int(np.sum((cnt + 3) // 4))
-    return vm, bm
 
 
 def precision_study(case, prob32, torch, P, reps, log):

@@ -80,6 +80,10 @@ typedef struct vmat_problem {
     int32_t circular;         /* 0: open chain of eq. 2; 1: add the wrap pair (N,1)       */
     int32_t max_leaf_step;    /* delta: columns a leaf may move per beam index step when  */
                               /* a new aperture is priced; < 0 means unconstrained        */
+    int32_t layout;           /* device layout of D: 0 auto (tiled when every voxel block */
+                              /* fits, else plain), 1 plain quad CSR, 2 tiled (fails with */
+                              /* VMAT_ERR_UNSUPPORTED when a block does not fit)          */
+    int32_t reserved;
 } vmat_problem;
 
 /* Copies D, alpha, beta, T into the library's own device layouts (beamlet-major
@@ -90,6 +94,24 @@ vmat_status vmat_destroy(vmat_handle h);
 const char* vmat_last_error(void);
 /* Device bytes held by the handle (all layouts and work buffers). */
 vmat_status vmat_device_bytes(vmat_handle h, int64_t* bytes);
+
+/* The device layout of D chosen by vmat_create and the bytes one product has to
+ * move through HBM with it (the figure the achieved bandwidth is quoted on):
+ * stored entries x (value + index bytes), row pointers, the gathered vector
+ * read once, the output written once, and for the tiled layout the per-block
+ * beamlet lists, the slot sums (written and read) and their index map.        */
+typedef struct vmat_layout_info {
+    int32_t tiled;          /* 1: tiled layout (LDS-staged gathers), 0: plain quad CSR   */
+    int32_t n_blocks;       /* voxel blocks of the tiled layout                          */
+    int32_t fwd_lanes;      /* lanes per row of the forward kernel                        */
+    int32_t adj_lanes;      /* lanes per row of the adjoint kernel                        */
+    int64_t fwd_entries;    /* stored entries of the forward layout, padding included     */
+    int64_t adj_entries;    /* stored entries of the adjoint layout, padding included     */
+    int64_t slots;          /* (block, beamlet) pairs of the tiled layout                 */
+    int64_t fwd_bytes;      /* algorithmic HBM bytes of one vmat_forward                  */
+    int64_t adj_bytes;      /* algorithmic HBM bytes of one vmat_adjoint                  */
+} vmat_layout_info;
+vmat_status vmat_layout(vmat_handle h, vmat_layout_info* out);
 
 /* Dose of a plan (Sec. 2.1; the constraint of eq. 3):
  *   z_j = sum_k y_k sum_{i in A_k} D_ij, accumulated in FP64, stored as FP32.

@@ -390,7 +390,8 @@ def line_search(z, dz, alpha, beta, T, gG_slope0, gG_curv, t_max, max_steps=50):
     return lo, nev
 
 
-def master(D, alpha, beta, T, theta_deg, gamma, circular, R, C, l, r, occ, y0, opts=MasterOpts()):
+def master(D, alpha, beta, T, theta_deg, gamma, circular, R, C, l, r, occ, y0, opts=MasterOpts(),
+           start=None):
     """Solve min F(z) + gamma G(y), y >= 0, over the intensities of the current
     apertures (Sec. 2.2 master problem: model (3) with the A_k fixed) by
     gradient projection.  Unoccupied beams keep y_k = 0.
@@ -401,15 +402,25 @@ def master(D, alpha, beta, T, theta_deg, gamma, circular, R, C, l, r, occ, y0, o
     conjugate direction.  The step is the exact minimiser of f along the
     direction up to the first bound that blocks (``line_search``); blocking
     intensities are set to 0.  Stops when max_k |min(y_k, grad_k)| <= tol*ref.
+
+    ``start`` = (z, g) carries the dose and beamlet prices of y0 over from the
+    caller (column generation adds an aperture at y = 0, which changes
+    neither); without it both are computed from y0.
     """
     occ_b = np.asarray(occ).astype(bool)
     y = np.where(occ_b, np.asarray(y0, dtype=np.float64), 0.0)
-    z = dose(D, fluence(y, l, r, occ, R, C))            # fresh dose at the start
-    F, dF = penalty(z, alpha, beta, T)
-    g = D @ dF
+    if start is None:
+        z = dose(D, fluence(y, l, r, occ, R, C))
+        F, dF = penalty(z, alpha, beta, T)
+        g = D @ dF
+        n_fwd, n_adj = 1, 1
+    else:
+        z, g = start
+        F, dF = penalty(z, alpha, beta, T)
+        n_fwd, n_adj = 0, 0
     G, dG = smoothing(y, theta_deg, circular)
     grad = beam_sums(g, l, r, occ, R, C) + gamma * dG
-    n_fwd, n_adj, n_ls = 1, 1, 0
+    n_ls = 0
 
     def kkt_of(y, grad):
         v = np.abs(np.minimum(y, grad))[occ_b]
@@ -491,7 +502,9 @@ class SolveResult:
 def solve(D, alpha, beta, T, theta_deg, gamma, circular, R, C, delta, max_cg_iter=None,
           master_opts=MasterOpts(), with_margins=True):
     """Column generation: price one aperture over the unoccupied beams, add it,
-    re-solve the master, until every beam has an aperture (Sec. 2.2; abstract)."""
+    re-solve the master, until every beam has an aperture (Sec. 2.2; abstract).
+    The dose and prices of the current plan carry over from one master solve to
+    the next: the new aperture starts at intensity 0."""
     N = len(theta_deg)
     occ = np.zeros(N, dtype=np.uint8)
     l = np.zeros(N * R, dtype=np.int64)
@@ -515,7 +528,7 @@ def solve(D, alpha, beta, T, theta_deg, gamma, circular, R, C, delta, max_cg_ite
         if ref is None:
             ref = abs(pr.price) if pr.price != 0.0 else 1.0
         mo = dataclasses.replace(master_opts, kkt_ref=ref)
-        m = master(D, alpha, beta, T, theta_deg, gamma, circular, R, C, l, r, occ, y, mo)
+        m = master(D, alpha, beta, T, theta_deg, gamma, circular, R, C, l, r, occ, y, mo, start=(z, g))
         y, z, g = m.y, m.z, m.g
         out.order.append(k)
         out.prices.append(pr.price)

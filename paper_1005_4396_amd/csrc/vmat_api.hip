@@ -61,13 +61,13 @@ vmat_status forward_from_fluence(vmat_ctx* h, const double* x, hipStream_t st) {
         VMAT_LAUNCH_CHECK();
         xs = h->x;
     }
-    return launch_spmv(h, h->vm, xs, h->z, nullptr, st);
+    return launch_fwd(h, xs, h->z, nullptr, st);
 }
 
 vmat_status forward_from_plan(vmat_ctx* h, const double* y, const int32_t* l, const int32_t* r,
                               const uint8_t* occ, double* zout, const int32_t* skip, hipStream_t st) {
     TRY(launch_fluence(h, y, l, r, occ, h->bm.scale, h->x, skip, st));
-    return launch_spmv(h, h->vm, h->x, zout, skip, st);
+    return launch_fwd(h, h->x, zout, skip, st);
 }
 
 vmat_master_opts defaults(const vmat_master_opts* o) {
@@ -95,20 +95,22 @@ vmat_status sync_state(vmat_ctx* h, hipStream_t st) {
 
 // One master solve (Sec. 2.2) on the device; the host only enqueues and reads
 // the done / line-search flags once per iteration.
+// fresh == 0: the handle's z, F'(z) and g already belong to y (the column-
+// generation driver adds apertures at y = 0), so no product is needed to start.
 vmat_status run_master(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
-                       const vmat_master_opts& o, vmat_master_report* rep, hipStream_t st) {
+                       const vmat_master_opts& o, vmat_master_report* rep, hipStream_t st, int fresh = 1) {
     const int32_t* done = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(h->ms) +
                                                            offsetof(MasterState, done));
-    TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, st));
-    TRY(forward_from_plan(h, y, l, r, occ, h->z, nullptr, st));
+    TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, fresh, st));
+    if (fresh) TRY(forward_from_plan(h, y, l, r, occ, h->z, nullptr, st));
     TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
-    TRY(launch_spmv(h, h->bm, h->rz, h->g, nullptr, st));
+    if (fresh) TRY(launch_adj(h, h->rz, h->g, nullptr, st));
     TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, nullptr, st));
-    TRY(launch_master_grad(h, y, occ, 1, st));
+    TRY(launch_master_grad(h, y, occ, fresh ? 1 : 2, st));
     for (;;) {
         TRY(launch_master_dir(h, y, occ, st));
         TRY(launch_fluence(h, h->md, l, r, occ, h->bm.scale, h->x, done, st));
-        TRY(launch_spmv(h, h->vm, h->x, h->dz, done, st));
+        TRY(launch_fwd(h, h->x, h->dz, done, st));
         for (int i = 0; i < 3; ++i) {
             TRY(launch_ls_eval(h, st));
             TRY(launch_ls_ctrl(h, st));
@@ -124,7 +126,7 @@ vmat_status run_master(vmat_ctx* h, const int32_t* l, const int32_t* r, const ui
         }
         TRY(launch_master_step(h, y, st));
         TRY(launch_update(h, st));
-        TRY(launch_spmv(h, h->bm, h->rz, h->g, done, st));
+        TRY(launch_adj(h, h->rz, h->g, done, st));
         TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, done, st));
         TRY(launch_master_grad(h, y, occ, 0, st));
     }
@@ -171,13 +173,13 @@ extern "C" vmat_status vmat_forward(vmat_handle h, const double* x, double* z, h
         VMAT_LAUNCH_CHECK();
         xs = h->x;
     }
-    return launch_spmv(h, h->vm, xs, z, nullptr, st);
+    return launch_fwd(h, xs, z, nullptr, st);
 }
 
 extern "C" vmat_status vmat_adjoint(vmat_handle h, const float* w, double* g, hipStream_t st) {
     TRY(check_handle(h));
     if (!w || !g) return fail(VMAT_ERR_INVALID_ARG, "null w or g");
-    return launch_spmv(h, h->bm, w, g, nullptr, st);
+    return launch_adj(h, w, g, nullptr, st);
 }
 
 extern "C" vmat_status vmat_grad(vmat_handle h, const double* y, const int32_t* l, const int32_t* r,
@@ -189,7 +191,7 @@ extern "C" vmat_status vmat_grad(vmat_handle h, const double* y, const int32_t* 
     double* gout = g ? g : h->g;
     TRY(forward_from_plan(h, y, l, r, occ, h->z, nullptr, st));
     TRY(launch_penalty(h, h->z, z, dFdz, st));
-    TRY(launch_spmv(h, h->bm, h->rz, gout, nullptr, st));
+    TRY(launch_adj(h, h->rz, gout, nullptr, st));
     TRY(launch_beam_sums(h, gout, l, r, occ, h->mgF, nullptr, st));
     return launch_grad_finish(h, y, h->mgF, cost, dfdy, st);
 }
@@ -200,7 +202,7 @@ extern "C" vmat_status vmat_grad_fluence(vmat_handle h, const double* x, double*
     if (!x || !cost) return fail(VMAT_ERR_INVALID_ARG, "null x or cost");
     TRY(forward_from_fluence(h, x, st));
     TRY(launch_penalty(h, h->z, z, dFdz, st));
-    if (g) TRY(launch_spmv(h, h->bm, h->rz, g, nullptr, st));
+    if (g) TRY(launch_adj(h, h->rz, g, nullptr, st));
     return launch_cost_only(h, cost, st);
 }
 
@@ -212,6 +214,35 @@ extern "C" vmat_status vmat_price(vmat_handle h, const double* g, const double* 
     if (!g || !out_beam || !out_price) return fail(VMAT_ERR_INVALID_ARG, "null g or output");
     return launch_price(h, g, y, l, r, occ, out_beam, out_price, beam_prices, 0, 0, nullptr, nullptr, nullptr,
                         nullptr, st);
+}
+
+extern "C" vmat_status vmat_layout(vmat_handle h, vmat_layout_info* out) {
+    TRY(check_handle(h));
+    if (!out) return fail(VMAT_ERR_INVALID_ARG, "null output");
+    const int64_t vb = h->d_store == VMAT_F32 ? 4 : (h->d_store == VMAT_FP8_E4M3 ? 1 : 2);
+    const int64_t nb = h->nb, nv = h->nv, sc = h->d_store == VMAT_FP8_E4M3 ? 4 * nb : 0;
+    vmat_layout_info L = {};
+    L.tiled = h->tl.on ? 1 : 0;
+    L.fwd_entries = h->vm.n_quads * 4;
+    if (h->tl.on) {
+        const Tiled& t = h->tl;
+        L.n_blocks = t.nblk;
+        L.fwd_lanes = t.fG;
+        L.adj_lanes = t.aG;
+        L.adj_entries = t.a_quads * 4;
+        L.slots = t.S;
+        L.fwd_bytes = L.fwd_entries * (vb + 2) + 4 * (nv + 1) + 4 * t.S + 8 * nb + 8 * nv;
+        L.adj_bytes = L.adj_entries * (vb + 2) + 4 * (t.S + 1) + 4 * nv + 16 * t.S + 4 * (nb + 1) + 4 * t.S +
+                      8 * nb + sc;
+    } else {
+        L.fwd_lanes = h->vm.lanes_per_row;
+        L.adj_lanes = h->bm.lanes_per_row;
+        L.adj_entries = h->bm.n_quads * 4;
+        L.fwd_bytes = L.fwd_entries * (vb + 4) + 4 * (nv + 1) + 8 * nb + 8 * nv;
+        L.adj_bytes = L.adj_entries * (vb + 4) + 4 * (nb + 1) + 4 * nv + 8 * nb + sc;
+    }
+    *out = L;
+    return VMAT_OK;
 }
 
 extern "C" vmat_status vmat_master(vmat_handle h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
@@ -260,7 +291,7 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
     } else {
         VMAT_HIP(hipMemsetAsync(h->z, 0, h->nv * sizeof(double), st));
         TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
-        TRY(launch_spmv(h, h->bm, h->rz, h->g, nullptr, st));
+        TRY(launch_adj(h, h->rz, h->g, nullptr, st));
         TRY(launch_cost_only(h, h->cost2, st));
         R.n_adjoint += 1;
         double c0 = 0.0;
@@ -278,7 +309,7 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
         }
         vmat_master_opts mo = so.master;
         mo.kkt_ref = ref;
-        vmat_status rc = run_master(h, l, r, occ, y, mo, &mr, st);
+        vmat_status rc = run_master(h, l, r, occ, y, mo, &mr, st, /*fresh=*/0);
         if (rc != VMAT_OK && rc != VMAT_ERR_NOT_CONVERGED) return rc;
         if (rc == VMAT_ERR_NOT_CONVERGED) R.not_converged++;
         R.master_iters += mr.iters; R.n_forward += mr.n_forward; R.n_adjoint += mr.n_adjoint;

@@ -305,6 +305,28 @@ static vmat_status scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint64
     return VMAT_OK;
 }
 
+vmat_status scan_u32_dev(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t st) {
+    uint64_t* tiles = nullptr;
+    int* ovf = nullptr;
+    const int64_t ntiles = n / SCAN_TILE + 2;
+    if (hipMalloc((void**)&tiles, (ntiles + 1) * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc((void**)&ovf, sizeof(int)) != hipSuccess) {
+        if (tiles) (void)hipFree(tiles);
+        return fail(VMAT_ERR_ALLOC, "hipMalloc failed in scan");
+    }
+    int flag = 0;
+    vmat_status rc = VMAT_OK;
+    if (hipMemsetAsync(ovf, 0, sizeof(int), st) != hipSuccess) rc = fail(VMAT_ERR_DEVICE, "hipMemsetAsync failed");
+    if (rc == VMAT_OK) rc = scan_u32(in, n, out, tiles, ovf, st);
+    if (rc == VMAT_OK && (hipMemcpyAsync(&flag, ovf, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                          hipStreamSynchronize(st) != hipSuccess))
+        rc = fail(VMAT_ERR_DEVICE, "scan readback failed");
+    (void)hipFree(tiles);
+    (void)hipFree(ovf);
+    if (rc == VMAT_OK && flag) rc = fail(VMAT_ERR_UNSUPPORTED, "index range exceeds 32 bits");
+    return rc;
+}
+
 template <int FMT>
 static vmat_status build_layouts(vmat_ctx* h, const vmat_problem* p, hipStream_t st, int* dflag) {
     const int64_t nb = h->nb, nv = h->nv;
@@ -394,6 +416,23 @@ static vmat_status build_layouts(vmat_ctx* h, const vmat_problem* p, hipStream_t
     h->vm.lanes_per_row = pick_lanes(nv > 0 ? 4.0 * (double)h->vm.n_quads / (double)nv : 0.0);
     h->vm.scale = nullptr;
     cleanup();
+    if (h->layout_req != 1) {
+        rc = build_tiled(h, p, st);
+        if (rc != VMAT_OK) {
+            free_tiled(h);
+            if (h->layout_req == 2 || rc != VMAT_ERR_UNSUPPORTED) return rc;
+            set_error("");
+        } else {
+            // the tiled copies replace the plain index arrays and beamlet-major values
+            (void)hipFree(h->vm.col);
+            (void)hipFree(h->bm.col);
+            (void)hipFree(h->bm.val);
+            h->bytes -= (int64_t)h->vm.n_quads * 16 + (int64_t)h->bm.n_quads * 4 * (4 + vb);
+            h->vm.col = nullptr;
+            h->bm.col = nullptr;
+            h->bm.val = nullptr;
+        }
+    }
     return VMAT_OK;
 #undef TRY_C
 #undef HIP_C
@@ -408,6 +447,7 @@ static void free_all(vmat_ctx* h) {
     F(h->my); F(h->mgrad); F(h->mgrad_prev); F(h->md); F(h->md_prev); F(h->mgF); F(h->mW); F(h->mW_prev);
     F(h->ms);
     if (h->ms_host) (void)hipHostFree(h->ms_host);
+    free_tiled(h);
     F(h->row_S); F(h->row_l); F(h->row_r); F(h->row_m); F(h->bprice); F(h->pbeam); F(h->pscore); F(h->cost2);
     F(h->tr.beam); F(h->tr.price); F(h->tr.margin); F(h->tr.row_margin); F(h->tr.cost); F(h->tr.miters);
 }
@@ -432,6 +472,8 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     if (!p->theta_deg || !p->row_ptr || (p->nnz > 0 && (!p->col || !p->val)) || !p->alpha || !p->beta || !p->T)
         return fail(VMAT_ERR_INVALID_ARG, "null array in problem");
     if (p->d_store < VMAT_F32 || p->d_store > VMAT_FP8_E4M3) return fail(VMAT_ERR_INVALID_ARG, "unknown d_store");
+    if (p->layout < 0 || p->layout > 2) return fail(VMAT_ERR_INVALID_ARG, "unknown layout");
+    if (p->n_beams > 4096) return fail(VMAT_ERR_UNSUPPORTED, "more than 4096 beams");
     if (!std::isfinite(p->gamma) || p->gamma < 0.0) return fail(VMAT_ERR_INVALID_ARG, "gamma must be finite and >= 0");
     for (int k = 0; k < p->n_beams; ++k) {
         const double t = p->theta_deg[k];
@@ -446,6 +488,7 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     h->nb = nb; h->nv = p->n_voxels; h->nnz = p->nnz;
     h->d_store = p->d_store; h->gamma = p->gamma;
     h->circular = p->circular ? 1 : 0; h->delta = p->max_leaf_step;
+    h->layout_req = p->layout;
     h->theta.assign(p->theta_deg, p->theta_deg + p->n_beams);
     (void)hipGetDevice(&h->device);
 

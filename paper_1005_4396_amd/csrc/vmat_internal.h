@@ -39,6 +39,46 @@ struct QuadCsr {
     int lanes_per_row = 16;     // lanes cooperating on one row (power of 2, <= 64)
 };
 
+// Tiled layouts of D.  The voxels are cut into blocks of consecutive indices
+// (at most TILE_VOXELS each) such that the distinct beamlets reaching a block
+// (its list) number at most TILE_LIST.  Per block:
+//   forward: the block's voxel rows (voxel-major quad CSR, as `vm`) with 16-bit
+//            indices into the block's beamlet list; the list's x values are
+//            staged in LDS (FP64) and gathered from there;
+//   adjoint: one row per list entry (slot) holding that beamlet's entries in
+//            the block, with 16-bit voxel offsets from the block start; the
+//            block's slice of the gathered vector is staged in LDS (FP32); the
+//            slot results are summed per beamlet over its blocks in block order.
+constexpr int TILE_VOXELS = 16384;
+constexpr int TILE_LIST = 8192;
+constexpr int TILE_THREADS = 512;
+constexpr int TILE_ROWS = 2048;   // rows per work item (their starts are staged in LDS)
+
+struct Tiled {
+    bool on = false;
+    int nblk = 0;
+    int64_t S = 0;                // total list length (slots)
+    int32_t* bounds = nullptr;    // [nblk+1] voxel boundaries
+    uint32_t* loff = nullptr;     // [nblk+1] list offsets
+    uint32_t* list = nullptr;     // [S] beamlet of each slot
+    // forward
+    uint16_t* fcol = nullptr;     // [4 * vm.n_quads]
+    int4* fwork = nullptr;        // (block, first row, end row, 0)
+    int n_fwork = 0;
+    int fG = 8;
+    // adjoint
+    uint32_t* aqptr = nullptr;    // [S+1] slot row starts in quads
+    uint16_t* acol = nullptr;     // [4 * a_quads]
+    void* aval = nullptr;         // [4 * a_quads]
+    int64_t a_quads = 0;
+    int4* awork = nullptr;        // (block, first slot, end slot, 0)
+    int n_awork = 0;
+    int aG = 4;
+    double* part = nullptr;       // [S] slot sums
+    uint32_t* red_ptr = nullptr;  // [nb+1]
+    uint32_t* red_slot = nullptr; // [S] slots of each beamlet, in block order
+};
+
 // Scalars and small vectors of the master iteration, resident on the device.
 struct MasterState {
     // line search
@@ -76,6 +116,8 @@ struct vmat_ctx {
 
     vmat::QuadCsr bm;              // beamlet-major (rows = beamlets): adjoint g = D r
     vmat::QuadCsr vm;              // voxel-major (rows = voxels): forward z = D^T x
+    vmat::Tiled tl;                // tiled forms of both (used when tl.on)
+    int32_t layout_req = 0;
     float4* abT = nullptr;         // [nv] (alpha, beta, T, 0)
 
     // work buffers

@@ -21,6 +21,14 @@ vmat_status launch_spmv(const vmat_ctx* h, const QuadCsr& A, const double* x, do
 vmat_status launch_spmv(const vmat_ctx* h, const QuadCsr& A, const float* x, double* out,
                         const int32_t* skip, hipStream_t st);
 
+// Dispatch to the tiled or the plain layout.
+// forward: out = D^T x (x: fluence, FP8 scale already folded in); adjoint: g = D w.
+vmat_status launch_fwd(const vmat_ctx* h, const double* x, double* out, const int32_t* skip, hipStream_t st);
+vmat_status launch_adj(const vmat_ctx* h, const float* w, double* g, const int32_t* skip, hipStream_t st);
+vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st);
+void free_tiled(vmat_ctx* h);
+vmat_status scan_u32_dev(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t st);
+
 // F'(z) into rz (FP32, for the adjoint gather), optional FP32 copies of z and
 // F'(z), and block partial sums of F(z) into part slot 0.
 vmat_status launch_penalty(const vmat_ctx* h, const double* z, float* z_out, float* dF_out, hipStream_t st);
@@ -37,7 +45,8 @@ vmat_status launch_cost_only(const vmat_ctx* h, double* cost, hipStream_t st);
 
 // ---- master iteration pieces (device-resident state in h->ms)
 vmat_status launch_master_begin(const vmat_ctx* h, double* y, const uint8_t* occ, int max_iter, int ls_max,
-                                double tol, double kkt_ref, hipStream_t st);
+                                double tol, double kkt_ref, int fresh, hipStream_t st);
+// first: 0 after a master step, 1 at a fresh start, 2 at a carried-over start.
 vmat_status launch_master_grad(const vmat_ctx* h, const double* y, const uint8_t* occ, int first,
                                hipStream_t st);
 vmat_status launch_master_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, hipStream_t st);

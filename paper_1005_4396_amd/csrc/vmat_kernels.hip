@@ -9,6 +9,7 @@
 
 #include <cmath>
 
+#include "vmat_block.h"
 #include "vmat_formats.h"
 #include "vmat_internal.h"
 #include "vmat_kernels.h"
@@ -39,45 +40,6 @@ __device__ __forceinline__ double reduce_part(const double* part, int n, double*
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += BLOCK) s += part[i];
     return block_sum(s, sh);
-}
-
-// ---------------------------------------------------------------- eq. 2 on the device
-// Pairs in the fixed order (0,1), (1,2), ..., (N-2,N-1), then (N-1,0) if circular.
-
-__device__ double smoothing_dev(const double* y, const double* th, int N, int circ, double* dG) {
-    double G = 0.0;
-    if (dG)
-        for (int k = 0; k < N; ++k) dG[k] = 0.0;
-    for (int k = 0; k + 1 < N; ++k) {
-        const double w = th[k + 1] - th[k], diff = y[k + 1] - y[k];
-        G += diff * diff / w;
-        if (dG) {
-            dG[k] -= 2.0 * diff / w;
-            dG[k + 1] += 2.0 * diff / w;
-        }
-    }
-    if (circ && N > 1) {
-        const double w = th[0] + 360.0 - th[N - 1], diff = y[0] - y[N - 1];
-        G += diff * diff / w;
-        if (dG) {
-            dG[N - 1] -= 2.0 * diff / w;
-            dG[0] += 2.0 * diff / w;
-        }
-    }
-    return G;
-}
-
-__device__ double smoothing_curv_dev(const double* d, const double* th, int N, int circ) {
-    double c = 0.0;
-    for (int k = 0; k + 1 < N; ++k) {
-        const double w = th[k + 1] - th[k], e = d[k + 1] - d[k];
-        c += 2.0 * e * e / w;
-    }
-    if (circ && N > 1) {
-        const double w = th[0] + 360.0 - th[N - 1], e = d[0] - d[N - 1];
-        c += 2.0 * e * e / w;
-    }
-    return c;
 }
 
 // ---------------------------------------------------------------- fluence
@@ -249,162 +211,184 @@ vmat_status launch_beam_sums(const vmat_ctx* h, const double* g, const int32_t* 
 
 // ---------------------------------------------------------------- cost assembly
 
-__global__ __launch_bounds__(BLOCK) void k_grad_finish(int N, const double* __restrict__ part, int n_part,
-                                                       const double* __restrict__ y, const double* __restrict__ th,
-                                                       int circ, double gamma, const double* __restrict__ gF,
-                                                       double* __restrict__ cost, double* __restrict__ dfdy,
-                                                       int cost_only) {
-    extern __shared__ double dG[];
+__global__ __launch_bounds__(CTRL) void k_grad_finish(int N, const double* __restrict__ part, int n_part,
+                                                      const double* __restrict__ y, const double* __restrict__ th,
+                                                      int circ, double gamma, const double* __restrict__ gF,
+                                                      double* __restrict__ cost, double* __restrict__ dfdy,
+                                                      int cost_only) {
     __shared__ double sh[4];
     const double F = reduce_part(part, n_part, sh);
-    if (threadIdx.x != 0) return;
-    cost[0] = F;
-    if (cost_only) return;
-    const double G = smoothing_dev(y, th, N, circ, dG);
-    cost[1] = gamma * G;
+    if (cost_only) {
+        if (threadIdx.x == 0) cost[0] = F;
+        return;
+    }
+    const double G = smoothing_G(y, th, N, circ, sh);
+    if (threadIdx.x == 0) {
+        cost[0] = F;
+        cost[1] = gamma * G;
+    }
     if (dfdy)
-        for (int k = 0; k < N; ++k) dfdy[k] = gF[k] + gamma * dG[k];
+        for (int k = threadIdx.x; k < N; k += CTRL) dfdy[k] = gF[k] + gamma * dG_at(k, y, th, N, circ);
 }
 
 vmat_status launch_grad_finish(const vmat_ctx* h, const double* y, const double* gF, double* cost, double* dfdy,
                                hipStream_t st) {
-    k_grad_finish<<<1, BLOCK, h->N * sizeof(double), st>>>(h->N, h->part, h->n_part, y, h->d_theta, h->circular,
-                                                          h->gamma, gF, cost, dfdy, 0);
+    k_grad_finish<<<1, CTRL, 0, st>>>(h->N, h->part, h->n_part, y, h->d_theta, h->circular, h->gamma, gF, cost,
+                                     dfdy, 0);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
 
 vmat_status launch_cost_only(const vmat_ctx* h, double* cost, hipStream_t st) {
-    k_grad_finish<<<1, BLOCK, h->N * sizeof(double), st>>>(h->N, h->part, h->n_part, nullptr, h->d_theta,
-                                                          h->circular, h->gamma, nullptr, cost, nullptr, 1);
+    k_grad_finish<<<1, CTRL, 0, st>>>(h->N, h->part, h->n_part, nullptr, h->d_theta, h->circular, h->gamma,
+                                     nullptr, cost, nullptr, 1);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
 
 // ---------------------------------------------------------------- master control (one workgroup)
+// All per-beam work is spread over the 256 threads; scalars are combined with
+// fixed-order block reductions and written by thread 0.
 
-__global__ void k_master_begin(int N, double* __restrict__ y, const uint8_t* __restrict__ occ, MasterState* ms,
-                               int max_iter, int ls_max, double tol, double kkt_ref) {
-    if (threadIdx.x != 0) return;
-    for (int k = 0; k < N; ++k)
+__global__ __launch_bounds__(CTRL) void k_master_begin(int N, double* __restrict__ y,
+                                                       const uint8_t* __restrict__ occ, MasterState* ms,
+                                                       int max_iter, int ls_max, double tol, double kkt_ref,
+                                                       int fresh) {
+    for (int k = threadIdx.x; k < N; k += CTRL)
         if (!occ[k]) y[k] = 0.0;
-    MasterState s = {};
-    s.max_iter = max_iter;
-    s.ls_max = ls_max;
-    s.tol = tol;
-    s.kkt_ref = kkt_ref;
-    s.n_fwd = 1;
-    s.ls_done = 1;
-    *ms = s;
+    if (threadIdx.x == 0) {
+        MasterState s = {};
+        s.max_iter = max_iter;
+        s.ls_max = ls_max;
+        s.tol = tol;
+        s.kkt_ref = kkt_ref;
+        s.n_fwd = fresh ? 1 : 0;
+        s.ls_done = 1;
+        *ms = s;
+    }
 }
 
 vmat_status launch_master_begin(const vmat_ctx* h, double* y, const uint8_t* occ, int max_iter, int ls_max,
-                                double tol, double kkt_ref, hipStream_t st) {
-    k_master_begin<<<1, 64, 0, st>>>(h->N, y, occ, h->ms, max_iter, ls_max, tol, kkt_ref);
+                                double tol, double kkt_ref, int fresh, hipStream_t st) {
+    k_master_begin<<<1, CTRL, 0, st>>>(h->N, y, occ, h->ms, max_iter, ls_max, tol, kkt_ref, fresh);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
 
 // After the adjoint: grad = sum over the aperture + gamma dG/dy; cost; iteration count.
-__global__ __launch_bounds__(BLOCK) void k_master_grad(int N, const double* __restrict__ part, int n_part,
-                                                       const double* __restrict__ y, const uint8_t* __restrict__ occ,
-                                                       const double* __restrict__ th, int circ, double gamma,
-                                                       const double* __restrict__ gF, double* __restrict__ grad,
-                                                       MasterState* ms, int first) {
-    extern __shared__ double dG[];
+__global__ __launch_bounds__(CTRL) void k_master_grad(int N, const double* __restrict__ part, int n_part,
+                                                      const double* __restrict__ y, const uint8_t* __restrict__ occ,
+                                                      const double* __restrict__ th, int circ, double gamma,
+                                                      const double* __restrict__ gF, double* __restrict__ grad,
+                                                      MasterState* ms, int first) {
     __shared__ double sh[4];
     if (!first && ms->done) return;
     const double F = reduce_part(part, n_part, sh);
+    const double G = smoothing_G(y, th, N, circ, sh);
+    double ref = 0.0;
+    for (int k = threadIdx.x; k < N; k += CTRL) {
+        const double gk = gF[k] + gamma * dG_at(k, y, th, N, circ);
+        grad[k] = gk;
+        if (occ[k]) ref = fmax(ref, fabs(gk));
+    }
+    ref = bmax(ref, sh);
     if (threadIdx.x != 0) return;
     MasterState& s = *ms;
-    const double G = smoothing_dev(y, th, N, circ, dG);
-    for (int k = 0; k < N; ++k) grad[k] = gF[k] + gamma * dG[k];
     s.F = F;
     s.gG = gamma * G;
-    s.n_adj += 1;
+    if (first != 2) s.n_adj += 1;
     if (first) {
         s.it = 0;
-        if (!(s.kkt_ref > 0.0)) {
-            double ref = 0.0;
-            for (int k = 0; k < N; ++k)
-                if (occ[k]) ref = fmax(ref, fabs(grad[k]));
-            s.kkt_ref = ref == 0.0 ? 1.0 : ref;
-        }
+        if (!(s.kkt_ref > 0.0)) s.kkt_ref = ref == 0.0 ? 1.0 : ref;
     } else {
         s.it += 1;
     }
 }
 
 vmat_status launch_master_grad(const vmat_ctx* h, const double* y, const uint8_t* occ, int first, hipStream_t st) {
-    k_master_grad<<<1, BLOCK, h->N * sizeof(double), st>>>(h->N, h->part, h->n_part, y, occ, h->d_theta,
-                                                          h->circular, h->gamma, h->mgF, h->mgrad, h->ms, first);
+    k_master_grad<<<1, CTRL, 0, st>>>(h->N, h->part, h->n_part, y, occ, h->d_theta, h->circular, h->gamma, h->mgF,
+                                     h->mgrad, h->ms, first);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
 
 // KKT test, then the search direction on the free face and the line-search set-up.
-__global__ void k_master_dir(int N, const double* __restrict__ y, const double* __restrict__ grad,
-                             const double* __restrict__ grad_prev, double* __restrict__ d,
-                             const double* __restrict__ d_prev, uint8_t* __restrict__ W,
-                             const uint8_t* __restrict__ W_prev, const uint8_t* __restrict__ occ,
-                             const double* __restrict__ th, int circ, double gamma, MasterState* ms) {
-    extern __shared__ double dG[];
-    if (threadIdx.x != 0) return;
-    MasterState& s = *ms;
-    if (s.done) return;
+__global__ __launch_bounds__(CTRL) void k_master_dir(int N, const double* __restrict__ y,
+                                                     const double* __restrict__ grad,
+                                                     const double* __restrict__ grad_prev, double* __restrict__ d,
+                                                     const double* __restrict__ d_prev, uint8_t* __restrict__ W,
+                                                     const uint8_t* __restrict__ W_prev,
+                                                     const uint8_t* __restrict__ occ, const double* __restrict__ th,
+                                                     int circ, double gamma, MasterState* ms) {
+    __shared__ double sh[4];
+    __shared__ int shi[4];
+    if (ms->done) return;
+    const int have_prev = ms->have_prev;
     double kkt = 0.0;
-    for (int k = 0; k < N; ++k)
+    int changed = 0;
+    for (int k = threadIdx.x; k < N; k += CTRL) {
         if (occ[k]) kkt = fmax(kkt, fabs(fmin(y[k], grad[k])));
-    s.kkt = kkt;
-    if (kkt <= s.tol * s.kkt_ref) {
-        s.converged = 1;
-        s.done = 1;
-        return;
-    }
-    if (s.it >= s.max_iter) {
-        s.done = 1;
-        return;
-    }
-    int same = s.have_prev;
-    for (int k = 0; k < N; ++k) {
         const uint8_t w = occ[k] && (y[k] > 0.0 || grad[k] < 0.0);
         W[k] = w;
-        if (w != W_prev[k]) same = 0;
+        if (w != W_prev[k]) changed = 1;
         d[k] = w ? -grad[k] : 0.0;
     }
-    if (same) {
+    kkt = bmax(kkt, sh);
+    changed = bor(changed, shi);
+    const double tol_abs = ms->tol * ms->kkt_ref;
+    if (kkt <= tol_abs || ms->it >= ms->max_iter) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ms->kkt = kkt;
+            ms->converged = kkt <= tol_abs;
+            ms->done = 1;
+        }
+        return;
+    }
+    double b_cg = 0.0;
+    if (have_prev && !changed) {
         double den = 0.0, num = 0.0;
-        for (int k = 0; k < N; ++k) {
+        for (int k = threadIdx.x; k < N; k += CTRL) {
             const double gp = W[k] ? grad_prev[k] : 0.0, gw = W[k] ? grad[k] : 0.0;
             den += gp * gp;
             num += gw * (gw - gp);
         }
-        const double b = den > 0.0 ? fmax(0.0, num / den) : 0.0;
+        den = bsum(den, sh);
+        num = bsum(num, sh);
+        b_cg = den > 0.0 ? fmax(0.0, num / den) : 0.0;
         double slope = 0.0;
-        for (int k = 0; k < N; ++k) {
-            const double dc = W[k] ? -grad[k] + b * d_prev[k] : 0.0;
+        for (int k = threadIdx.x; k < N; k += CTRL) {
+            const double dc = W[k] ? -grad[k] + b_cg * d_prev[k] : 0.0;
             slope += dc * grad[k];
         }
+        slope = bsum(slope, sh);
         if (slope < 0.0)
-            for (int k = 0; k < N; ++k) d[k] = W[k] ? -grad[k] + b * d_prev[k] : 0.0;
-        s.beta_cg = b;
+            for (int k = threadIdx.x; k < N; k += CTRL) d[k] = W[k] ? -grad[k] + b_cg * d_prev[k] : 0.0;
+        __syncthreads();
     }
-    double t_max = INFINITY;
+    double tmax = INFINITY, sl = 0.0;
     int any = 0;
-    for (int k = 0; k < N; ++k) {
-        if (d[k] < 0.0) t_max = fmin(t_max, y[k] / (-d[k]));
-        if (d[k] != 0.0) any = 1;
+    for (int k = threadIdx.x; k < N; k += CTRL) {
+        const double dk = d[k];
+        if (dk < 0.0) tmax = fmin(tmax, y[k] / (-dk));
+        if (dk != 0.0) any = 1;
+        sl += dG_at(k, y, th, N, circ) * dk;
     }
+    tmax = bmin(tmax, sh);
+    any = bor(any, shi);
+    sl = bsum(sl, sh);
+    const double curv = smoothing_dHd(d, th, N, circ, sh);
+    if (threadIdx.x != 0) return;
+    MasterState& s = *ms;
+    s.kkt = kkt;
     if (!any) {
         s.done = 1;
         return;
     }
-    smoothing_dev(y, th, N, circ, dG);
-    double sl = 0.0;
-    for (int k = 0; k < N; ++k) sl += dG[k] * d[k];
+    s.beta_cg = b_cg;
     s.slope0 = gamma * sl;
-    s.curv = gamma * smoothing_curv_dev(d, th, N, circ);
-    s.t_max = t_max;
+    s.curv = gamma * curv;
+    s.t_max = tmax;
     s.ls_phase = 0;
     s.t_eval = 0.0;
     s.ls_steps = 0;
@@ -413,8 +397,8 @@ __global__ void k_master_dir(int N, const double* __restrict__ y, const double* 
 }
 
 vmat_status launch_master_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, hipStream_t st) {
-    k_master_dir<<<1, 64, h->N * sizeof(double), st>>>(h->N, y, h->mgrad, h->mgrad_prev, h->md, h->md_prev, h->mW,
-                                                      h->mW_prev, occ, h->d_theta, h->circular, h->gamma, h->ms);
+    k_master_dir<<<1, CTRL, 0, st>>>(h->N, y, h->mgrad, h->mgrad_prev, h->md, h->md_prev, h->mW, h->mW_prev, occ,
+                                    h->d_theta, h->circular, h->gamma, h->ms);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
@@ -512,28 +496,26 @@ vmat_status launch_ls_ctrl(const vmat_ctx* h, hipStream_t st) {
 }
 
 // y <- max(0, y + t* d); bounds that block at t* = t_max become exactly 0.
-__global__ void k_master_step(int N, double* __restrict__ y, const double* __restrict__ d,
-                              double* __restrict__ d_prev, const double* __restrict__ grad,
-                              double* __restrict__ grad_prev, const uint8_t* __restrict__ W,
-                              uint8_t* __restrict__ W_prev, MasterState* ms) {
-    if (threadIdx.x != 0) return;
-    MasterState& s = *ms;
-    if (s.done) return;
-    const double t = s.t_star;
-    for (int k = 0; k < N; ++k) {
+__global__ __launch_bounds__(CTRL) void k_master_step(int N, double* __restrict__ y, const double* __restrict__ d,
+                                                      double* __restrict__ d_prev, const double* __restrict__ grad,
+                                                      double* __restrict__ grad_prev, const uint8_t* __restrict__ W,
+                                                      uint8_t* __restrict__ W_prev, MasterState* ms) {
+    if (ms->done) return;
+    const double t = ms->t_star, tmax = ms->t_max;
+    for (int k = threadIdx.x; k < N; k += CTRL) {
         const double yo = y[k], dk = d[k];
         double yn = fmax(0.0, yo + t * dk);
-        if (t == s.t_max && dk < 0.0 && yo / (-dk) == s.t_max) yn = 0.0;
+        if (t == tmax && dk < 0.0 && yo / (-dk) == tmax) yn = 0.0;
         y[k] = yn;
         d_prev[k] = dk;
         grad_prev[k] = grad[k];
         W_prev[k] = W[k];
     }
-    s.have_prev = 1;
+    if (threadIdx.x == 0) ms->have_prev = 1;
 }
 
 vmat_status launch_master_step(const vmat_ctx* h, double* y, hipStream_t st) {
-    k_master_step<<<1, 64, 0, st>>>(h->N, y, h->md, h->md_prev, h->mgrad, h->mgrad_prev, h->mW, h->mW_prev, h->ms);
+    k_master_step<<<1, CTRL, 0, st>>>(h->N, y, h->md, h->md_prev, h->mgrad, h->mgrad_prev, h->mW, h->mW_prev, h->ms);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }

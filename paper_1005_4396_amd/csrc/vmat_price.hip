@@ -10,6 +10,7 @@
 
 #include <cmath>
 
+#include "vmat_block.h"
 #include "vmat_internal.h"
 #include "vmat_kernels.h"
 
@@ -127,17 +128,29 @@ __global__ __launch_bounds__(256) void k_price_rows(int N, int R, int C, int del
 }
 
 // Beam prices, the chosen beam, and (apply) the update of the plan state.
-__global__ __launch_bounds__(256) void k_price_beams(int N, int R, double gamma, int circ,
-                                                     const double* __restrict__ th, const double* __restrict__ y,
-                                                     const uint8_t* __restrict__ occ,
-                                                     const double* __restrict__ rowS, const int32_t* __restrict__ rowl,
-                                                     const int32_t* __restrict__ rowr, const double* __restrict__ rowm,
-                                                     double* __restrict__ bprice, int32_t* __restrict__ out_beam,
-                                                     double* __restrict__ out_price, double* __restrict__ user_bp,
-                                                     int apply, int iter, int32_t* __restrict__ lw,
-                                                     int32_t* __restrict__ rw, uint8_t* __restrict__ occw,
-                                                     double* __restrict__ yw, SolveTraceDev tr) {
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+__device__ __forceinline__ void better(double& p, int& k, double p2, int k2) {
+    if (k2 >= 0 && (k < 0 || p2 < p || (p2 == p && k2 < k))) {
+        p = p2;
+        k = k2;
+    }
+}
+
+__global__ __launch_bounds__(CTRL) void k_price_beams(int N, int R, double gamma, int circ,
+                                                      const double* __restrict__ th, const double* __restrict__ y,
+                                                      const uint8_t* __restrict__ occ,
+                                                      const double* __restrict__ rowS, const int32_t* __restrict__ rowl,
+                                                      const int32_t* __restrict__ rowr, const double* __restrict__ rowm,
+                                                      double* __restrict__ bprice, int32_t* __restrict__ out_beam,
+                                                      double* __restrict__ out_price, double* __restrict__ user_bp,
+                                                      int apply, int iter, int32_t* __restrict__ lw,
+                                                      int32_t* __restrict__ rw, uint8_t* __restrict__ occw,
+                                                      double* __restrict__ yw, SolveTraceDev tr) {
+    __shared__ double shp[4];
+    __shared__ int shk[4];
+    __shared__ double sh[4];
+    double pb = INFINITY;
+    int kb = -1;
+    for (int k = threadIdx.x; k < N; k += CTRL) {
         double p = INFINITY;
         if (!occ[k]) {
             double tot = 0.0;
@@ -157,43 +170,55 @@ __global__ __launch_bounds__(256) void k_price_beams(int N, int R, double gamma,
                 dG -= 2.0 * (y[b] - 0.0) / w;
             }
             p = tot + gamma * dG;
+            better(pb, kb, p, k);
         }
         bprice[k] = p;
         if (user_bp) user_bp[k] = p;
     }
+    // block argmin with ties to the smallest k
+    for (int off = 32; off > 0; off >>= 1) {
+        const double p2 = __shfl_down(pb, off, 64);
+        const int k2 = __shfl_down(kb, off, 64);
+        better(pb, kb, p2, k2);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        shp[threadIdx.x >> 6] = pb;
+        shk[threadIdx.x >> 6] = kb;
+    }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    int ks = -1;
-    double pb = INFINITY;
-    for (int k = 0; k < N; ++k)
-        if (!occ[k] && (ks < 0 || bprice[k] < pb)) {
-            ks = k;
-            pb = bprice[k];
-        }
+    double pbest = shp[0];
+    int ks = shk[0];
+    for (int i = 1; i < 4; ++i) better(pbest, ks, shp[i], shk[i]);
+    __syncthreads();
     double second = INFINITY;
-    for (int k = 0; k < N; ++k)
+    for (int k = threadIdx.x; k < N; k += CTRL)
         if (!occ[k] && k != ks) second = fmin(second, bprice[k]);
+    second = bmin(second, sh);
     double rm = INFINITY;
     if (ks >= 0)
-        for (int rho = 0; rho < R; ++rho) rm = fmin(rm, rowm[(int64_t)ks * R + rho]);
-    const double margin = ks >= 0 && isfinite(second) ? second - pb : INFINITY;
-    out_beam[0] = ks;
-    for (int rho = 0; rho < R; ++rho) {
-        out_beam[1 + rho] = ks >= 0 ? rowl[(int64_t)ks * R + rho] : 0;
-        out_beam[1 + R + rho] = ks >= 0 ? rowr[(int64_t)ks * R + rho] : 0;
+        for (int rho = threadIdx.x; rho < R; rho += CTRL) rm = fmin(rm, rowm[(int64_t)ks * R + rho]);
+    rm = bmin(rm, sh);
+    for (int rho = threadIdx.x; rho < R; rho += CTRL) {
+        const int32_t lv = ks >= 0 ? rowl[(int64_t)ks * R + rho] : 0;
+        const int32_t rv = ks >= 0 ? rowr[(int64_t)ks * R + rho] : 0;
+        out_beam[1 + rho] = lv;
+        out_beam[1 + R + rho] = rv;
+        if (apply && ks >= 0) {
+            lw[(int64_t)ks * R + rho] = lv;
+            rw[(int64_t)ks * R + rho] = rv;
+        }
     }
-    out_price[0] = pb;
+    if (threadIdx.x != 0) return;
+    const double margin = ks >= 0 && isfinite(second) ? second - pbest : INFINITY;
+    out_beam[0] = ks;
+    out_price[0] = ks >= 0 ? pbest : INFINITY;
     out_price[1] = margin;
     out_price[2] = rm;
     if (apply && ks >= 0) {
         occw[ks] = 1;
         yw[ks] = 0.0;
-        for (int rho = 0; rho < R; ++rho) {
-            lw[(int64_t)ks * R + rho] = rowl[(int64_t)ks * R + rho];
-            rw[(int64_t)ks * R + rho] = rowr[(int64_t)ks * R + rho];
-        }
         tr.beam[iter] = ks;
-        tr.price[iter] = pb;
+        tr.price[iter] = pbest;
         tr.margin[iter] = margin;
         tr.row_margin[iter] = rm;
     }
@@ -206,7 +231,7 @@ vmat_status launch_price(const vmat_ctx* h, const double* g, const double* y, co
     k_price_rows<<<(unsigned)((NR + 3) / 4), 256, 0, st>>>(h->N, h->R, h->C, h->delta, h->circular, g, l, r, occ,
                                                            h->row_S, h->row_l, h->row_r, h->row_m);
     VMAT_LAUNCH_CHECK();
-    k_price_beams<<<1, 256, 0, st>>>(h->N, h->R, h->gamma, h->circular, h->d_theta, y, occ, h->row_S, h->row_l,
+    k_price_beams<<<1, CTRL, 0, st>>>(h->N, h->R, h->gamma, h->circular, h->d_theta, y, occ, h->row_S, h->row_l,
                                      h->row_r, h->row_m, h->bprice, out_beam, out_price, beam_prices, apply, iter,
                                      lw, rw, occw, yw, h->tr);
     VMAT_LAUNCH_CHECK();

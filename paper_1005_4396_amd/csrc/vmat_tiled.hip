@@ -1,0 +1,678 @@
+// Tiled dose product and adjoint with LDS-staged gathers (layout described
+// with `Tiled` in vmat_internal.h), and the builder of that layout.
+//
+// Why: in the plain quad-CSR kernels each non-zero gathers one x (or w) value
+// from global memory at a scattered address; the texture path serves such a
+// gather at about one cache line per lane, which bounds the product well below
+// the HBM rate.  Here a block's gathered values sit in LDS, the column indices
+// shrink to 16 bits (6 B per FP32 non-zero instead of 8), and the global
+// traffic is the coalesced stream of D plus small per-block staging.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vmat_formats.h"
+#include "vmat_internal.h"
+#include "vmat_kernels.h"
+
+namespace vmat {
+
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- kernels
+//
+// A work item is (block, rows [r0, r1)) with at most TILE_ROWS rows.  Its row
+// starts are staged in LDS with the gathered values, so no global load sits
+// between one row and the next.  G lanes share a row; each lane issues the
+// loads of up to U quads of a row at once, and the loads of the group's next
+// row are issued before the current row is summed (two rows in flight per
+// lane group).  Longer rows finish in extra passes.
+
+template <int FMT, int U>
+struct RowBuf {
+    float4 v[U];
+    u16x4 c[U];
+};
+
+template <int FMT, int G, int U>
+__device__ __forceinline__ void load_pass(RowBuf<FMT, U>& b, const void* __restrict__ val, const u16x4* __restrict__ c4,
+                                          uint32_t q, uint32_t q1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t qq = q + (uint32_t)(u * G);
+        if (qq < q1) {
+            b.v[u] = Quad<FMT>::load(val, qq);
+            b.c[u] = __builtin_nontemporal_load(c4 + qq);
+        } else {
+            b.v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            b.c[u] = u16x4{0, 0, 0, 0};
+        }
+    }
+}
+
+template <int FMT, int U, typename ST>
+__device__ __forceinline__ double use_pass(const RowBuf<FMT, U>& b, const ST* __restrict__ xs, double acc) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        acc = fma((double)b.v[u].x, (double)xs[b.c[u].x], acc);
+        acc = fma((double)b.v[u].y, (double)xs[b.c[u].y], acc);
+        acc = fma((double)b.v[u].z, (double)xs[b.c[u].z], acc);
+        acc = fma((double)b.v[u].w, (double)xs[b.c[u].w], acc);
+    }
+    return acc;
+}
+
+// Rows of one work item: rq[k] = start quad of row r0 + k (k <= nrows).
+template <int FMT, int G, int U, typename ST>
+__device__ __forceinline__ void rows_of_item(const uint32_t* __restrict__ rq, int nrows, int row_base,
+                                             const void* __restrict__ val, const u16x4* __restrict__ c4,
+                                             const ST* __restrict__ xs, double* __restrict__ out) {
+    const int grp = threadIdx.x / G, lane = threadIdx.x & (G - 1);
+    constexpr int NGRP = TILE_THREADS / G;
+    int row = grp;
+    RowBuf<FMT, U> cur, nxt;
+    if (row < nrows) load_pass<FMT, G, U>(cur, val, c4, rq[row] + lane, rq[row + 1]);
+    while (row < nrows) {
+        const int next = row + NGRP;
+        if (next < nrows) load_pass<FMT, G, U>(nxt, val, c4, rq[next] + lane, rq[next + 1]);
+        double acc = use_pass<FMT, U>(cur, xs, 0.0);
+        const uint32_t q1 = rq[row + 1];
+        for (uint32_t q = rq[row] + lane + U * G; q < q1; q += U * G) {
+            RowBuf<FMT, U> more;
+            load_pass<FMT, G, U>(more, val, c4, q, q1);
+            acc = use_pass<FMT, U>(more, xs, acc);
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        if (lane == 0) out[row_base + row] = acc;
+        cur = nxt;
+        row = next;
+    }
+}
+
+// Row starts of a work item into LDS, all loads issued before the stores.
+__device__ __forceinline__ void stage_rows(uint32_t* __restrict__ rq, const uint32_t* __restrict__ src, int nrows) {
+    constexpr int K = (TILE_ROWS + TILE_THREADS) / TILE_THREADS;
+    uint32_t v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int u = threadIdx.x + k * TILE_THREADS;
+        v[k] = u <= nrows ? src[u] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int u = threadIdx.x + k * TILE_THREADS;
+        if (u <= nrows) rq[u] = v[k];
+    }
+}
+
+// Forward: rows are voxels of the block; x values of the block's beamlets
+// are staged in LDS.
+template <int FMT, int G, int U>
+__global__ __launch_bounds__(TILE_THREADS) void k_fwd_tiled(const int4* __restrict__ work,
+                                                          const uint32_t* __restrict__ loff,
+                                                          const uint32_t* __restrict__ list,
+                                                          const uint32_t* __restrict__ qptr,
+                                                          const uint16_t* __restrict__ col16,
+                                                          const void* __restrict__ val,
+                                                          const double* __restrict__ x, double* __restrict__ out,
+                                                          const int32_t* __restrict__ skip) {
+    __shared__ double xs[TILE_LIST];
+    __shared__ uint32_t rq[TILE_ROWS + 1];
+    if (skip && *skip) return;
+    const int4 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    const uint32_t l0 = loff[wk.x], ln = loff[wk.x + 1] - l0;
+    const int nrows = wk.z - wk.y;
+    stage_rows(rq, qptr + wk.y, nrows);
+    {
+        constexpr int K = TILE_LIST / TILE_THREADS;
+        uint32_t id[K];
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t u = threadIdx.x + k * TILE_THREADS;
+            id[k] = u < ln ? list[l0 + u] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t u = threadIdx.x + k * TILE_THREADS;
+            v[k] = u < ln ? x[id[k]] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t u = threadIdx.x + k * TILE_THREADS;
+            if (u < ln) xs[u] = v[k];
+        }
+    }
+    __syncthreads();
+    rows_of_item<FMT, G, U, double>(rq, nrows, wk.y, val, reinterpret_cast<const u16x4*>(col16), xs, out);
+}
+
+// Adjoint: rows are the block's slots; the block's slice of w is staged in
+// LDS; each slot row's sum goes to part[slot].
+template <int FMT, int G, int U>
+__global__ __launch_bounds__(TILE_THREADS) void k_adj_tiled(const int4* __restrict__ work,
+                                                          const int32_t* __restrict__ bounds,
+                                                          const uint32_t* __restrict__ aqptr,
+                                                          const uint16_t* __restrict__ col16,
+                                                          const void* __restrict__ val,
+                                                          const float* __restrict__ w, double* __restrict__ part,
+                                                          const int32_t* __restrict__ skip) {
+    __shared__ float ws[TILE_VOXELS];
+    __shared__ uint32_t rq[TILE_ROWS + 1];
+    if (skip && *skip) return;
+    const int4 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    const int32_t j0 = bounds[wk.x], jn = bounds[wk.x + 1] - j0;
+    const int nrows = wk.z - wk.y;
+    stage_rows(rq, aqptr + wk.y, nrows);
+    {
+        constexpr int K = TILE_VOXELS / TILE_THREADS;
+        float v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int u = threadIdx.x + k * TILE_THREADS;
+            v[k] = u < jn ? w[j0 + u] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int u = threadIdx.x + k * TILE_THREADS;
+            if (u < jn) ws[u] = v[k];
+        }
+    }
+    __syncthreads();
+    rows_of_item<FMT, G, U, float>(rq, nrows, wk.y, val, reinterpret_cast<const u16x4*>(col16), ws, part);
+}
+
+// g_i = scale_i * sum of beamlet i's slot sums, in block order.
+__global__ __launch_bounds__(256) void k_adj_reduce(int64_t nb, const uint32_t* __restrict__ red_ptr,
+                                                    const uint32_t* __restrict__ red_slot,
+                                                    const double* __restrict__ part,
+                                                    const float* __restrict__ scale, double* __restrict__ g,
+                                                    const int32_t* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nb) return;
+    double s = 0.0;
+    for (uint32_t k = red_ptr[i]; k < red_ptr[i + 1]; ++k) s += part[red_slot[k]];
+    g[i] = scale ? s * (double)scale[i] : s;
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <int FMT>
+static vmat_status fwd_fmt(const vmat_ctx* h, const double* x, double* out, const int32_t* skip, hipStream_t st) {
+    const Tiled& t = h->tl;
+    const unsigned grid = (unsigned)t.n_fwork;
+    if (grid == 0) return VMAT_OK;
+
+#define FWD(GG) k_fwd_tiled<FMT, GG, 4><<<grid, TILE_THREADS, 0, st>>>(t.fwork, t.loff, t.list, h->vm.qptr, \
+                                                                       t.fcol, h->vm.val, x, out, skip)
+    switch (t.fG) {
+        case 2: FWD(2); break;
+        case 4: FWD(4); break;
+        case 8: FWD(8); break;
+        case 16: FWD(16); break;
+        default: FWD(32); break;
+    }
+#undef FWD
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
+template <int FMT>
+static vmat_status adj_fmt(const vmat_ctx* h, const float* w, double* g, const int32_t* skip, hipStream_t st) {
+    const Tiled& t = h->tl;
+    if (t.n_awork > 0) {
+#define ADJ(GG) k_adj_tiled<FMT, GG, 4><<<(unsigned)t.n_awork, TILE_THREADS, 0, st>>>(t.awork, t.bounds, \
+                                                                                      t.aqptr, t.acol, t.aval, w, \
+                                                                                      t.part, skip)
+        switch (t.aG) {
+            case 2: ADJ(2); break;
+            case 4: ADJ(4); break;
+            case 8: ADJ(8); break;
+            case 16: ADJ(16); break;
+            default: ADJ(32); break;
+        }
+#undef ADJ
+        VMAT_LAUNCH_CHECK();
+    }
+    k_adj_reduce<<<(unsigned)((h->nb + 255) / 256), 256, 0, st>>>(h->nb, t.red_ptr, t.red_slot, t.part, h->bm.scale,
+                                                                  g, skip);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
+vmat_status launch_fwd(const vmat_ctx* h, const double* x, double* out, const int32_t* skip, hipStream_t st) {
+    if (!h->tl.on) return launch_spmv(h, h->vm, x, out, skip, st);
+    switch (h->d_store) {
+        case VMAT_F32: return fwd_fmt<FMT_F32>(h, x, out, skip, st);
+        case VMAT_F16: return fwd_fmt<FMT_F16>(h, x, out, skip, st);
+        case VMAT_BF16: return fwd_fmt<FMT_BF16>(h, x, out, skip, st);
+        default: return fwd_fmt<FMT_FP8>(h, x, out, skip, st);
+    }
+}
+
+vmat_status launch_adj(const vmat_ctx* h, const float* w, double* g, const int32_t* skip, hipStream_t st) {
+    if (!h->tl.on) return launch_spmv(h, h->bm, w, g, skip, st);
+    switch (h->d_store) {
+        case VMAT_F32: return adj_fmt<FMT_F32>(h, w, g, skip, st);
+        case VMAT_F16: return adj_fmt<FMT_F16>(h, w, g, skip, st);
+        case VMAT_BF16: return adj_fmt<FMT_BF16>(h, w, g, skip, st);
+        default: return adj_fmt<FMT_FP8>(h, w, g, skip, st);
+    }
+}
+
+// ---------------------------------------------------------------- builder kernels
+
+// Mark the beamlets of every block in a bitmap (one bitmap of W words per block).
+__global__ void k_blk_mark(int nblk, const int32_t* __restrict__ bounds, const uint32_t* __restrict__ vqptr,
+                           const int32_t* __restrict__ vcol, int64_t W, uint32_t* __restrict__ bits) {
+    const int b = blockIdx.y;
+    if (b >= nblk) return;
+    const int64_t e0 = (int64_t)vqptr[bounds[b]] * 4, e1 = (int64_t)vqptr[bounds[b + 1]] * 4;
+    uint32_t* bm = bits + (int64_t)b * W;
+    for (int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = (uint32_t)vcol[e];
+        atomicOr(&bm[i >> 5], 1u << (i & 31));
+    }
+}
+
+__global__ void k_blk_popc(int nblk, int64_t W, const uint32_t* __restrict__ bits, uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t sh[256];
+    const int b = blockIdx.x;
+    uint32_t c = 0;
+    for (int64_t w = threadIdx.x; w < W; w += 256) c += __popc(bits[(int64_t)b * W + w]);
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[b] = sh[0];
+}
+
+// List of each block (ascending beamlet ids) and per-word rank prefixes.
+__global__ void k_blk_list(int64_t W, const uint32_t* __restrict__ bits, const uint32_t* __restrict__ loff,
+                           uint32_t* __restrict__ wpref, uint32_t* __restrict__ list) {
+    __shared__ uint32_t sh[256];
+    const int b = blockIdx.x;
+    const int64_t per = (W + 255) / 256;
+    const int64_t w0 = min(W, (int64_t)threadIdx.x * per), w1 = min(W, w0 + per);
+    const uint32_t* bm = bits + (int64_t)b * W;
+    uint32_t c = 0;
+    for (int64_t w = w0; w < w1; ++w) c += __popc(bm[w]);
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int t = 0; t < 256; ++t) {
+            const uint32_t v = sh[t];
+            sh[t] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    uint32_t pos = sh[threadIdx.x];
+    for (int64_t w = w0; w < w1; ++w) {
+        wpref[(int64_t)b * W + w] = pos;
+        uint32_t word = bm[w];
+        while (word) {
+            const int bit = __ffs(word) - 1;
+            list[loff[b] + pos] = (uint32_t)(w * 32 + bit);
+            ++pos;
+            word &= word - 1;
+        }
+    }
+}
+
+// 16-bit list index of every voxel-major entry.
+__global__ void k_fw_col16(int nblk, const int32_t* __restrict__ bounds, const uint32_t* __restrict__ vqptr,
+                           const int32_t* __restrict__ vcol, int64_t W, const uint32_t* __restrict__ bits,
+                           const uint32_t* __restrict__ wpref, uint16_t* __restrict__ fcol) {
+    const int b = blockIdx.y;
+    if (b >= nblk) return;
+    const int64_t e0 = (int64_t)vqptr[bounds[b]] * 4, e1 = (int64_t)vqptr[bounds[b + 1]] * 4;
+    const uint32_t* bm = bits + (int64_t)b * W;
+    const uint32_t* wp = wpref + (int64_t)b * W;
+    for (int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = (uint32_t)vcol[e];
+        const uint32_t below = bm[i >> 5] & ((1u << (i & 31)) - 1u);
+        fcol[e] = (uint16_t)(wp[i >> 5] + __popc(below));
+    }
+}
+
+__device__ __forceinline__ int64_t lower_bound_i32(const int32_t* a, int64_t lo, int64_t hi, int32_t key) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Segment of every slot's beamlet row inside its block (from the caller's CSR).
+__global__ void k_adj_len(int64_t S, int nblk, const uint32_t* __restrict__ loff, const int32_t* __restrict__ bounds,
+                          const uint32_t* __restrict__ list, const int64_t* __restrict__ rp,
+                          const int32_t* __restrict__ col, int64_t* __restrict__ seg_lo,
+                          uint32_t* __restrict__ quads) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= S) return;
+    int lo = 0, hi = nblk;  // block of slot s: loff[b] <= s < loff[b+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)loff[mid] <= s) lo = mid; else hi = mid;
+    }
+    const int b = lo;
+    const uint32_t i = list[s];
+    const int64_t a = lower_bound_i32(col, rp[i], rp[i + 1], bounds[b]);
+    const int64_t e = lower_bound_i32(col, a, rp[i + 1], bounds[b + 1]);
+    seg_lo[s] = a;
+    quads[s] = (uint32_t)((e - a + 3) >> 2);
+}
+
+// Copy every slot's segment (encoded values from the beamlet-major copy) with
+// 16-bit offsets from the block start; pad to whole quads.  One wave per slot.
+template <typename VT>
+__global__ void k_adj_fill(int64_t S, int nblk, const uint32_t* __restrict__ loff,
+                           const int32_t* __restrict__ bounds, const uint32_t* __restrict__ list,
+                           const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           const uint32_t* __restrict__ bm_qptr, const VT* __restrict__ bm_val,
+                           const int64_t* __restrict__ seg_lo, const uint32_t* __restrict__ aqptr,
+                           uint16_t* __restrict__ acol, VT* __restrict__ aval) {
+    const int64_t s = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (s >= S) return;
+    int lo = 0, hi = nblk;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)loff[mid] <= s) lo = mid; else hi = mid;
+    }
+    const int32_t j0 = bounds[lo], j1 = bounds[lo + 1];
+    const uint32_t i = list[s];
+    const int64_t a = seg_lo[s];
+    const int64_t n = lower_bound_i32(col, a, rp[i + 1], j1) - a;   // entries of row i inside the block
+    const int64_t dst = (int64_t)aqptr[s] * 4, npad = (int64_t)(aqptr[s + 1] - aqptr[s]) * 4;
+    const int64_t src = (int64_t)bm_qptr[i] * 4 + (a - rp[i]);
+    for (int64_t e = lane; e < npad; e += 64) {
+        const bool real = e < n;
+        acol[dst + e] = real ? (uint16_t)(col[a + e] - j0) : (uint16_t)0;
+        aval[dst + e] = real ? bm_val[src + e] : (VT)0;
+    }
+}
+
+__global__ void k_red_count(int64_t S, const uint32_t* __restrict__ list, uint32_t* __restrict__ cnt) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s < S) atomicAdd(&cnt[list[s]], 1u);
+}
+
+__global__ void k_red_fill(int64_t S, const uint32_t* __restrict__ list, const uint32_t* __restrict__ red_ptr,
+                           uint32_t* __restrict__ fill, uint32_t* __restrict__ slot) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= S) return;
+    const uint32_t i = list[s];
+    slot[red_ptr[i] + atomicAdd(&fill[i], 1u)] = (uint32_t)s;
+}
+
+__global__ void k_red_sort(int64_t nb, const uint32_t* __restrict__ red_ptr, uint32_t* __restrict__ slot) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nb) return;
+    const uint32_t a = red_ptr[i], b = red_ptr[i + 1];
+    for (uint32_t k = a + 1; k < b; ++k) {
+        const uint32_t v = slot[k];
+        uint32_t m = k;
+        while (m > a && slot[m - 1] > v) {
+            slot[m] = slot[m - 1];
+            --m;
+        }
+        slot[m] = v;
+    }
+}
+
+// ---------------------------------------------------------------- builder (host)
+
+vmat_status scan_u32_dev(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t st);  // vmat_build.hip
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    template <typename T>
+    T* as() { return reinterpret_cast<T*>(p); }
+};
+
+hipError_t dmalloc(DevBuf& b, size_t bytes) {
+    return hipMalloc(&b.p, std::max<size_t>(bytes, 16));
+}
+
+int pow2_floor_clamp(double v, int lo, int hi) {
+    int g = lo;
+    while (g * 2 <= hi && g * 2 <= v) g *= 2;
+    return g;
+}
+
+// Work items of about `qpw` quads each, never crossing a block; placed so
+// that consecutive items (same block) land on the same XCD (workgroup w runs
+// on XCD w mod 8).
+std::vector<int4> make_work(const std::vector<int64_t>& row_begin_of_block, const std::vector<uint32_t>& rowq,
+                            int nblk, int64_t qpw, int64_t max_rows) {
+    std::vector<int4> items;
+    for (int b = 0; b < nblk; ++b) {
+        const int64_t r0 = row_begin_of_block[b], r1 = row_begin_of_block[b + 1];
+        int64_t start = r0;
+        uint64_t acc = 0;
+        for (int64_t r = r0; r < r1; ++r) {
+            acc += rowq[r + 1] - rowq[r];
+            if ((int64_t)acc >= qpw || r + 1 - start >= max_rows) {
+                items.push_back(make_int4(b, (int)start, (int)(r + 1), 0));
+                start = r + 1;
+                acc = 0;
+            }
+        }
+        if (start < r1) items.push_back(make_int4(b, (int)start, (int)r1, 0));
+    }
+    const int n = (int)items.size();
+    const int per = (n + 7) / 8;
+    std::vector<int4> out((size_t)per * 8, make_int4(-1, 0, 0, 0));
+    for (int p = 0; p < n; ++p) {
+        const int xcd = p / per, pos = p % per;
+        out[(size_t)pos * 8 + xcd] = items[p];
+    }
+    return out;
+}
+
+}  // namespace
+
+// Builds h->tl from the voxel-major and beamlet-major copies and the caller's
+// CSR.  Returns VMAT_ERR_UNSUPPORTED when some block cannot be made to fit.
+vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
+    Tiled& t = h->tl;
+    const int64_t nv = h->nv, nb = h->nb;
+    const int64_t W = (nb + 31) / 32;
+    std::vector<int64_t> bounds;
+    for (int64_t j = 0; j < nv; j += TILE_VOXELS) bounds.push_back(j);
+    bounds.push_back(nv);
+
+    DevBuf d_bounds, d_bits, d_cnt;
+    std::vector<uint32_t> cnt;
+    for (int round = 0;; ++round) {
+        const int nblk = (int)bounds.size() - 1;
+        if ((double)nblk * (double)W * 4.0 > 2e9 || nblk > 60000)
+            return fail(VMAT_ERR_UNSUPPORTED, "voxel blocking needs too many blocks");
+        std::vector<int32_t> b32(bounds.begin(), bounds.end());
+        d_bounds = DevBuf();
+        d_bits = DevBuf();
+        d_cnt = DevBuf();
+        VMAT_HIP(dmalloc(d_bounds, b32.size() * 4));
+        VMAT_HIP(dmalloc(d_bits, (size_t)nblk * W * 4));
+        VMAT_HIP(dmalloc(d_cnt, (size_t)nblk * 4));
+        VMAT_HIP(hipMemcpyAsync(d_bounds.p, b32.data(), b32.size() * 4, hipMemcpyHostToDevice, st));
+        VMAT_HIP(hipMemsetAsync(d_bits.p, 0, (size_t)nblk * W * 4, st));
+        k_blk_mark<<<dim3(64, nblk), 256, 0, st>>>(nblk, d_bounds.as<int32_t>(), h->vm.qptr, h->vm.col, W,
+                                                  d_bits.as<uint32_t>());
+        VMAT_LAUNCH_CHECK();
+        k_blk_popc<<<nblk, 256, 0, st>>>(nblk, W, d_bits.as<uint32_t>(), d_cnt.as<uint32_t>());
+        VMAT_LAUNCH_CHECK();
+        cnt.assign(nblk, 0);
+        VMAT_HIP(hipMemcpyAsync(cnt.data(), d_cnt.p, (size_t)nblk * 4, hipMemcpyDeviceToHost, st));
+        VMAT_HIP(hipStreamSynchronize(st));
+        std::vector<int64_t> nb2;
+        bool split = false, stuck = false;
+        for (int b = 0; b < nblk; ++b) {
+            nb2.push_back(bounds[b]);
+            if (cnt[b] > (uint32_t)TILE_LIST) {
+                const int64_t len = bounds[b + 1] - bounds[b];
+                if (len <= 64) {
+                    stuck = true;
+                } else {
+                    nb2.push_back(bounds[b] + len / 2);
+                    split = true;
+                }
+            }
+        }
+        nb2.push_back(nv);
+        if (stuck) return fail(VMAT_ERR_UNSUPPORTED, "a 64-voxel block reaches more than 8192 beamlets");
+        if (!split) break;
+        bounds.swap(nb2);
+        if (round > 20) return fail(VMAT_ERR_UNSUPPORTED, "voxel blocking did not converge");
+    }
+    const int nblk = (int)bounds.size() - 1;
+    t.nblk = nblk;
+    std::vector<uint32_t> loff(nblk + 1, 0);
+    for (int b = 0; b < nblk; ++b) loff[b + 1] = loff[b] + cnt[b];
+    t.S = loff[nblk];
+
+    auto alloc = [&](void** ptr, size_t bytes) -> vmat_status {
+        hipError_t e = hipMalloc(ptr, std::max<size_t>(bytes, 16));
+        if (e != hipSuccess) return fail(VMAT_ERR_ALLOC, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        h->bytes += (int64_t)bytes;
+        return VMAT_OK;
+    };
+#define A(ptr, bytes) do { vmat_status r_ = alloc((void**)&(ptr), (bytes)); if (r_ != VMAT_OK) return r_; } while (0)
+    A(t.bounds, (nblk + 1) * 4);
+    VMAT_HIP(hipMemcpyAsync(t.bounds, d_bounds.p, (nblk + 1) * 4, hipMemcpyDeviceToDevice, st));
+    A(t.loff, (nblk + 1) * 4);
+    VMAT_HIP(hipMemcpyAsync(t.loff, loff.data(), (nblk + 1) * 4, hipMemcpyHostToDevice, st));
+    A(t.list, t.S * 4);
+    DevBuf d_wpref;
+    VMAT_HIP(dmalloc(d_wpref, (size_t)nblk * W * 4));
+    k_blk_list<<<nblk, 256, 0, st>>>(W, d_bits.as<uint32_t>(), t.loff, d_wpref.as<uint32_t>(), t.list);
+    VMAT_LAUNCH_CHECK();
+
+    // forward indices
+    A(t.fcol, (size_t)h->vm.n_quads * 4 * 2);
+    k_fw_col16<<<dim3(64, nblk), 256, 0, st>>>(nblk, t.bounds, h->vm.qptr, h->vm.col, W, d_bits.as<uint32_t>(),
+                                              d_wpref.as<uint32_t>(), t.fcol);
+    VMAT_LAUNCH_CHECK();
+
+    // adjoint slot rows
+    DevBuf d_seglo, d_aq;
+    VMAT_HIP(dmalloc(d_seglo, (size_t)t.S * 8));
+    VMAT_HIP(dmalloc(d_aq, (size_t)(t.S + 1) * 4));
+    if (t.S > 0) {
+        k_adj_len<<<(unsigned)((t.S + 255) / 256), 256, 0, st>>>(t.S, nblk, t.loff, t.bounds, t.list, p->row_ptr,
+                                                                 p->col, d_seglo.as<int64_t>(), d_aq.as<uint32_t>());
+        VMAT_LAUNCH_CHECK();
+    }
+    A(t.aqptr, (t.S + 1) * 4);
+    {
+        vmat_status rc = scan_u32_dev(d_aq.as<uint32_t>(), t.S, t.aqptr, st);
+        if (rc != VMAT_OK) return rc;
+    }
+    uint32_t aq_tot = 0;
+    VMAT_HIP(hipMemcpyAsync(&aq_tot, t.aqptr + t.S, 4, hipMemcpyDeviceToHost, st));
+    VMAT_HIP(hipStreamSynchronize(st));
+    t.a_quads = aq_tot;
+    const int vb = fmt_bytes(h->d_store);  // vmat_dtype values equal the Fmt values
+    A(t.acol, (size_t)t.a_quads * 4 * 2);
+    A(t.aval, (size_t)t.a_quads * 4 * vb);
+    if (t.S > 0) {
+        const unsigned g4 = (unsigned)((t.S + 3) / 4);
+        if (vb == 4)
+            k_adj_fill<float><<<g4, 256, 0, st>>>(t.S, nblk, t.loff, t.bounds, t.list, p->row_ptr, p->col,
+                                                  h->bm.qptr, (const float*)h->bm.val, d_seglo.as<int64_t>(),
+                                                  t.aqptr, t.acol, (float*)t.aval);
+        else if (vb == 2)
+            k_adj_fill<uint16_t><<<g4, 256, 0, st>>>(t.S, nblk, t.loff, t.bounds, t.list, p->row_ptr, p->col,
+                                                     h->bm.qptr, (const uint16_t*)h->bm.val, d_seglo.as<int64_t>(),
+                                                     t.aqptr, t.acol, (uint16_t*)t.aval);
+        else
+            k_adj_fill<uint8_t><<<g4, 256, 0, st>>>(t.S, nblk, t.loff, t.bounds, t.list, p->row_ptr, p->col,
+                                                    h->bm.qptr, (const uint8_t*)h->bm.val, d_seglo.as<int64_t>(),
+                                                    t.aqptr, t.acol, (uint8_t*)t.aval);
+        VMAT_LAUNCH_CHECK();
+    }
+
+    // per-beamlet slot lists, in block order
+    A(t.part, t.S * 8);
+    A(t.red_ptr, (nb + 1) * 4);
+    A(t.red_slot, t.S * 4);
+    DevBuf d_rc, d_rf;
+    VMAT_HIP(dmalloc(d_rc, (size_t)(nb + 1) * 4));
+    VMAT_HIP(dmalloc(d_rf, (size_t)(nb + 1) * 4));
+    VMAT_HIP(hipMemsetAsync(d_rc.p, 0, (size_t)(nb + 1) * 4, st));
+    VMAT_HIP(hipMemsetAsync(d_rf.p, 0, (size_t)(nb + 1) * 4, st));
+    if (t.S > 0) {
+        k_red_count<<<(unsigned)((t.S + 255) / 256), 256, 0, st>>>(t.S, t.list, d_rc.as<uint32_t>());
+        VMAT_LAUNCH_CHECK();
+    }
+    {
+        vmat_status rc = scan_u32_dev(d_rc.as<uint32_t>(), nb, t.red_ptr, st);
+        if (rc != VMAT_OK) return rc;
+    }
+    if (t.S > 0) {
+        k_red_fill<<<(unsigned)((t.S + 255) / 256), 256, 0, st>>>(t.S, t.list, t.red_ptr, d_rf.as<uint32_t>(),
+                                                                  t.red_slot);
+        VMAT_LAUNCH_CHECK();
+    }
+    k_red_sort<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nb, t.red_ptr, t.red_slot);
+    VMAT_LAUNCH_CHECK();
+
+    // work lists
+    std::vector<uint32_t> vq(nv + 1), aq(t.S + 1);
+    VMAT_HIP(hipMemcpyAsync(vq.data(), h->vm.qptr, (nv + 1) * 4, hipMemcpyDeviceToHost, st));
+    VMAT_HIP(hipMemcpyAsync(aq.data(), t.aqptr, (t.S + 1) * 4, hipMemcpyDeviceToHost, st));
+    VMAT_HIP(hipStreamSynchronize(st));
+    int64_t target_items = 1024;
+    if (const char* e = getenv("VMAT_WORK_ITEMS")) target_items = std::max(64, atoi(e));
+    const int64_t fq = std::max<int64_t>(1, (int64_t)vq[nv]);
+    const int64_t aqn = std::max<int64_t>(1, (int64_t)aq[t.S]);
+    std::vector<int64_t> rb(bounds.begin(), bounds.end());
+    std::vector<int64_t> sb(nblk + 1);
+    for (int b = 0; b <= nblk; ++b) sb[b] = loff[b];
+    const int64_t mrows = TILE_ROWS;
+    std::vector<int4> fw = make_work(rb, vq, nblk, std::max<int64_t>(256, fq / target_items), mrows);
+    std::vector<int4> aw = make_work(sb, aq, nblk, std::max<int64_t>(256, aqn / target_items), mrows);
+    A(t.fwork, fw.size() * sizeof(int4));
+    A(t.awork, aw.size() * sizeof(int4));
+    VMAT_HIP(hipMemcpyAsync(t.fwork, fw.data(), fw.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(t.awork, aw.data(), aw.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+    t.n_fwork = (int)fw.size();
+    t.n_awork = (int)aw.size();
+    // about one pass of U = 4 quads per lane for a mean row
+    t.fG = pow2_floor_clamp(nv > 0 ? (double)fq / (double)nv / 4.0 * 1.5 : 1.0, 2, 32);
+    t.aG = pow2_floor_clamp(t.S > 0 ? (double)aqn / (double)t.S / 4.0 * 1.5 : 1.0, 2, 32);
+    if (const char* e = getenv("VMAT_FWD_LANES")) t.fG = std::max(2, std::min(32, atoi(e)));
+    if (const char* e = getenv("VMAT_ADJ_LANES")) t.aG = std::max(2, std::min(32, atoi(e)));
+    VMAT_HIP(hipStreamSynchronize(st));
+#undef A
+    t.on = true;
+    return VMAT_OK;
+}
+
+void free_tiled(vmat_ctx* h) {
+    Tiled& t = h->tl;
+    void* ps[] = {t.bounds, t.loff, t.list, t.fcol, t.fwork, t.aqptr, t.acol, t.aval, t.awork, t.part, t.red_ptr,
+                  t.red_slot};
+    for (void* q : ps)
+        if (q) (void)hipFree(q);
+    t = Tiled();
+}
+
+}  // namespace vmat

@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "vmat.h")
 
 VMAT_OK, VMAT_ERR_INVALID_ARG, VMAT_ERR_DEVICE, VMAT_ERR_ALLOC, VMAT_ERR_NOT_CONVERGED, VMAT_ERR_UNSUPPORTED = range(6)
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
+LAYOUTS = {"auto": 0, "plain": 1, "tiled": 2}
 
 _lib = None
 
@@ -37,7 +38,14 @@ class _Problem(ctypes.Structure):
         ("theta_deg", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
         ("val", ctypes.c_void_p), ("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p), ("T", ctypes.c_void_p),
         ("gamma", ctypes.c_double), ("circular", ctypes.c_int32), ("max_leaf_step", ctypes.c_int32),
+        ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
+
+
+class LayoutInfo(ctypes.Structure):
+    _fields_ = [("tiled", ctypes.c_int32), ("n_blocks", ctypes.c_int32), ("fwd_lanes", ctypes.c_int32),
+                ("adj_lanes", ctypes.c_int32), ("fwd_entries", ctypes.c_int64), ("adj_entries", ctypes.c_int64),
+                ("slots", ctypes.c_int64), ("fwd_bytes", ctypes.c_int64), ("adj_bytes", ctypes.c_int64)]
 
 
 class MasterOpts(ctypes.Structure):
@@ -85,6 +93,7 @@ def lib():
             "vmat_create": [ctypes.POINTER(_Problem), P, ctypes.POINTER(P)],
             "vmat_destroy": [P],
             "vmat_device_bytes": [P, ctypes.POINTER(I64)],
+            "vmat_layout": [P, ctypes.POINTER(LayoutInfo)],
             "vmat_dose": [P, P, P, P, P, P, P],
             "vmat_dose_fluence": [P, P, P, P],
             "vmat_forward": [P, P, P, P],
@@ -144,7 +153,7 @@ class Problem:
     """A handle over one problem (D, voxel weights, beams) on the current GPU."""
 
     def __init__(self, n_beams, n_rows, n_cols, n_voxels, theta_deg, row_ptr, col, val, alpha, beta, T,
-                 gamma, circular=1, max_leaf_step=2, d_store="f32"):
+                 gamma, circular=1, max_leaf_step=2, d_store="f32", layout="auto"):
         import torch
         self.N, self.R, self.C, self.nv = int(n_beams), int(n_rows), int(n_cols), int(n_voxels)
         self.nb = self.N * self.R * self.C
@@ -157,7 +166,7 @@ class Problem:
         p = _Problem(self.N, self.R, self.C, DTYPES[d_store], self.nv, int(col.numel()),
                      self._theta.ctypes.data, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr(),
                      alpha.data_ptr(), beta.data_ptr(), T.data_ptr(), float(gamma), int(circular),
-                     int(max_leaf_step))
+                     int(max_leaf_step), LAYOUTS[layout], 0)
         h = ctypes.c_void_p()
         _check(lib().vmat_create(ctypes.byref(p), _stream(), ctypes.byref(h)))
         self._h = h
@@ -165,13 +174,13 @@ class Problem:
         self.gamma, self.circular, self.max_leaf_step = float(gamma), int(circular), int(max_leaf_step)
 
     @classmethod
-    def from_case(cls, case, d_store="f32", device="cuda"):
+    def from_case(cls, case, d_store="f32", device="cuda", layout="auto"):
         import torch
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
         rp, col, val = t(case.row_ptr), t(case.col), t(case.val)
         a, b, T = t(case.alpha), t(case.beta), t(case.T)
         prob = cls(case.n_beams, case.n_rows, case.n_cols, case.n_voxels, case.theta_deg, rp, col, val, a, b, T,
-                   case.gamma, case.circular, case.max_leaf_step, d_store)
+                   case.gamma, case.circular, case.max_leaf_step, d_store, layout)
         torch.cuda.synchronize()
         return prob
 
@@ -191,6 +200,11 @@ class Problem:
         v = ctypes.c_int64()
         _check(lib().vmat_device_bytes(self._h, ctypes.byref(v)))
         return int(v.value)
+
+    def layout(self) -> dict:
+        info = LayoutInfo()
+        _check(lib().vmat_layout(self._h, ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in LayoutInfo._fields_}
 
     # ------------------------------------------------------------ helpers
     def empty_plan(self):

