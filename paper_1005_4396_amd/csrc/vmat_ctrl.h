@@ -1,0 +1,249 @@
+// Control logic of the gradient-projection master (Sec. 2.2), shared by the
+// separate-kernel and the fused master pipelines.  Each function runs on one
+// workgroup of CTRL threads; scalars are combined with fixed-order reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "vmat_block.h"
+#include "vmat_internal.h"
+
+namespace vmat {
+
+struct Pen {
+    double F, dF, curv;
+};
+
+__device__ __forceinline__ Pen penalty_at(double z, float4 p) {
+    const double a = p.x, b = p.y, T = p.z;
+    const double under = fmax(0.0, T - z), over = fmax(0.0, z - T);
+    Pen r;
+    r.F = a * under * under + b * over * over;
+    r.dF = 2.0 * b * over - 2.0 * a * under;
+    r.curv = z < T ? 2.0 * a : 2.0 * b;
+    return r;
+}
+
+
+struct MasterPtrs {
+    int N, R, C, circ;
+    double gamma;
+    const double* th;
+    double* y;
+    const uint8_t* occ;
+    const int32_t* l;
+    const int32_t* r;
+    double* grad;
+    double* grad_prev;
+    double* d;
+    double* d_prev;
+    uint8_t* W;
+    uint8_t* W_prev;
+    double* gF;
+    MasterState* ms;
+};
+
+inline MasterPtrs master_ptrs(const vmat_ctx* h, double* y, const uint8_t* occ, const int32_t* l, const int32_t* r) {
+    MasterPtrs m;
+    m.N = h->N; m.R = h->R; m.C = h->C; m.circ = h->circular; m.gamma = h->gamma;
+    m.th = h->d_theta; m.y = y; m.occ = occ; m.l = l; m.r = r;
+    m.grad = h->mgrad; m.grad_prev = h->mgrad_prev; m.d = h->md; m.d_prev = h->md_prev;
+    m.W = h->mW; m.W_prev = h->mW_prev; m.gF = h->mgF; m.ms = h->ms;
+    return m;
+}
+
+// grad = gF + gamma dG/dy; cost; iteration count.  first: 0 after a step,
+// 1 at a fresh start, 2 at a carried-over start.
+__device__ inline void ctrl_grad(const MasterPtrs& m, double F, int first, double* sh) {
+    const int N = m.N;
+    const double G = smoothing_G(m.y, m.th, N, m.circ, sh);
+    double ref = 0.0;
+    for (int k = threadIdx.x; k < N; k += CTRL) {
+        const double gk = m.gF[k] + m.gamma * dG_at(k, m.y, m.th, N, m.circ);
+        m.grad[k] = gk;
+        if (m.occ[k]) ref = fmax(ref, fabs(gk));
+    }
+    ref = bmax(ref, sh);
+    if (threadIdx.x != 0) return;
+    MasterState& s = *m.ms;
+    s.F = F;
+    s.gG = m.gamma * G;
+    if (first != 2) s.n_adj += 1;
+    if (first) {
+        s.it = 0;
+        if (!(s.kkt_ref > 0.0)) s.kkt_ref = ref == 0.0 ? 1.0 : ref;
+    } else {
+        s.it += 1;
+    }
+}
+
+// KKT test; if not converged, the direction on the free face (steepest
+// descent after a face change, else Polak-Ribiere(+)), the first blocking
+// bound and the line-search set-up.  Sets the pipeline phase.
+__device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi) {
+    const int N = m.N;
+    MasterState& s0 = *m.ms;
+    const double* y = m.y;
+    const double* grad = m.grad;
+    const double* grad_prev = m.grad_prev;
+    double* d = m.d;
+    const double* d_prev = m.d_prev;
+    uint8_t* W = m.W;
+    const uint8_t* W_prev = m.W_prev;
+    const uint8_t* occ = m.occ;
+    const double* th = m.th;
+    const int circ = m.circ;
+    const double gamma = m.gamma;
+    if (s0.done) return;
+    const int have_prev = s0.have_prev;
+    double kkt = 0.0;
+    int changed = 0;
+    for (int k = threadIdx.x; k < N; k += CTRL) {
+        if (occ[k]) kkt = fmax(kkt, fabs(fmin(y[k], grad[k])));
+        const uint8_t w = occ[k] && (y[k] > 0.0 || grad[k] < 0.0);
+        W[k] = w;
+        if (w != W_prev[k]) changed = 1;
+        d[k] = w ? -grad[k] : 0.0;
+    }
+    kkt = bmax(kkt, sh);
+    changed = bor(changed, shi);
+    const double tol_abs = s0.tol * s0.kkt_ref;
+    if (kkt <= tol_abs || s0.it >= s0.max_iter) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s0.kkt = kkt;
+            s0.converged = kkt <= tol_abs;
+            s0.done = 1;
+            s0.phase = PH_DONE;
+        }
+        return;
+    }
+    double b_cg = 0.0;
+    if (have_prev && !changed) {
+        double den = 0.0, num = 0.0;
+        for (int k = threadIdx.x; k < N; k += CTRL) {
+            const double gp = W[k] ? grad_prev[k] : 0.0, gw = W[k] ? grad[k] : 0.0;
+            den += gp * gp;
+            num += gw * (gw - gp);
+        }
+        den = bsum(den, sh);
+        num = bsum(num, sh);
+        b_cg = den > 0.0 ? fmax(0.0, num / den) : 0.0;
+        double slope = 0.0;
+        for (int k = threadIdx.x; k < N; k += CTRL) {
+            const double dc = W[k] ? -grad[k] + b_cg * d_prev[k] : 0.0;
+            slope += dc * grad[k];
+        }
+        slope = bsum(slope, sh);
+        if (slope < 0.0)
+            for (int k = threadIdx.x; k < N; k += CTRL) d[k] = W[k] ? -grad[k] + b_cg * d_prev[k] : 0.0;
+        __syncthreads();
+    }
+    double tmax = INFINITY, sl = 0.0;
+    int any = 0;
+    for (int k = threadIdx.x; k < N; k += CTRL) {
+        const double dk = d[k];
+        if (dk < 0.0) tmax = fmin(tmax, y[k] / (-dk));
+        if (dk != 0.0) any = 1;
+        sl += dG_at(k, y, th, N, circ) * dk;
+    }
+    tmax = bmin(tmax, sh);
+    any = bor(any, shi);
+    sl = bsum(sl, sh);
+    const double curv = smoothing_dHd(d, th, N, circ, sh);
+    if (threadIdx.x != 0) return;
+    MasterState& s = s0;
+    s.kkt = kkt;
+    if (!any) {
+        s.done = 1;
+        s.phase = PH_DONE;
+        return;
+    }
+    s.beta_cg = b_cg;
+    s.slope0 = gamma * sl;
+    s.curv = gamma * curv;
+    s.t_max = tmax;
+    s.ls_phase = 0;
+    s.t_eval = 0.0;
+    s.ls_steps = 0;
+    s.ls_done = 0;
+    s.n_fwd += 1;
+    s.phase = PH_READY;
+}
+
+// One step of the exact line search: safeguarded Newton on the piecewise-
+// linear, non-decreasing phi' inside a bracket (thread 0).  pF, hF: the voxel
+// sums of phi'(t_eval) and phi''(t_eval); the smoothing part is added here.
+__device__ inline void ctrl_ls_step(MasterState& s, double pF, double hF) {
+    const double t = s.t_eval;
+    const double p = pF + s.slope0 + t * s.curv;
+    const double hh = hF + s.curv;
+    s.n_ls += 1;
+    bool fin = false;
+    double ts = 0.0;
+    bool prop = false;
+    if (s.ls_phase == 0) {
+        s.p0 = p;
+        s.h0 = hh;
+        if (!(p < 0.0)) {
+            fin = true;
+            ts = 0.0;
+        } else if (isfinite(s.t_max)) {
+            s.ls_phase = 1;
+            s.t_eval = s.t_max;
+        } else {
+            s.lo = 0.0; s.hi = INFINITY; s.t = 0.0; s.p = p; s.h = hh;
+            s.ls_phase = 2; s.ls_steps = 0;
+            prop = true;
+        }
+    } else if (s.ls_phase == 1) {
+        if (p <= 0.0) {
+            fin = true;
+            ts = s.t_max;
+        } else {
+            s.lo = 0.0; s.hi = s.t_max; s.t = 0.0; s.p = s.p0; s.h = s.h0;
+            s.ls_phase = 2; s.ls_steps = 0;
+            prop = true;
+        }
+    } else {
+        s.t = t; s.p = p; s.h = hh;
+        s.ls_steps += 1;
+        if (p <= 0.0) s.lo = t; else s.hi = t;
+        if (fabs(p) <= 1e-12 * fabs(s.p0)) { fin = true; ts = t; }
+        else if (isfinite(s.hi) && s.hi - s.lo <= 1e-15 * s.hi) { fin = true; ts = s.lo; }
+        else if (s.ls_steps >= s.ls_max) { fin = true; ts = s.lo; }
+        else prop = true;
+    }
+    if (fin) {
+        s.t_star = ts;
+        s.ls_done = 1;
+        s.phase = PH_LS_DONE;
+    } else {
+        s.phase = PH_LS;
+        if (prop) {
+            double tn = s.h > 0.0 ? s.t - s.p / s.h : NAN;
+            if (!(s.lo < tn && tn < s.hi)) tn = isfinite(s.hi) ? 0.5 * (s.lo + s.hi) : (s.lo > 0.0 ? 2.0 * s.lo : 1.0);
+            s.t_eval = tn;
+        }
+    }
+}
+
+// y <- max(0, y + t* d); bounds that block at t* = t_max become exactly 0;
+// the direction, gradient and face become the previous ones.
+__device__ inline void ctrl_step(const MasterPtrs& m) {
+    const double t = m.ms->t_star, tmax = m.ms->t_max;
+    for (int k = threadIdx.x; k < m.N; k += CTRL) {
+        const double yo = m.y[k], dk = m.d[k];
+        double yn = fmax(0.0, yo + t * dk);
+        if (t == tmax && dk < 0.0 && yo / (-dk) == tmax) yn = 0.0;
+        m.y[k] = yn;
+        m.d_prev[k] = dk;
+        m.grad_prev[k] = m.grad[k];
+        m.W_prev[k] = m.W[k];
+    }
+    if (threadIdx.x == 0) m.ms->have_prev = 1;
+}
+
+}  // namespace vmat

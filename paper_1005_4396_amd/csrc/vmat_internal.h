@@ -61,6 +61,7 @@ struct Tiled {
     int32_t* bounds = nullptr;    // [nblk+1] voxel boundaries
     uint32_t* loff = nullptr;     // [nblk+1] list offsets
     uint32_t* list = nullptr;     // [S] beamlet of each slot
+    uint32_t* lpack = nullptr;    // [S] (beam << 20) | (leaf row << 8) | column of each slot
     // forward
     uint16_t* fcol = nullptr;     // [4 * vm.n_quads]
     int4* fwork = nullptr;        // (block, first row, end row, 0)
@@ -79,6 +80,15 @@ struct Tiled {
     uint32_t* red_slot = nullptr; // [S] slots of each beamlet, in block order
 };
 
+// Launch gate: a kernel given a gate returns at once unless the device-side
+// value *p is one of the values in `mask` (bit v set: value v admitted).
+// A default gate (p == nullptr) always runs.
+struct Gate {
+    const int32_t* p = nullptr;
+    uint32_t mask = 0;
+    __host__ __device__ bool closed() const { return p && !((1u << *p) & mask); }
+};
+
 // Scalars and small vectors of the master iteration, resident on the device.
 struct MasterState {
     // line search
@@ -88,8 +98,13 @@ struct MasterState {
     int32_t it, max_iter, done, converged;
     int32_t ls_phase, ls_steps, ls_max, ls_done;
     int32_t n_fwd, n_adj, n_ls, have_prev;
-    int32_t blocked, pad0, pad1, pad2;
+    int32_t phase;                // pipeline phase of the fused master iteration
+    uint32_t cnt_a, cnt_b, cnt_c; // arrival counters of the last-block reductions
 };
+
+// Phases of the fused master iteration: every kernel of an iteration runs only
+// in its phase, and the last workgroup of a kernel moves the phase on.
+enum : int32_t { PH_READY = 1, PH_LS = 2, PH_LS_DONE = 3, PH_UPDATED = 4, PH_DONE = 6 };
 
 // Per-iteration record of vmat_solve, resident on the device.
 struct SolveTraceDev {

@@ -9,23 +9,28 @@
 namespace vmat {
 
 // x_i = v_k if beamlet i of beam k is exposed (occ_k, l <= c < r), else 0;
-// times the per-beamlet FP8 scale when `scale` is given.  Skipped when *skip.
+// times the per-beamlet FP8 scale when `scale` is given.  Runs only when the gate is open.
 vmat_status launch_fluence(const vmat_ctx* h, const double* v, const int32_t* l, const int32_t* r,
-                           const uint8_t* occ, const float* scale, double* x, const int32_t* skip,
+                           const uint8_t* occ, const float* scale, double* x, Gate gate,
                            hipStream_t st);
 
 // out_row = sum_e val_e x[col_e] (FP64 accumulation) for every row of A; the
-// per-row scale of A multiplies the result when present.  Skipped when *skip.
+// per-row scale of A multiplies the result when present.  Runs only when the gate is open.
 vmat_status launch_spmv(const vmat_ctx* h, const QuadCsr& A, const double* x, double* out,
-                        const int32_t* skip, hipStream_t st);
+                        Gate gate, hipStream_t st);
 vmat_status launch_spmv(const vmat_ctx* h, const QuadCsr& A, const float* x, double* out,
-                        const int32_t* skip, hipStream_t st);
+                        Gate gate, hipStream_t st);
 
 // Dispatch to the tiled or the plain layout.
 // forward: out = D^T x (x: fluence, FP8 scale already folded in); adjoint: g = D w.
-vmat_status launch_fwd(const vmat_ctx* h, const double* x, double* out, const int32_t* skip, hipStream_t st);
-vmat_status launch_adj(const vmat_ctx* h, const float* w, double* g, const int32_t* skip, hipStream_t st);
+vmat_status launch_fwd(const vmat_ctx* h, const double* x, double* out, Gate gate, hipStream_t st);
+vmat_status launch_adj(const vmat_ctx* h, const float* w, double* g, Gate gate, hipStream_t st);
+// Tiled adjoint up to the slot sums (h->tl.part).
+vmat_status launch_adj_slots(const vmat_ctx* h, const float* w, Gate gate, hipStream_t st);
 vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st);
+// Fused master solve over the tiled layout (see vmat_master.hip).
+vmat_status run_master_fused(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
+                             const vmat_master_opts& o, int fresh, hipStream_t st);
 void free_tiled(vmat_ctx* h);
 vmat_status scan_u32_dev(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t st);
 
@@ -33,9 +38,9 @@ vmat_status scan_u32_dev(const uint32_t* in, int64_t n, uint32_t* out, hipStream
 // F'(z), and block partial sums of F(z) into part slot 0.
 vmat_status launch_penalty(const vmat_ctx* h, const double* z, float* z_out, float* dF_out, hipStream_t st);
 
-// sum_k-per-beam sums over apertures: out[k] = sum_{i in A_k} g_i.  Skipped when *skip.
+// sum_k-per-beam sums over apertures: out[k] = sum_{i in A_k} g_i.  Runs only when the gate is open.
 vmat_status launch_beam_sums(const vmat_ctx* h, const double* g, const int32_t* l, const int32_t* r,
-                             const uint8_t* occ, double* out, const int32_t* skip, hipStream_t st);
+                             const uint8_t* occ, double* out, Gate gate, hipStream_t st);
 
 // cost[0] = F (from partial slot 0), cost[1] = gamma G(y); dfdy = gF + gamma dG/dy.
 vmat_status launch_grad_finish(const vmat_ctx* h, const double* y, const double* gF, double* cost,

@@ -17,10 +17,10 @@
 #include "vmat_formats.h"
 #include "vmat_internal.h"
 #include "vmat_kernels.h"
+#include "vmat_rows.h"
 
 namespace vmat {
 
-typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- kernels
 //
@@ -30,84 +30,6 @@ typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 // loads of up to U quads of a row at once, and the loads of the group's next
 // row are issued before the current row is summed (two rows in flight per
 // lane group).  Longer rows finish in extra passes.
-
-template <int FMT, int U>
-struct RowBuf {
-    float4 v[U];
-    u16x4 c[U];
-};
-
-template <int FMT, int G, int U>
-__device__ __forceinline__ void load_pass(RowBuf<FMT, U>& b, const void* __restrict__ val, const u16x4* __restrict__ c4,
-                                          uint32_t q, uint32_t q1) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint32_t qq = q + (uint32_t)(u * G);
-        if (qq < q1) {
-            b.v[u] = Quad<FMT>::load(val, qq);
-            b.c[u] = __builtin_nontemporal_load(c4 + qq);
-        } else {
-            b.v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-            b.c[u] = u16x4{0, 0, 0, 0};
-        }
-    }
-}
-
-template <int FMT, int U, typename ST>
-__device__ __forceinline__ double use_pass(const RowBuf<FMT, U>& b, const ST* __restrict__ xs, double acc) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        acc = fma((double)b.v[u].x, (double)xs[b.c[u].x], acc);
-        acc = fma((double)b.v[u].y, (double)xs[b.c[u].y], acc);
-        acc = fma((double)b.v[u].z, (double)xs[b.c[u].z], acc);
-        acc = fma((double)b.v[u].w, (double)xs[b.c[u].w], acc);
-    }
-    return acc;
-}
-
-// Rows of one work item: rq[k] = start quad of row r0 + k (k <= nrows).
-template <int FMT, int G, int U, typename ST>
-__device__ __forceinline__ void rows_of_item(const uint32_t* __restrict__ rq, int nrows, int row_base,
-                                             const void* __restrict__ val, const u16x4* __restrict__ c4,
-                                             const ST* __restrict__ xs, double* __restrict__ out) {
-    const int grp = threadIdx.x / G, lane = threadIdx.x & (G - 1);
-    constexpr int NGRP = TILE_THREADS / G;
-    int row = grp;
-    RowBuf<FMT, U> cur, nxt;
-    if (row < nrows) load_pass<FMT, G, U>(cur, val, c4, rq[row] + lane, rq[row + 1]);
-    while (row < nrows) {
-        const int next = row + NGRP;
-        if (next < nrows) load_pass<FMT, G, U>(nxt, val, c4, rq[next] + lane, rq[next + 1]);
-        double acc = use_pass<FMT, U>(cur, xs, 0.0);
-        const uint32_t q1 = rq[row + 1];
-        for (uint32_t q = rq[row] + lane + U * G; q < q1; q += U * G) {
-            RowBuf<FMT, U> more;
-            load_pass<FMT, G, U>(more, val, c4, q, q1);
-            acc = use_pass<FMT, U>(more, xs, acc);
-        }
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
-        if (lane == 0) out[row_base + row] = acc;
-        cur = nxt;
-        row = next;
-    }
-}
-
-// Row starts of a work item into LDS, all loads issued before the stores.
-__device__ __forceinline__ void stage_rows(uint32_t* __restrict__ rq, const uint32_t* __restrict__ src, int nrows) {
-    constexpr int K = (TILE_ROWS + TILE_THREADS) / TILE_THREADS;
-    uint32_t v[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int u = threadIdx.x + k * TILE_THREADS;
-        v[k] = u <= nrows ? src[u] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int u = threadIdx.x + k * TILE_THREADS;
-        if (u <= nrows) rq[u] = v[k];
-    }
-}
 
 // Forward: rows are voxels of the block; x values of the block's beamlets
 // are staged in LDS.
@@ -119,10 +41,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_fwd_tiled(const int4* __restri
                                                           const uint16_t* __restrict__ col16,
                                                           const void* __restrict__ val,
                                                           const double* __restrict__ x, double* __restrict__ out,
-                                                          const int32_t* __restrict__ skip) {
+                                                          Gate gate) {
     __shared__ double xs[TILE_LIST];
     __shared__ uint32_t rq[TILE_ROWS + 1];
-    if (skip && *skip) return;
+    if (gate.closed()) return;
     const int4 wk = work[blockIdx.x];
     if (wk.x < 0) return;
     const uint32_t l0 = loff[wk.x], ln = loff[wk.x + 1] - l0;
@@ -149,7 +71,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_fwd_tiled(const int4* __restri
         }
     }
     __syncthreads();
-    rows_of_item<FMT, G, U, double>(rq, nrows, wk.y, val, reinterpret_cast<const u16x4*>(col16), xs, out);
+    StoreRow epi{out};
+    rows_of_item<FMT, G, U, double>(rq, nrows, wk.y, val, reinterpret_cast<const u16x4*>(col16), xs, epi);
 }
 
 // Adjoint: rows are the block's slots; the block's slice of w is staged in
@@ -161,10 +84,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_adj_tiled(const int4* __restri
                                                           const uint16_t* __restrict__ col16,
                                                           const void* __restrict__ val,
                                                           const float* __restrict__ w, double* __restrict__ part,
-                                                          const int32_t* __restrict__ skip) {
+                                                          Gate gate) {
     __shared__ float ws[TILE_VOXELS];
     __shared__ uint32_t rq[TILE_ROWS + 1];
-    if (skip && *skip) return;
+    if (gate.closed()) return;
     const int4 wk = work[blockIdx.x];
     if (wk.x < 0) return;
     const int32_t j0 = bounds[wk.x], jn = bounds[wk.x + 1] - j0;
@@ -185,7 +108,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_adj_tiled(const int4* __restri
         }
     }
     __syncthreads();
-    rows_of_item<FMT, G, U, float>(rq, nrows, wk.y, val, reinterpret_cast<const u16x4*>(col16), ws, part);
+    StoreRow epi{part};
+    rows_of_item<FMT, G, U, float>(rq, nrows, wk.y, val, reinterpret_cast<const u16x4*>(col16), ws, epi);
 }
 
 // g_i = scale_i * sum of beamlet i's slot sums, in block order.
@@ -193,8 +117,8 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int64_t nb, const uint32_t* 
                                                     const uint32_t* __restrict__ red_slot,
                                                     const double* __restrict__ part,
                                                     const float* __restrict__ scale, double* __restrict__ g,
-                                                    const int32_t* __restrict__ skip) {
-    if (skip && *skip) return;
+                                                    Gate gate) {
+    if (gate.closed()) return;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= nb) return;
     double s = 0.0;
@@ -205,13 +129,13 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int64_t nb, const uint32_t* 
 // ---------------------------------------------------------------- launchers
 
 template <int FMT>
-static vmat_status fwd_fmt(const vmat_ctx* h, const double* x, double* out, const int32_t* skip, hipStream_t st) {
+static vmat_status fwd_fmt(const vmat_ctx* h, const double* x, double* out, Gate gate, hipStream_t st) {
     const Tiled& t = h->tl;
     const unsigned grid = (unsigned)t.n_fwork;
     if (grid == 0) return VMAT_OK;
 
 #define FWD(GG) k_fwd_tiled<FMT, GG, 4><<<grid, TILE_THREADS, 0, st>>>(t.fwork, t.loff, t.list, h->vm.qptr, \
-                                                                       t.fcol, h->vm.val, x, out, skip)
+                                                                       t.fcol, h->vm.val, x, out, gate)
     switch (t.fG) {
         case 2: FWD(2); break;
         case 4: FWD(4); break;
@@ -225,12 +149,13 @@ static vmat_status fwd_fmt(const vmat_ctx* h, const double* x, double* out, cons
 }
 
 template <int FMT>
-static vmat_status adj_fmt(const vmat_ctx* h, const float* w, double* g, const int32_t* skip, hipStream_t st) {
+static vmat_status adj_fmt(const vmat_ctx* h, const float* w, double* g, Gate gate, hipStream_t st,
+                           bool slots_only = false) {
     const Tiled& t = h->tl;
     if (t.n_awork > 0) {
 #define ADJ(GG) k_adj_tiled<FMT, GG, 4><<<(unsigned)t.n_awork, TILE_THREADS, 0, st>>>(t.awork, t.bounds, \
                                                                                       t.aqptr, t.acol, t.aval, w, \
-                                                                                      t.part, skip)
+                                                                                      t.part, gate)
         switch (t.aG) {
             case 2: ADJ(2); break;
             case 4: ADJ(4); break;
@@ -241,29 +166,39 @@ static vmat_status adj_fmt(const vmat_ctx* h, const float* w, double* g, const i
 #undef ADJ
         VMAT_LAUNCH_CHECK();
     }
+    if (slots_only) return VMAT_OK;
     k_adj_reduce<<<(unsigned)((h->nb + 255) / 256), 256, 0, st>>>(h->nb, t.red_ptr, t.red_slot, t.part, h->bm.scale,
-                                                                  g, skip);
+                                                                  g, gate);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
 
-vmat_status launch_fwd(const vmat_ctx* h, const double* x, double* out, const int32_t* skip, hipStream_t st) {
-    if (!h->tl.on) return launch_spmv(h, h->vm, x, out, skip, st);
+vmat_status launch_fwd(const vmat_ctx* h, const double* x, double* out, Gate gate, hipStream_t st) {
+    if (!h->tl.on) return launch_spmv(h, h->vm, x, out, gate, st);
     switch (h->d_store) {
-        case VMAT_F32: return fwd_fmt<FMT_F32>(h, x, out, skip, st);
-        case VMAT_F16: return fwd_fmt<FMT_F16>(h, x, out, skip, st);
-        case VMAT_BF16: return fwd_fmt<FMT_BF16>(h, x, out, skip, st);
-        default: return fwd_fmt<FMT_FP8>(h, x, out, skip, st);
+        case VMAT_F32: return fwd_fmt<FMT_F32>(h, x, out, gate, st);
+        case VMAT_F16: return fwd_fmt<FMT_F16>(h, x, out, gate, st);
+        case VMAT_BF16: return fwd_fmt<FMT_BF16>(h, x, out, gate, st);
+        default: return fwd_fmt<FMT_FP8>(h, x, out, gate, st);
     }
 }
 
-vmat_status launch_adj(const vmat_ctx* h, const float* w, double* g, const int32_t* skip, hipStream_t st) {
-    if (!h->tl.on) return launch_spmv(h, h->bm, w, g, skip, st);
+vmat_status launch_adj_slots(const vmat_ctx* h, const float* w, Gate gate, hipStream_t st) {
     switch (h->d_store) {
-        case VMAT_F32: return adj_fmt<FMT_F32>(h, w, g, skip, st);
-        case VMAT_F16: return adj_fmt<FMT_F16>(h, w, g, skip, st);
-        case VMAT_BF16: return adj_fmt<FMT_BF16>(h, w, g, skip, st);
-        default: return adj_fmt<FMT_FP8>(h, w, g, skip, st);
+        case VMAT_F32: return adj_fmt<FMT_F32>(h, w, nullptr, gate, st, true);
+        case VMAT_F16: return adj_fmt<FMT_F16>(h, w, nullptr, gate, st, true);
+        case VMAT_BF16: return adj_fmt<FMT_BF16>(h, w, nullptr, gate, st, true);
+        default: return adj_fmt<FMT_FP8>(h, w, nullptr, gate, st, true);
+    }
+}
+
+vmat_status launch_adj(const vmat_ctx* h, const float* w, double* g, Gate gate, hipStream_t st) {
+    if (!h->tl.on) return launch_spmv(h, h->bm, w, g, gate, st);
+    switch (h->d_store) {
+        case VMAT_F32: return adj_fmt<FMT_F32>(h, w, g, gate, st);
+        case VMAT_F16: return adj_fmt<FMT_F16>(h, w, g, gate, st);
+        case VMAT_BF16: return adj_fmt<FMT_BF16>(h, w, g, gate, st);
+        default: return adj_fmt<FMT_FP8>(h, w, g, gate, st);
     }
 }
 
@@ -404,6 +339,14 @@ __global__ void k_adj_fill(int64_t S, int nblk, const uint32_t* __restrict__ lof
     }
 }
 
+__global__ void k_list_pack(int64_t S, const uint32_t* __restrict__ list, uint32_t R, uint32_t C,
+                            uint32_t* __restrict__ lpack) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= S) return;
+    const uint32_t i = list[s], c = i % C, kr = i / C, rho = kr % R, k = kr / R;
+    lpack[s] = (k << 20) | (rho << 8) | c;
+}
+
 __global__ void k_red_count(int64_t S, const uint32_t* __restrict__ list, uint32_t* __restrict__ cnt) {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s < S) atomicAdd(&cnt[list[s]], 1u);
@@ -495,6 +438,7 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     Tiled& t = h->tl;
     const int64_t nv = h->nv, nb = h->nb;
     const int64_t W = (nb + 31) / 32;
+    if (h->R > 4095 || h->N > 4095) return fail(VMAT_ERR_UNSUPPORTED, "tiled layout needs N, R < 4096");
     std::vector<int64_t> bounds;
     for (int64_t j = 0; j < nv; j += TILE_VOXELS) bounds.push_back(j);
     bounds.push_back(nv);
@@ -564,6 +508,13 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     VMAT_HIP(dmalloc(d_wpref, (size_t)nblk * W * 4));
     k_blk_list<<<nblk, 256, 0, st>>>(W, d_bits.as<uint32_t>(), t.loff, d_wpref.as<uint32_t>(), t.list);
     VMAT_LAUNCH_CHECK();
+
+    A(t.lpack, t.S * 4);
+    if (t.S > 0) {
+        k_list_pack<<<(unsigned)((t.S + 255) / 256), 256, 0, st>>>(t.S, t.list, (uint32_t)h->R, (uint32_t)h->C,
+                                                                   t.lpack);
+        VMAT_LAUNCH_CHECK();
+    }
 
     // forward indices
     A(t.fcol, (size_t)h->vm.n_quads * 4 * 2);
@@ -668,7 +619,7 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
 
 void free_tiled(vmat_ctx* h) {
     Tiled& t = h->tl;
-    void* ps[] = {t.bounds, t.loff, t.list, t.fcol, t.fwork, t.aqptr, t.acol, t.aval, t.awork, t.part, t.red_ptr,
+    void* ps[] = {t.bounds, t.loff, t.list, t.lpack, t.fcol, t.fwork, t.aqptr, t.acol, t.aval, t.awork, t.part, t.red_ptr,
                   t.red_slot};
     for (void* q : ps)
         if (q) (void)hipFree(q);
