@@ -128,10 +128,18 @@ vmat_status vmat_dose(vmat_handle h, const double* y, const int32_t* l, const in
  *   dFdz (nullable) DEVICE float  [nv] F'(z_j) = 2b(z-T)+ - 2a(T-z)+
  *   g    (nullable) DEVICE double [nb] beamlet prices g_i = sum_j D_ij F'(z_j)
  *   dfdy (nullable) DEVICE double [N]  sum_{i in A_k} g_i + gamma dG/dy_k
- * Inputs as for vmat_dose.                                                     */
+ * Inputs as for vmat_dose.  With g and dfdy both null no adjoint product runs. */
 vmat_status vmat_grad(vmat_handle h, const double* y, const int32_t* l, const int32_t* r,
                       const uint8_t* occ, double* cost, float* z, float* dFdz, double* g,
                       double* dfdy, hipStream_t stream);
+
+/* Gradient in the aperture intensities for a given dose derivative w = F'(z):
+ *   dfdy[k] = sum_{i in A_k} (D w)_i + gamma dG/dy_k   (eq. 2, eq. 3)
+ *   w: DEVICE float [nv]; g (nullable): DEVICE double [nb] receives D w;
+ *   dfdy: DEVICE double [N].  This is the backward of vmat_grad's cost.      */
+vmat_status vmat_grad_apertures(vmat_handle h, const double* y, const int32_t* l, const int32_t* r,
+                                const uint8_t* occ, const float* w, double* g, double* dfdy,
+                                hipStream_t stream);
 
 /* Fluence-space forms (beamlet intensities x instead of apertures):
  *   vmat_dose_fluence:  z = D^T x                   x: DEVICE double [nb]

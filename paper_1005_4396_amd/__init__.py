@@ -5,3 +5,4 @@ libvmat.so in-tree.
 """
 from . import vmat  # noqa: F401
 from .vmat import Problem, VmatError, master_opts  # noqa: F401
+from .autograd import aperture_cost, fluence_cost  # noqa: F401

@@ -208,9 +208,22 @@ extern "C" vmat_status vmat_grad(vmat_handle h, const double* y, const int32_t* 
     double* gout = g ? g : h->g;
     TRY(forward_from_plan(h, y, l, r, occ, h->z, Gate{}, st));
     TRY(launch_penalty(h, h->z, z, dFdz, st));
+    if (!g && !dfdy) return launch_grad_finish(h, y, h->mgF, cost, nullptr, st);
     TRY(launch_adj(h, h->rz, gout, Gate{}, st));
     TRY(launch_beam_sums(h, gout, l, r, occ, h->mgF, Gate{}, st));
     return launch_grad_finish(h, y, h->mgF, cost, dfdy, st);
+}
+
+extern "C" vmat_status vmat_grad_apertures(vmat_handle h, const double* y, const int32_t* l, const int32_t* r,
+                                           const uint8_t* occ, const float* w, double* g, double* dfdy,
+                                           hipStream_t st) {
+    TRY(check_handle(h));
+    TRY(check_plan(y, l, r, occ));
+    if (!w || !dfdy) return fail(VMAT_ERR_INVALID_ARG, "null w or dfdy");
+    double* gout = g ? g : h->g;
+    TRY(launch_adj(h, w, gout, Gate{}, st));
+    TRY(launch_beam_sums(h, gout, l, r, occ, h->mgF, Gate{}, st));
+    return launch_dfdy(h, y, h->mgF, dfdy, st);
 }
 
 extern "C" vmat_status vmat_grad_fluence(vmat_handle h, const double* x, double* cost, float* z, float* dFdz,

@@ -45,6 +45,8 @@ vmat_status launch_beam_sums(const vmat_ctx* h, const double* g, const int32_t* 
 // cost[0] = F (from partial slot 0), cost[1] = gamma G(y); dfdy = gF + gamma dG/dy.
 vmat_status launch_grad_finish(const vmat_ctx* h, const double* y, const double* gF, double* cost,
                                double* dfdy, hipStream_t st);
+// dfdy = gF + gamma dG/dy.
+vmat_status launch_dfdy(const vmat_ctx* h, const double* y, const double* gF, double* dfdy, hipStream_t st);
 // cost[0] = F only (fluence form).
 vmat_status launch_cost_only(const vmat_ctx* h, double* cost, hipStream_t st);
 

@@ -226,6 +226,18 @@ vmat_status launch_grad_finish(const vmat_ctx* h, const double* y, const double*
     return VMAT_OK;
 }
 
+__global__ __launch_bounds__(CTRL) void k_dfdy(int N, const double* __restrict__ y, const double* __restrict__ th,
+                                               int circ, double gamma, const double* __restrict__ gF,
+                                               double* __restrict__ dfdy) {
+    for (int k = threadIdx.x; k < N; k += CTRL) dfdy[k] = gF[k] + gamma * dG_at(k, y, th, N, circ);
+}
+
+vmat_status launch_dfdy(const vmat_ctx* h, const double* y, const double* gF, double* dfdy, hipStream_t st) {
+    k_dfdy<<<1, CTRL, 0, st>>>(h->N, y, h->d_theta, h->circular, h->gamma, gF, dfdy);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
 vmat_status launch_cost_only(const vmat_ctx* h, double* cost, hipStream_t st) {
     k_grad_finish<<<1, CTRL, 0, st>>>(h->N, h->part, h->n_part, nullptr, h->d_theta, h->circular, h->gamma,
                                      nullptr, cost, nullptr, 1);

@@ -100,6 +100,7 @@ def lib():
             "vmat_adjoint": [P, P, P, P],
             "vmat_grad": [P, P, P, P, P, P, P, P, P, P, P],
             "vmat_grad_fluence": [P, P, P, P, P, P, P],
+            "vmat_grad_apertures": [P, P, P, P, P, P, P, P, P],
             "vmat_price": [P, P, P, P, P, P, P, P, P, P],
             "vmat_master": [P, P, P, P, P, ctypes.POINTER(MasterOpts), ctypes.POINTER(MasterReport), P],
             "vmat_solve": [P, ctypes.POINTER(SolveOpts), P, P, P, P, P, ctypes.POINTER(SolveReport),
@@ -257,6 +258,15 @@ class Problem:
         _check(lib().vmat_grad(self._h, _ptr(y), _ptr(l), _ptr(r), _ptr(occ), _ptr(cost), _ptr(z), _ptr(dF),
                                _ptr(g), _ptr(dfdy), _stream()))
         return {"cost": cost, "z": z, "dF": dF, "g": g, "dfdy": dfdy}
+
+    def grad_apertures(self, y, l, r, occ, w, want_g=False):
+        """dfdy = sum over each aperture of (D w) + gamma dG/dy (w: FP32 dose derivative)."""
+        import torch
+        g = torch.empty(self.nb, dtype=torch.float64, device=self.device) if want_g else None
+        dfdy = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        _check(lib().vmat_grad_apertures(self._h, _ptr(y), _ptr(l), _ptr(r), _ptr(occ), _ptr(w), _ptr(g),
+                                         _ptr(dfdy), _stream()))
+        return dfdy, g
 
     def grad_fluence(self, x, want=("z", "dF", "g")):
         import torch

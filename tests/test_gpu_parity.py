@@ -225,6 +225,29 @@ def test_master_matches_oracle(small_prob):
         assert abs(rep.iters - ref.iters) <= 2
 
 
+def test_master_pipelined_matches_oracle(monkeypatch):
+    """The phase-gated master pipeline (several iterations per state read)."""
+    monkeypatch.setenv("VMAT_PIPELINED_MASTER", "1")
+    for layout in ("tiled", "plain"):
+        c = small_case(n_beams=7, n_rows=4, n_cols=9, grid=(16, 14, 10), seed=5)
+        D = oracle_D(c)
+        prob = P.Problem.from_case(c, layout=layout)
+        try:
+            l, r, occ, y0 = random_plan(c, 41, p_occ=0.9)
+            ref = O.master(D, c.alpha, c.beta, c.T, c.theta_deg, c.gamma, c.circular, c.n_rows, c.n_cols, l, r,
+                           occ, y0, O.MasterOpts(max_iter=300, tol_rel=1e-7))
+            yt = T(y0, torch.float64)
+            rep = prob.master(T(l, torch.int32), T(r, torch.int32), T(occ, torch.uint8), yt,
+                              P.master_opts(max_iter=300, tol_rel=1e-7))
+            assert rep.converged == 1
+            assert rep.F + rep.gG == pytest.approx(ref.F + ref.gG, rel=1e-9)
+            assert rel_inf(yt.cpu().numpy(), ref.y) <= 1e-5
+            assert abs(rep.iters - ref.iters) <= 2
+            _compare_solve(c, D, prob)
+        finally:
+            prob.close()
+
+
 def test_master_iteration_cap_reports_not_converged():
     c = small_case()
     prob = P.Problem.from_case(c)
