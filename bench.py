@@ -70,6 +70,11 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--variants", type=int, default=64)
+    ap.add_argument("--no-batched-solve", action="store_true")
+    ap.add_argument("--sequential-variants", type=int, default=64,
+                    help="variants solved one at a time for the batched-solve comparison")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -178,6 +183,12 @@ def main():
     if not args.no_precision and args.d_store == "f32":
         out["precision"] = precision_study(case, prob, torch, P, args.kernel_reps, log)
 
+    if not args.no_batched:
+        out["batched"] = batched_study(case, prob, torch, args.variants, max(3, args.kernel_reps // 10), log)
+    if not args.no_batched_solve:
+        out["batched_solve"] = batched_solve_study(case, prob, torch, P, args.variants, args.sequential_variants,
+                                                   log)
+
     if not args.no_cpu_baseline:
         nf, na, n_it, dt = cpu_baseline(case, args.cpu_iters)
         cpu_bytes = nf * fwd_b + na * adj_b
@@ -189,6 +200,82 @@ def main():
 
     prob.close()
     print(json.dumps(out), flush=True)
+
+
+def batched_study(case, prob, torch, B, reps, log):
+    """B objective variants (alpha, beta ~ U[0.5, 2] x base per structure,
+    target T ~ U[0.95, 1.05] x base) sharing D: one batched cost + gradient
+    (forward SpMM, eq. 1 per variant, adjoint SpMM) against B sequential
+    single-variant evaluations (forward SpMV, eq. 1, adjoint SpMV)."""
+    import casegen
+    tab = casegen.variant_table(case, B, seed=1)
+    rng = np.random.default_rng(5)
+    X = rng.random((case.n_beamlets, B)).astype(np.float32)
+    t0 = time.perf_counter()
+    fw, aw, times = prob.tune_batched(B, reps=3)
+    log(f"[bench] tuned B={B}: forward tile {fw}, adjoint tile {aw} ({time.perf_counter() - t0:.1f}s) {times}")
+    lab = torch.as_tensor(case.label, device="cuda")
+    tabt = torch.as_tensor(tab, device="cuda")
+    Xt = torch.as_tensor(X, device="cuda")
+    b_ms = time_kernel(lambda: prob.grad_batched(lab, tabt, Xt), reps, torch)
+    # sequential: the same work one variant at a time through the single-RHS path
+    xs = [Xt[:, b].double().contiguous() for b in range(B)]
+    Pb = [None] * B
+
+    def seq():
+        for b in range(B):
+            Pb[b] = prob.grad_fluence(xs[b], want=("dF", "g"))
+    s_ms = time_kernel(seq, max(1, reps // 3), torch)
+    lay = prob.layout()
+    seq_bytes = B * (lay["fwd_bytes"] + lay["adj_bytes"])
+    res = {"variants": B, "forward_tile": fw, "adjoint_tile": aw,
+           "tune_ms": {k: {str(w): (round(v, 4) if v != float("inf") else None) for w, v in d.items()}
+                       for k, d in times.items()},
+           "batched_ms": round(b_ms, 3), "sequential_ms": round(s_ms, 3), "speedup": round(s_ms / b_ms, 2),
+           "spmv_equiv_GBs": round(seq_bytes / b_ms / 1e6, 1)}
+    log(f"[bench] batched {B} variants: {b_ms:.2f} ms vs sequential {s_ms:.2f} ms ({s_ms / b_ms:.1f}x)")
+    return res
+
+
+def batched_solve_study(case, prob, torch, P, B, n_seq, log):
+    """B plan variants solved by one lockstep column-generation run (every
+    product an SpMM over the variants) against n_seq of them solved one after
+    another by the single-plan solver (scaled to B if n_seq < B)."""
+    import dataclasses
+
+    import casegen
+    tab = casegen.variant_table(case, B, seed=1)
+    lab = torch.as_tensor(case.label, device="cuda")
+    tabt = torch.as_tensor(tab, device="cuda")
+    prob.reserve_batched(B)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plans, reps, _, cnt = prob.solve_batched(lab, tabt, want_trace=False)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    log(f"[bench] batched solve of {B} variants: {t_b:.2f}s, {cnt[0]} forward + {cnt[1]} adjoint SpMM")
+    t_seq = 0.0
+    seq_iters = []
+    n_seq = min(n_seq, B)
+    for b in range(n_seq):
+        w = tab[b][np.minimum(case.label, tab.shape[1] - 1)]
+        cb = dataclasses.replace(case, alpha=w[:, 0].copy(), beta=w[:, 1].copy(), T=w[:, 2].copy())
+        pb = P.Problem.from_case(cb)
+        l, r, occ, y = pb.empty_plan()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep, _ = pb.solve(l, r, occ, y, want_trace=False)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        seq_iters.append(rep.master_iters)
+        pb.close()
+    t_seq_B = t_seq * B / n_seq
+    log(f"[bench] {n_seq} sequential single-variant plans: {t_seq:.2f}s (x{B / n_seq:.2f} -> {t_seq_B:.2f}s)")
+    return {"variants": B, "batched_s": round(t_b, 3), "sequential_s": round(t_seq_B, 3),
+            "sequential_measured": n_seq, "speedup": round(t_seq_B / t_b, 2),
+            "plans_per_s": round(B / t_b, 2), "spmm_forward": int(cnt[0]), "spmm_adjoint": int(cnt[1]),
+            "master_iters_mean": round(float(np.mean([r.master_iters for r in reps])), 1),
+            "costs_first": [round(r.F + r.gG, 3) for r in reps[:4]]}
 
 
 def precision_study(case, prob32, torch, P, reps, log):

@@ -218,3 +218,21 @@ def xi(seed: int, i: int, j: int) -> float:
 
 
 from .presets import PRESETS, preset, tiny_case  # noqa: E402,F401
+
+
+def variant_table(case: Case, n_variants: int, seed: int = 0, spread=(0.5, 2.0), t_spread=(0.95, 1.05)):
+    """Objective variants of one case: float32 [B, S, 3] of (alpha, beta, T)
+    per variant and structure label (0 body, 1.. shapes).  Each weight is the
+    structure's base weight times a U[spread] factor; thresholds of structures
+    with an under-dose weight (targets) are scaled by U[t_spread]."""
+    spec = case.spec
+    base = [(spec.body[1], spec.body[2], spec.body[0])] + [(s.alpha, s.beta, s.T) for s in spec.shapes]
+    base = np.asarray(base, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    B, S = n_variants, base.shape[0]
+    tab = np.empty((B, S, 3), dtype=np.float64)
+    tab[:, :, 0] = base[:, 0] * rng.uniform(*spread, (B, S))
+    tab[:, :, 1] = base[:, 1] * rng.uniform(*spread, (B, S))
+    t_fac = np.where(base[:, 0] > 0, rng.uniform(*t_spread, (B, S)), 1.0)
+    tab[:, :, 2] = base[:, 2] * t_fac
+    return tab.astype(np.float32)

@@ -157,6 +157,40 @@ vmat_status vmat_grad_fluence(vmat_handle h, const double* x, double* cost, floa
 vmat_status vmat_forward(vmat_handle h, const double* x, double* z, hipStream_t stream);
 vmat_status vmat_adjoint(vmat_handle h, const float* w, double* g, hipStream_t stream);
 
+/* Plan variants sharing one D (many right-hand sides, one launch per product).
+ * The variants differ in the voxel weights and thresholds of eq. 1; the dose
+ * of eq. 3 and the beamlet prices of Sec. 2.2 are the same linear maps applied
+ * to B columns at once.  RHS-contiguous layout: element (row, b) at row*B + b.
+ *   vmat_forward_batched:  Z = D^T X   X: DEVICE float [nb*B], Z: DEVICE double [nv*B]
+ *   vmat_adjoint_batched:  G = D W     W: DEVICE float [nv*B], G: DEVICE double [nb*B]
+ *   vmat_grad_batched:     Z = D^T X; cost[b] = F_b(Z[:, b]) (eq. 1 with the
+ *       weights of variant b); dF[j*B+b] = F_b'(Z[j, b]) (float); G = D dF
+ *       (skipped when G is null).
+ *       label: DEVICE uint8 [nv], the structure of each voxel, 0..n_struct-1
+ *              (larger labels are read as n_struct-1);
+ *       table: DEVICE float [B][n_struct][3] = (alpha, beta, T) per variant
+ *              and structure; cost: DEVICE double [B]; dF: DEVICE float [nv*B]
+ *   vmat_tune_batched: times every RHS tile width (1, 2, 4, 8, 16, 32, 64;
+ *       widths of 2B and more are skipped, their time +inf) for both products on the
+ *       given buffers, reps launches each, and keeps the fastest for later
+ *       calls with this B.  best: HOST int32 [2] (forward, adjoint tile);
+ *       times_ms: HOST float [14] (nullable): forward then adjoint, per width.
+ *   vmat_set_batched_tile: sets the tile widths used at B right-hand sides
+ *       (0 = default; otherwise 1, 2, 4, ..., 64), e.g. from an earlier tuning.
+ * 1 <= B <= 64, 1 <= n_struct <= 16, FP64 accumulation, any storage format.
+ * Results are deterministic (no atomics); a tile width changes no result.  */
+vmat_status vmat_forward_batched(vmat_handle h, int32_t B, const float* X, double* Z,
+                                 hipStream_t stream);
+vmat_status vmat_adjoint_batched(vmat_handle h, int32_t B, const float* W, double* G,
+                                 hipStream_t stream);
+vmat_status vmat_grad_batched(vmat_handle h, int32_t B, int32_t n_struct, const uint8_t* label,
+                              const float* table, const float* X, double* Z, double* cost,
+                              float* dF, double* G, hipStream_t stream);
+vmat_status vmat_set_batched_tile(vmat_handle h, int32_t B, int32_t fwd_tile, int32_t adj_tile);
+vmat_status vmat_tune_batched(vmat_handle h, int32_t B, const float* X, double* Z, const float* W,
+                              double* G, int32_t reps, int32_t* best, float* times_ms,
+                              hipStream_t stream);
+
 /* Pricing (Sec. 2.2): the best deliverable aperture over the unoccupied beams.
  * Per unoccupied beam and leaf row, one left-to-right pass minimises
  * S(l,r) = sum_{c=l}^{r-1} g_c over leaf pairs within delta*(index distance)
@@ -227,6 +261,29 @@ typedef struct vmat_solve_trace {
 vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, int32_t* l, int32_t* r,
                        uint8_t* occ, double* y, float* z, vmat_solve_report* rep,
                        vmat_solve_trace* trace, hipStream_t stream);
+
+/* Batched column generation: B plan variants (the objective of eq. 1 with
+ * per-variant weights and thresholds, as in vmat_grad_batched) sharing D,
+ * each solved by the column-generation loop of vmat_solve, in lockstep: every
+ * dose and adjoint product is one SpMM over all variants; pricing and the
+ * master's control run per variant; a variant whose master has stopped keeps
+ * its state while the others iterate.  Directions enter the products in FP32
+ * (rounded before the step, so y and the carried dose stay consistent).
+ *   vmat_reserve_batched: allocates the work state for up to max_variants
+ *       (1..64) variants (about (12 nb + 20 nv) * max_variants bytes); once,
+ *       before vmat_solve_batched.
+ *   vmat_solve_batched: plans start empty (occ all 0, else UNSUPPORTED) and
+ *       run min(N, opts->max_cg_iter or N) iterations.
+ *       l, r: DEVICE int32 [B][N*R]; occ: DEVICE uint8 [B][N]; y: DEVICE
+ *       double [B][N] (outputs: the plans); label/table as in
+ *       vmat_grad_batched; rep: HOST [B] reports; trace: HOST [B] (nullable,
+ *       each field nullable, arrays as in vmat_solve); n_spmm: HOST int64 [2]
+ *       (nullable): forward and adjoint SpMM launches.                        */
+vmat_status vmat_reserve_batched(vmat_handle h, int32_t max_variants);
+vmat_status vmat_solve_batched(vmat_handle h, const vmat_solve_opts* opts, int32_t B, int32_t n_struct,
+                               const uint8_t* label, const float* table, int32_t* l, int32_t* r,
+                               uint8_t* occ, double* y, vmat_solve_report* rep,
+                               vmat_solve_trace* trace, int64_t* n_spmm, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -420,17 +420,15 @@ static vmat_status build_layouts(vmat_ctx* h, const vmat_problem* p, hipStream_t
         rc = build_tiled(h, p, st);
         if (rc != VMAT_OK) {
             free_tiled(h);
+    free_batch(h);
             if (h->layout_req == 2 || rc != VMAT_ERR_UNSUPPORTED) return rc;
             set_error("");
         } else {
-            // the tiled copies replace the plain index arrays and beamlet-major values
+            // the tiled copy replaces the voxel-major column indices; the
+            // beamlet-major copy stays for the many-right-hand-side adjoint
             (void)hipFree(h->vm.col);
-            (void)hipFree(h->bm.col);
-            (void)hipFree(h->bm.val);
-            h->bytes -= (int64_t)h->vm.n_quads * 16 + (int64_t)h->bm.n_quads * 4 * (4 + vb);
+            h->bytes -= (int64_t)h->vm.n_quads * 16;
             h->vm.col = nullptr;
-            h->bm.col = nullptr;
-            h->bm.val = nullptr;
         }
     }
     return VMAT_OK;
@@ -443,7 +441,7 @@ static void free_all(vmat_ctx* h) {
     F(h->d_theta);
     F(h->bm.qptr); F(h->bm.col); F(h->bm.val); F(h->bm.scale);
     F(h->vm.qptr); F(h->vm.col); F(h->vm.val); F(h->vm.scale);
-    F(h->abT); F(h->x); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->part);
+    F(h->abT); F(h->x); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->part); F(h->part_b);
     F(h->my); F(h->mgrad); F(h->mgrad_prev); F(h->md); F(h->md_prev); F(h->mgF); F(h->mW); F(h->mW_prev);
     F(h->ms);
     if (h->ms_host) (void)hipHostFree(h->ms_host);
@@ -540,6 +538,7 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     if ((rc = dalloc(h, &h->rz, h->nv)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->g, h->nb)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->part, (size_t)h->n_part * 4)) != VMAT_OK) return bail(rc);
+    if ((rc = dalloc(h, &h->part_b, (size_t)h->n_part * 64)) != VMAT_OK) return bail(rc);
     double** vecs[] = {&h->my, &h->mgrad, &h->mgrad_prev, &h->md, &h->md_prev, &h->mgF};
     for (double** v : vecs)
         if ((rc = dalloc(h, v, N)) != VMAT_OK) return bail(rc);

@@ -81,8 +81,11 @@ __device__ inline void ctrl_grad(const MasterPtrs& m, double F, int first, doubl
 
 // KKT test; if not converged, the direction on the free face (steepest
 // descent after a face change, else Polak-Ribiere(+)), the first blocking
-// bound and the line-search set-up.  Sets the pipeline phase.
-__device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi) {
+// bound and the line-search set-up.  Sets the pipeline phase.  f32_dir: the
+// direction is rounded to FP32, the precision in which the batched products
+// take it, so that y and the carried dose move by the same step.
+__device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi, bool f32_dir = false) {
+    auto rnd = [f32_dir](double v) { return f32_dir ? (double)(float)v : v; };
     const int N = m.N;
     MasterState& s0 = *m.ms;
     const double* y = m.y;
@@ -105,7 +108,7 @@ __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi) {
         const uint8_t w = occ[k] && (y[k] > 0.0 || grad[k] < 0.0);
         W[k] = w;
         if (w != W_prev[k]) changed = 1;
-        d[k] = w ? -grad[k] : 0.0;
+        d[k] = w ? rnd(-grad[k]) : 0.0;
     }
     kkt = bmax(kkt, sh);
     changed = bor(changed, shi);
@@ -138,7 +141,7 @@ __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi) {
         }
         slope = bsum(slope, sh);
         if (slope < 0.0)
-            for (int k = threadIdx.x; k < N; k += CTRL) d[k] = W[k] ? -grad[k] + b_cg * d_prev[k] : 0.0;
+            for (int k = threadIdx.x; k < N; k += CTRL) d[k] = W[k] ? rnd(-grad[k] + b_cg * d_prev[k]) : 0.0;
         __syncthreads();
     }
     double tmax = INFINITY, sl = 0.0;

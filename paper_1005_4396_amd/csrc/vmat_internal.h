@@ -118,6 +118,34 @@ struct SolveTraceDev {
 
 }  // namespace vmat
 
+namespace vmat {
+// Work state of batched plan solves (plan variants sharing D), allocated by
+// vmat_reserve_batched for up to `cap` variants.  Large vectors are RHS-
+// contiguous ([rows][B]); per-beam and per-row arrays are variant-major.
+struct BatchState {
+    int cap = 0;
+    float* X = nullptr;       // [nb][cap] fluence of the search direction
+    double* Z = nullptr;      // [nv][cap] dose
+    double* dZ = nullptr;     // [nv][cap] dose of the direction
+    float* RZ = nullptr;      // [nv][cap] F'(z)
+    double* G = nullptr;      // [nb][cap] beamlet prices
+    double *grad = nullptr, *grad_prev = nullptr, *d = nullptr, *d_prev = nullptr, *gF = nullptr;  // [cap][N]
+    uint8_t *W = nullptr, *W_prev = nullptr;                                                    // [cap][N]
+    MasterState* ms = nullptr;       // [cap]
+    MasterState* ms_host = nullptr;  // [cap], pinned
+    double *pp = nullptr, *qq = nullptr, *pf = nullptr;  // [cap][n_part] partial sums
+    double *rowS = nullptr, *rowm = nullptr;             // [cap][N*R]
+    int32_t *rowl = nullptr, *rowr = nullptr;            // [cap][N*R]
+    double* bprice = nullptr;                            // [cap][N]
+    int32_t* pbeam = nullptr;                            // [cap][1+2R]
+    double* pscore = nullptr;                            // [cap][3]
+    double* kref = nullptr;                              // [cap]
+    double* cost = nullptr;                              // [cap]
+    SolveTraceDev tr{};                                  // [cap][N] each
+    int64_t bytes = 0;
+};
+}  // namespace vmat
+
 struct vmat_ctx {
     int32_t N, R, C;
     int64_t nb, nv, nnz;
@@ -143,6 +171,10 @@ struct vmat_ctx {
     double* g = nullptr;           // [nb] beamlet prices
     double* part = nullptr;        // [n_part * 4] block partial sums
     int n_part = 0;
+    double* part_b = nullptr;      // [64 * n_part] per-variant partial sums (batched cost)
+    int32_t tune_fwd[65] = {};     // tuned RHS tile width of the batched products, by B (0: default)
+    int32_t tune_adj[65] = {};
+    vmat::BatchState* bs = nullptr; // batched solves (vmat_reserve_batched)
     // master vectors [N]
     double *my = nullptr, *mgrad = nullptr, *mgrad_prev = nullptr, *md = nullptr, *md_prev = nullptr,
            *mgF = nullptr;

@@ -32,6 +32,7 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st);
 vmat_status run_master_fused(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
                              const vmat_master_opts& o, int fresh, hipStream_t st);
 void free_tiled(vmat_ctx* h);
+void free_batch(vmat_ctx* h);  // batched-solve state (vmat_batch.hip)
 vmat_status scan_u32_dev(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t st);
 
 // F'(z) into rz (FP32, for the adjoint gather), optional FP32 copies of z and
@@ -69,5 +70,12 @@ vmat_status launch_price(const vmat_ctx* h, const double* g, const double* y, co
                          const int32_t* r, const uint8_t* occ, int32_t* out_beam, double* out_price,
                          double* beam_prices, int apply, int iter, int32_t* lw, int32_t* rw, uint8_t* occw,
                          double* yw, hipStream_t st);
+// B plan variants at once: g RHS-contiguous [nb][B]; plan, row, price and
+// trace arrays variant-major.
+vmat_status launch_price_variants(const vmat_ctx* h, int B, const double* g, const double* y, const int32_t* l,
+                                  const int32_t* r, const uint8_t* occ, double* rowS, int32_t* rowl, int32_t* rowr,
+                                  double* rowm, double* bprice, int32_t* out_beam, double* out_price,
+                                  double* beam_prices, int apply, int iter, int32_t* lw, int32_t* rw, uint8_t* occw,
+                                  double* yw, SolveTraceDev tr, hipStream_t st);
 
 }  // namespace vmat

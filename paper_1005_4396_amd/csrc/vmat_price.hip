@@ -27,12 +27,26 @@ __device__ __forceinline__ bool less_key(const Cand& a, const Cand& b) {
     return a.l < b.l;
 }
 
-__global__ __launch_bounds__(256) void k_price_rows(int N, int R, int C, int delta, int circ,
+// Plan variants (blockIdx.y = variant b of B): g is RHS-contiguous (beamlet
+// i of variant b at i*B + b), the plan and row arrays are variant-major.
+__global__ __launch_bounds__(256) void k_price_rows(int N, int R, int C, int delta, int circ, int B,
                                                     const double* __restrict__ g, const int32_t* __restrict__ l,
                                                     const int32_t* __restrict__ r, const uint8_t* __restrict__ occ,
                                                     double* __restrict__ rowS, int32_t* __restrict__ rowl,
                                                     int32_t* __restrict__ rowr, double* __restrict__ rowm) {
     __shared__ double P[4][65];
+    {
+        const int b = blockIdx.y;
+        const int64_t NR = (int64_t)N * R;
+        g += b;
+        l += b * NR;
+        r += b * NR;
+        occ += (int64_t)b * N;
+        rowS += b * NR;
+        rowl += b * NR;
+        rowr += b * NR;
+        rowm += b * NR;
+    }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t kr = (int64_t)blockIdx.x * 4 + w;
     const bool valid = kr < (int64_t)N * R;
@@ -63,11 +77,11 @@ __global__ __launch_bounds__(256) void k_price_rows(int N, int R, int C, int del
         }
     }
     // prefix sums P[0..C] in column order; lane t holds P[t] and P[t+64]
-    const double* gr = g + kr * C;
+    const double* gr = g + kr * C * B;
     if (active) {
         for (int pos = lane; pos <= C; pos += 64) {
             double acc = 0.0;
-            for (int c = 0; c < pos; ++c) acc = acc + gr[c];
+            for (int c = 0; c < pos; ++c) acc = acc + gr[(int64_t)c * B];
             P[w][pos] = acc;
         }
     }
@@ -145,6 +159,31 @@ __global__ __launch_bounds__(CTRL) void k_price_beams(int N, int R, double gamma
                                                       int apply, int iter, int32_t* __restrict__ lw,
                                                       int32_t* __restrict__ rw, uint8_t* __restrict__ occw,
                                                       double* __restrict__ yw, SolveTraceDev tr) {
+    {
+        // variant blockIdx.x: variant-major plan, row and trace arrays
+        const int b = blockIdx.x;
+        const int64_t NR = (int64_t)N * R;
+        y += (int64_t)b * N;
+        occ += (int64_t)b * N;
+        rowS += b * NR;
+        rowl += b * NR;
+        rowr += b * NR;
+        rowm += b * NR;
+        bprice += (int64_t)b * N;
+        out_beam += (int64_t)b * (1 + 2 * R);
+        out_price += (int64_t)b * 3;
+        if (user_bp) user_bp += (int64_t)b * N;
+        if (apply) {
+            lw += b * NR;
+            rw += b * NR;
+            occw += (int64_t)b * N;
+            yw += (int64_t)b * N;
+            tr.beam += (int64_t)b * N;
+            tr.price += (int64_t)b * N;
+            tr.margin += (int64_t)b * N;
+            tr.row_margin += (int64_t)b * N;
+        }
+    }
     __shared__ double shp[4];
     __shared__ int shk[4];
     __shared__ double sh[4];
@@ -227,13 +266,23 @@ __global__ __launch_bounds__(CTRL) void k_price_beams(int N, int R, double gamma
 vmat_status launch_price(const vmat_ctx* h, const double* g, const double* y, const int32_t* l, const int32_t* r,
                          const uint8_t* occ, int32_t* out_beam, double* out_price, double* beam_prices, int apply,
                          int iter, int32_t* lw, int32_t* rw, uint8_t* occw, double* yw, hipStream_t st) {
+    return launch_price_variants(h, 1, g, y, l, r, occ, h->row_S, h->row_l, h->row_r, h->row_m, h->bprice, out_beam,
+                                 out_price, beam_prices, apply, iter, lw, rw, occw, yw, h->tr, st);
+}
+
+vmat_status launch_price_variants(const vmat_ctx* h, int B, const double* g, const double* y, const int32_t* l,
+                                  const int32_t* r, const uint8_t* occ, double* rowS, int32_t* rowl, int32_t* rowr,
+                                  double* rowm, double* bprice, int32_t* out_beam, double* out_price,
+                                  double* beam_prices, int apply, int iter, int32_t* lw, int32_t* rw, uint8_t* occw,
+                                  double* yw, SolveTraceDev tr, hipStream_t st) {
     const int64_t NR = (int64_t)h->N * h->R;
-    k_price_rows<<<(unsigned)((NR + 3) / 4), 256, 0, st>>>(h->N, h->R, h->C, h->delta, h->circular, g, l, r, occ,
-                                                           h->row_S, h->row_l, h->row_r, h->row_m);
+    k_price_rows<<<dim3((unsigned)((NR + 3) / 4), (unsigned)B), 256, 0, st>>>(h->N, h->R, h->C, h->delta,
+                                                                             h->circular, B, g, l, r, occ, rowS,
+                                                                             rowl, rowr, rowm);
     VMAT_LAUNCH_CHECK();
-    k_price_beams<<<1, CTRL, 0, st>>>(h->N, h->R, h->gamma, h->circular, h->d_theta, y, occ, h->row_S, h->row_l,
-                                     h->row_r, h->row_m, h->bprice, out_beam, out_price, beam_prices, apply, iter,
-                                     lw, rw, occw, yw, h->tr);
+    k_price_beams<<<(unsigned)B, CTRL, 0, st>>>(h->N, h->R, h->gamma, h->circular, h->d_theta, y, occ, rowS, rowl,
+                                               rowr, rowm, bprice, out_beam, out_price, beam_prices, apply, iter,
+                                               lw, rw, occw, yw, tr);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }

@@ -102,6 +102,14 @@ def lib():
             "vmat_grad_fluence": [P, P, P, P, P, P, P],
             "vmat_grad_apertures": [P, P, P, P, P, P, P, P, P],
             "vmat_price": [P, P, P, P, P, P, P, P, P, P],
+            "vmat_forward_batched": [P, I32, P, P, P],
+            "vmat_adjoint_batched": [P, I32, P, P, P],
+            "vmat_grad_batched": [P, I32, I32, P, P, P, P, P, P, P, P],
+            "vmat_tune_batched": [P, I32, P, P, P, P, I32, P, P, P],
+            "vmat_set_batched_tile": [P, I32, I32, I32],
+            "vmat_reserve_batched": [P, I32],
+            "vmat_solve_batched": [P, ctypes.POINTER(SolveOpts), I32, I32, P, P, P, P, P, P,
+                                   ctypes.POINTER(SolveReport), ctypes.POINTER(SolveTrace), P, P],
             "vmat_master": [P, P, P, P, P, ctypes.POINTER(MasterOpts), ctypes.POINTER(MasterReport), P],
             "vmat_solve": [P, ctypes.POINTER(SolveOpts), P, P, P, P, P, ctypes.POINTER(SolveReport),
                            ctypes.POINTER(SolveTrace), P],
@@ -246,6 +254,93 @@ class Problem:
             g = torch.empty(self.nb, dtype=torch.float64, device=self.device)
         _check(lib().vmat_adjoint(self._h, _ptr(w), _ptr(g), _stream()))
         return g
+
+    def forward_batched(self, X, Z=None):
+        """Z = D^T X for B right-hand sides: X float [nb, B] -> Z double [nv, B]."""
+        import torch
+        B = X.shape[1]
+        if Z is None:
+            Z = torch.empty(self.nv, B, dtype=torch.float64, device=self.device)
+        _check(lib().vmat_forward_batched(self._h, B, _ptr(X), _ptr(Z), _stream()))
+        return Z
+
+    def adjoint_batched(self, W, G=None):
+        """G = D W for B right-hand sides: W float [nv, B] -> G double [nb, B]."""
+        import torch
+        B = W.shape[1]
+        if G is None:
+            G = torch.empty(self.nb, B, dtype=torch.float64, device=self.device)
+        _check(lib().vmat_adjoint_batched(self._h, B, _ptr(W), _ptr(G), _stream()))
+        return G
+
+    def grad_batched(self, label, table, X, with_g=True):
+        """Eq. 1 for B objective variants at once.  label uint8 [nv]; table
+        float [B, S, 3] of (alpha, beta, T); X float [nb, B].  Returns cost
+        double [B], Z double [nv, B], dF float [nv, B] and G double [nb, B]."""
+        import torch
+        B, S = table.shape[0], table.shape[1]
+        dev = self.device
+        Z = torch.empty(self.nv, B, dtype=torch.float64, device=dev)
+        dF = torch.empty(self.nv, B, dtype=torch.float32, device=dev)
+        cost = torch.empty(B, dtype=torch.float64, device=dev)
+        G = torch.empty(self.nb, B, dtype=torch.float64, device=dev) if with_g else None
+        _check(lib().vmat_grad_batched(self._h, B, S, _ptr(label), _ptr(table), _ptr(X), _ptr(Z), _ptr(cost),
+                                       _ptr(dF), _ptr(G), _stream()))
+        return {"cost": cost, "Z": Z, "dF": dF, "G": G}
+
+    def reserve_batched(self, max_variants):
+        _check(lib().vmat_reserve_batched(self._h, max_variants))
+
+    def solve_batched(self, label, table, opts: SolveOpts | None = None, want_trace=True):
+        """Column generation for B objective variants at once (table float
+        [B, S, 3] of (alpha, beta, T) per structure label).  Returns the plans
+        (l [B, N*R], r, occ [B, N], y [B, N]), the B reports, the B traces and
+        the numbers of forward and adjoint SpMM launches."""
+        import torch
+        B, S = table.shape[0], table.shape[1]
+        dev, N, R = self.device, self.N, self.R
+        l = torch.zeros(B, N * R, dtype=torch.int32, device=dev)
+        r = torch.zeros(B, N * R, dtype=torch.int32, device=dev)
+        occ = torch.zeros(B, N, dtype=torch.uint8, device=dev)
+        y = torch.zeros(B, N, dtype=torch.float64, device=dev)
+        reps = (SolveReport * B)()
+        trs, tr_c = None, None
+        if want_trace:
+            trs = [{"beam": np.zeros(N, np.int32), "price": np.zeros(N), "margin": np.zeros(N),
+                    "row_margin": np.zeros(N), "cost": np.zeros(N + 1), "master_iters": np.zeros(N, np.int32)}
+                   for _ in range(B)]
+            tr_c = (SolveTrace * B)(*[SolveTrace(*(t[k].ctypes.data for k in
+                                                   ("beam", "price", "margin", "row_margin", "cost",
+                                                    "master_iters"))) for t in trs])
+        cnt = (ctypes.c_int64 * 2)()
+        _check(lib().vmat_solve_batched(self._h, ctypes.byref(opts) if opts is not None else None, B, S,
+                                        _ptr(label), _ptr(table), _ptr(l), _ptr(r), _ptr(occ), _ptr(y), reps,
+                                        tr_c, cnt, _stream()))
+        reports = [reps[b] for b in range(B)]
+        if trs is not None:
+            trs = [{k: (v[:rep.cg_iters + 1] if k == "cost" else v[:rep.cg_iters]) for k, v in t.items()}
+                   for t, rep in zip(trs, reports)]
+        return (l, r, occ, y), reports, trs, (cnt[0], cnt[1])
+
+    def set_batched_tile(self, B, fwd_tile, adj_tile):
+        _check(lib().vmat_set_batched_tile(self._h, B, fwd_tile, adj_tile))
+
+    def tune_batched(self, B, reps=5, seed=0):
+        """Times every RHS tile width for both products at B right-hand sides
+        and keeps the fastest.  Returns (forward tile, adjoint tile, times)."""
+        import torch
+        dev = self.device
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        X = torch.rand(self.nb, B, generator=g).to(dev, torch.float32)
+        W = torch.randn(self.nv, B, generator=g).to(dev, torch.float32)
+        Z = torch.empty(self.nv, B, dtype=torch.float64, device=dev)
+        G = torch.empty(self.nb, B, dtype=torch.float64, device=dev)
+        best = (ctypes.c_int32 * 2)()
+        times = (ctypes.c_float * 14)()
+        _check(lib().vmat_tune_batched(self._h, B, _ptr(X), _ptr(Z), _ptr(W), _ptr(G), reps, best, times,
+                                       _stream()))
+        widths = (1, 2, 4, 8, 16, 32, 64)
+        return best[0], best[1], {"forward": dict(zip(widths, times[:7])), "adjoint": dict(zip(widths, times[7:]))}
 
     def grad(self, y, l, r, occ, want=("z", "dF", "g", "dfdy")):
         import torch

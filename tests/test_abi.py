@@ -1,0 +1,68 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/vmat.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+
+import pytest
+
+import paper_1005_4396_amd as P
+from paper_1005_4396_amd import vmat as V
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    if not os.path.exists(V.LIB_PATH):
+        pytest.skip("libvmat.so not built (run __graft_entry__.build())")
+    return V.lib()
+
+
+def test_header_declares_the_paper_entry_points():
+    names = V.header_symbols()
+    for n in ("vmat_dose", "vmat_grad", "vmat_price", "vmat_master", "vmat_solve", "vmat_create",
+              "vmat_destroy", "vmat_forward_batched", "vmat_adjoint_batched", "vmat_grad_batched",
+              "vmat_tune_batched"):
+        assert n in names, n
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    missing = [n for n in V.header_symbols() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_null_handle_rejected():
+    L = _lib()
+    assert L.vmat_dose(None, None, None, None, None, None, None) == V.VMAT_ERR_INVALID_ARG
+    assert "handle" in V.last_error()
+    assert L.vmat_forward_batched(None, 4, None, None, None) == V.VMAT_ERR_INVALID_ARG
+    assert L.vmat_set_batched_tile(None, 4, 8, 8) == V.VMAT_ERR_INVALID_ARG
+    assert L.vmat_destroy(None) in (V.VMAT_OK, V.VMAT_ERR_INVALID_ARG)
+
+
+def test_create_rejects_bad_problem_without_device():
+    L = _lib()
+    h = ctypes.c_void_p()
+    assert L.vmat_create(None, None, ctypes.byref(h)) == V.VMAT_ERR_INVALID_ARG
+    p = V._Problem()
+    p.n_beams, p.n_rows, p.n_cols = 0, 4, 4     # no beams
+    assert L.vmat_create(ctypes.byref(p), None, ctypes.byref(h)) == V.VMAT_ERR_INVALID_ARG
+    assert V.last_error()
+
+
+def test_status_codes_match_header():
+    with open(os.path.join(ROOT, "include", "vmat.h")) as f:
+        text = f.read()
+    for name in ("VMAT_OK", "VMAT_ERR_INVALID_ARG", "VMAT_ERR_DEVICE", "VMAT_ERR_ALLOC",
+                 "VMAT_ERR_NOT_CONVERGED", "VMAT_ERR_UNSUPPORTED"):
+        assert name in text
+        assert hasattr(V, name)
+
+
+def test_product_path_has_no_fallback(monkeypatch):
+    """Without the built library the binding raises instead of computing."""
+    monkeypatch.setattr(V, "_lib", None)
+    monkeypatch.setattr(V, "LIB_PATH", os.path.join(ROOT, "no_such_libvmat.so"))
+    with pytest.raises(RuntimeError):
+        V.lib()
+    assert not hasattr(P, "oracle")

@@ -1,0 +1,247 @@
+"""Plan variants sharing one D: products with many right-hand sides and the
+batched cost/gradient, against the FP64 reference applied column by column.
+
+Tile widths change no result: every width gives the same bits.
+"""
+import numpy as np
+import pytest
+
+import casegen
+import oracle as O
+from _cases import oracle_D, preset_case, small_case
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1005_4396_amd as P  # noqa: E402
+
+WIDTHS = (1, 2, 4, 8, 16, 32, 64)
+
+
+def T(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def rel_inf(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _inputs(c, B, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.random((c.n_beamlets, B)).astype(np.float32)
+    X[rng.random(c.n_beamlets) < 0.3] = 0.0
+    return X
+
+
+def _reference(D, c, X, tab):
+    """Column-by-column eq. 1 with per-variant weights, FP64."""
+    B = X.shape[1]
+    lab = np.minimum(c.label, tab.shape[1] - 1)
+    Z = np.empty((c.n_voxels, B))
+    dF = np.empty((c.n_voxels, B))
+    cost = np.empty(B)
+    for b in range(B):
+        Z[:, b] = O.dose(D, X[:, b].astype(np.float64))
+        w = tab[b].astype(np.float64)[lab]
+        cost[b], dF[:, b] = O.penalty(Z[:, b], w[:, 0], w[:, 1], w[:, 2])
+    return Z, dF, cost
+
+
+CASES = [("small", lambda: small_case(n_beams=6, n_rows=4, n_cols=8, grid=(16, 16, 10))),
+         ("tiny36", lambda: preset_case("tiny36"))]
+
+
+@pytest.mark.parametrize("layout", ["tiled", "plain"])
+@pytest.mark.parametrize("name,B", [("small", 1), ("small", 5), ("small", 64), ("tiny36", 64), ("tiny36", 13)])
+def test_batched_products_and_cost(name, B, layout):
+    c = dict(CASES)[name]()
+    D = oracle_D(c)
+    X = _inputs(c, B, B)
+    tab = casegen.variant_table(c, B, seed=B)
+    Z, dF, cost = _reference(D, c, X, tab)
+    prob = P.Problem.from_case(c, layout=layout)
+    try:
+        out = prob.grad_batched(T(c.label, torch.uint8), T(tab, torch.float32), T(X, torch.float32))
+        Zg = out["Z"].cpu().numpy()
+        assert rel_inf(Zg, Z) <= 1e-12
+        assert np.allclose(out["cost"].cpu().numpy(), cost, rtol=1e-9, atol=0)
+        dFg = out["dF"].cpu().numpy().astype(np.float64)
+        assert np.abs(dFg - dF).max() <= 2.0 ** -23 * np.abs(dF).max() * 4
+        # adjoint of the library's own dF against the reference product
+        G_ref = D @ dFg
+        assert rel_inf(out["G"].cpu().numpy(), G_ref) <= 1e-12
+        # every tile width gives the same bits
+        Xt, Wt = T(X, torch.float32), out["dF"]
+        ref_z, ref_g = None, None
+        for w in WIDTHS:
+            prob.set_batched_tile(B, w, w)
+            z = prob.forward_batched(Xt).cpu().numpy()
+            g = prob.adjoint_batched(Wt).cpu().numpy()
+            if ref_z is None:
+                ref_z, ref_g = z, g
+            assert np.array_equal(z, ref_z) and np.array_equal(g, ref_g), w
+        fw, aw, times = prob.tune_batched(B, reps=2)
+        assert fw in WIDTHS and aw in WIDTHS and fw <= max(B, 1) * 2 and aw <= max(B, 1) * 2
+        assert np.array_equal(prob.forward_batched(Xt).cpu().numpy(), ref_z)
+    finally:
+        prob.close()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16", "fp8"])
+def test_batched_reduced_precision(fmt):
+    c = small_case(n_beams=6, n_rows=4, n_cols=8, grid=(16, 16, 10))
+    if fmt == "fp8":
+        s, q = O.fp8_quantise(c.row_ptr, c.val)
+        vals = O.fp8_dequantise(c.row_ptr, s, q)
+    else:
+        vals = O.bf16_round(c.val) if fmt == "bf16" else O.fp16_round(c.val)
+    D = oracle_D(c, vals)
+    B = 16
+    X = _inputs(c, B, 7)
+    W = np.random.default_rng(8).standard_normal((c.n_voxels, B)).astype(np.float32)
+    prob = P.Problem.from_case(c, d_store=fmt)
+    try:
+        Zg = prob.forward_batched(T(X, torch.float32)).cpu().numpy()
+        Gg = prob.adjoint_batched(T(W, torch.float32)).cpu().numpy()
+    finally:
+        prob.close()
+    assert rel_inf(Zg, D.T @ X.astype(np.float64)) <= 1e-6
+    assert rel_inf(Gg, D @ W.astype(np.float64)) <= 1e-6
+
+
+def test_batched_prostate_full_size():
+    """64 variants of the prostate-shaped problem: sampled voxel and beamlet
+    rows against the reference, costs against the reference on all voxels."""
+    c = preset_case("prostate180")
+    D = oracle_D(c)
+    B = 64
+    X = _inputs(c, B, 3)
+    tab = casegen.variant_table(c, B, seed=3)
+    prob = P.Problem.from_case(c)
+    try:
+        prob.tune_batched(B, reps=2)
+        out = prob.grad_batched(T(c.label, torch.uint8), T(tab, torch.float32), T(X, torch.float32))
+        Zg, dFg = out["Z"].cpu().numpy(), out["dF"].cpu().numpy().astype(np.float64)
+        Gg, cost = out["G"].cpu().numpy(), out["cost"].cpu().numpy()
+    finally:
+        prob.close()
+    rng = np.random.default_rng(4)
+    Dt = D.T.tocsr()
+    vox = rng.choice(c.n_voxels, 4096, replace=False)
+    Zs = Dt[vox] @ X.astype(np.float64)
+    assert rel_inf(Zg[vox], Zs) <= 1e-12
+    rows = rng.choice(c.n_beamlets, 4096, replace=False)
+    Gs = D[rows] @ dFg
+    assert rel_inf(Gg[rows], Gs) <= 1e-12
+    lab = c.label
+    for b in range(0, B, 9):
+        w = tab[b].astype(np.float64)[lab]
+        Zb = O.dose(D, X[:, b].astype(np.float64))
+        Fb, _ = O.penalty(Zb, w[:, 0], w[:, 1], w[:, 2])
+        assert cost[b] == pytest.approx(Fb, rel=1e-9)
+
+
+# ---------------------------------------------------------------- batched solves
+
+def _variant_weights(c, tab, b):
+    w = tab[b][np.minimum(c.label, tab.shape[1] - 1)]
+    return w[:, 0].copy(), w[:, 1].copy(), w[:, 2].copy()
+
+
+def _compare_plan(c, ref, tr, lk, rk, rep, eps_rel=1e-5, cost_rel=1e-6):
+    """Iteration by iteration the chosen beam and its leaf pairs must equal the
+    reference's; the first difference is excused only where the reference's
+    beam or row margin is at most eps_rel * |price|."""
+    R = c.n_rows
+    assert rep.cg_iters == len(ref.order)
+    matched = 0
+    for t in range(len(ref.order)):
+        k = ref.order[t]
+        same = (tr["beam"][t] == k and np.array_equal(lk[k * R:(k + 1) * R], ref.apertures[t][0])
+                and np.array_equal(rk[k * R:(k + 1) * R], ref.apertures[t][1]))
+        if not same:
+            eps = eps_rel * abs(ref.prices[t])
+            assert ref.margins[t] <= eps or ref.row_margins[t] <= eps, \
+                f"iteration {t}: beam {tr['beam'][t]} vs {k}, margins {ref.margins[t]}, {ref.row_margins[t]}"
+            break
+        assert abs(tr["price"][t] - ref.prices[t]) <= 1e-4 * abs(ref.prices[0])
+        matched += 1
+    if matched == len(ref.order):
+        assert rep.F + rep.gG == pytest.approx(ref.costs[-1], rel=cost_rel)
+        np.testing.assert_allclose(tr["cost"], ref.costs, rtol=cost_rel)
+    cost = tr["cost"]
+    assert np.all(cost[1:] <= cost[:-1] * (1 + 1e-12))
+    assert sorted(tr["beam"].tolist()) == list(range(c.n_beams))
+    L, Rr = lk.reshape(c.n_beams, R), rk.reshape(c.n_beams, R)
+    assert np.all(L <= Rr)
+    N = c.n_beams
+    pairs = [(k, k + 1) for k in range(N - 1)] + ([(N - 1, 0)] if c.circular else [])
+    for a, b in pairs:
+        assert np.all(np.abs(L[a] - L[b]) <= c.max_leaf_step)
+        assert np.all(np.abs(Rr[a] - Rr[b]) <= c.max_leaf_step)
+    return matched
+
+
+@pytest.mark.parametrize("name,B", [("small", 5), ("tiny36", 3)])
+def test_batched_solve_matches_oracle(name, B):
+    c = dict(CASES)[name]()
+    D = oracle_D(c)
+    tab = casegen.variant_table(c, B, seed=11)
+    prob = P.Problem.from_case(c)
+    try:
+        prob.reserve_batched(B)
+        (l, r, occ, y), reps, trs, cnt = prob.solve_batched(T(c.label, torch.uint8), T(tab, torch.float32))
+        lg, rg = l.cpu().numpy(), r.cpu().numpy()
+    finally:
+        prob.close()
+    assert cnt[0] >= 1 and cnt[1] >= 1
+    matched = []
+    for b in range(B):
+        al, be, tt = _variant_weights(c, tab, b)
+        ref = O.solve(D, al, be, tt, c.theta_deg, c.gamma, c.circular, c.n_rows, c.n_cols, c.max_leaf_step)
+        matched.append(_compare_plan(c, ref, trs[b], lg[b], rg[b], reps[b]))
+    print(f"{name}: iterations matched per variant {matched} of {c.n_beams}")
+    assert sum(m == c.n_beams for m in matched) >= B // 2
+
+
+def test_batched_solve_prostate_first_iterations():
+    """Two variants of the prostate-shaped problem, four column-generation
+    iterations, against the single-plan GPU solve of each variant (which the
+    other tests hold to the reference)."""
+    import dataclasses
+    c = preset_case("prostate180")
+    B, iters = 2, 4
+    tab = casegen.variant_table(c, B, seed=12)
+    opts = P.vmat.SolveOpts()
+    opts.max_cg_iter = iters
+    opts.master = P.master_opts()
+    prob = P.Problem.from_case(c)
+    try:
+        prob.reserve_batched(B)
+        (l, r, occ, y), reps, trs, cnt = prob.solve_batched(T(c.label, torch.uint8), T(tab, torch.float32), opts)
+        lg, rg = l.cpu().numpy(), r.cpu().numpy()
+    finally:
+        prob.close()
+    R = c.n_rows
+    for b in range(B):
+        al, be, tt = _variant_weights(c, tab, b)
+        cb = dataclasses.replace(c, alpha=al, beta=be, T=tt)
+        single = P.Problem.from_case(cb)
+        try:
+            l1, r1, o1, y1 = single.empty_plan()
+            rep1, tr1 = single.solve(l1, r1, o1, y1, opts)
+            l1, r1 = l1.cpu().numpy(), r1.cpu().numpy()
+        finally:
+            single.close()
+        assert reps[b].cg_iters == iters
+        for t in range(iters):
+            k = tr1["beam"][t]
+            same = trs[b]["beam"][t] == k and np.array_equal(lg[b][k * R:(k + 1) * R], l1[k * R:(k + 1) * R]) \
+                and np.array_equal(rg[b][k * R:(k + 1) * R], r1[k * R:(k + 1) * R])
+            if not same:
+                eps = 1e-5 * abs(tr1["price"][t])
+                assert tr1["margin"][t] <= eps or tr1["row_margin"][t] <= eps, (b, t)
+                break
+            np.testing.assert_allclose(trs[b]["cost"][t + 1], tr1["cost"][t + 1], rtol=1e-6)
