@@ -262,6 +262,40 @@ vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, int32_t* l, i
                        uint8_t* occ, double* y, float* z, vmat_solve_report* rep,
                        vmat_solve_trace* trace, hipStream_t stream);
 
+/* Dose-rate feasibility of a final plan (Sec. 3): the smoothing term of eq. 3
+ * only penalises intensity changes between neighbouring angles; when the
+ * final plan still changes faster than the machine allows, gamma is raised
+ * and the intensities are re-optimised with the apertures fixed, until the
+ * plan is feasible.  Rate = max over the eq. 2 pairs (a, b) of
+ * |y_b - y_a| / (theta_b - theta_a), per degree.  Each round multiplies gamma
+ * by `factor` and runs vmat_master from the previous intensities; the first
+ * check is on y as given (a feasible y is returned unchanged, rounds = 0).
+ * The handle's gamma is left as created.
+ *   y: DEVICE double [N], in: the plan's intensities, out: re-optimised;
+ *   l, r, occ: DEVICE, the fixed apertures; rep: HOST.                      */
+typedef struct {
+    double rate_max;        /* largest allowed change per degree, >= 0        */
+    double factor;          /* gamma multiplier per round, > 1                 */
+    int32_t max_rounds;     /* >= 0                                            */
+    int32_t reserved;
+    vmat_master_opts master;/* options of every re-optimisation; fields <= 0
+                             * take the defaults (200, 50, 1e-5, reference 0) */
+} vmat_rate_opts;
+
+typedef struct {
+    int32_t rounds;         /* re-optimisations run                            */
+    int32_t feasible;       /* 1 if the returned y meets rate_max               */
+    int32_t master_iters;   /* summed over the rounds                          */
+    int32_t not_converged;  /* rounds whose master hit its iteration cap       */
+    double gamma;           /* gamma of the last round                         */
+    double rate;            /* max rate of the returned y                      */
+    double F, gG;           /* cost terms at the returned y (gG at `gamma`)    */
+} vmat_rate_report;
+
+vmat_status vmat_enforce_rate(vmat_handle h, const vmat_rate_opts* opts, const int32_t* l,
+                              const int32_t* r, const uint8_t* occ, double* y,
+                              vmat_rate_report* rep, hipStream_t stream);
+
 /* Batched column generation: B plan variants (the objective of eq. 1 with
  * per-variant weights and thresholds, as in vmat_grad_batched) sharing D,
  * each solved by the column-generation loop of vmat_solve, in lockstep: every

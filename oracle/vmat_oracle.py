@@ -542,6 +542,57 @@ def solve(D, alpha, beta, T, theta_deg, gamma, circular, R, C, delta, max_cg_ite
 
 
 # --------------------------------------------------------------------------
+# Dose-rate feasibility of the final plan (Sec. 3): the smoothing term is a
+# soft constraint; when the final intensities still change too fast between
+# neighbouring angles, gamma is raised and the intensities re-optimised with
+# the apertures fixed, until the plan is feasible.
+# --------------------------------------------------------------------------
+
+
+def max_rate(y, theta_deg, circular):
+    """Largest intensity change per degree over the neighbour pairs of eq. 2."""
+    y = np.asarray(y, dtype=np.float64)
+    rates = [abs(y[b] - y[a]) / w for a, b, w in smoothing_pairs(theta_deg, circular)]
+    return max(rates) if rates else 0.0
+
+
+@dataclasses.dataclass
+class RateResult:
+    y: np.ndarray
+    gamma: float
+    rounds: int           # re-optimisations run
+    feasible: bool
+    rate: float           # max_rate of the returned y
+    costs: list           # F + gamma G after each round (at that round's gamma)
+    smoothing: list       # G after each round
+
+
+def enforce_rate(D, alpha, beta, T, theta_deg, gamma, circular, R, C, l, r, occ, y, rate_max,
+                 factor=10.0, max_rounds=8, opts=MasterOpts()):
+    """Raise gamma by ``factor`` and re-solve the master (apertures fixed, warm
+    start from the previous intensities) until max_rate(y) <= rate_max or
+    ``max_rounds`` re-optimisations have run.  The first check is on y as
+    given; a feasible y is returned unchanged."""
+    y = np.where(np.asarray(occ).astype(bool), np.asarray(y, dtype=np.float64), 0.0)
+    g_now = float(gamma)
+    rounds = 0
+    costs, smooth = [], []
+    rate = max_rate(y, theta_deg, circular)
+    start = None
+    while rate > rate_max and rounds < max_rounds:
+        g_now *= factor
+        res = master(D, alpha, beta, T, theta_deg, g_now, circular, R, C, l, r, occ, y, opts, start=start)
+        y = res.y
+        start = (res.z, res.g)
+        rounds += 1
+        costs.append(res.F + res.gG)
+        smooth.append(res.gG / g_now if g_now > 0 else 0.0)
+        rate = max_rate(y, theta_deg, circular)
+    return RateResult(y=y, gamma=g_now, rounds=rounds, feasible=rate <= rate_max, rate=rate, costs=costs,
+                      smoothing=smooth)
+
+
+# --------------------------------------------------------------------------
 # Reduced-precision storage of D (bf16 / fp16 / fp8 E4M3 with per-beamlet scale)
 # --------------------------------------------------------------------------
 

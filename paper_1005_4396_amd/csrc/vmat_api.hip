@@ -371,3 +371,56 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
     if (rep) *rep = R;
     return VMAT_OK;
 }
+
+extern "C" vmat_status vmat_enforce_rate(vmat_handle h, const vmat_rate_opts* opts, const int32_t* l,
+                                         const int32_t* r, const uint8_t* occ, double* y, vmat_rate_report* rep,
+                                         hipStream_t st) {
+    TRY(check_handle(h));
+    TRY(check_plan(y, l, r, occ));
+    if (!opts || !rep) return fail(VMAT_ERR_INVALID_ARG, "null options or report");
+    if (!(opts->rate_max >= 0.0) || !std::isfinite(opts->rate_max))
+        return fail(VMAT_ERR_INVALID_ARG, "rate_max must be finite and >= 0");
+    if (!(opts->factor > 1.0) || !std::isfinite(opts->factor)) return fail(VMAT_ERR_INVALID_ARG, "factor must be > 1");
+    if (opts->max_rounds < 0) return fail(VMAT_ERR_INVALID_ARG, "max_rounds must be >= 0");
+    vmat_master_opts mo = opts->master;
+    if (mo.max_iter <= 0) mo.max_iter = 200;
+    if (mo.ls_max_steps <= 0) mo.ls_max_steps = 50;
+    if (!(mo.tol_rel > 0.0)) mo.tol_rel = 1e-5;
+    TRY(check_opts(mo));
+    vmat_rate_report R = {};
+    const double gamma0 = h->gamma;
+    double g_now = gamma0;
+    double rate_G[2];
+    auto read_rate = [&]() -> vmat_status {
+        TRY(launch_max_rate(h, y, h->cost2, st));
+        VMAT_HIP(hipMemcpyAsync(rate_G, h->cost2, sizeof(rate_G), hipMemcpyDeviceToHost, st));
+        VMAT_HIP(hipStreamSynchronize(st));
+        return VMAT_OK;
+    };
+    // unoccupied beams carry y = 0 (as in the master) before the first check
+    TRY(launch_master_begin(h, y, occ, 1, 1, 1.0, 0.0, 1, st));
+    TRY(read_rate());
+    vmat_status rc = VMAT_OK;
+    while (rate_G[0] > opts->rate_max && R.rounds < opts->max_rounds) {
+        g_now *= opts->factor;
+        h->gamma = g_now;
+        vmat_master_report mr{};
+        rc = run_master(h, l, r, occ, y, mo, &mr, st, R.rounds == 0 ? 1 : 0);
+        if (rc != VMAT_OK && rc != VMAT_ERR_NOT_CONVERGED) break;
+        if (rc == VMAT_ERR_NOT_CONVERGED) R.not_converged++;
+        rc = VMAT_OK;
+        R.rounds++;
+        R.master_iters += mr.iters;
+        R.F = mr.F;
+        R.gG = mr.gG;
+        if ((rc = read_rate()) != VMAT_OK) break;
+    }
+    h->gamma = gamma0;
+    if (rc != VMAT_OK) return rc;
+    R.gamma = g_now;
+    R.rate = rate_G[0];
+    R.feasible = rate_G[0] <= opts->rate_max ? 1 : 0;
+    if (R.rounds == 0) R.gG = g_now * rate_G[1];
+    *rep = R;
+    return VMAT_OK;
+}

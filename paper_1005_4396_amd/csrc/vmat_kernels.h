@@ -63,6 +63,9 @@ vmat_status launch_ls_ctrl(const vmat_ctx* h, hipStream_t st);
 vmat_status launch_master_step(const vmat_ctx* h, double* y, hipStream_t st);
 vmat_status launch_update(const vmat_ctx* h, hipStream_t st);
 
+// max over eq. 2 pairs of |y_b - y_a| / (theta_b - theta_a) -> out[0]; G(y) -> out[1]
+vmat_status launch_max_rate(const vmat_ctx* h, const double* y, double* out, hipStream_t st);
+
 // ---- pricing
 // apply != 0: also occupy the chosen beam in (l, r, occ, y), record the trace
 // entry `iter` and set the master's reference scale on the first call.

@@ -245,6 +245,31 @@ vmat_status launch_cost_only(const vmat_ctx* h, double* cost, hipStream_t st) {
     return VMAT_OK;
 }
 
+// Largest intensity change per degree over the eq. 2 pairs, and G.
+__global__ __launch_bounds__(CTRL) void k_max_rate(int N, int circ, const double* __restrict__ y,
+                                                   const double* __restrict__ th, double* __restrict__ out) {
+    __shared__ double sh[4];
+    double m = 0.0;
+    for (int p = threadIdx.x; p < n_pairs(N, circ); p += CTRL) {
+        int a, b;
+        double w;
+        smoothing_pair(p, N, circ, th, a, b, w);
+        m = fmax(m, fabs(y[b] - y[a]) / w);
+    }
+    m = bmax(m, sh);
+    const double G = smoothing_G(y, th, N, circ, sh);
+    if (threadIdx.x == 0) {
+        out[0] = m;
+        out[1] = G;
+    }
+}
+
+vmat_status launch_max_rate(const vmat_ctx* h, const double* y, double* out, hipStream_t st) {
+    k_max_rate<<<1, CTRL, 0, st>>>(h->N, h->circular, y, h->d_theta, out);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
 // ---------------------------------------------------------------- master control (one workgroup)
 // All per-beam work is spread over the 256 threads; scalars are combined with
 // fixed-order block reductions and written by thread 0.

@@ -75,6 +75,17 @@ class SolveTrace(ctypes.Structure):
                 ("row_margin", ctypes.c_void_p), ("cost", ctypes.c_void_p), ("master_iters", ctypes.c_void_p)]
 
 
+class RateOpts(ctypes.Structure):
+    _fields_ = [("rate_max", ctypes.c_double), ("factor", ctypes.c_double), ("max_rounds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("master", MasterOpts)]
+
+
+class RateReport(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("feasible", ctypes.c_int32), ("master_iters", ctypes.c_int32),
+                ("not_converged", ctypes.c_int32), ("gamma", ctypes.c_double), ("rate", ctypes.c_double),
+                ("F", ctypes.c_double), ("gG", ctypes.c_double)]
+
+
 def header_symbols():
     """Names of the functions declared in include/vmat.h."""
     with open(HEADER) as f:
@@ -108,6 +119,7 @@ def lib():
             "vmat_tune_batched": [P, I32, P, P, P, P, I32, P, P, P],
             "vmat_set_batched_tile": [P, I32, I32, I32],
             "vmat_reserve_batched": [P, I32],
+            "vmat_enforce_rate": [P, ctypes.POINTER(RateOpts), P, P, P, P, ctypes.POINTER(RateReport), P],
             "vmat_solve_batched": [P, ctypes.POINTER(SolveOpts), I32, I32, P, P, P, P, P, P,
                                    ctypes.POINTER(SolveReport), ctypes.POINTER(SolveTrace), P, P],
             "vmat_master": [P, P, P, P, P, ctypes.POINTER(MasterOpts), ctypes.POINTER(MasterReport), P],
@@ -287,6 +299,16 @@ class Problem:
         _check(lib().vmat_grad_batched(self._h, B, S, _ptr(label), _ptr(table), _ptr(X), _ptr(Z), _ptr(cost),
                                        _ptr(dF), _ptr(G), _stream()))
         return {"cost": cost, "Z": Z, "dF": dF, "G": G}
+
+    def enforce_rate(self, l, r, occ, y, rate_max, factor=10.0, max_rounds=8, master=None) -> RateReport:
+        """Dose-rate feasibility of a final plan: raise gamma by `factor` and
+        re-optimise y (in place) until the largest change per degree between
+        neighbouring angles is at most rate_max."""
+        o = RateOpts(rate_max, factor, max_rounds, 0, master if master is not None else MasterOpts(0, 0, 0.0, 0.0))
+        rep = RateReport()
+        _check(lib().vmat_enforce_rate(self._h, ctypes.byref(o), _ptr(l), _ptr(r), _ptr(occ), _ptr(y),
+                                       ctypes.byref(rep), _stream()))
+        return rep
 
     def reserve_batched(self, max_variants):
         _check(lib().vmat_reserve_batched(self._h, max_variants))

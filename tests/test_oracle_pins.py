@@ -477,3 +477,77 @@ def test_fp8_quantisation_error_bound():
     x = np.random.default_rng(19).random(D.shape[0])
     B = O.quantisation_bound(D, Dh, x)
     assert np.all(np.abs(O.dose(Dh, x) - O.dose(D, x)) <= B * (1 + 1e-12) + 1e-300)
+
+
+# ---------------------------------------------------------------- dose-rate feasibility (Sec. 3)
+
+def _two_beam_problem(T1, T2):
+    """Two beams (open chain, 10 degrees apart), one beamlet each, each dosing
+    its own voxel with D = 1; alpha = beta = 1, so F = (y1-T1)^2 + (y2-T2)^2 in
+    every regime and the master optimum solves
+    [1 + g/10, -g/10; -g/10, 1 + g/10] y = (T1, T2):  y2 - y1 = (T2-T1)/(1 + g/5)."""
+    D = sp.csr_matrix(np.eye(2))
+    th = np.array([0.0, 10.0])
+    one = np.ones(2)
+    return D, th, one, np.array([T1, T2])
+
+
+def _two_beam_optimum(T1, T2, g):
+    diff = (T2 - T1) / (1.0 + g / 5.0)
+    s = T1 + T2
+    return np.array([(s - diff) / 2, (s + diff) / 2])
+
+
+def test_rate_continuation_two_beams_closed_form():
+    T1, T2 = 10.0, 20.0
+    D, th, one, T = _two_beam_problem(T1, T2)
+    l, r, occ = np.zeros(2, int), np.ones(2, int), np.ones(2, np.uint8)
+    y0 = _two_beam_optimum(T1, T2, 0.1)
+    # rates per degree: 1/(1+g/5) at g = 0.1, 1, 10, 100 -> 0.980, 0.833, 0.333, 0.0476
+    res = O.enforce_rate(D, one, one, T, th, 0.1, 0, 1, 1, l, r, occ, y0, rate_max=0.2, factor=10.0,
+                         opts=O.MasterOpts(tol_rel=1e-12))
+    assert res.rounds == 3 and res.feasible
+    assert res.gamma == pytest.approx(100.0, rel=1e-12)
+    np.testing.assert_allclose(res.y, _two_beam_optimum(T1, T2, 100.0), rtol=1e-9)
+    assert res.rate == pytest.approx(1.0 / 21.0, rel=1e-8)
+    # G of each round's optimum: ((T2-T1)/(1+g/5))^2 / 10 for g = 1, 10, 100
+    np.testing.assert_allclose(res.smoothing, [(10 / (1 + g / 5)) ** 2 / 10 for g in (1.0, 10.0, 100.0)],
+                               rtol=1e-8)
+
+
+def test_rate_continuation_feasible_plan_untouched_and_round_cap():
+    T1, T2 = 10.0, 20.0
+    D, th, one, T = _two_beam_problem(T1, T2)
+    l, r, occ = np.zeros(2, int), np.ones(2, int), np.ones(2, np.uint8)
+    y0 = _two_beam_optimum(T1, T2, 0.1)
+    res = O.enforce_rate(D, one, one, T, th, 0.1, 0, 1, 1, l, r, occ, y0, rate_max=1.0)
+    assert res.rounds == 0 and res.feasible and res.gamma == 0.1
+    np.testing.assert_array_equal(res.y, y0)
+    res = O.enforce_rate(D, one, one, T, th, 0.1, 0, 1, 1, l, r, occ, y0, rate_max=1e-6, max_rounds=2)
+    assert res.rounds == 2 and not res.feasible and res.gamma == pytest.approx(10.0)
+
+
+def test_rate_continuation_on_generated_case():
+    """After a full plan: G of the re-optimised intensities never increases
+    from round to round (the optimum's G is non-increasing in gamma for a
+    convex objective), and the last round is a KKT point at its gamma."""
+    import casegen
+    c = casegen.make_case(casegen.tiny_case(n_beams=8, n_rows=3, n_cols=6, grid=(12, 12, 8), thr=0.3))
+    D = O.dose_matrix(c.row_ptr, c.col, c.val, c.n_voxels)
+    sol = O.solve(D, c.alpha, c.beta, c.T, c.theta_deg, c.gamma, c.circular, c.n_rows, c.n_cols,
+                  c.max_leaf_step)
+    G0, _ = O.smoothing(sol.y, c.theta_deg, c.circular)
+    rate0 = O.max_rate(sol.y, c.theta_deg, c.circular)
+    assert rate0 > 0
+    opts = O.MasterOpts(tol_rel=1e-10, max_iter=2000)
+    res = O.enforce_rate(D, c.alpha, c.beta, c.T, c.theta_deg, c.gamma, c.circular, c.n_rows, c.n_cols,
+                         sol.l, sol.r, sol.occ, sol.y, rate_max=0.25 * rate0, factor=4.0, opts=opts)
+    assert res.rounds >= 1
+    Gs = [G0] + res.smoothing
+    assert all(b <= a * (1 + 1e-9) + 1e-12 for a, b in zip(Gs, Gs[1:]))
+    assert res.feasible == (res.rate <= 0.25 * rate0)
+    F, gG, z, dF, g, grad = O.objective(D, (c.alpha, c.beta, c.T), res.y, sol.l, sol.r, sol.occ, res.gamma,
+                                        c.theta_deg, c.circular, c.n_rows, c.n_cols)
+    occ = sol.occ.astype(bool)
+    kkt = np.abs(np.minimum(res.y, grad))[occ].max()
+    assert kkt <= 1e-8 * abs(sol.prices[0])
