@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--variants", type=int, default=64)
     ap.add_argument("--no-batched-solve", action="store_true")
+    ap.add_argument("--products-only", action="store_true",
+                    help="no plans and no side studies: only the per-kernel product timing (for profiling)")
     ap.add_argument("--sequential-variants", type=int, default=64,
                     help="variants solved one at a time for the batched-solve comparison")
     args = ap.parse_args()
@@ -103,6 +105,9 @@ def main():
         rep, tr = prob.solve(l, r, occ, y, want_trace=True)
         return rep, tr
 
+    if args.products_only:
+        args.steps = args.warmup = 0
+        args.no_precision = args.no_batched = args.no_batched_solve = args.no_cpu_baseline = True
     for w in range(args.warmup):
         rep, tr = one_plan()
         torch.cuda.synchronize()
@@ -117,7 +122,7 @@ def main():
         reps.append(rep)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    ms_per_step = wall * 1e3 / args.steps
+    ms_per_step = wall * 1e3 / args.steps if args.steps else None
 
     # algorithmic bytes of the products run during the timed plans
     lay = prob.layout()
@@ -125,8 +130,9 @@ def main():
     n_fwd = sum(r.n_forward for r in reps)
     n_adj = sum(r.n_adjoint for r in reps)
     total_bytes = n_fwd * fwd_b + n_adj * adj_b
-    value = total_bytes / wall / 1e9
-    log(f"[bench] {args.steps} plans in {wall:.2f}s: {ms_per_step:.1f} ms/plan, fwd={n_fwd} adj={n_adj}")
+    value = total_bytes / wall / 1e9 if args.steps else None
+    if args.steps:
+        log(f"[bench] {args.steps} plans in {wall:.2f}s: {ms_per_step:.1f} ms/plan, fwd={n_fwd} adj={n_adj}")
 
     # per-kernel timing of the two products (HIP events on torch's current stream)
     rng = np.random.default_rng(0)
@@ -151,12 +157,12 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": round(value, 2),
+        "value": round(value, 2) if value is not None else None,
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(ms_per_step, 3) if ms_per_step else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -166,10 +172,10 @@ def main():
                    "voxels": case.n_voxels, "nnz": case.nnz, "d_store": args.d_store,
                    "layout": "tiled" if lay["tiled"] else "plain",
                    "step": "one full column-generation plan"},
-        "plan_s": round(ms_per_step / 1e3, 4),
+        "plan_s": round(ms_per_step / 1e3, 4) if ms_per_step else None,
         "plan": {"cg_iters": reps[-1].cg_iters, "master_iters": reps[-1].master_iters,
                  "n_forward": reps[-1].n_forward, "n_adjoint": reps[-1].n_adjoint,
-                 "n_ls_evals": reps[-1].n_ls_evals, "cost": reps[-1].F + reps[-1].gG},
+                 "n_ls_evals": reps[-1].n_ls_evals, "cost": reps[-1].F + reps[-1].gG} if reps else None,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(dom_gbs, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(dom_gbs / PEAK_HBM_GBS, 4), "traffic": None,
                      "bytes_per_launch": dom_bytes},
