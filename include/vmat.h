@@ -232,11 +232,19 @@ vmat_status vmat_master(vmat_handle h, const int32_t* l, const int32_t* r, const
 
 typedef struct vmat_solve_opts {
     int32_t max_cg_iter;     /* apertures to add (<= 0 or > free beams: until all occupied) */
-    int32_t reserved;
+    int32_t master_mode;     /* 0: the master's products stream D (one forward per
+                              *    direction, one adjoint per step);
+                              * 1: aperture doses d_k = D^T 1_{A_k} are stored when an
+                              *    aperture opens (one forward each) and the master works
+                              *    on them alone; one adjoint per column-generation
+                              *    iteration gives the prices.  Same iterates up to
+                              *    rounding; the store (about 32 B per non-zero of the
+                              *    aperture doses) is allocated on first use.          */
     vmat_master_opts master; /* master.kkt_ref <= 0: |p| of the first priced aperture       */
 } vmat_solve_opts;
 
 typedef struct vmat_solve_report {
+    /* n_forward, n_adjoint: products with D (either master mode)                */
     int32_t cg_iters, master_iters, n_forward, n_adjoint, n_ls_evals, not_converged;
     double F, gG, kkt_ref;
 } vmat_solve_report;

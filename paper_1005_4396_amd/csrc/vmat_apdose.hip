@@ -1,0 +1,331 @@
+// Aperture doses for the master over the generated apertures (Sec. 2.2).
+//
+// The master problem keeps the apertures fixed and optimises one intensity
+// per aperture, so the dose is z = sum_k y_k d_k with d_k = D^T 1_{A_k}.  Each
+// d_k is computed once, when its aperture is opened (one dose product), and
+// stored sparsely; the master's dose products and its beam gradients
+// dF/dy_k = <d_k, F'(z)> then touch only these vectors, which hold far fewer
+// entries than D (an aperture exposes a small part of its beam).
+//
+// Storage (ApDose in vmat_internal.h): an aperture-major copy, appended per
+// aperture with voxels ascending, for the per-aperture sums; a voxel-major
+// copy, rebuilt by merging each new aperture into the previous one, for the
+// dose.  Every sum runs in a fixed order: deterministic results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "vmat_block.h"
+#include "vmat_internal.h"
+#include "vmat_kernels.h"
+
+namespace vmat {
+
+constexpr int AP_CHUNK = 1024;  // voxels per chunk of the compaction
+constexpr int AP_T = 256;       // threads per block (4 voxels each)
+
+// Unit intensity on the aperture being stored: beam = *src if src, else beam_h.
+__global__ __launch_bounds__(AP_T) void k_ap_unit(int N, const int32_t* __restrict__ src, int beam_h,
+                                                  double* __restrict__ unit, int32_t* __restrict__ beam_out) {
+    const int kb = src ? src[0] : beam_h;
+    for (int k = threadIdx.x; k < N; k += AP_T) unit[k] = k == kb ? 1.0 : 0.0;
+    if (threadIdx.x == 0) beam_out[0] = kb;
+}
+
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t* sh, uint32_t* total) {
+    // sh: AP_T + 1 entries; fixed sequential scan by thread 0 over the block
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int t = 0; t < AP_T; ++t) {
+            const uint32_t c = sh[t];
+            sh[t] = run;
+            run += c;
+        }
+        sh[AP_T] = run;
+    }
+    __syncthreads();
+    const uint32_t r = sh[threadIdx.x];
+    *total = sh[AP_T];
+    __syncthreads();
+    return r;
+}
+
+// Non-zeros of d per chunk of AP_CHUNK voxels.
+__global__ __launch_bounds__(AP_T) void k_ap_count(int64_t nv, const double* __restrict__ d,
+                                                   uint32_t* __restrict__ chunk) {
+    __shared__ uint32_t sh[AP_T + 1];
+    const int64_t j0 = (int64_t)blockIdx.x * AP_CHUNK + threadIdx.x * 4;
+    uint32_t c = 0;
+    for (int u = 0; u < 4; ++u)
+        if (j0 + u < nv && d[j0 + u] != 0.0) ++c;
+    uint32_t tot;
+    (void)block_excl_scan_u32(c, sh, &tot);
+    if (threadIdx.x == 0) chunk[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the chunk counts (one block, tiles of AP_T in order);
+// chunk[n] = total.
+__global__ __launch_bounds__(AP_T) void k_ap_scan(int n, uint32_t* __restrict__ chunk) {
+    __shared__ uint32_t sh[AP_T + 1];
+    uint32_t carry = 0;
+    for (int base = 0; base < n; base += AP_T) {
+        const int i = base + threadIdx.x;
+        const uint32_t v = i < n ? chunk[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan_u32(v, sh, &tot);
+        if (i < n) chunk[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) chunk[n] = carry;
+}
+
+// Appends the non-zeros of d (voxels ascending) to the aperture-major copy at
+// offset top, and merges them into the voxel-major copy (old -> new):
+// new_ptr[j] = old_ptr[j] + (non-zeros before voxel j).
+__global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, const double* __restrict__ d,
+                                                  const uint32_t* __restrict__ chunk,
+                                                  const int32_t* __restrict__ beam, uint32_t top,
+                                                  uint32_t* __restrict__ col_vox, double* __restrict__ col_val,
+                                                  const uint32_t* __restrict__ optr,
+                                                  const uint16_t* __restrict__ obeam,
+                                                  const double* __restrict__ oval, uint32_t* __restrict__ nptr,
+                                                  uint16_t* __restrict__ nbeam, double* __restrict__ nval) {
+    __shared__ uint32_t sh[AP_T + 1];
+    const int64_t j0 = (int64_t)blockIdx.x * AP_CHUNK + threadIdx.x * 4;
+    double v[4];
+    uint32_t c = 0;
+    for (int u = 0; u < 4; ++u) {
+        v[u] = j0 + u < nv ? d[j0 + u] : 0.0;
+        if (v[u] != 0.0) ++c;
+    }
+    uint32_t tot;
+    uint32_t p = chunk[blockIdx.x] + block_excl_scan_u32(c, sh, &tot);
+    const uint16_t kb = (uint16_t)beam[0];
+    for (int u = 0; u < 4; ++u) {
+        const int64_t j = j0 + u;
+        if (j >= nv) break;
+        const uint32_t o0 = optr[j], o1 = optr[j + 1];
+        const uint32_t n0 = o0 + p;
+        nptr[j] = n0;
+        for (uint32_t e = o0; e < o1; ++e) {
+            nbeam[n0 + (e - o0)] = obeam[e];
+            nval[n0 + (e - o0)] = oval[e];
+        }
+        if (v[u] != 0.0) {
+            nbeam[n0 + (o1 - o0)] = kb;
+            nval[n0 + (o1 - o0)] = v[u];
+            col_vox[top + p] = (uint32_t)j;
+            col_val[top + p] = v[u];
+            ++p;
+        }
+        if (j == nv - 1) nptr[nv] = optr[nv] + chunk[n_chunks];
+    }
+}
+
+__global__ void k_ap_slot(int slot, const int32_t* __restrict__ beam, const uint32_t* __restrict__ chunk,
+                          int n_chunks, uint32_t* __restrict__ col_ptr, int32_t* __restrict__ beam_slot) {
+    col_ptr[slot + 1] = col_ptr[slot] + chunk[n_chunks];
+    beam_slot[beam[0]] = slot;
+}
+
+// out_j = sum over voxel j's entries (opening order) of val * vec[beam].
+__global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, const uint32_t* __restrict__ ptr,
+                                                  const uint16_t* __restrict__ beam,
+                                                  const double* __restrict__ val, const double* __restrict__ vec,
+                                                  double* __restrict__ out, Gate gate) {
+    if (gate.closed()) return;
+    const int64_t j = (int64_t)blockIdx.x * AP_T + threadIdx.x;
+    if (j >= nv) return;
+    double s = 0.0;
+    for (uint32_t e = ptr[j]; e < ptr[j + 1]; ++e) s = fma(val[e], vec[beam[e]], s);
+    out[j] = s;
+}
+
+// gF_k = <d_k, w> for every beam (0 for beams without a stored aperture).
+__global__ __launch_bounds__(CTRL) void k_ap_grad(const uint32_t* __restrict__ col_ptr,
+                                                  const uint32_t* __restrict__ col_vox,
+                                                  const double* __restrict__ col_val,
+                                                  const int32_t* __restrict__ beam_slot,
+                                                  const float* __restrict__ w, double* __restrict__ gF, Gate gate) {
+    __shared__ double sh[4];
+    if (gate.closed()) return;
+    const int k = blockIdx.x;
+    const int s = beam_slot[k];
+    if (s < 0) {
+        if (threadIdx.x == 0) gF[k] = 0.0;
+        return;
+    }
+    double acc = 0.0;
+    for (uint32_t e = col_ptr[s] + threadIdx.x; e < col_ptr[s + 1]; e += CTRL)
+        acc = fma(col_val[e], (double)w[col_vox[e]], acc);
+    acc = bsum(acc, sh);
+    if (threadIdx.x == 0) gF[k] = acc;
+}
+
+static int n_chunks_of(int64_t nv) { return (int)((nv + AP_CHUNK - 1) / AP_CHUNK); }
+
+template <typename T>
+static vmat_status ap_alloc(ApDose* a, T** p, size_t count) {
+    const size_t n = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc((void**)p, n) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(VMAT_ERR_ALLOC, "device allocation failed (aperture doses)");
+    }
+    a->bytes += (int64_t)n;
+    return VMAT_OK;
+}
+
+static void ap_free_entries(ApDose* a) {
+    auto F = [](void* p) { if (p) (void)hipFree(p); };
+    F(a->col_vox); F(a->col_val);
+    F(a->vx_beam[0]); F(a->vx_beam[1]); F(a->vx_val[0]); F(a->vx_val[1]);
+    a->col_vox = nullptr; a->col_val = nullptr;
+    a->vx_beam[0] = a->vx_beam[1] = nullptr;
+    a->vx_val[0] = a->vx_val[1] = nullptr;
+    a->bytes -= a->cap * (int64_t)(4 + 8 + 2 * (2 + 8));
+    a->cap = 0;
+}
+
+static vmat_status ap_alloc_entries(ApDose* a, int64_t cap) {
+    vmat_status rc = VMAT_OK;
+    auto A = [&](auto** p) { if (rc == VMAT_OK) rc = ap_alloc(a, p, (size_t)cap); };
+    A(&a->col_vox); A(&a->col_val);
+    A(&a->vx_beam[0]); A(&a->vx_beam[1]); A(&a->vx_val[0]); A(&a->vx_val[1]);
+    a->cap = cap;
+    return rc;
+}
+
+void free_apdose(vmat_ctx* h) {
+    ApDose* a = h->ap;
+    if (!a) return;
+    auto F = [](void* p) { if (p) (void)hipFree(p); };
+    ap_free_entries(a);
+    F(a->col_ptr); F(a->beam_slot); F(a->vx_ptr[0]); F(a->vx_ptr[1]); F(a->chunk); F(a->unit);
+    if (a->total_host) (void)hipHostFree(a->total_host);
+    h->bytes -= a->bytes;
+    delete a;
+    h->ap = nullptr;
+}
+
+// Empty store (allocated on first use, kept until the handle is destroyed).
+vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
+    if (!h->ap) {
+        ApDose* a = new ApDose();
+        h->ap = a;
+        const int64_t nch = n_chunks_of(h->nv);
+        vmat_status rc = VMAT_OK;
+        auto A = [&](auto** p, size_t n) { if (rc == VMAT_OK) rc = ap_alloc(a, p, n); };
+        A(&a->col_ptr, (size_t)h->N + 1);
+        A(&a->beam_slot, (size_t)h->N);
+        A(&a->vx_ptr[0], (size_t)h->nv + 1);
+        A(&a->vx_ptr[1], (size_t)h->nv + 1);
+        A(&a->chunk, (size_t)nch + 2);
+        A(&a->unit, (size_t)h->N + 1);  // unit[N] keeps the beam index being stored
+        if (rc == VMAT_OK) rc = ap_alloc_entries(a, std::max<int64_t>(1 << 20, 4 * h->nv));
+        if (rc == VMAT_OK && hipHostMalloc((void**)&a->total_host, sizeof(uint32_t)) != hipSuccess) {
+            a->total_host = nullptr;
+            rc = fail(VMAT_ERR_ALLOC, "pinned host allocation failed");
+        }
+        h->bytes += a->bytes;
+        if (rc != VMAT_OK) {
+            free_apdose(h);
+            return rc;
+        }
+    }
+    ApDose* a = h->ap;
+    a->top = 0;
+    a->n_slots = 0;
+    a->cur = 0;
+    VMAT_HIP(hipMemsetAsync(a->col_ptr, 0, sizeof(uint32_t) * (h->N + 1), st));
+    VMAT_HIP(hipMemsetAsync(a->beam_slot, 0xFF, sizeof(int32_t) * h->N, st));
+    VMAT_HIP(hipMemsetAsync(a->vx_ptr[0], 0, sizeof(uint32_t) * (h->nv + 1), st));
+    return VMAT_OK;
+}
+
+// Grows the entry arrays to hold `need` entries, keeping the stored ones.
+static vmat_status ap_grow(vmat_ctx* h, int64_t need, hipStream_t st) {
+    ApDose* a = h->ap;
+    ApDose fresh;
+    const int64_t cap = std::max<int64_t>(need, 2 * a->cap);
+    if (cap >= ((int64_t)1 << 32)) return fail(VMAT_ERR_UNSUPPORTED, "aperture doses exceed 2^32 entries");
+    vmat_status rc = ap_alloc_entries(&fresh, cap);
+    if (rc != VMAT_OK) {
+        ap_free_entries(&fresh);
+        return rc;
+    }
+    const size_t n = (size_t)a->top;
+    const int c = a->cur;
+    VMAT_HIP(hipMemcpyAsync(fresh.col_vox, a->col_vox, n * 4, hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(fresh.col_val, a->col_val, n * 8, hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(fresh.vx_beam[c], a->vx_beam[c], n * 2, hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(fresh.vx_val[c], a->vx_val[c], n * 8, hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipStreamSynchronize(st));
+    h->bytes -= a->bytes;
+    ap_free_entries(a);
+    a->col_vox = fresh.col_vox; a->col_val = fresh.col_val;
+    for (int i = 0; i < 2; ++i) {
+        a->vx_beam[i] = fresh.vx_beam[i];
+        a->vx_val[i] = fresh.vx_val[i];
+    }
+    a->cap = fresh.cap;
+    a->bytes += fresh.bytes;
+    h->bytes += a->bytes;
+    return VMAT_OK;
+}
+
+// Stores the dose of the aperture of one beam: beam_dev (device, e.g. the
+// pricing result) or, if null, beam_h.  One dose product plus compaction.
+vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ,
+                      const int32_t* beam_dev, int beam_h, hipStream_t st) {
+    ApDose* a = h->ap;
+    if (!a) return fail(VMAT_ERR_INVALID_ARG, "aperture doses not initialised");
+    if (a->n_slots >= h->N) return fail(VMAT_ERR_INVALID_ARG, "more apertures than beams");
+    int32_t* kb = reinterpret_cast<int32_t*>(a->unit + h->N);
+    k_ap_unit<<<1, AP_T, 0, st>>>(h->N, beam_dev, beam_h, a->unit, kb);
+    VMAT_LAUNCH_CHECK();
+    vmat_status rc = launch_fluence(h, a->unit, l, r, occ, h->bm.scale, h->x, Gate{}, st);
+    if (rc != VMAT_OK) return rc;
+    if ((rc = launch_fwd(h, h->x, h->dz, Gate{}, st)) != VMAT_OK) return rc;
+    const int nch = n_chunks_of(h->nv);
+    k_ap_count<<<nch, AP_T, 0, st>>>(h->nv, h->dz, a->chunk);
+    VMAT_LAUNCH_CHECK();
+    k_ap_scan<<<1, AP_T, 0, st>>>(nch, a->chunk);
+    VMAT_LAUNCH_CHECK();
+    VMAT_HIP(hipMemcpyAsync(a->total_host, a->chunk + nch, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    VMAT_HIP(hipStreamSynchronize(st));
+    const int64_t total = *a->total_host;
+    if (a->top + total > a->cap && (rc = ap_grow(h, a->top + total, st)) != VMAT_OK) return rc;
+    const int c = a->cur, n = 1 - c;
+    k_ap_emit<<<nch, AP_T, 0, st>>>(h->nv, nch, h->dz, a->chunk, kb, (uint32_t)a->top, a->col_vox, a->col_val,
+                                    a->vx_ptr[c], a->vx_beam[c], a->vx_val[c], a->vx_ptr[n], a->vx_beam[n],
+                                    a->vx_val[n]);
+    VMAT_LAUNCH_CHECK();
+    k_ap_slot<<<1, 1, 0, st>>>(a->n_slots, kb, a->chunk, nch, a->col_ptr, a->beam_slot);
+    VMAT_LAUNCH_CHECK();
+    a->top += total;
+    a->n_slots += 1;
+    a->cur = n;
+    return VMAT_OK;
+}
+
+vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate, hipStream_t st) {
+    const ApDose* a = h->ap;
+    const int c = a->cur;
+    k_ap_dose<<<(unsigned)((h->nv + AP_T - 1) / AP_T), AP_T, 0, st>>>(h->nv, a->vx_ptr[c], a->vx_beam[c],
+                                                                      a->vx_val[c], vec, out, gate);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
+vmat_status ap_grad(const vmat_ctx* h, const float* w, double* gF, Gate gate, hipStream_t st) {
+    const ApDose* a = h->ap;
+    k_ap_grad<<<h->N, CTRL, 0, st>>>(a->col_ptr, a->col_vox, a->col_val, a->beam_slot, w, gF, gate);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
+}  // namespace vmat

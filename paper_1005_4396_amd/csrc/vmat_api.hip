@@ -135,14 +135,54 @@ vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, co
     return VMAT_OK;
 }
 
+// The same iterations over the stored aperture doses: the dose of a direction
+// is sum_k d_k dir_k and the beam gradient <d_k, F'(z)>, so no product with D
+// runs inside the master.  The beamlet prices g are not maintained here.
+vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
+                          const vmat_master_opts& o, int fresh, hipStream_t st) {
+    Gate done;
+    done.p = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(h->ms) + offsetof(MasterState, done));
+    done.mask = 1u;
+    TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, fresh, st));
+    if (fresh) TRY(ap_dose(h, y, h->z, Gate{}, st));
+    TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
+    TRY(ap_grad(h, h->rz, h->mgF, Gate{}, st));
+    TRY(launch_master_grad(h, y, occ, fresh ? 1 : 2, st));
+    for (;;) {
+        TRY(launch_master_dir(h, y, occ, st));
+        TRY(ap_dose(h, h->md, h->dz, done, st));
+        for (int i = 0; i < 3; ++i) {
+            TRY(launch_ls_eval(h, st));
+            TRY(launch_ls_ctrl(h, st));
+        }
+        TRY(sync_state(h, st));
+        if (h->ms_host->done) break;
+        while (!h->ms_host->ls_done) {
+            for (int i = 0; i < 4; ++i) {
+                TRY(launch_ls_eval(h, st));
+                TRY(launch_ls_ctrl(h, st));
+            }
+            TRY(sync_state(h, st));
+        }
+        TRY(launch_master_step(h, y, st));
+        TRY(launch_update(h, st));
+        TRY(ap_grad(h, h->rz, h->mgF, done, st));
+        TRY(launch_master_grad(h, y, occ, 0, st));
+    }
+    return VMAT_OK;
+}
+
 // fresh == 0: the handle's z, F'(z) and g already belong to y (the column-
 // generation driver adds apertures at y = 0), so no product is needed to start.
 vmat_status run_master(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
-                       const vmat_master_opts& o, vmat_master_report* rep, hipStream_t st, int fresh = 1) {
+                       const vmat_master_opts& o, vmat_master_report* rep, hipStream_t st, int fresh = 1,
+                       int mode = 0) {
     // The gated pipeline (one state read per chunk of iterations) measured no
     // faster than one read per iteration on the prostate case; the separate-
     // kernel driver stays the default and the pipeline is selectable.
-    if (getenv("VMAT_PIPELINED_MASTER")) {
+    if (mode == 1) {
+        TRY(run_master_ap(h, l, r, occ, y, o, fresh, st));
+    } else if (getenv("VMAT_PIPELINED_MASTER")) {
         TRY(run_master_fused(h, l, r, occ, y, o, fresh, st));
     } else {
         TRY(run_master_plain(h, l, r, occ, y, o, fresh, st));
@@ -291,10 +331,12 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
     TRY(check_plan(y, l, r, occ));
     vmat_solve_opts so;
     so.max_cg_iter = 0;
-    so.reserved = 0;
+    so.master_mode = 0;
     so.master = defaults(nullptr);
     if (opts) so = *opts;
     TRY(check_opts(so.master));
+    if (so.master_mode != 0 && so.master_mode != 1) return fail(VMAT_ERR_INVALID_ARG, "master_mode must be 0 or 1");
+    const int mode = so.master_mode;
     const int N = h->N;
     std::vector<uint8_t> occ_h(N);
     VMAT_HIP(hipMemcpyAsync(occ_h.data(), occ, N, hipMemcpyDeviceToHost, st));
@@ -309,13 +351,35 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
     std::vector<int32_t> miters(iters, 0);
     double ref = so.master.kkt_ref;
     vmat_master_report mr{};
+    // D products of one master solve: in mode 0 each direction takes a
+    // forward and each step an adjoint; in mode 1 the master runs on the
+    // aperture doses and the column-generation loop adds the products
+    auto count = [&](const vmat_master_report& m) {
+        R.master_iters += m.iters;
+        R.n_ls_evals += m.n_ls_evals;
+        if (mode == 0) {
+            R.n_forward += m.n_forward;
+            R.n_adjoint += m.n_adjoint;
+        }
+    };
+    if (mode == 1) TRY(ap_reset(h, st));
     if (n_occ > 0) {
+        if (mode == 1) {
+            for (int k = 0; k < N; ++k)
+                if (occ_h[k]) {
+                    TRY(ap_append(h, l, r, occ, nullptr, k, st));
+                    R.n_forward += 1;
+                }
+        }
         vmat_master_opts mo = so.master;
-        vmat_status rc = run_master(h, l, r, occ, y, mo, &mr, st);
+        vmat_status rc = run_master(h, l, r, occ, y, mo, &mr, st, 1, mode);
         if (rc != VMAT_OK && rc != VMAT_ERR_NOT_CONVERGED) return rc;
         if (rc == VMAT_ERR_NOT_CONVERGED) R.not_converged++;
-        R.master_iters += mr.iters; R.n_forward += mr.n_forward; R.n_adjoint += mr.n_adjoint;
-        R.n_ls_evals += mr.n_ls_evals;
+        count(mr);
+        if (mode == 1 && iters > 0) {
+            TRY(launch_adj(h, h->rz, h->g, Gate{}, st));
+            R.n_adjoint += 1;
+        }
         if (!(ref > 0.0)) ref = mr.kkt_ref;
         costs[0] = mr.F + mr.gG;
     } else {
@@ -337,13 +401,21 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
             VMAT_HIP(hipStreamSynchronize(st));
             ref = ps[0] != 0.0 && std::isfinite(ps[0]) ? std::fabs(ps[0]) : 1.0;
         }
+        if (mode == 1) {
+            TRY(ap_append(h, l, r, occ, h->pbeam, -1, st));
+            R.n_forward += 1;
+        }
         vmat_master_opts mo = so.master;
         mo.kkt_ref = ref;
-        vmat_status rc = run_master(h, l, r, occ, y, mo, &mr, st, /*fresh=*/0);
+        vmat_status rc = run_master(h, l, r, occ, y, mo, &mr, st, /*fresh=*/0, mode);
         if (rc != VMAT_OK && rc != VMAT_ERR_NOT_CONVERGED) return rc;
         if (rc == VMAT_ERR_NOT_CONVERGED) R.not_converged++;
-        R.master_iters += mr.iters; R.n_forward += mr.n_forward; R.n_adjoint += mr.n_adjoint;
-        R.n_ls_evals += mr.n_ls_evals;
+        count(mr);
+        if (mode == 1 && t + 1 < iters) {
+            // beamlet prices for the next pricing
+            TRY(launch_adj(h, h->rz, h->g, Gate{}, st));
+            R.n_adjoint += 1;
+        }
         costs[t + 1] = mr.F + mr.gG;
         miters[t] = mr.iters;
         R.cg_iters = t + 1;

@@ -839,7 +839,7 @@ extern "C" vmat_status vmat_solve_batched(vmat_handle h, const vmat_solve_opts* 
         return fail(VMAT_ERR_INVALID_ARG, "the handle belongs to another device than the current one");
     vmat_solve_opts so;
     so.max_cg_iter = 0;
-    so.reserved = 0;
+    so.master_mode = 0;
     so.master.max_iter = 200;
     so.master.ls_max_steps = 50;
     so.master.tol_rel = 1e-5;

@@ -421,6 +421,7 @@ static vmat_status build_layouts(vmat_ctx* h, const vmat_problem* p, hipStream_t
         if (rc != VMAT_OK) {
             free_tiled(h);
     free_batch(h);
+    free_apdose(h);
             if (h->layout_req == 2 || rc != VMAT_ERR_UNSUPPORTED) return rc;
             set_error("");
         } else {

@@ -53,6 +53,10 @@ constexpr int TILE_VOXELS = 16384;
 constexpr int TILE_LIST = 8192;
 constexpr int TILE_THREADS = 512;
 constexpr int TILE_ROWS = 2048;   // rows per work item (their starts are staged in LDS)
+// Quads per lane and pass of the tiled forward.  Voxel rows are short (about
+// 27 quads on the prostate case), so wide lane groups with 2 quads each beat
+// narrower groups with 4 (measured: 16 x 2 about 9% faster than 8 x 4).
+constexpr int FWD_U = 2;
 
 struct Tiled {
     bool on = false;
@@ -146,6 +150,32 @@ struct BatchState {
 };
 }  // namespace vmat
 
+namespace vmat {
+// Aperture doses (master over the generated apertures): d_k = D^T 1_{A_k} for
+// every occupied beam, built once when the aperture is opened.  Two copies:
+// aperture-major (col_*: entries of slot s in [col_ptr[s], col_ptr[s+1]),
+// voxels ascending) for the per-aperture sums of F'(z), and voxel-major
+// (vx_*: ping-pong pair rebuilt by merging each new aperture, entries of a
+// voxel in opening order) for the dose of an intensity vector.
+struct ApDose {
+    int64_t cap = 0;               // entries each array can hold
+    int64_t top = 0;               // entries in use
+    int n_slots = 0;               // apertures stored
+    int cur = 0;                   // voxel-major copy in use (0/1)
+    uint32_t* col_vox = nullptr;   // [cap]
+    double* col_val = nullptr;     // [cap]
+    uint32_t* col_ptr = nullptr;   // [N+1]
+    int32_t* beam_slot = nullptr;  // [N], -1 for beams without a stored aperture
+    uint32_t* vx_ptr[2] = {nullptr, nullptr};  // [nv+1]
+    uint16_t* vx_beam[2] = {nullptr, nullptr}; // [cap]
+    double* vx_val[2] = {nullptr, nullptr};    // [cap]
+    uint32_t* chunk = nullptr;     // [n_chunks + 1] non-zero counts, then offsets; [n_chunks+1] = total
+    double* unit = nullptr;        // [N] unit intensity vector of the aperture being stored
+    uint32_t* total_host = nullptr;// pinned
+    int64_t bytes = 0;
+};
+}  // namespace vmat
+
 struct vmat_ctx {
     int32_t N, R, C;
     int64_t nb, nv, nnz;
@@ -175,6 +205,7 @@ struct vmat_ctx {
     int32_t tune_fwd[65] = {};     // tuned RHS tile width of the batched products, by B (0: default)
     int32_t tune_adj[65] = {};
     vmat::BatchState* bs = nullptr; // batched solves (vmat_reserve_batched)
+    vmat::ApDose* ap = nullptr;     // aperture doses (aperture-dose master)
     // master vectors [N]
     double *my = nullptr, *mgrad = nullptr, *mgrad_prev = nullptr, *md = nullptr, *md_prev = nullptr,
            *mgF = nullptr;

@@ -33,6 +33,18 @@ vmat_status run_master_fused(vmat_ctx* h, const int32_t* l, const int32_t* r, co
                              const vmat_master_opts& o, int fresh, hipStream_t st);
 void free_tiled(vmat_ctx* h);
 void free_batch(vmat_ctx* h);  // batched-solve state (vmat_batch.hip)
+
+// ---- aperture doses (vmat_apdose.hip)
+void free_apdose(vmat_ctx* h);
+// empty store, allocated on first use
+vmat_status ap_reset(vmat_ctx* h, hipStream_t st);
+// stores d_k = D^T 1_{A_k} for beam *beam_dev (device) or beam_h (beam_dev null)
+vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ,
+                      const int32_t* beam_dev, int beam_h, hipStream_t st);
+// out = sum_k vec_k d_k over the stored apertures
+vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate, hipStream_t st);
+// gF_k = <d_k, w> (0 for beams without a stored aperture)
+vmat_status ap_grad(const vmat_ctx* h, const float* w, double* gF, Gate gate, hipStream_t st);
 vmat_status scan_u32_dev(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t st);
 
 // F'(z) into rz (FP32, for the adjoint gather), optional FP32 copies of z and

@@ -196,7 +196,7 @@ __global__ __launch_bounds__(CTRL) void k_mdir(MasterPtrs m) {
 template <int FMT>
 static void launch_mfwd(const vmat_ctx* h, const MasterPtrs& m, hipStream_t st) {
     const Tiled& t = h->tl;
-#define MF(GG) k_mfwd<FMT, GG, 4><<<(unsigned)t.n_fwork, TILE_THREADS, 0, st>>>( \
+#define MF(GG) k_mfwd<FMT, GG, FWD_U><<<(unsigned)t.n_fwork, TILE_THREADS, 0, st>>>( \
         t.fwork, t.loff, t.list, t.lpack, h->vm.qptr, t.fcol, h->vm.val, h->bm.scale, m, h->dz)
     switch (t.fG) {
         case 2: MF(2); break;

@@ -32,7 +32,7 @@ namespace vmat {
 // lane group).  Longer rows finish in extra passes.
 
 // Forward: rows are voxels of the block; x values of the block's beamlets
-// are staged in LDS.
+// are staged in LDS (FWD_U quads per lane and pass).
 template <int FMT, int G, int U>
 __global__ __launch_bounds__(TILE_THREADS) void k_fwd_tiled(const int4* __restrict__ work,
                                                           const uint32_t* __restrict__ loff,
@@ -134,7 +134,7 @@ static vmat_status fwd_fmt(const vmat_ctx* h, const double* x, double* out, Gate
     const unsigned grid = (unsigned)t.n_fwork;
     if (grid == 0) return VMAT_OK;
 
-#define FWD(GG) k_fwd_tiled<FMT, GG, 4><<<grid, TILE_THREADS, 0, st>>>(t.fwork, t.loff, t.list, h->vm.qptr, \
+#define FWD(GG) k_fwd_tiled<FMT, GG, FWD_U><<<grid, TILE_THREADS, 0, st>>>(t.fwork, t.loff, t.list, h->vm.qptr, \
                                                                        t.fcol, h->vm.val, x, out, gate)
     switch (t.fG) {
         case 2: FWD(2); break;
@@ -607,7 +607,7 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     t.n_fwork = (int)fw.size();
     t.n_awork = (int)aw.size();
     // about one pass of U = 4 quads per lane for a mean row
-    t.fG = pow2_floor_clamp(nv > 0 ? (double)fq / (double)nv / 4.0 * 1.5 : 1.0, 2, 32);
+    t.fG = pow2_floor_clamp(nv > 0 ? (double)fq / (double)nv / FWD_U * 1.5 : 1.0, 2, 32);
     t.aG = pow2_floor_clamp(t.S > 0 ? (double)aqn / (double)t.S / 4.0 * 1.5 : 1.0, 2, 32);
     if (const char* e = getenv("VMAT_FWD_LANES")) t.fG = std::max(2, std::min(32, atoi(e)));
     if (const char* e = getenv("VMAT_ADJ_LANES")) t.aG = std::max(2, std::min(32, atoi(e)));

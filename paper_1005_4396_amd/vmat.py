@@ -61,7 +61,7 @@ class MasterReport(ctypes.Structure):
 
 
 class SolveOpts(ctypes.Structure):
-    _fields_ = [("max_cg_iter", ctypes.c_int32), ("reserved", ctypes.c_int32), ("master", MasterOpts)]
+    _fields_ = [("max_cg_iter", ctypes.c_int32), ("master_mode", ctypes.c_int32), ("master", MasterOpts)]
 
 
 class SolveReport(ctypes.Structure):

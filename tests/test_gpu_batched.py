@@ -8,7 +8,7 @@ import pytest
 
 import casegen
 import oracle as O
-from _cases import oracle_D, preset_case, small_case
+from _cases import compare_plan, oracle_D, preset_case, small_case
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -150,40 +150,6 @@ def _variant_weights(c, tab, b):
     return w[:, 0].copy(), w[:, 1].copy(), w[:, 2].copy()
 
 
-def _compare_plan(c, ref, tr, lk, rk, rep, eps_rel=1e-5, cost_rel=1e-6):
-    """Iteration by iteration the chosen beam and its leaf pairs must equal the
-    reference's; the first difference is excused only where the reference's
-    beam or row margin is at most eps_rel * |price|."""
-    R = c.n_rows
-    assert rep.cg_iters == len(ref.order)
-    matched = 0
-    for t in range(len(ref.order)):
-        k = ref.order[t]
-        same = (tr["beam"][t] == k and np.array_equal(lk[k * R:(k + 1) * R], ref.apertures[t][0])
-                and np.array_equal(rk[k * R:(k + 1) * R], ref.apertures[t][1]))
-        if not same:
-            eps = eps_rel * abs(ref.prices[t])
-            assert ref.margins[t] <= eps or ref.row_margins[t] <= eps, \
-                f"iteration {t}: beam {tr['beam'][t]} vs {k}, margins {ref.margins[t]}, {ref.row_margins[t]}"
-            break
-        assert abs(tr["price"][t] - ref.prices[t]) <= 1e-4 * abs(ref.prices[0])
-        matched += 1
-    if matched == len(ref.order):
-        assert rep.F + rep.gG == pytest.approx(ref.costs[-1], rel=cost_rel)
-        np.testing.assert_allclose(tr["cost"], ref.costs, rtol=cost_rel)
-    cost = tr["cost"]
-    assert np.all(cost[1:] <= cost[:-1] * (1 + 1e-12))
-    assert sorted(tr["beam"].tolist()) == list(range(c.n_beams))
-    L, Rr = lk.reshape(c.n_beams, R), rk.reshape(c.n_beams, R)
-    assert np.all(L <= Rr)
-    N = c.n_beams
-    pairs = [(k, k + 1) for k in range(N - 1)] + ([(N - 1, 0)] if c.circular else [])
-    for a, b in pairs:
-        assert np.all(np.abs(L[a] - L[b]) <= c.max_leaf_step)
-        assert np.all(np.abs(Rr[a] - Rr[b]) <= c.max_leaf_step)
-    return matched
-
-
 @pytest.mark.parametrize("name,B", [("small", 5), ("tiny36", 3)])
 def test_batched_solve_matches_oracle(name, B):
     c = dict(CASES)[name]()
@@ -201,7 +167,7 @@ def test_batched_solve_matches_oracle(name, B):
     for b in range(B):
         al, be, tt = _variant_weights(c, tab, b)
         ref = O.solve(D, al, be, tt, c.theta_deg, c.gamma, c.circular, c.n_rows, c.n_cols, c.max_leaf_step)
-        matched.append(_compare_plan(c, ref, trs[b], lg[b], rg[b], reps[b]))
+        matched.append(compare_plan(c, ref, trs[b], lg[b], rg[b], reps[b]))
     print(f"{name}: iterations matched per variant {matched} of {c.n_beams}")
     assert sum(m == c.n_beams for m in matched) >= B // 2
 
