@@ -131,41 +131,69 @@ __global__ void k_ap_slot(int slot, const int32_t* __restrict__ beam, const uint
     beam_slot[beam[0]] = slot;
 }
 
-// out_j = sum over voxel j's entries (opening order) of val * vec[beam].
-__global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, const uint32_t* __restrict__ ptr,
+// out_j = sum over voxel j's entries (opening order) of val * vec[beam]; the
+// per-beam vector is staged in LDS.
+__global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, int N, const uint32_t* __restrict__ ptr,
                                                   const uint16_t* __restrict__ beam,
                                                   const double* __restrict__ val, const double* __restrict__ vec,
                                                   double* __restrict__ out, Gate gate) {
+    extern __shared__ double vs[];  // [N]
     if (gate.closed()) return;
+    for (int k = threadIdx.x; k < N; k += AP_T) vs[k] = vec[k];
+    __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * AP_T + threadIdx.x;
     if (j >= nv) return;
     double s = 0.0;
-    for (uint32_t e = ptr[j]; e < ptr[j + 1]; ++e) s = fma(val[e], vec[beam[e]], s);
+    const uint32_t e1 = ptr[j + 1];
+    uint32_t e = ptr[j];
+    for (; e + 1 < e1; e += 2) {
+        const double v0 = val[e], v1 = val[e + 1];
+        const uint16_t b0 = beam[e], b1 = beam[e + 1];
+        s = fma(v0, vs[b0], s);
+        s = fma(v1, vs[b1], s);
+    }
+    if (e < e1) s = fma(val[e], vs[beam[e]], s);
     out[j] = s;
 }
 
-// gF_k = <d_k, w> for every beam (0 for beams without a stored aperture).
-__global__ __launch_bounds__(CTRL) void k_ap_grad(const uint32_t* __restrict__ col_ptr,
+// Beam gradients in two fixed-order stages: block (c, k) sums chunk c of
+// beam k's stored aperture dose against w; then one block per beam adds its
+// chunk sums in order.  gF_k = <d_k, w> (0 without a stored aperture).
+constexpr int AP_GCHUNK = 4096;
+
+__global__ __launch_bounds__(CTRL) void k_ap_grad(int max_chunks, const uint32_t* __restrict__ col_ptr,
                                                   const uint32_t* __restrict__ col_vox,
                                                   const double* __restrict__ col_val,
                                                   const int32_t* __restrict__ beam_slot,
-                                                  const float* __restrict__ w, double* __restrict__ gF, Gate gate) {
+                                                  const float* __restrict__ w, double* __restrict__ gpart,
+                                                  Gate gate) {
     __shared__ double sh[4];
     if (gate.closed()) return;
-    const int k = blockIdx.x;
+    const int c = blockIdx.x, k = blockIdx.y;
     const int s = beam_slot[k];
-    if (s < 0) {
-        if (threadIdx.x == 0) gF[k] = 0.0;
-        return;
-    }
     double acc = 0.0;
-    for (uint32_t e = col_ptr[s] + threadIdx.x; e < col_ptr[s + 1]; e += CTRL)
-        acc = fma(col_val[e], (double)w[col_vox[e]], acc);
+    if (s >= 0) {
+        const uint32_t e0 = col_ptr[s] + (uint32_t)c * AP_GCHUNK;
+        const uint32_t e1 = min(col_ptr[s + 1], e0 + AP_GCHUNK);
+        for (uint32_t e = e0 + threadIdx.x; e < e1; e += CTRL) acc = fma(col_val[e], (double)w[col_vox[e]], acc);
+    }
     acc = bsum(acc, sh);
-    if (threadIdx.x == 0) gF[k] = acc;
+    if (threadIdx.x == 0) gpart[(int64_t)k * max_chunks + c] = acc;
+}
+
+__global__ __launch_bounds__(64) void k_ap_grad_sum(int N, int n_chunks, int max_chunks,
+                                                    const double* __restrict__ gpart, double* __restrict__ gF,
+                                                    Gate gate) {
+    if (gate.closed()) return;
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= N) return;
+    double s = 0.0;
+    for (int c = 0; c < n_chunks; ++c) s += gpart[(int64_t)k * max_chunks + c];
+    gF[k] = s;
 }
 
 static int n_chunks_of(int64_t nv) { return (int)((nv + AP_CHUNK - 1) / AP_CHUNK); }
+static int max_gchunks(int64_t nv) { return (int)((nv + AP_GCHUNK - 1) / AP_GCHUNK); }
 
 template <typename T>
 static vmat_status ap_alloc(ApDose* a, T** p, size_t count) {
@@ -204,7 +232,7 @@ void free_apdose(vmat_ctx* h) {
     if (!a) return;
     auto F = [](void* p) { if (p) (void)hipFree(p); };
     ap_free_entries(a);
-    F(a->col_ptr); F(a->beam_slot); F(a->vx_ptr[0]); F(a->vx_ptr[1]); F(a->chunk); F(a->unit);
+    F(a->col_ptr); F(a->beam_slot); F(a->vx_ptr[0]); F(a->vx_ptr[1]); F(a->chunk); F(a->unit); F(a->gpart);
     if (a->total_host) (void)hipHostFree(a->total_host);
     h->bytes -= a->bytes;
     delete a;
@@ -225,6 +253,7 @@ vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
         A(&a->vx_ptr[1], (size_t)h->nv + 1);
         A(&a->chunk, (size_t)nch + 2);
         A(&a->unit, (size_t)h->N + 1);  // unit[N] keeps the beam index being stored
+        A(&a->gpart, (size_t)h->N * max_gchunks(h->nv));
         if (rc == VMAT_OK) rc = ap_alloc_entries(a, std::max<int64_t>(1 << 20, 4 * h->nv));
         if (rc == VMAT_OK && hipHostMalloc((void**)&a->total_host, sizeof(uint32_t)) != hipSuccess) {
             a->total_host = nullptr;
@@ -240,6 +269,7 @@ vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
     a->top = 0;
     a->n_slots = 0;
     a->cur = 0;
+    a->max_len = 0;
     VMAT_HIP(hipMemsetAsync(a->col_ptr, 0, sizeof(uint32_t) * (h->N + 1), st));
     VMAT_HIP(hipMemsetAsync(a->beam_slot, 0xFF, sizeof(int32_t) * h->N, st));
     VMAT_HIP(hipMemsetAsync(a->vx_ptr[0], 0, sizeof(uint32_t) * (h->nv + 1), st));
@@ -307,6 +337,7 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
     k_ap_slot<<<1, 1, 0, st>>>(a->n_slots, kb, a->chunk, nch, a->col_ptr, a->beam_slot);
     VMAT_LAUNCH_CHECK();
     a->top += total;
+    a->max_len = std::max(a->max_len, total);
     a->n_slots += 1;
     a->cur = n;
     return VMAT_OK;
@@ -315,7 +346,8 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
 vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate, hipStream_t st) {
     const ApDose* a = h->ap;
     const int c = a->cur;
-    k_ap_dose<<<(unsigned)((h->nv + AP_T - 1) / AP_T), AP_T, 0, st>>>(h->nv, a->vx_ptr[c], a->vx_beam[c],
+    k_ap_dose<<<(unsigned)((h->nv + AP_T - 1) / AP_T), AP_T, sizeof(double) * h->N, st>>>(
+        h->nv, h->N, a->vx_ptr[c], a->vx_beam[c],
                                                                       a->vx_val[c], vec, out, gate);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
@@ -323,7 +355,12 @@ vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate
 
 vmat_status ap_grad(const vmat_ctx* h, const float* w, double* gF, Gate gate, hipStream_t st) {
     const ApDose* a = h->ap;
-    k_ap_grad<<<h->N, CTRL, 0, st>>>(a->col_ptr, a->col_vox, a->col_val, a->beam_slot, w, gF, gate);
+    const int mc = max_gchunks(h->nv);
+    const int nch = std::max(1, (int)((a->max_len + AP_GCHUNK - 1) / AP_GCHUNK));
+    k_ap_grad<<<dim3((unsigned)nch, (unsigned)h->N), CTRL, 0, st>>>(mc, a->col_ptr, a->col_vox, a->col_val,
+                                                                    a->beam_slot, w, a->gpart, gate);
+    VMAT_LAUNCH_CHECK();
+    k_ap_grad_sum<<<(unsigned)((h->N + 63) / 64), 64, 0, st>>>(h->N, nch, mc, a->gpart, gF, gate);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }

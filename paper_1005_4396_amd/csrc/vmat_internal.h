@@ -171,6 +171,8 @@ struct ApDose {
     double* vx_val[2] = {nullptr, nullptr};    // [cap]
     uint32_t* chunk = nullptr;     // [n_chunks + 1] non-zero counts, then offsets; [n_chunks+1] = total
     double* unit = nullptr;        // [N] unit intensity vector of the aperture being stored
+    double* gpart = nullptr;       // [N][max_chunks] partial sums of the beam gradients
+    int64_t max_len = 0;           // entries of the longest stored aperture dose
     uint32_t* total_host = nullptr;// pinned
     int64_t bytes = 0;
 };

@@ -21,11 +21,11 @@ CASES = [("small", lambda: small_case(n_beams=8, n_rows=4, n_cols=6, grid=(12, 1
          ("tiny36", lambda: preset_case("tiny36"))]
 
 
-def _opts(mode, max_cg_iter=0):
+def _opts(mode, max_cg_iter=0, tol_rel=1e-5, max_iter=200):
     o = P.vmat.SolveOpts()
     o.max_cg_iter = max_cg_iter
     o.master_mode = mode
-    o.master = P.master_opts()
+    o.master = P.master_opts(max_iter=max_iter, tol_rel=tol_rel)
     return o
 
 
@@ -91,13 +91,15 @@ def test_aperture_master_resume_from_partial_plan():
 
 
 def test_aperture_master_prostate_matches_streaming_master():
+    """Both master modes with tight masters (KKT 1e-9 of the first price), so
+    that the pricing decisions do not hinge on where a master stops."""
     c = preset_case("prostate180")
     prob = P.Problem.from_case(c)
     try:
         res = {}
         for mode in (0, 1):
             l, r, occ, y = prob.empty_plan()
-            rep, tr = prob.solve(l, r, occ, y, _opts(mode))
+            rep, tr = prob.solve(l, r, occ, y, _opts(mode, tol_rel=1e-9, max_iter=5000))
             res[mode] = (rep, tr, l.cpu().numpy(), r.cpu().numpy(), y.cpu().numpy())
     finally:
         prob.close()
