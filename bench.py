@@ -5,6 +5,10 @@ A step is one full plan (column generation until every beam has an aperture:
 pricing, master solves with their dose products, adjoints and line searches)
 on the prostate-shaped case: 180 beams at 2 deg, 40x40 beamlets at 5 mm
 (288,000 beamlets), 128x128x64 voxels at 2.5 mm, about 1.09e8 non-zeros of D.
+The timed step uses the master that streams D in every iteration (one forward
+and one adjoint per master iteration), the configuration whose products the
+metric counts; the plan time of the master over stored aperture doses is
+reported beside it (`aperture_master`).
 
 value = algorithmic bytes of all D.x (forward) and D^T.r (adjoint) products
 run during the timed plans / wall time of those plans (GB/s).  The roofline
@@ -73,6 +77,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--variants", type=int, default=64)
     ap.add_argument("--no-batched-solve", action="store_true")
+    ap.add_argument("--no-aperture-master", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--products-only", action="store_true",
                     help="no plans and no side studies: only the per-kernel product timing (for profiling)")
     ap.add_argument("--sequential-variants", type=int, default=64,
@@ -189,6 +195,12 @@ def main():
     if not args.no_precision and args.d_store == "f32":
         out["precision"] = precision_study(case, prob, torch, P, args.kernel_reps, log)
 
+    if not args.no_aperture_master and args.steps:
+        out["aperture_master"] = aperture_master_study(prob, P, torch, args.steps, ms_per_step, reps[-1], log)
+
+    if not args.no_mixed and args.steps:
+        out["mixed_resolution"] = mixed_resolution_study(case, prob, P, torch, log)
+
     if not args.no_batched:
         out["batched"] = batched_study(case, prob, torch, args.variants, max(3, args.kernel_reps // 10), log)
     if not args.no_batched_solve:
@@ -241,6 +253,67 @@ def batched_study(case, prob, torch, B, reps, log):
            "spmv_equiv_GBs": round(seq_bytes / b_ms / 1e6, 1)}
     log(f"[bench] batched {B} variants: {b_ms:.2f} ms vs sequential {s_ms:.2f} ms ({s_ms / b_ms:.1f}x)")
     return res
+
+
+def aperture_master_study(prob, P, torch, steps, ms_stream, rep_stream, log):
+    """The same plans with the master over stored aperture doses (master_mode
+    1): D is streamed once per opened aperture (forward) and once per pricing
+    (adjoint); the master iterations work on the aperture doses."""
+    o = P.vmat.SolveOpts()
+    o.max_cg_iter = 0
+    o.master_mode = 1
+    o.master = P.master_opts()
+    l, r, occ, y = prob.empty_plan()
+    prob.solve(l, r, occ, y, o, want_trace=False)  # warm-up (allocates the aperture-dose store)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        l, r, occ, y = prob.empty_plan()
+        rep, _ = prob.solve(l, r, occ, y, o, want_trace=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    log(f"[bench] aperture-dose master: {ms:.1f} ms/plan (streaming master {ms_stream:.1f}), "
+        f"cost {rep.F + rep.gG:.9g} vs {rep_stream.F + rep_stream.gG:.9g}")
+    return {"plan_s": round(ms / 1e3, 4), "streaming_master_plan_s": round(ms_stream / 1e3, 4),
+            "speedup": round(ms_stream / ms, 2), "cost": rep.F + rep.gG,
+            "cost_rel_diff_vs_streaming": abs(rep.F + rep.gG - (rep_stream.F + rep_stream.gG)) /
+            (rep_stream.F + rep_stream.gG),
+            "master_iters": rep.master_iters, "d_products": [rep.n_forward, rep.n_adjoint]}
+
+
+def mixed_resolution_study(case, prob_full, P, torch, log):
+    """Unspecified tissue at twice the voxel size (Sec. 3): plan on the mixed
+    problem (aperture-dose master), then one full-resolution dose and cost of
+    that plan, against the plan optimised at full resolution."""
+    import casegen
+    t0 = time.perf_counter()
+    m, _ = casegen.mixed_resolution(case)
+    t_build = time.perf_counter() - t0
+    pm = P.Problem.from_case(m)
+    o = P.vmat.SolveOpts()
+    o.max_cg_iter = 0
+    o.master_mode = 1
+    o.master = P.master_opts()
+    l, r, occ, y = pm.empty_plan()
+    pm.solve(l, r, occ, y, o, want_trace=False)       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    l, r, occ, y = pm.empty_plan()
+    rep, _ = pm.solve(l, r, occ, y, o, want_trace=False)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    cm = prob_full.grad(y, l, r, occ, want=())["cost"].cpu().numpy()
+    t_eval = time.perf_counter() - t0
+    pm.close()
+    l2, r2, occ2, y2 = prob_full.empty_plan()
+    rep_f, _ = prob_full.solve(l2, r2, occ2, y2, o, want_trace=False)
+    full = rep_f.F + rep_f.gG
+    log(f"[bench] mixed resolution: nv {case.n_voxels} -> {m.n_voxels}, nnz {case.nnz} -> {m.nnz}, plan "
+        f"{t_plan * 1e3:.1f} ms, full-resolution cost {cm[0] + cm[1]:.6g} vs full plan {full:.6g}")
+    return {"voxels": m.n_voxels, "nnz": m.nnz, "plan_s": round(t_plan, 4), "full_eval_s": round(t_eval, 4),
+            "build_s": round(t_build, 2), "full_res_cost": float(cm[0] + cm[1]), "full_plan_cost": full,
+            "cost_ratio": float((cm[0] + cm[1]) / full)}
 
 
 def batched_solve_study(case, prob, torch, P, B, n_seq, log):

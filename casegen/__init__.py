@@ -236,3 +236,46 @@ def variant_table(case: Case, n_variants: int, seed: int = 0, spread=(0.5, 2.0),
     t_fac = np.where(base[:, 0] > 0, rng.uniform(*t_spread, (B, S)), 1.0)
     tab[:, :, 2] = base[:, 2] * t_fac
     return tab.astype(np.float32)
+
+
+def mixed_resolution(case: Case, factor: int = 2):
+    """The case with unspecified tissue at `factor` times the voxel size per
+    dimension: every factor^3 group of full-resolution voxels that holds only
+    unlabelled voxels becomes one coarse voxel, whose dose coefficients are the
+    mean of its members' (the dose at the coarse voxel as the average over its
+    volume); groups that touch a target or organ keep their voxels.  A coarse
+    voxel stands for the volume of its members, so its weights alpha and beta
+    are the members' times their number (F keeps approximating the sum over
+    the full-resolution voxels).  Mixed voxels are numbered in the order of
+    their first full-resolution member.
+
+    Returns (mixed case, owner), owner[j] = mixed voxel of full voxel j."""
+    import scipy.sparse as sp
+    nx, ny, nz = case.spec.grid
+    j = np.arange(case.n_voxels)
+    ix, iy, iz = j % nx, (j // nx) % ny, j // (nx * ny)
+    gx, gy, gz = (nx + factor - 1) // factor, (ny + factor - 1) // factor, (nz + factor - 1) // factor
+    group = (iz // factor) * (gy * gx) + (iy // factor) * gx + (ix // factor)
+    labelled = np.zeros(gx * gy * gz, dtype=bool)
+    np.logical_or.at(labelled, group, case.label != 0)
+    merged = ~labelled[group]
+    # key of a mixed voxel: its group for merged voxels, else its own index
+    key = np.where(merged, -(group + 1), j)
+    _, first_idx, inv = np.unique(key, return_index=True, return_inverse=True)
+    rank = np.empty(len(first_idx), dtype=np.int64)
+    rank[np.argsort(first_idx, kind="stable")] = np.arange(len(first_idx))
+    owner = rank[inv.ravel()]
+    n = len(first_idx)
+    count = np.bincount(owner, minlength=n).astype(np.float64)
+    P = sp.csr_matrix((1.0 / count[owner], (j, owner)), shape=(case.n_voxels, n))
+    D = sp.csr_matrix((case.val.astype(np.float64), case.col, case.row_ptr),
+                      shape=(case.n_beamlets, case.n_voxels))
+    Dm = (D @ P).tocsr()
+    Dm.sort_indices()
+    rep = np.full(n, case.n_voxels, dtype=np.int64)
+    np.minimum.at(rep, owner, j)        # first member of each mixed voxel
+    vol = count.astype(np.float32)
+    mixed = Case(case.spec, case.n_beams, case.n_rows, case.n_cols, n, case.theta_deg.copy(),
+                 Dm.indptr.astype(np.int64), Dm.indices.astype(np.int32), Dm.data.astype(np.float32),
+                 case.alpha[rep] * vol, case.beta[rep] * vol, case.T[rep].copy(), case.label[rep].copy())
+    return mixed, owner
