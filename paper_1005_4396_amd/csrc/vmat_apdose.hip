@@ -133,16 +133,18 @@ __global__ void k_ap_slot(int slot, const int32_t* __restrict__ beam, const uint
 
 // out_j = sum over voxel j's entries (opening order) of val * vec[beam]; the
 // per-beam vector is staged in LDS.
-__global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, int N, const uint32_t* __restrict__ ptr,
-                                                  const uint16_t* __restrict__ beam,
-                                                  const double* __restrict__ val, const double* __restrict__ vec,
-                                                  double* __restrict__ out, Gate gate) {
+__global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, int N, const ApView* __restrict__ view,
+                                                  const double* __restrict__ vec, double* __restrict__ out,
+                                                  Gate gate) {
     extern __shared__ double vs[];  // [N]
     if (gate.closed()) return;
     for (int k = threadIdx.x; k < N; k += AP_T) vs[k] = vec[k];
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * AP_T + threadIdx.x;
     if (j >= nv) return;
+    const uint32_t* __restrict__ ptr = view->vx_ptr;
+    const uint16_t* __restrict__ beam = view->vx_beam;
+    const double* __restrict__ val = view->vx_val;
     double s = 0.0;
     const uint32_t e1 = ptr[j + 1];
     uint32_t e = ptr[j];
@@ -156,44 +158,48 @@ __global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, int N, const uint3
     out[j] = s;
 }
 
-// Beam gradients in two fixed-order stages: block (c, k) sums chunk c of
-// beam k's stored aperture dose against w; then one block per beam adds its
-// chunk sums in order.  gF_k = <d_k, w> (0 without a stored aperture).
-constexpr int AP_GCHUNK = 4096;
+// gF_k = <d_k, w> (0 without a stored aperture): one block of AP_GT threads
+// per beam; thread t takes entries t, t + AP_GT, ... with four loads in flight,
+// then a fixed reduction tree.
+constexpr int AP_GT = 1024;
 
-__global__ __launch_bounds__(CTRL) void k_ap_grad(int max_chunks, const uint32_t* __restrict__ col_ptr,
-                                                  const uint32_t* __restrict__ col_vox,
-                                                  const double* __restrict__ col_val,
-                                                  const int32_t* __restrict__ beam_slot,
-                                                  const float* __restrict__ w, double* __restrict__ gpart,
-                                                  Gate gate) {
-    __shared__ double sh[4];
+__global__ __launch_bounds__(AP_GT) void k_ap_grad(const ApView* __restrict__ view, const float* __restrict__ w,
+                                                   double* __restrict__ gF, Gate gate) {
+    __shared__ double sh[AP_GT / 64];
     if (gate.closed()) return;
-    const int c = blockIdx.x, k = blockIdx.y;
-    const int s = beam_slot[k];
+    const int k = blockIdx.x;
+    const int s = view->beam_slot[k];
     double acc = 0.0;
     if (s >= 0) {
-        const uint32_t e0 = col_ptr[s] + (uint32_t)c * AP_GCHUNK;
-        const uint32_t e1 = min(col_ptr[s + 1], e0 + AP_GCHUNK);
-        for (uint32_t e = e0 + threadIdx.x; e < e1; e += CTRL) acc = fma(col_val[e], (double)w[col_vox[e]], acc);
+        const uint32_t* __restrict__ vox = view->col_vox;
+        const double* __restrict__ val = view->col_val;
+        const uint32_t e0 = view->col_ptr[s], e1 = view->col_ptr[s + 1];
+        uint32_t e = e0 + threadIdx.x;
+        for (; e + 3 * AP_GT < e1; e += 4 * AP_GT) {
+            const uint32_t j0 = vox[e], j1 = vox[e + AP_GT], j2 = vox[e + 2 * AP_GT], j3 = vox[e + 3 * AP_GT];
+            const double v0 = val[e], v1 = val[e + AP_GT], v2 = val[e + 2 * AP_GT], v3 = val[e + 3 * AP_GT];
+            const float w0 = w[j0], w1 = w[j1], w2 = w[j2], w3 = w[j3];
+            acc = fma(v0, (double)w0, acc);
+            acc = fma(v1, (double)w1, acc);
+            acc = fma(v2, (double)w2, acc);
+            acc = fma(v3, (double)w3, acc);
+        }
+        for (; e < e1; e += AP_GT) acc = fma(val[e], (double)w[vox[e]], acc);
     }
-    acc = bsum(acc, sh);
-    if (threadIdx.x == 0) gpart[(int64_t)k * max_chunks + c] = acc;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < AP_GT / 64; ++i) t += sh[i];
+        gF[k] = t;
+    }
 }
 
-__global__ __launch_bounds__(64) void k_ap_grad_sum(int N, int n_chunks, int max_chunks,
-                                                    const double* __restrict__ gpart, double* __restrict__ gF,
-                                                    Gate gate) {
-    if (gate.closed()) return;
-    const int k = blockIdx.x * 64 + threadIdx.x;
-    if (k >= N) return;
-    double s = 0.0;
-    for (int c = 0; c < n_chunks; ++c) s += gpart[(int64_t)k * max_chunks + c];
-    gF[k] = s;
-}
+__global__ void k_ap_view(ApView* view, ApView v) { *view = v; }
 
 static int n_chunks_of(int64_t nv) { return (int)((nv + AP_CHUNK - 1) / AP_CHUNK); }
-static int max_gchunks(int64_t nv) { return (int)((nv + AP_GCHUNK - 1) / AP_GCHUNK); }
+
 
 template <typename T>
 static vmat_status ap_alloc(ApDose* a, T** p, size_t count) {
@@ -232,11 +238,21 @@ void free_apdose(vmat_ctx* h) {
     if (!a) return;
     auto F = [](void* p) { if (p) (void)hipFree(p); };
     ap_free_entries(a);
-    F(a->col_ptr); F(a->beam_slot); F(a->vx_ptr[0]); F(a->vx_ptr[1]); F(a->chunk); F(a->unit); F(a->gpart);
+    F(a->col_ptr); F(a->beam_slot); F(a->vx_ptr[0]); F(a->vx_ptr[1]); F(a->chunk); F(a->unit); F(a->view);
     if (a->total_host) (void)hipHostFree(a->total_host);
     h->bytes -= a->bytes;
     delete a;
     h->ap = nullptr;
+}
+
+// Writes the current pointers to the device view.
+static vmat_status ap_publish(vmat_ctx* h, hipStream_t st) {
+    const ApDose* a = h->ap;
+    const int c = a->cur;
+    ApView v{a->vx_ptr[c], a->vx_beam[c], a->vx_val[c], a->col_ptr, a->col_vox, a->col_val, a->beam_slot};
+    k_ap_view<<<1, 1, 0, st>>>(a->view, v);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
 }
 
 // Empty store (allocated on first use, kept until the handle is destroyed).
@@ -253,7 +269,7 @@ vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
         A(&a->vx_ptr[1], (size_t)h->nv + 1);
         A(&a->chunk, (size_t)nch + 2);
         A(&a->unit, (size_t)h->N + 1);  // unit[N] keeps the beam index being stored
-        A(&a->gpart, (size_t)h->N * max_gchunks(h->nv));
+        A(&a->view, 1);
         if (rc == VMAT_OK) rc = ap_alloc_entries(a, std::max<int64_t>(1 << 20, 4 * h->nv));
         if (rc == VMAT_OK && hipHostMalloc((void**)&a->total_host, sizeof(uint32_t)) != hipSuccess) {
             a->total_host = nullptr;
@@ -269,11 +285,10 @@ vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
     a->top = 0;
     a->n_slots = 0;
     a->cur = 0;
-    a->max_len = 0;
     VMAT_HIP(hipMemsetAsync(a->col_ptr, 0, sizeof(uint32_t) * (h->N + 1), st));
     VMAT_HIP(hipMemsetAsync(a->beam_slot, 0xFF, sizeof(int32_t) * h->N, st));
     VMAT_HIP(hipMemsetAsync(a->vx_ptr[0], 0, sizeof(uint32_t) * (h->nv + 1), st));
-    return VMAT_OK;
+    return ap_publish(h, st);
 }
 
 // Grows the entry arrays to hold `need` entries, keeping the stored ones.
@@ -337,30 +352,20 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
     k_ap_slot<<<1, 1, 0, st>>>(a->n_slots, kb, a->chunk, nch, a->col_ptr, a->beam_slot);
     VMAT_LAUNCH_CHECK();
     a->top += total;
-    a->max_len = std::max(a->max_len, total);
     a->n_slots += 1;
     a->cur = n;
-    return VMAT_OK;
+    return ap_publish(h, st);
 }
 
 vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate, hipStream_t st) {
-    const ApDose* a = h->ap;
-    const int c = a->cur;
-    k_ap_dose<<<(unsigned)((h->nv + AP_T - 1) / AP_T), AP_T, sizeof(double) * h->N, st>>>(
-        h->nv, h->N, a->vx_ptr[c], a->vx_beam[c],
-                                                                      a->vx_val[c], vec, out, gate);
+    k_ap_dose<<<(unsigned)((h->nv + AP_T - 1) / AP_T), AP_T, sizeof(double) * h->N, st>>>(h->nv, h->N, h->ap->view,
+                                                                                       vec, out, gate);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
 
 vmat_status ap_grad(const vmat_ctx* h, const float* w, double* gF, Gate gate, hipStream_t st) {
-    const ApDose* a = h->ap;
-    const int mc = max_gchunks(h->nv);
-    const int nch = std::max(1, (int)((a->max_len + AP_GCHUNK - 1) / AP_GCHUNK));
-    k_ap_grad<<<dim3((unsigned)nch, (unsigned)h->N), CTRL, 0, st>>>(mc, a->col_ptr, a->col_vox, a->col_val,
-                                                                    a->beam_slot, w, a->gpart, gate);
-    VMAT_LAUNCH_CHECK();
-    k_ap_grad_sum<<<(unsigned)((h->N + 63) / 64), 64, 0, st>>>(h->N, nch, mc, a->gpart, gF, gate);
+    k_ap_grad<<<h->N, AP_GT, 0, st>>>(h->ap->view, w, gF, gate);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }

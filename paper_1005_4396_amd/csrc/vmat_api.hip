@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -98,25 +99,85 @@ vmat_status sync_state(vmat_ctx* h, hipStream_t st) {
 // the done / line-search flags once per iteration.
 // Master solve with separate kernels and one state read per iteration (used
 // with the plain layout).
+// gamma enters the captured control kernels by value: part of the graph key
+uint64_t gamma_bits(const vmat_ctx* h) {
+    uint64_t b;
+    std::memcpy(&b, &h->gamma, sizeof(b));
+    return b;
+}
+
+// Enqueues `body` (one master iteration's kernels) on st: replayed from a
+// graph captured once per plan-pointer key, or launched directly when
+// VMAT_NO_GRAPH is set.  The graph holds kernels only.
+template <class F>
+vmat_status run_iteration(vmat_ctx* h, int kind, const uint64_t key[6], F body, hipStream_t st) {
+    if (getenv("VMAT_NO_GRAPH")) return body(st);
+    hipGraphExec_t& exec = h->iter_graph[kind];
+    bool same = exec != nullptr;
+    for (int i = 0; i < 6; ++i) same = same && h->iter_key[kind][i] == key[i];
+    if (!same) {
+        if (exec) {
+            (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
+        }
+        if (!h->cap_stream) VMAT_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        VMAT_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        vmat_status rc = body(h->cap_stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+        if (rc != VMAT_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(VMAT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            exec = nullptr;
+            return fail(VMAT_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        }
+        for (int i = 0; i < 6; ++i) h->iter_key[kind][i] = key[i];
+    }
+    VMAT_HIP(hipGraphLaunch(exec, st));
+    return VMAT_OK;
+}
+
+// Master solve with separate kernels and one state read per iteration.  The
+// kernels between two reads (step, dose update, adjoint, gradient, next
+// direction, its dose product, three line-search evaluations) form one graph.
 vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
                              const vmat_master_opts& o, int fresh, hipStream_t st) {
     Gate done;  // open while the solve is not done
     done.p = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(h->ms) + offsetof(MasterState, done));
     done.mask = 1u;
+    auto dir_and_search = [&](hipStream_t s) -> vmat_status {
+        TRY(launch_master_dir(h, y, occ, s));
+        TRY(launch_fluence(h, h->md, l, r, occ, h->bm.scale, h->x, done, s));
+        TRY(launch_fwd(h, h->x, h->dz, done, s));
+        for (int i = 0; i < 3; ++i) {
+            TRY(launch_ls_eval(h, s));
+            TRY(launch_ls_ctrl(h, s));
+        }
+        return VMAT_OK;
+    };
+    auto iteration = [&](hipStream_t s) -> vmat_status {
+        TRY(launch_master_step(h, y, s));
+        TRY(launch_update(h, s));
+        TRY(launch_adj(h, h->rz, h->g, done, s));
+        TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, done, s));
+        TRY(launch_master_grad(h, y, occ, 0, s));
+        return dir_and_search(s);
+    };
+    const uint64_t key[6] = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)l, (uint64_t)(uintptr_t)r,
+                             (uint64_t)(uintptr_t)occ, gamma_bits(h), 0};
     TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, fresh, st));
     if (fresh) TRY(forward_from_plan(h, y, l, r, occ, h->z, Gate{}, st));
     TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
     if (fresh) TRY(launch_adj(h, h->rz, h->g, Gate{}, st));
     TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, Gate{}, st));
     TRY(launch_master_grad(h, y, occ, fresh ? 1 : 2, st));
+    TRY(dir_and_search(st));
     for (;;) {
-        TRY(launch_master_dir(h, y, occ, st));
-        TRY(launch_fluence(h, h->md, l, r, occ, h->bm.scale, h->x, done, st));
-        TRY(launch_fwd(h, h->x, h->dz, done, st));
-        for (int i = 0; i < 3; ++i) {
-            TRY(launch_ls_eval(h, st));
-            TRY(launch_ls_ctrl(h, st));
-        }
         TRY(sync_state(h, st));
         if (h->ms_host->done) break;
         while (!h->ms_host->ls_done) {
@@ -126,11 +187,7 @@ vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, co
             }
             TRY(sync_state(h, st));
         }
-        TRY(launch_master_step(h, y, st));
-        TRY(launch_update(h, st));
-        TRY(launch_adj(h, h->rz, h->g, done, st));
-        TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, done, st));
-        TRY(launch_master_grad(h, y, occ, 0, st));
+        TRY(run_iteration(h, 0, key, iteration, st));
     }
     return VMAT_OK;
 }
@@ -143,18 +200,31 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
     Gate done;
     done.p = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(h->ms) + offsetof(MasterState, done));
     done.mask = 1u;
+    auto dir_and_search = [&](hipStream_t s) -> vmat_status {
+        TRY(launch_master_dir(h, y, occ, s));
+        TRY(ap_dose(h, h->md, h->dz, done, s));
+        for (int i = 0; i < 3; ++i) {
+            TRY(launch_ls_eval(h, s));
+            TRY(launch_ls_ctrl(h, s));
+        }
+        return VMAT_OK;
+    };
+    // the kernels reach the stored doses through the store's device view, so
+    // the captured iteration stays valid as apertures are added
+    auto iteration = [&](hipStream_t s) -> vmat_status {
+        TRY(launch_master_step(h, y, s));
+        TRY(launch_update(h, s));
+        TRY(ap_grad(h, h->rz, h->mgF, done, s));
+        TRY(launch_master_grad(h, y, occ, 0, s));
+        return dir_and_search(s);
+    };
     TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, fresh, st));
     if (fresh) TRY(ap_dose(h, y, h->z, Gate{}, st));
     TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
     TRY(ap_grad(h, h->rz, h->mgF, Gate{}, st));
     TRY(launch_master_grad(h, y, occ, fresh ? 1 : 2, st));
+    TRY(dir_and_search(st));
     for (;;) {
-        TRY(launch_master_dir(h, y, occ, st));
-        TRY(ap_dose(h, h->md, h->dz, done, st));
-        for (int i = 0; i < 3; ++i) {
-            TRY(launch_ls_eval(h, st));
-            TRY(launch_ls_ctrl(h, st));
-        }
         TRY(sync_state(h, st));
         if (h->ms_host->done) break;
         while (!h->ms_host->ls_done) {
@@ -164,10 +234,9 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
             }
             TRY(sync_state(h, st));
         }
-        TRY(launch_master_step(h, y, st));
-        TRY(launch_update(h, st));
-        TRY(ap_grad(h, h->rz, h->mgF, done, st));
-        TRY(launch_master_grad(h, y, occ, 0, st));
+        const uint64_t key[6] = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)occ,
+                                 (uint64_t)(uintptr_t)h->ap->view, gamma_bits(h), 0, 0};
+        TRY(run_iteration(h, 1, key, iteration, st));
     }
     return VMAT_OK;
 }

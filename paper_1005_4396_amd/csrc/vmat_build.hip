@@ -422,6 +422,9 @@ static vmat_status build_layouts(vmat_ctx* h, const vmat_problem* p, hipStream_t
             free_tiled(h);
     free_batch(h);
     free_apdose(h);
+    for (auto& g : h->iter_graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
             if (h->layout_req == 2 || rc != VMAT_ERR_UNSUPPORTED) return rc;
             set_error("");
         } else {

@@ -151,6 +151,18 @@ struct BatchState {
 }  // namespace vmat
 
 namespace vmat {
+// Device-side view of the aperture-dose store, read by the master's kernels,
+// so that a captured master iteration stays valid while the store grows.
+struct ApView {
+    const uint32_t* vx_ptr;
+    const uint16_t* vx_beam;
+    const double* vx_val;
+    const uint32_t* col_ptr;
+    const uint32_t* col_vox;
+    const double* col_val;
+    const int32_t* beam_slot;
+};
+
 // Aperture doses (master over the generated apertures): d_k = D^T 1_{A_k} for
 // every occupied beam, built once when the aperture is opened.  Two copies:
 // aperture-major (col_*: entries of slot s in [col_ptr[s], col_ptr[s+1]),
@@ -171,8 +183,7 @@ struct ApDose {
     double* vx_val[2] = {nullptr, nullptr};    // [cap]
     uint32_t* chunk = nullptr;     // [n_chunks + 1] non-zero counts, then offsets; [n_chunks+1] = total
     double* unit = nullptr;        // [N] unit intensity vector of the aperture being stored
-    double* gpart = nullptr;       // [N][max_chunks] partial sums of the beam gradients
-    int64_t max_len = 0;           // entries of the longest stored aperture dose
+    ApView* view = nullptr;        // device copy of the current pointers
     uint32_t* total_host = nullptr;// pinned
     int64_t bytes = 0;
 };
@@ -208,6 +219,11 @@ struct vmat_ctx {
     int32_t tune_adj[65] = {};
     vmat::BatchState* bs = nullptr; // batched solves (vmat_reserve_batched)
     vmat::ApDose* ap = nullptr;     // aperture doses (aperture-dose master)
+    // one master iteration's kernels as a replayable graph, per master kind;
+    // captured on cap_stream, keyed by the plan pointers its kernels take
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t iter_graph[2] = {nullptr, nullptr};
+    uint64_t iter_key[2][6] = {};
     // master vectors [N]
     double *my = nullptr, *mgrad = nullptr, *mgrad_prev = nullptr, *md = nullptr, *md_prev = nullptr,
            *mgF = nullptr;

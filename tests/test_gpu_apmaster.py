@@ -122,3 +122,33 @@ def test_aperture_master_prostate_matches_streaming_master():
         assert r1.F + r1.gG == pytest.approx(r0.F + r0.gG, rel=1e-6)
         np.testing.assert_allclose(t1["cost"], t0["cost"], rtol=1e-6)
     assert np.all(t1["cost"][1:] <= t1["cost"][:-1] * (1 + 1e-12))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("name", ["small", "prostate"])
+def test_graph_replay_matches_direct_launches(mode, name, monkeypatch):
+    """Master iterations replayed from a captured graph give the same bits as
+    the same kernels launched one by one (every replay is compared through the
+    per-iteration costs, the plan and the final intensities)."""
+    c = dict(CASES)["small"]() if name == "small" else preset_case("prostate180")
+    iters = 0 if name == "small" else 12
+    prob = P.Problem.from_case(c)
+    try:
+        out = []
+        for no_graph in (False, True, False):
+            if no_graph:
+                monkeypatch.setenv("VMAT_NO_GRAPH", "1")
+            else:
+                monkeypatch.delenv("VMAT_NO_GRAPH", raising=False)
+            l, r, occ, y = prob.empty_plan()
+            rep, tr = prob.solve(l, r, occ, y, _opts(mode, max_cg_iter=iters))
+            out.append((tr, y.cpu().numpy(), l.cpu().numpy(), r.cpu().numpy(), rep.master_iters))
+    finally:
+        prob.close()
+    for tr, y, l, r, mi in out[1:]:
+        assert mi == out[0][4]
+        np.testing.assert_array_equal(tr["cost"], out[0][0]["cost"])
+        np.testing.assert_array_equal(tr["beam"], out[0][0]["beam"])
+        np.testing.assert_array_equal(y, out[0][1])
+        np.testing.assert_array_equal(l, out[0][2])
+        np.testing.assert_array_equal(r, out[0][3])
