@@ -57,6 +57,8 @@ constexpr int TILE_ROWS = 2048;   // rows per work item (their starts are staged
 // 27 quads on the prostate case), so wide lane groups with 2 quads each beat
 // narrower groups with 4 (measured: 16 x 2 about 9% faster than 8 x 4).
 constexpr int FWD_U = 2;
+// Quads in flight per lane in the sliced forward.
+constexpr int SELL_U = 4;
 
 struct Tiled {
     bool on = false;
@@ -68,9 +70,19 @@ struct Tiled {
     uint32_t* lpack = nullptr;    // [S] (beam << 20) | (leaf row << 8) | column of each slot
     // forward
     uint16_t* fcol = nullptr;     // [4 * vm.n_quads]
-    int4* fwork = nullptr;        // (block, first row, end row, 0)
+    int4* fwork = nullptr;        // (block, first row, end row, first slice)
     int n_fwork = 0;
     int fG = 8;
+    // forward, sliced: each work item's rows sorted by length (longest first)
+    // and cut into slices of 64 rows; a slice stores its quads column-major
+    // (quad k of its 64 rows contiguous), padded to its longest row
+    int64_t n_slices = 0;
+    int64_t s_quads = 0;          // stored quads including padding
+    uint32_t* s_off = nullptr;    // [n_slices] first quad of each slice
+    uint32_t* s_len = nullptr;    // [n_slices] quads per row of each slice
+    uint32_t* s_row = nullptr;    // [64 * n_slices] voxel of each slice row, ~0 for padding
+    uint16_t* s_col = nullptr;    // [4 * s_quads] local column indices
+    void* s_val = nullptr;        // [4 * s_quads] values (storage format)
     // adjoint
     uint32_t* aqptr = nullptr;    // [S+1] slot row starts in quads
     uint16_t* acol = nullptr;     // [4 * a_quads]

@@ -75,6 +75,114 @@ __global__ __launch_bounds__(TILE_THREADS) void k_fwd_tiled(const int4* __restri
     rows_of_item<FMT, G, U, double>(rq, nrows, wk.y, val, reinterpret_cast<const u16x4*>(col16), xs, epi);
 }
 
+// Forward over the sliced layout: after the block's x values are staged in
+// LDS, wave w takes the item's slices w, w + 8, ...; lane i owns row i of the
+// slice and walks its quads in order (quad k of the 64 rows is one contiguous
+// 1-KB load for FP32 values), U quads in flight per lane, no cross-lane sums.
+template <int FMT, int U>
+__global__ __launch_bounds__(TILE_THREADS) void k_fwd_sell(const int4* __restrict__ work,
+                                                         const uint32_t* __restrict__ loff,
+                                                         const uint32_t* __restrict__ list,
+                                                         const uint32_t* __restrict__ s_off,
+                                                         const uint32_t* __restrict__ s_len,
+                                                         const uint32_t* __restrict__ s_row,
+                                                         const uint16_t* __restrict__ s_col,
+                                                         const void* __restrict__ s_val,
+                                                         const double* __restrict__ x, double* __restrict__ out,
+                                                         Gate gate) {
+    __shared__ double xs[TILE_LIST];
+    if (gate.closed()) return;
+    const int4 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    const uint32_t l0 = loff[wk.x], ln = loff[wk.x + 1] - l0;
+    {
+        constexpr int K = TILE_LIST / TILE_THREADS;
+        uint32_t id[K];
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t u = threadIdx.x + k * TILE_THREADS;
+            id[k] = u < ln ? list[l0 + u] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t u = threadIdx.x + k * TILE_THREADS;
+            v[k] = u < ln ? x[id[k]] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t u = threadIdx.x + k * TILE_THREADS;
+            if (u < ln) xs[u] = v[k];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nsl = (wk.z - wk.y + 63) / 64;
+    const u16x4* __restrict__ c4 = reinterpret_cast<const u16x4*>(s_col);
+    for (int j = wave; j < nsl; j += TILE_THREADS / 64) {
+        const int64_t sl = (int64_t)wk.w + j;
+        const uint32_t base = s_off[sl] + lane, len = s_len[sl];
+        const uint32_t row = s_row[sl * 64 + lane];
+        double acc = 0.0;
+        uint32_t k = 0;
+        for (; k + U <= len; k += U) {
+            float4 v[U];
+            u16x4 c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                v[u] = Quad<FMT>::load(s_val, base + (k + u) * 64);
+                c[u] = __builtin_nontemporal_load(c4 + base + (k + u) * 64);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                acc = fma((double)v[u].x, xs[c[u].x], acc);
+                acc = fma((double)v[u].y, xs[c[u].y], acc);
+                acc = fma((double)v[u].z, xs[c[u].z], acc);
+                acc = fma((double)v[u].w, xs[c[u].w], acc);
+            }
+        }
+        for (; k < len; ++k) {
+            const float4 v = Quad<FMT>::load(s_val, base + k * 64);
+            const u16x4 c = __builtin_nontemporal_load(c4 + base + k * 64);
+            acc = fma((double)v.x, xs[c.x], acc);
+            acc = fma((double)v.y, xs[c.y], acc);
+            acc = fma((double)v.z, xs[c.z], acc);
+            acc = fma((double)v.w, xs[c.w], acc);
+        }
+        if (row != 0xFFFFFFFFu) out[row] = acc;
+    }
+}
+
+// Builder of the sliced layout: one wave per slice copies each row's quads
+// (values and local columns) to their column-major places, zero quads with
+// column 0 after a row's end.  QT: the bytes of one quad of values.
+template <typename QT>
+__global__ __launch_bounds__(64) void k_sell_fill(const uint32_t* __restrict__ s_off,
+                                                  const uint32_t* __restrict__ s_len,
+                                                  const uint32_t* __restrict__ s_row,
+                                                  const uint32_t* __restrict__ qptr,
+                                                  const uint16_t* __restrict__ fcol, const QT* __restrict__ val,
+                                                  uint16_t* __restrict__ scol, QT* __restrict__ sval) {
+    const int64_t sl = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t row = s_row[sl * 64 + lane];
+    const uint32_t q0 = row != 0xFFFFFFFFu ? qptr[row] : 0u;
+    const uint32_t rl = row != 0xFFFFFFFFu ? qptr[row + 1] - q0 : 0u;
+    const uint32_t base = s_off[sl] + lane, len = s_len[sl];
+    const u16x4* __restrict__ c4 = reinterpret_cast<const u16x4*>(fcol);
+    u16x4* __restrict__ o4 = reinterpret_cast<u16x4*>(scol);
+    for (uint32_t k = 0; k < len; ++k) {
+        const uint32_t d = base + k * 64;
+        if (k < rl) {
+            sval[d] = val[q0 + k];
+            o4[d] = c4[q0 + k];
+        } else {
+            sval[d] = QT{};
+            o4[d] = u16x4{0, 0, 0, 0};
+        }
+    }
+}
+
 // Adjoint: rows are the block's slots; the block's slice of w is staged in
 // LDS; each slot row's sum goes to part[slot].
 template <int FMT, int G, int U>
@@ -133,6 +241,20 @@ static vmat_status fwd_fmt(const vmat_ctx* h, const double* x, double* out, Gate
     const Tiled& t = h->tl;
     const unsigned grid = (unsigned)t.n_fwork;
     if (grid == 0) return VMAT_OK;
+    static const bool csr = getenv("VMAT_FWD_CSR") != nullptr;
+    if (t.s_val && !csr) {
+        static const int su = getenv("VMAT_SELL_U") ? atoi(getenv("VMAT_SELL_U")) : SELL_U;
+#define SELL(UU) k_fwd_sell<FMT, UU><<<grid, TILE_THREADS, 0, st>>>(t.fwork, t.loff, t.list, t.s_off, t.s_len, \
+                                                                  t.s_row, t.s_col, t.s_val, x, out, gate)
+        switch (su) {
+            case 2: SELL(2); break;
+            case 8: SELL(8); break;
+            default: SELL(4); break;
+        }
+#undef SELL
+        VMAT_LAUNCH_CHECK();
+        return VMAT_OK;
+    }
 
 #define FWD(GG) k_fwd_tiled<FMT, GG, FWD_U><<<grid, TILE_THREADS, 0, st>>>(t.fwork, t.loff, t.list, h->vm.qptr, \
                                                                        t.fcol, h->vm.val, x, out, gate)
@@ -600,12 +722,65 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     const int64_t mrows = TILE_ROWS;
     std::vector<int4> fw = make_work(rb, vq, nblk, std::max<int64_t>(256, fq / target_items), mrows);
     std::vector<int4> aw = make_work(sb, aq, nblk, std::max<int64_t>(256, aqn / target_items), mrows);
+    // sliced forward layout: rows of each item sorted by length, 64 per slice
+    std::vector<uint32_t> s_off, s_len, s_row;
+    {
+        uint64_t off = 0;
+        std::vector<std::pair<uint32_t, uint32_t>> rows;
+        for (int4& it : fw) {
+            it.w = (int)s_len.size();
+            if (it.x < 0) continue;
+            rows.clear();
+            for (int r = it.y; r < it.z; ++r) rows.push_back({vq[r + 1] - vq[r], (uint32_t)r});
+            std::stable_sort(rows.begin(), rows.end(),
+                             [](const std::pair<uint32_t, uint32_t>& a, const std::pair<uint32_t, uint32_t>& b) {
+                                 return a.first > b.first;
+                             });
+            for (size_t j = 0; j < rows.size(); j += 64) {
+                s_off.push_back((uint32_t)off);
+                s_len.push_back(rows[j].first);
+                off += (uint64_t)rows[j].first * 64;
+                for (size_t i = j; i < j + 64; ++i) s_row.push_back(i < rows.size() ? rows[i].second : 0xFFFFFFFFu);
+            }
+        }
+        if (off >= ((uint64_t)1 << 32)) return fail(VMAT_ERR_UNSUPPORTED, "sliced forward exceeds 2^32 quads");
+        t.n_slices = (int64_t)s_len.size();
+        t.s_quads = (int64_t)off;
+    }
     A(t.fwork, fw.size() * sizeof(int4));
     A(t.awork, aw.size() * sizeof(int4));
     VMAT_HIP(hipMemcpyAsync(t.fwork, fw.data(), fw.size() * sizeof(int4), hipMemcpyHostToDevice, st));
     VMAT_HIP(hipMemcpyAsync(t.awork, aw.data(), aw.size() * sizeof(int4), hipMemcpyHostToDevice, st));
     t.n_fwork = (int)fw.size();
     t.n_awork = (int)aw.size();
+    {
+        const int vb = h->d_store == VMAT_F32 ? 4 : (h->d_store == VMAT_FP8_E4M3 ? 1 : 2);
+        const size_t ns = (size_t)std::max<int64_t>(t.n_slices, 1);
+        A(t.s_off, ns * 4);
+        A(t.s_len, ns * 4);
+        A(t.s_row, ns * 64 * 4);
+        A(t.s_col, (size_t)std::max<int64_t>(t.s_quads, 1) * 8);
+        A(t.s_val, (size_t)std::max<int64_t>(t.s_quads, 1) * 4 * vb);
+        if (t.n_slices > 0) {
+            VMAT_HIP(hipMemcpyAsync(t.s_off, s_off.data(), s_off.size() * 4, hipMemcpyHostToDevice, st));
+            VMAT_HIP(hipMemcpyAsync(t.s_len, s_len.data(), s_len.size() * 4, hipMemcpyHostToDevice, st));
+            VMAT_HIP(hipMemcpyAsync(t.s_row, s_row.data(), s_row.size() * 4, hipMemcpyHostToDevice, st));
+            const unsigned g = (unsigned)t.n_slices;
+            if (vb == 4)
+                k_sell_fill<f32x4><<<g, 64, 0, st>>>(t.s_off, t.s_len, t.s_row, h->vm.qptr, t.fcol,
+                                                    reinterpret_cast<const f32x4*>(h->vm.val), t.s_col,
+                                                    reinterpret_cast<f32x4*>(t.s_val));
+            else if (vb == 2)
+                k_sell_fill<u32x2><<<g, 64, 0, st>>>(t.s_off, t.s_len, t.s_row, h->vm.qptr, t.fcol,
+                                                    reinterpret_cast<const u32x2*>(h->vm.val), t.s_col,
+                                                    reinterpret_cast<u32x2*>(t.s_val));
+            else
+                k_sell_fill<uint32_t><<<g, 64, 0, st>>>(t.s_off, t.s_len, t.s_row, h->vm.qptr, t.fcol,
+                                                       reinterpret_cast<const uint32_t*>(h->vm.val), t.s_col,
+                                                       reinterpret_cast<uint32_t*>(t.s_val));
+            VMAT_HIP(hipGetLastError());
+        }
+    }
     // about one pass of U = 4 quads per lane for a mean row
     t.fG = pow2_floor_clamp(nv > 0 ? (double)fq / (double)nv / FWD_U * 1.5 : 1.0, 2, 32);
     t.aG = pow2_floor_clamp(t.S > 0 ? (double)aqn / (double)t.S / 4.0 * 1.5 : 1.0, 2, 32);
@@ -620,7 +795,7 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
 void free_tiled(vmat_ctx* h) {
     Tiled& t = h->tl;
     void* ps[] = {t.bounds, t.loff, t.list, t.lpack, t.fcol, t.fwork, t.aqptr, t.acol, t.aval, t.awork, t.part, t.red_ptr,
-                  t.red_slot};
+                  t.red_slot, t.s_off, t.s_len, t.s_row, t.s_col, t.s_val};
     for (void* q : ps)
         if (q) (void)hipFree(q);
     t = Tiled();
