@@ -83,6 +83,11 @@ struct Tiled {
     uint32_t* s_row = nullptr;    // [64 * n_slices] voxel of each slice row, ~0 for padding
     uint16_t* s_col = nullptr;    // [4 * s_quads] local column indices
     void* s_val = nullptr;        // [4 * s_quads] values (storage format)
+    // adjoint, sliced the same way over the slot rows of each work item
+    int64_t an_slices = 0, as_quads = 0;
+    uint32_t *as_off = nullptr, *as_len = nullptr, *as_row = nullptr;
+    uint16_t* as_col = nullptr;
+    void* as_val = nullptr;
     // adjoint
     uint32_t* aqptr = nullptr;    // [S+1] slot row starts in quads
     uint16_t* acol = nullptr;     // [4 * a_quads]

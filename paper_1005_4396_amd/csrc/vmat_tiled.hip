@@ -75,6 +75,50 @@ __global__ __launch_bounds__(TILE_THREADS) void k_fwd_tiled(const int4* __restri
     rows_of_item<FMT, G, U, double>(rq, nrows, wk.y, val, reinterpret_cast<const u16x4*>(col16), xs, epi);
 }
 
+// The slices of one work item: wave w takes slices w, w + 8, ...; lane i owns
+// row i of the slice and walks its quads in order, U quads in flight.
+template <int FMT, int U, typename ST>
+__device__ __forceinline__ void sell_rows(const int4 wk, const uint32_t* __restrict__ s_off,
+                                          const uint32_t* __restrict__ s_len, const uint32_t* __restrict__ s_row,
+                                          const uint16_t* __restrict__ s_col, const void* __restrict__ s_val,
+                                          const ST* __restrict__ xs, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nsl = (wk.z - wk.y + 63) / 64;
+    const u16x4* __restrict__ c4 = reinterpret_cast<const u16x4*>(s_col);
+    for (int j = wave; j < nsl; j += TILE_THREADS / 64) {
+        const int64_t sl = (int64_t)wk.w + j;
+        const uint32_t base = s_off[sl] + lane, len = s_len[sl];
+        const uint32_t row = s_row[sl * 64 + lane];
+        double acc = 0.0;
+        uint32_t k = 0;
+        for (; k + U <= len; k += U) {
+            float4 v[U];
+            u16x4 c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                v[u] = Quad<FMT>::load(s_val, base + (k + u) * 64);
+                c[u] = __builtin_nontemporal_load(c4 + base + (k + u) * 64);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                acc = fma((double)v[u].x, (double)xs[c[u].x], acc);
+                acc = fma((double)v[u].y, (double)xs[c[u].y], acc);
+                acc = fma((double)v[u].z, (double)xs[c[u].z], acc);
+                acc = fma((double)v[u].w, (double)xs[c[u].w], acc);
+            }
+        }
+        for (; k < len; ++k) {
+            const float4 v = Quad<FMT>::load(s_val, base + k * 64);
+            const u16x4 c = __builtin_nontemporal_load(c4 + base + k * 64);
+            acc = fma((double)v.x, (double)xs[c.x], acc);
+            acc = fma((double)v.y, (double)xs[c.y], acc);
+            acc = fma((double)v.z, (double)xs[c.z], acc);
+            acc = fma((double)v.w, (double)xs[c.w], acc);
+        }
+        if (row != 0xFFFFFFFFu) out[row] = acc;
+    }
+}
+
 // Forward over the sliced layout: after the block's x values are staged in
 // LDS, wave w takes the item's slices w, w + 8, ...; lane i owns row i of the
 // slice and walks its quads in order (quad k of the 64 rows is one contiguous
@@ -116,41 +160,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_fwd_sell(const int4* __restric
         }
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nsl = (wk.z - wk.y + 63) / 64;
-    const u16x4* __restrict__ c4 = reinterpret_cast<const u16x4*>(s_col);
-    for (int j = wave; j < nsl; j += TILE_THREADS / 64) {
-        const int64_t sl = (int64_t)wk.w + j;
-        const uint32_t base = s_off[sl] + lane, len = s_len[sl];
-        const uint32_t row = s_row[sl * 64 + lane];
-        double acc = 0.0;
-        uint32_t k = 0;
-        for (; k + U <= len; k += U) {
-            float4 v[U];
-            u16x4 c[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                v[u] = Quad<FMT>::load(s_val, base + (k + u) * 64);
-                c[u] = __builtin_nontemporal_load(c4 + base + (k + u) * 64);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                acc = fma((double)v[u].x, xs[c[u].x], acc);
-                acc = fma((double)v[u].y, xs[c[u].y], acc);
-                acc = fma((double)v[u].z, xs[c[u].z], acc);
-                acc = fma((double)v[u].w, xs[c[u].w], acc);
-            }
-        }
-        for (; k < len; ++k) {
-            const float4 v = Quad<FMT>::load(s_val, base + k * 64);
-            const u16x4 c = __builtin_nontemporal_load(c4 + base + k * 64);
-            acc = fma((double)v.x, xs[c.x], acc);
-            acc = fma((double)v.y, xs[c.y], acc);
-            acc = fma((double)v.z, xs[c.z], acc);
-            acc = fma((double)v.w, xs[c.w], acc);
-        }
-        if (row != 0xFFFFFFFFu) out[row] = acc;
-    }
+    sell_rows<FMT, U>(wk, s_off, s_len, s_row, s_col, s_val, xs, out);
 }
 
 // Builder of the sliced layout: one wave per slice copies each row's quads
@@ -220,6 +230,41 @@ __global__ __launch_bounds__(TILE_THREADS) void k_adj_tiled(const int4* __restri
     rows_of_item<FMT, G, U, float>(rq, nrows, wk.y, val, reinterpret_cast<const u16x4*>(col16), ws, epi);
 }
 
+// Adjoint over the sliced layout: rows are the block's slots, the block's
+// slice of w is staged in LDS; each slot row's sum goes to part[slot].
+template <int FMT, int U>
+__global__ __launch_bounds__(TILE_THREADS) void k_adj_sell(const int4* __restrict__ work,
+                                                         const int32_t* __restrict__ bounds,
+                                                         const uint32_t* __restrict__ s_off,
+                                                         const uint32_t* __restrict__ s_len,
+                                                         const uint32_t* __restrict__ s_row,
+                                                         const uint16_t* __restrict__ s_col,
+                                                         const void* __restrict__ s_val,
+                                                         const float* __restrict__ w, double* __restrict__ part,
+                                                         Gate gate) {
+    __shared__ float ws[TILE_VOXELS];
+    if (gate.closed()) return;
+    const int4 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    const int32_t j0 = bounds[wk.x], jn = bounds[wk.x + 1] - j0;
+    {
+        constexpr int K = TILE_VOXELS / TILE_THREADS;
+        float v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int u = threadIdx.x + k * TILE_THREADS;
+            v[k] = u < jn ? w[j0 + u] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int u = threadIdx.x + k * TILE_THREADS;
+            if (u < jn) ws[u] = v[k];
+        }
+    }
+    __syncthreads();
+    sell_rows<FMT, U>(wk, s_off, s_len, s_row, s_col, s_val, ws, part);
+}
+
 // g_i = scale_i * sum of beamlet i's slot sums, in block order.
 __global__ __launch_bounds__(256) void k_adj_reduce(int64_t nb, const uint32_t* __restrict__ red_ptr,
                                                     const uint32_t* __restrict__ red_slot,
@@ -274,7 +319,13 @@ template <int FMT>
 static vmat_status adj_fmt(const vmat_ctx* h, const float* w, double* g, Gate gate, hipStream_t st,
                            bool slots_only = false) {
     const Tiled& t = h->tl;
-    if (t.n_awork > 0) {
+    static const bool acsr = getenv("VMAT_ADJ_CSR") != nullptr;
+    if (t.n_awork > 0 && t.as_val && !acsr) {
+        k_adj_sell<FMT, SELL_U><<<(unsigned)t.n_awork, TILE_THREADS, 0, st>>>(t.awork, t.bounds, t.as_off, t.as_len,
+                                                                           t.as_row, t.as_col, t.as_val, w, t.part,
+                                                                           gate);
+        VMAT_LAUNCH_CHECK();
+    } else if (t.n_awork > 0) {
 #define ADJ(GG) k_adj_tiled<FMT, GG, 4><<<(unsigned)t.n_awork, TILE_THREADS, 0, st>>>(t.awork, t.bounds, \
                                                                                       t.aqptr, t.acol, t.aval, w, \
                                                                                       t.part, gate)
@@ -552,6 +603,34 @@ std::vector<int4> make_work(const std::vector<int64_t>& row_begin_of_block, cons
     return out;
 }
 
+// Sliced layout of the rows of every work item (item.w becomes its first
+// slice): rows sorted by quad count, longest first (ties by row), 64 per
+// slice, each slice padded to its first row's length.  False if the quads
+// exceed 32-bit offsets.
+bool make_slices(std::vector<int4>& items, const std::vector<uint32_t>& qp, std::vector<uint32_t>& s_off,
+                 std::vector<uint32_t>& s_len, std::vector<uint32_t>& s_row, uint64_t& quads) {
+    uint64_t off = 0;
+    std::vector<std::pair<uint32_t, uint32_t>> rows;
+    for (int4& it : items) {
+        it.w = (int)s_len.size();
+        if (it.x < 0) continue;
+        rows.clear();
+        for (int r = it.y; r < it.z; ++r) rows.push_back({qp[r + 1] - qp[r], (uint32_t)r});
+        std::stable_sort(rows.begin(), rows.end(),
+                         [](const std::pair<uint32_t, uint32_t>& a, const std::pair<uint32_t, uint32_t>& b) {
+                             return a.first > b.first;
+                         });
+        for (size_t j = 0; j < rows.size(); j += 64) {
+            s_off.push_back((uint32_t)off);
+            s_len.push_back(rows[j].first);
+            off += (uint64_t)rows[j].first * 64;
+            for (size_t i = j; i < j + 64; ++i) s_row.push_back(i < rows.size() ? rows[i].second : 0xFFFFFFFFu);
+        }
+    }
+    quads = off;
+    return off < ((uint64_t)1 << 32);
+}
+
 }  // namespace
 
 // Builds h->tl from the voxel-major and beamlet-major copies and the caller's
@@ -722,30 +801,16 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     const int64_t mrows = TILE_ROWS;
     std::vector<int4> fw = make_work(rb, vq, nblk, std::max<int64_t>(256, fq / target_items), mrows);
     std::vector<int4> aw = make_work(sb, aq, nblk, std::max<int64_t>(256, aqn / target_items), mrows);
-    // sliced forward layout: rows of each item sorted by length, 64 per slice
-    std::vector<uint32_t> s_off, s_len, s_row;
+    // sliced layouts: rows of each work item sorted by length, 64 per slice
+    std::vector<uint32_t> s_off, s_len, s_row, as_off, as_len, as_row;
     {
-        uint64_t off = 0;
-        std::vector<std::pair<uint32_t, uint32_t>> rows;
-        for (int4& it : fw) {
-            it.w = (int)s_len.size();
-            if (it.x < 0) continue;
-            rows.clear();
-            for (int r = it.y; r < it.z; ++r) rows.push_back({vq[r + 1] - vq[r], (uint32_t)r});
-            std::stable_sort(rows.begin(), rows.end(),
-                             [](const std::pair<uint32_t, uint32_t>& a, const std::pair<uint32_t, uint32_t>& b) {
-                                 return a.first > b.first;
-                             });
-            for (size_t j = 0; j < rows.size(); j += 64) {
-                s_off.push_back((uint32_t)off);
-                s_len.push_back(rows[j].first);
-                off += (uint64_t)rows[j].first * 64;
-                for (size_t i = j; i < j + 64; ++i) s_row.push_back(i < rows.size() ? rows[i].second : 0xFFFFFFFFu);
-            }
-        }
-        if (off >= ((uint64_t)1 << 32)) return fail(VMAT_ERR_UNSUPPORTED, "sliced forward exceeds 2^32 quads");
+        uint64_t fq_s = 0, aq_s = 0;
+        if (!make_slices(fw, vq, s_off, s_len, s_row, fq_s) || !make_slices(aw, aq, as_off, as_len, as_row, aq_s))
+            return fail(VMAT_ERR_UNSUPPORTED, "sliced layout exceeds 2^32 quads");
         t.n_slices = (int64_t)s_len.size();
-        t.s_quads = (int64_t)off;
+        t.s_quads = (int64_t)fq_s;
+        t.an_slices = (int64_t)as_len.size();
+        t.as_quads = (int64_t)aq_s;
     }
     A(t.fwork, fw.size() * sizeof(int4));
     A(t.awork, aw.size() * sizeof(int4));
@@ -755,31 +820,42 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     t.n_awork = (int)aw.size();
     {
         const int vb = h->d_store == VMAT_F32 ? 4 : (h->d_store == VMAT_FP8_E4M3 ? 1 : 2);
-        const size_t ns = (size_t)std::max<int64_t>(t.n_slices, 1);
-        A(t.s_off, ns * 4);
-        A(t.s_len, ns * 4);
-        A(t.s_row, ns * 64 * 4);
-        A(t.s_col, (size_t)std::max<int64_t>(t.s_quads, 1) * 8);
-        A(t.s_val, (size_t)std::max<int64_t>(t.s_quads, 1) * 4 * vb);
-        if (t.n_slices > 0) {
-            VMAT_HIP(hipMemcpyAsync(t.s_off, s_off.data(), s_off.size() * 4, hipMemcpyHostToDevice, st));
-            VMAT_HIP(hipMemcpyAsync(t.s_len, s_len.data(), s_len.size() * 4, hipMemcpyHostToDevice, st));
-            VMAT_HIP(hipMemcpyAsync(t.s_row, s_row.data(), s_row.size() * 4, hipMemcpyHostToDevice, st));
-            const unsigned g = (unsigned)t.n_slices;
+        auto sliced = [&](int64_t n_sl, int64_t quads, const std::vector<uint32_t>& so,
+                          const std::vector<uint32_t>& sn, const std::vector<uint32_t>& sr, const uint32_t* qp,
+                          const uint16_t* col, const void* val, uint32_t*& d_off, uint32_t*& d_len,
+                          uint32_t*& d_row, uint16_t*& d_col, void*& d_val) -> vmat_status {
+            const size_t ns = (size_t)std::max<int64_t>(n_sl, 1);
+            A(d_off, ns * 4);
+            A(d_len, ns * 4);
+            A(d_row, ns * 64 * 4);
+            A(d_col, (size_t)std::max<int64_t>(quads, 1) * 8);
+            A(d_val, (size_t)std::max<int64_t>(quads, 1) * 4 * vb);
+            if (n_sl == 0) return VMAT_OK;
+            VMAT_HIP(hipMemcpyAsync(d_off, so.data(), so.size() * 4, hipMemcpyHostToDevice, st));
+            VMAT_HIP(hipMemcpyAsync(d_len, sn.data(), sn.size() * 4, hipMemcpyHostToDevice, st));
+            VMAT_HIP(hipMemcpyAsync(d_row, sr.data(), sr.size() * 4, hipMemcpyHostToDevice, st));
+            const unsigned g = (unsigned)n_sl;
             if (vb == 4)
-                k_sell_fill<f32x4><<<g, 64, 0, st>>>(t.s_off, t.s_len, t.s_row, h->vm.qptr, t.fcol,
-                                                    reinterpret_cast<const f32x4*>(h->vm.val), t.s_col,
-                                                    reinterpret_cast<f32x4*>(t.s_val));
+                k_sell_fill<f32x4><<<g, 64, 0, st>>>(d_off, d_len, d_row, qp, col,
+                                                    reinterpret_cast<const f32x4*>(val), d_col,
+                                                    reinterpret_cast<f32x4*>(d_val));
             else if (vb == 2)
-                k_sell_fill<u32x2><<<g, 64, 0, st>>>(t.s_off, t.s_len, t.s_row, h->vm.qptr, t.fcol,
-                                                    reinterpret_cast<const u32x2*>(h->vm.val), t.s_col,
-                                                    reinterpret_cast<u32x2*>(t.s_val));
+                k_sell_fill<u32x2><<<g, 64, 0, st>>>(d_off, d_len, d_row, qp, col,
+                                                    reinterpret_cast<const u32x2*>(val), d_col,
+                                                    reinterpret_cast<u32x2*>(d_val));
             else
-                k_sell_fill<uint32_t><<<g, 64, 0, st>>>(t.s_off, t.s_len, t.s_row, h->vm.qptr, t.fcol,
-                                                       reinterpret_cast<const uint32_t*>(h->vm.val), t.s_col,
-                                                       reinterpret_cast<uint32_t*>(t.s_val));
+                k_sell_fill<uint32_t><<<g, 64, 0, st>>>(d_off, d_len, d_row, qp, col,
+                                                       reinterpret_cast<const uint32_t*>(val), d_col,
+                                                       reinterpret_cast<uint32_t*>(d_val));
             VMAT_HIP(hipGetLastError());
-        }
+            return VMAT_OK;
+        };
+        vmat_status rs = sliced(t.n_slices, t.s_quads, s_off, s_len, s_row, h->vm.qptr, t.fcol, h->vm.val, t.s_off,
+                                t.s_len, t.s_row, t.s_col, t.s_val);
+        if (rs != VMAT_OK) return rs;
+        rs = sliced(t.an_slices, t.as_quads, as_off, as_len, as_row, t.aqptr, t.acol, t.aval, t.as_off, t.as_len,
+                    t.as_row, t.as_col, t.as_val);
+        if (rs != VMAT_OK) return rs;
     }
     // about one pass of U = 4 quads per lane for a mean row
     t.fG = pow2_floor_clamp(nv > 0 ? (double)fq / (double)nv / FWD_U * 1.5 : 1.0, 2, 32);
@@ -795,7 +871,8 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
 void free_tiled(vmat_ctx* h) {
     Tiled& t = h->tl;
     void* ps[] = {t.bounds, t.loff, t.list, t.lpack, t.fcol, t.fwork, t.aqptr, t.acol, t.aval, t.awork, t.part, t.red_ptr,
-                  t.red_slot, t.s_off, t.s_len, t.s_row, t.s_col, t.s_val};
+                  t.red_slot, t.s_off, t.s_len, t.s_row, t.s_col, t.s_val, t.as_off, t.as_len, t.as_row, t.as_col,
+                  t.as_val};
     for (void* q : ps)
         if (q) (void)hipFree(q);
     t = Tiled();
