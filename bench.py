@@ -32,6 +32,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.0, calibrated on a
+# 512 MiB copy) + WRITE_SIZE, for the product kernels as they stand; see
+# profiles/fwd_adj_sell_prostate180_hbm_counters.md.  Used only when the
+# layout matches the one measured (same workload, storage and byte counts).
+MEASURED_TRAFFIC = {
+    ("prostate180", "f32", 676890628, 676191240): {
+        "forward": (343236.75 * 2 + 8397.84375) * 1024,
+        "adjoint": (352312.25 * 2 + 3621.40625 + 3748.3125 * 2 + 2250.0) * 1024,
+    },
+}
 METRIC = "D·x + Dᵀr HBM GB/s vs peak; plan s; bf16/fp8-D vs fp32 at stated dose error"
 
 
@@ -154,6 +165,9 @@ def main():
     dom_gbs, dom_bytes = (fwd_gbs, fwd_b) if dom == "forward" else (adj_gbs, adj_b)
     log(f"[bench] forward {fwd_ms:.4f} ms ({fwd_gbs:.0f} GB/s), adjoint {adj_ms:.4f} ms ({adj_gbs:.0f} GB/s)")
 
+    meas = MEASURED_TRAFFIC.get((args.workload, args.d_store, fwd_b, adj_b))
+    traffic = round(meas[dom]) if meas else None
+
     # device copy ceiling (context)
     big = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
     big2 = torch.empty_like(big)
@@ -183,7 +197,7 @@ def main():
                  "n_forward": reps[-1].n_forward, "n_adjoint": reps[-1].n_adjoint,
                  "n_ls_evals": reps[-1].n_ls_evals, "cost": reps[-1].F + reps[-1].gG} if reps else None,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(dom_gbs, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(dom_gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(dom_gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": dom_bytes},
         "products": {"forward_ms": round(fwd_ms, 5), "forward_GBs": round(fwd_gbs, 1), "forward_bytes": fwd_b,
                      "adjoint_ms": round(adj_ms, 5), "adjoint_GBs": round(adj_gbs, 1), "adjoint_bytes": adj_b,
