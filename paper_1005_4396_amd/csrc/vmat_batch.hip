@@ -382,7 +382,9 @@ __device__ __forceinline__ void variant_sums(VarTables& S_, int B, double a, dou
     S_.sh[t] = a;
     S_.sh2[t] = b2;
     __syncthreads();
-    if (t < B) {
+    // variants that took no part keep their partial sums (they still belong
+    // to their current dose)
+    if (t < B && S_.on[t]) {
         double s = 0.0, s2 = 0.0;
         for (int u = t; u < per * B; u += B) {
             s += S_.sh[u];
@@ -502,10 +504,13 @@ __device__ __forceinline__ double reduce_row(const double* part, int n, double* 
     return bsum(s, sh);
 }
 
+// vmask (nullable): only the variants that start a master solve now.
 __global__ __launch_bounds__(CTRL) void k_bmaster_begin(int N, double* __restrict__ y, const uint8_t* __restrict__ occ,
                                                         MasterState* ms, int max_iter, int ls_max, double tol,
-                                                        double kkt_ref, const double* __restrict__ kref) {
+                                                        double kkt_ref, const double* __restrict__ kref,
+                                                        const uint8_t* __restrict__ vmask) {
     const int b = blockIdx.x;
+    if (vmask && !vmask[b]) return;
     for (int k = threadIdx.x; k < N; k += CTRL)
         if (!occ[(int64_t)b * N + k]) y[(int64_t)b * N + k] = 0.0;
     if (threadIdx.x == 0) {
@@ -520,8 +525,9 @@ __global__ __launch_bounds__(CTRL) void k_bmaster_begin(int N, double* __restric
 }
 
 __global__ __launch_bounds__(CTRL) void k_bmaster_grad(MasterPtrs m0, const double* __restrict__ pf, int n_part,
-                                                       int first) {
+                                                       int first, const uint8_t* __restrict__ vmask) {
     __shared__ double sh[4];
+    if (vmask && !vmask[blockIdx.x]) return;
     const MasterPtrs m = variant_ptrs(m0, blockIdx.x);
     if (!first && m.ms->done) return;
     const double F = reduce_row(pf + (int64_t)blockIdx.x * n_part, n_part, sh);
@@ -680,8 +686,10 @@ void free_batch(vmat_ctx* h) {
     F(b->grad); F(b->grad_prev); F(b->d); F(b->d_prev); F(b->gF); F(b->W); F(b->W_prev);
     F(b->ms); F(b->pp); F(b->qq); F(b->pf);
     F(b->rowS); F(b->rowm); F(b->rowl); F(b->rowr); F(b->bprice); F(b->pbeam); F(b->pscore); F(b->kref);
-    F(b->cost); F(b->tr.beam); F(b->tr.price); F(b->tr.margin); F(b->tr.row_margin);
+    F(b->cost); F(b->tr.beam); F(b->tr.price); F(b->tr.margin); F(b->tr.row_margin); F(b->vmask); F(b->viter);
     if (b->ms_host) (void)hipHostFree(b->ms_host);
+    if (b->mask_host) (void)hipHostFree(b->mask_host);
+    if (b->iter_host) (void)hipHostFree(b->iter_host);
     h->bytes -= b->bytes;
     delete b;
     h->bs = nullptr;
@@ -731,58 +739,49 @@ struct BatchArgs {
     const float* table;
 };
 
-// One master solve for every variant in lockstep, from the carried dose and
-// prices (column generation opens apertures at y = 0).
-vmat_status batch_master(vmat_ctx* h, const BatchArgs& a, const int32_t* l, const int32_t* r, const uint8_t* occ,
-                         double* y, const vmat_master_opts& o, int64_t* n_spmm, hipStream_t st) {
+// One lockstep master iteration over the variants whose master is running
+// (the others keep their state: zero direction, no step).  Returns with the
+// states read back; *any_active = false when no master was running.
+vmat_status batch_iteration(vmat_ctx* h, const BatchArgs& a, const int32_t* l, const int32_t* r,
+                            const uint8_t* occ, double* y, int64_t* n_spmm, bool* any_active, hipStream_t st) {
     BatchState& bs = *h->bs;
     const int B = a.B, np = h->n_part;
     const MasterPtrs m = batch_ptrs(h, y, occ, l, r);
     const int64_t nbB = h->nb * B;
-    k_bmaster_begin<<<B, CTRL, 0, st>>>(h->N, y, occ, bs.ms, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref,
-                                        bs.kref);
+    k_bmaster_dir<<<B, CTRL, 0, st>>>(m);
     VMAT_LAUNCH_CHECK();
-    k_pen_batched<<<np, 256, 0, st>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.RZ, bs.pf);
+    BTRY(sync_batch(h, B, st));
+    bool active = false;
+    for (int b = 0; b < B; ++b) active = active || !bs.ms_host[b].done;
+    *any_active = active;
+    if (!active) return VMAT_OK;
+    k_bfluence<<<(unsigned)((nbB + BT - 1) / BT), BT, 0, st>>>(h->nb, h->N, h->R, h->C, B, bs.d, l, r, occ, bs.ms,
+                                                               bs.X);
     VMAT_LAUNCH_CHECK();
+    BTRY(launch_spmm(h, true, B, bs.X, bs.dZ, st, 0));
+    n_spmm[0] += 1;
+    for (;;) {
+        for (int i = 0; i < 3; ++i) {
+            k_bls_eval<<<np, BT, 0, st>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.pp, bs.qq);
+            VMAT_LAUNCH_CHECK();
+            k_bls_ctrl<<<B, CTRL, 0, st>>>(bs.ms, bs.pp, bs.qq, np);
+            VMAT_LAUNCH_CHECK();
+        }
+        BTRY(sync_batch(h, B, st));
+        bool searching = false;
+        for (int b = 0; b < B; ++b) searching = searching || (!bs.ms_host[b].done && !bs.ms_host[b].ls_done);
+        if (!searching) break;
+    }
+    k_bmaster_step<<<B, CTRL, 0, st>>>(m);
+    VMAT_LAUNCH_CHECK();
+    k_bupdate<<<np, BT, 0, st>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.RZ, bs.pf);
+    VMAT_LAUNCH_CHECK();
+    BTRY(launch_spmm(h, false, B, bs.RZ, bs.G, st, 0));
+    n_spmm[1] += 1;
     k_bbeam_sums<<<h->N, BT, 0, st>>>(h->N, h->R, h->C, B, bs.G, l, r, occ, bs.gF);
     VMAT_LAUNCH_CHECK();
-    k_bmaster_grad<<<B, CTRL, 0, st>>>(m, bs.pf, np, 2);
+    k_bmaster_grad<<<B, CTRL, 0, st>>>(m, bs.pf, np, 0, nullptr);
     VMAT_LAUNCH_CHECK();
-    for (;;) {
-        k_bmaster_dir<<<B, CTRL, 0, st>>>(m);
-        VMAT_LAUNCH_CHECK();
-        BTRY(sync_batch(h, B, st));
-        bool all_done = true;
-        for (int b = 0; b < B; ++b) all_done = all_done && bs.ms_host[b].done;
-        if (all_done) break;
-        k_bfluence<<<(unsigned)((nbB + BT - 1) / BT), BT, 0, st>>>(h->nb, h->N, h->R, h->C, B, bs.d, l, r, occ,
-                                                                   bs.ms, bs.X);
-        VMAT_LAUNCH_CHECK();
-        BTRY(launch_spmm(h, true, B, bs.X, bs.dZ, st, 0));
-        n_spmm[0] += 1;
-        for (;;) {
-            for (int i = 0; i < 3; ++i) {
-                k_bls_eval<<<np, BT, 0, st>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.pp, bs.qq);
-                VMAT_LAUNCH_CHECK();
-                k_bls_ctrl<<<B, CTRL, 0, st>>>(bs.ms, bs.pp, bs.qq, np);
-                VMAT_LAUNCH_CHECK();
-            }
-            BTRY(sync_batch(h, B, st));
-            bool searching = false;
-            for (int b = 0; b < B; ++b) searching = searching || (!bs.ms_host[b].done && !bs.ms_host[b].ls_done);
-            if (!searching) break;
-        }
-        k_bmaster_step<<<B, CTRL, 0, st>>>(m);
-        VMAT_LAUNCH_CHECK();
-        k_bupdate<<<np, BT, 0, st>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.RZ, bs.pf);
-        VMAT_LAUNCH_CHECK();
-        BTRY(launch_spmm(h, false, B, bs.RZ, bs.G, st, 0));
-        n_spmm[1] += 1;
-        k_bbeam_sums<<<h->N, BT, 0, st>>>(h->N, h->R, h->C, B, bs.G, l, r, occ, bs.gF);
-        VMAT_LAUNCH_CHECK();
-        k_bmaster_grad<<<B, CTRL, 0, st>>>(m, bs.pf, np, 0);
-        VMAT_LAUNCH_CHECK();
-    }
     return VMAT_OK;
 }
 
@@ -812,10 +811,11 @@ extern "C" vmat_status vmat_reserve_batched(vmat_handle h, int32_t max_variants)
     A(&b->bprice, B * N); A(&b->pbeam, B * (1 + 2 * (size_t)h->R)); A(&b->pscore, B * 3); A(&b->kref, B);
     A(&b->cost, B);
     A(&b->tr.beam, B * N); A(&b->tr.price, B * N); A(&b->tr.margin, B * N); A(&b->tr.row_margin, B * N);
-    if (rc == VMAT_OK && hipHostMalloc((void**)&b->ms_host, sizeof(MasterState) * B) != hipSuccess) {
-        b->ms_host = nullptr;
+    A(&b->vmask, B); A(&b->viter, B);
+    if (rc == VMAT_OK && (hipHostMalloc((void**)&b->ms_host, sizeof(MasterState) * B) != hipSuccess ||
+                          hipHostMalloc((void**)&b->mask_host, B) != hipSuccess ||
+                          hipHostMalloc((void**)&b->iter_host, sizeof(int32_t) * B) != hipSuccess))
         rc = fail(VMAT_ERR_ALLOC, "pinned host allocation failed");
-    }
     h->bytes += b->bytes;
     if (rc != VMAT_OK) {
         free_batch(h);
@@ -881,28 +881,67 @@ extern "C" vmat_status vmat_solve_batched(vmat_handle h, const vmat_solve_opts* 
         R[b].n_adjoint = 1;
         costs[b][0] = cost0[b];
     }
-    for (int t = 0; t < iters; ++t) {
-        BTRY(launch_price_variants(h, B, bs.G, y, l, r, occ, bs.rowS, bs.rowl, bs.rowr, bs.rowm, bs.bprice,
-                                   bs.pbeam, bs.pscore, nullptr, 1, t, l, r, occ, y, bs.tr, st));
-        if (t == 0) {
-            k_bkref<<<1, 64, 0, st>>>(B, bs.pscore, bs.kref);
-            VMAT_LAUNCH_CHECK();
-        }
-        BTRY(batch_master(h, a, l, r, occ, y, so.master, cnt, st));
+    // Each variant opens its next aperture as soon as its own master has
+    // stopped; the masters that are running advance together, one SpMM per
+    // product.  cg_t[b]: apertures opened by variant b.
+    std::vector<int> cg_t(B, 0);
+    std::vector<uint8_t> recorded(B, 1);
+    const MasterPtrs m = batch_ptrs(h, y, occ, l, r);
+    bool first = true;
+    for (;;) {
+        int n_restart = 0;
+        bool finished = true;
         for (int b = 0; b < B; ++b) {
             const MasterState& s = bs.ms_host[b];
-            R[b].master_iters += s.it;
-            R[b].n_forward += s.n_fwd;
-            R[b].n_adjoint += s.n_adj;
-            R[b].n_ls_evals += s.n_ls;
-            if (!s.converged) R[b].not_converged++;
-            R[b].cg_iters = t + 1;
-            R[b].F = s.F;
-            R[b].gG = s.gG;
-            R[b].kkt_ref = s.kkt_ref;
-            costs[b][t + 1] = s.F + s.gG;
-            miters[b][t] = s.it;
+            const bool ready = first || s.done;
+            if (ready && !recorded[b]) {
+                const int t = cg_t[b] - 1;
+                R[b].master_iters += s.it;
+                R[b].n_forward += s.n_fwd;
+                R[b].n_adjoint += s.n_adj;
+                R[b].n_ls_evals += s.n_ls;
+                if (!s.converged) R[b].not_converged++;
+                R[b].cg_iters = t + 1;
+                R[b].F = s.F;
+                R[b].gG = s.gG;
+                R[b].kkt_ref = s.kkt_ref;
+                costs[b][t + 1] = s.F + s.gG;
+                miters[b][t] = s.it;
+                recorded[b] = 1;
+            }
+            const bool go = ready && cg_t[b] < iters;
+            bs.mask_host[b] = go ? 1 : 0;
+            bs.iter_host[b] = cg_t[b];
+            n_restart += go ? 1 : 0;
+            finished = finished && ready && cg_t[b] >= iters;
         }
+        if (finished) break;
+        if (n_restart > 0) {
+            VMAT_HIP(hipMemcpyAsync(bs.vmask, bs.mask_host, B, hipMemcpyHostToDevice, st));
+            VMAT_HIP(hipMemcpyAsync(bs.viter, bs.iter_host, sizeof(int32_t) * B, hipMemcpyHostToDevice, st));
+            BTRY(launch_price_variants(h, B, bs.G, y, l, r, occ, bs.rowS, bs.rowl, bs.rowr, bs.rowm, bs.bprice,
+                                       bs.pbeam, bs.pscore, nullptr, 1, 0, l, r, occ, y, bs.tr, st, bs.vmask,
+                                       bs.viter));
+            if (first) {
+                k_bkref<<<1, 64, 0, st>>>(B, bs.pscore, bs.kref);
+                VMAT_LAUNCH_CHECK();
+            }
+            k_bmaster_begin<<<B, CTRL, 0, st>>>(h->N, y, occ, bs.ms, so.master.max_iter, so.master.ls_max_steps,
+                                                so.master.tol_rel, so.master.kkt_ref, bs.kref, bs.vmask);
+            VMAT_LAUNCH_CHECK();
+            k_bbeam_sums<<<h->N, BT, 0, st>>>(h->N, h->R, h->C, B, bs.G, l, r, occ, bs.gF);
+            VMAT_LAUNCH_CHECK();
+            k_bmaster_grad<<<B, CTRL, 0, st>>>(m, bs.pf, h->n_part, 2, bs.vmask);
+            VMAT_LAUNCH_CHECK();
+            for (int b = 0; b < B; ++b)
+                if (bs.mask_host[b]) {
+                    cg_t[b] += 1;
+                    recorded[b] = 0;
+                }
+        }
+        first = false;
+        bool active = false;
+        BTRY(batch_iteration(h, a, l, r, occ, y, cnt, &active, st));
     }
     for (int b = 0; b < B; ++b) rep[b] = R[b];
     if (n_spmm) {

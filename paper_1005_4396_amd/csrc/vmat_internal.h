@@ -162,6 +162,10 @@ struct BatchState {
     double* pscore = nullptr;                            // [cap][3]
     double* kref = nullptr;                              // [cap]
     double* cost = nullptr;                              // [cap]
+    uint8_t* vmask = nullptr;                            // [cap] variants opening an aperture now
+    int32_t* viter = nullptr;                            // [cap] their aperture counts
+    uint8_t* mask_host = nullptr;                        // [cap], pinned
+    int32_t* iter_host = nullptr;                        // [cap], pinned
     SolveTraceDev tr{};                                  // [cap][N] each
     int64_t bytes = 0;
 };

@@ -86,11 +86,13 @@ vmat_status launch_price(const vmat_ctx* h, const double* g, const double* y, co
                          double* beam_prices, int apply, int iter, int32_t* lw, int32_t* rw, uint8_t* occw,
                          double* yw, hipStream_t st);
 // B plan variants at once: g RHS-contiguous [nb][B]; plan, row, price and
-// trace arrays variant-major.
+// trace arrays variant-major.  vmask (nullable, device [B]): variants to
+// price; iter_v (nullable, device [B]): trace index per variant.
 vmat_status launch_price_variants(const vmat_ctx* h, int B, const double* g, const double* y, const int32_t* l,
                                   const int32_t* r, const uint8_t* occ, double* rowS, int32_t* rowl, int32_t* rowr,
                                   double* rowm, double* bprice, int32_t* out_beam, double* out_price,
                                   double* beam_prices, int apply, int iter, int32_t* lw, int32_t* rw, uint8_t* occw,
-                                  double* yw, SolveTraceDev tr, hipStream_t st);
+                                  double* yw, SolveTraceDev tr, hipStream_t st, const uint8_t* vmask = nullptr,
+                                  const int32_t* iter_v = nullptr);
 
 }  // namespace vmat

@@ -29,12 +29,15 @@ __device__ __forceinline__ bool less_key(const Cand& a, const Cand& b) {
 
 // Plan variants (blockIdx.y = variant b of B): g is RHS-contiguous (beamlet
 // i of variant b at i*B + b), the plan and row arrays are variant-major.
+// vmask (nullable): variants to price; the others' blocks return at once.
 __global__ __launch_bounds__(256) void k_price_rows(int N, int R, int C, int delta, int circ, int B,
                                                     const double* __restrict__ g, const int32_t* __restrict__ l,
                                                     const int32_t* __restrict__ r, const uint8_t* __restrict__ occ,
                                                     double* __restrict__ rowS, int32_t* __restrict__ rowl,
-                                                    int32_t* __restrict__ rowr, double* __restrict__ rowm) {
+                                                    int32_t* __restrict__ rowr, double* __restrict__ rowm,
+                                                    const uint8_t* __restrict__ vmask) {
     __shared__ double P[4][65];
+    if (vmask && !vmask[blockIdx.y]) return;
     {
         const int b = blockIdx.y;
         const int64_t NR = (int64_t)N * R;
@@ -158,7 +161,11 @@ __global__ __launch_bounds__(CTRL) void k_price_beams(int N, int R, double gamma
                                                       double* __restrict__ out_price, double* __restrict__ user_bp,
                                                       int apply, int iter, int32_t* __restrict__ lw,
                                                       int32_t* __restrict__ rw, uint8_t* __restrict__ occw,
-                                                      double* __restrict__ yw, SolveTraceDev tr) {
+                                                      double* __restrict__ yw, SolveTraceDev tr,
+                                                      const uint8_t* __restrict__ vmask,
+                                                      const int32_t* __restrict__ iter_v) {
+    if (vmask && !vmask[blockIdx.x]) return;
+    if (iter_v) iter = iter_v[blockIdx.x];
     {
         // variant blockIdx.x: variant-major plan, row and trace arrays
         const int b = blockIdx.x;
@@ -267,22 +274,23 @@ vmat_status launch_price(const vmat_ctx* h, const double* g, const double* y, co
                          const uint8_t* occ, int32_t* out_beam, double* out_price, double* beam_prices, int apply,
                          int iter, int32_t* lw, int32_t* rw, uint8_t* occw, double* yw, hipStream_t st) {
     return launch_price_variants(h, 1, g, y, l, r, occ, h->row_S, h->row_l, h->row_r, h->row_m, h->bprice, out_beam,
-                                 out_price, beam_prices, apply, iter, lw, rw, occw, yw, h->tr, st);
+                                 out_price, beam_prices, apply, iter, lw, rw, occw, yw, h->tr, st, nullptr, nullptr);
 }
 
 vmat_status launch_price_variants(const vmat_ctx* h, int B, const double* g, const double* y, const int32_t* l,
                                   const int32_t* r, const uint8_t* occ, double* rowS, int32_t* rowl, int32_t* rowr,
                                   double* rowm, double* bprice, int32_t* out_beam, double* out_price,
                                   double* beam_prices, int apply, int iter, int32_t* lw, int32_t* rw, uint8_t* occw,
-                                  double* yw, SolveTraceDev tr, hipStream_t st) {
+                                  double* yw, SolveTraceDev tr, hipStream_t st, const uint8_t* vmask,
+                                  const int32_t* iter_v) {
     const int64_t NR = (int64_t)h->N * h->R;
     k_price_rows<<<dim3((unsigned)((NR + 3) / 4), (unsigned)B), 256, 0, st>>>(h->N, h->R, h->C, h->delta,
                                                                              h->circular, B, g, l, r, occ, rowS,
-                                                                             rowl, rowr, rowm);
+                                                                             rowl, rowr, rowm, vmask);
     VMAT_LAUNCH_CHECK();
     k_price_beams<<<(unsigned)B, CTRL, 0, st>>>(h->N, h->R, h->gamma, h->circular, h->d_theta, y, occ, rowS, rowl,
                                                rowr, rowm, bprice, out_beam, out_price, beam_prices, apply, iter,
-                                               lw, rw, occw, yw, tr);
+                                               lw, rw, occw, yw, tr, vmask, iter_v);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
