@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--precision-workload", default="headneck180")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--variants", type=int, default=64)
     ap.add_argument("--no-batched-solve", action="store_true")
@@ -207,7 +208,7 @@ def main():
     }
 
     if not args.no_precision and args.d_store == "f32":
-        out["precision"] = precision_study(case, prob, torch, P, args.kernel_reps, log)
+        out["precision"] = precision_study(args.precision_workload, torch, P, args.kernel_reps, log)
 
     if not args.no_aperture_master and args.steps:
         out["aperture_master"] = aperture_master_study(prob, P, torch, args.steps, ms_per_step, reps[-1], log)
@@ -371,37 +372,50 @@ def batched_solve_study(case, prob, torch, P, B, n_seq, log):
             "costs_first": [round(r.F + r.gG, 3) for r in reps[:4]]}
 
 
-def precision_study(case, prob32, torch, P, reps, log):
-    """Forward/adjoint speed of BF16 and FP8 storage against FP32 on this GPU, at the
-    dose error each gives against the FP64 reference for one full-open plan."""
-    import oracle as O
-    D = O.dose_matrix(case.row_ptr, case.col, case.val, case.n_voxels)
+def precision_study(workload, torch, P, reps, log):
+    """Forward/adjoint speed of BF16 and FP8 storage against FP32 on this GPU,
+    on the head-and-neck-shaped case, at the dose error each gives for one
+    full-open plan (every aperture fully open, random intensities) against an
+    FP64 CPU product of the FP32 D (scipy, computed here)."""
+    import scipy.sparse as sp
+
+    import casegen
+    t0 = time.perf_counter()
+    case = casegen.make_case(casegen.preset(workload))
+    log(f"[bench] precision case {workload}: nnz={case.nnz} gen {time.perf_counter() - t0:.1f}s")
     rng = np.random.default_rng(7)
     N, R, C = case.n_beams, case.n_rows, case.n_cols
     occ = np.ones(N, np.uint8)
     l = np.zeros(N * R, np.int32)
     r = np.full(N * R, C, np.int32)
     y = rng.random(N) + 0.5
-    zo = O.dose(D, O.fluence(y, l, r, occ, R, C))
+    # FP64 reference dose: all beamlets open, so x_i = y_k of beamlet i's beam
+    x_open = np.repeat(y, R * C)
+    D = sp.csr_matrix((case.val.astype(np.float64), case.col, case.row_ptr),
+                      shape=(case.n_beamlets, case.n_voxels))
+    zo = D.T @ x_open
+    del D
     T = lambda a, dt: torch.as_tensor(a, dtype=dt, device="cuda")  # noqa: E731
     yt, lt, rt, ot = T(y, torch.float64), T(l, torch.int32), T(r, torch.int32), T(occ, torch.uint8)
     x = torch.from_numpy(rng.random(case.n_beamlets)).cuda()
     w = torch.from_numpy(rng.standard_normal(case.n_voxels).astype(np.float32)).cuda()
     zb = torch.empty(case.n_voxels, dtype=torch.float64, device="cuda")
     gb = torch.empty(case.n_beamlets, dtype=torch.float64, device="cuda")
-    res = {}
+    res = {"workload": workload, "nnz": case.nnz}
     for fmt in ("f32", "bf16", "fp8"):
-        prob = prob32 if fmt == "f32" else P.Problem.from_case(case, d_store=fmt)
+        prob = P.Problem.from_case(case, d_store=fmt)
         zg = prob.dose(yt, lt, rt, ot).cpu().numpy().astype(np.float64)
         err_l2 = float(np.linalg.norm(zg - zo) / np.linalg.norm(zo))
         err_inf = float(np.abs(zg - zo).max() / np.abs(zo).max())
         f_ms = time_kernel(lambda: prob.forward(x, zb), reps, torch)
         a_ms = time_kernel(lambda: prob.adjoint(w, gb), reps, torch)
-        res[fmt] = {"forward_ms": round(f_ms, 5), "adjoint_ms": round(a_ms, 5), "dose_rel_l2": err_l2,
-                    "dose_rel_inf": err_inf}
+        lay = prob.layout()
+        res[fmt] = {"forward_ms": round(f_ms, 5), "adjoint_ms": round(a_ms, 5),
+                    "forward_GBs": round(lay["fwd_bytes"] / f_ms / 1e6, 1),
+                    "adjoint_GBs": round(lay["adj_bytes"] / a_ms / 1e6, 1),
+                    "dose_rel_l2": err_l2, "dose_rel_inf": err_inf}
         log(f"[bench] {fmt}: fwd {f_ms:.4f} ms adj {a_ms:.4f} ms dose err l2 {err_l2:.2e} inf {err_inf:.2e}")
-        if prob is not prob32:
-            prob.close()
+        prob.close()
     for fmt in ("bf16", "fp8"):
         res[fmt]["speedup_vs_f32"] = round((res["f32"]["forward_ms"] + res["f32"]["adjoint_ms"]) /
                                            (res[fmt]["forward_ms"] + res[fmt]["adjoint_ms"]), 3)

@@ -208,11 +208,22 @@ __global__ __launch_bounds__(SPMM_THREADS) void k_spmm_rows_w64(const uint32_t* 
                                                                int B, const float* __restrict__ X,
                                                                double* __restrict__ Z) {
     const int lane = threadIdx.x & 63;
-    const int64_t row = ((int64_t)blockIdx.x * SPMM_THREADS + threadIdx.x) / 64;
+    // the grid is a multiple of 8 blocks; workgroup w runs on XCD w mod 8, so
+    // XCD x takes the x-th eighth of the rows (neighbouring rows gather
+    // neighbouring right-hand-side rows through the same L2)
+    const int64_t per = gridDim.x / 8;
+    const int64_t blk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int64_t row = (blk * SPMM_THREADS + threadIdx.x) / 64;
     const int b = blockIdx.y * 64 + lane;
     if (row >= nrows) return;
     const double acc = row_w64<FMT, 1, CS>(qptr[row], qptr[row + 1], val, col, nullptr, cscale, B, b, X);
     if (b < B) Z[row * B + b] = rscale ? acc * (double)rscale[row] : acc;
+}
+
+// Blocks for nrows rows at rpb rows per block, rounded up to a multiple of 8.
+static unsigned xcd_grid(int64_t nrows, int64_t rpb) {
+    const int64_t n = (nrows + rpb - 1) / rpb;
+    return (unsigned)((n + 7) / 8 * 8);
 }
 
 template <int FMT, int TB>
@@ -225,7 +236,7 @@ static void spmm_fwd_t(const vmat_ctx* h, int B, const float* X, double* Z, hipS
                 t.fwork, t.loff, t.list, h->vm.qptr, t.fcol, h->vm.val, h->bm.scale, B, X, Z);
         } else {
             const int64_t rpb = SPMM_THREADS / 64;
-            k_spmm_rows_w64<FMT, FMT == FMT_FP8><<<dim3((unsigned)((h->nv + rpb - 1) / rpb), tiles), SPMM_THREADS, 0, st>>>(
+            k_spmm_rows_w64<FMT, FMT == FMT_FP8><<<dim3(xcd_grid(h->nv, rpb), tiles), SPMM_THREADS, 0, st>>>(
                 h->vm.qptr, h->vm.col, h->vm.val, h->bm.scale, nullptr, h->nv, B, X, Z);
         }
         return;
@@ -246,7 +257,7 @@ static void spmm_adj_t(const vmat_ctx* h, int B, const float* W, double* G, hipS
     const unsigned tiles = (unsigned)((B + TB - 1) / TB);
     if constexpr (TB == 64) {
         const int64_t rpb = SPMM_THREADS / 64;
-        k_spmm_rows_w64<FMT, false><<<dim3((unsigned)((h->nb + rpb - 1) / rpb), tiles), SPMM_THREADS, 0, st>>>(
+        k_spmm_rows_w64<FMT, false><<<dim3(xcd_grid(h->nb, rpb), tiles), SPMM_THREADS, 0, st>>>(
             h->bm.qptr, h->bm.col, h->bm.val, nullptr, h->bm.scale, h->nb, B, W, G);
         return;
     }
