@@ -309,7 +309,10 @@ vmat_status vmat_enforce_rate(vmat_handle h, const vmat_rate_opts* opts, const i
  * each solved by the column-generation loop of vmat_solve, in lockstep: every
  * dose and adjoint product is one SpMM over all variants; pricing and the
  * master's control run per variant; a variant whose master has stopped keeps
- * its state while the others iterate.  Directions enter the products in FP32
+ * its state while the others iterate, and a variant opens its next aperture
+ * as soon as its own master stops.  Each lockstep iteration replays two
+ * captured kernel sequences (direction + dose SpMM + line search; step +
+ * adjoint SpMM + gradients).  Directions enter the products in FP32
  * (rounded before the step, so y and the carried dose stay consistent).
  *   vmat_reserve_batched: allocates the work state for up to max_variants
  *       (1..64) variants (about (12 nb + 20 nv) * max_variants bytes); once,

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "vmat_internal.h"
+#include "vmat_graph.h"
 #include "vmat_kernels.h"
 
 using namespace vmat;
@@ -99,49 +100,6 @@ vmat_status sync_state(vmat_ctx* h, hipStream_t st) {
 // the done / line-search flags once per iteration.
 // Master solve with separate kernels and one state read per iteration (used
 // with the plain layout).
-// gamma enters the captured control kernels by value: part of the graph key
-uint64_t gamma_bits(const vmat_ctx* h) {
-    uint64_t b;
-    std::memcpy(&b, &h->gamma, sizeof(b));
-    return b;
-}
-
-// Enqueues `body` (one master iteration's kernels) on st: replayed from a
-// graph captured once per plan-pointer key, or launched directly when
-// VMAT_NO_GRAPH is set.  The graph holds kernels only.
-template <class F>
-vmat_status run_iteration(vmat_ctx* h, int kind, const uint64_t key[6], F body, hipStream_t st) {
-    if (getenv("VMAT_NO_GRAPH")) return body(st);
-    hipGraphExec_t& exec = h->iter_graph[kind];
-    bool same = exec != nullptr;
-    for (int i = 0; i < 6; ++i) same = same && h->iter_key[kind][i] == key[i];
-    if (!same) {
-        if (exec) {
-            (void)hipGraphExecDestroy(exec);
-            exec = nullptr;
-        }
-        if (!h->cap_stream) VMAT_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-        VMAT_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-        vmat_status rc = body(h->cap_stream);
-        hipGraph_t graph = nullptr;
-        const hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
-        if (rc != VMAT_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return rc;
-        }
-        if (e != hipSuccess) return fail(VMAT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ei != hipSuccess) {
-            exec = nullptr;
-            return fail(VMAT_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
-        }
-        for (int i = 0; i < 6; ++i) h->iter_key[kind][i] = key[i];
-    }
-    VMAT_HIP(hipGraphLaunch(exec, st));
-    return VMAT_OK;
-}
-
 // Master solve with separate kernels and one state read per iteration.  The
 // kernels between two reads (step, dose update, adjoint, gradient, next
 // direction, its dose product, three line-search evaluations) form one graph.
@@ -168,8 +126,8 @@ vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, co
         TRY(launch_master_grad(h, y, occ, 0, s));
         return dir_and_search(s);
     };
-    const uint64_t key[6] = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)l, (uint64_t)(uintptr_t)r,
-                             (uint64_t)(uintptr_t)occ, gamma_bits(h), 0};
+    const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)l, (uint64_t)(uintptr_t)r,
+                          (uint64_t)(uintptr_t)occ, gamma_bits(h)};
     TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, fresh, st));
     if (fresh) TRY(forward_from_plan(h, y, l, r, occ, h->z, Gate{}, st));
     TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
@@ -187,7 +145,7 @@ vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, co
             }
             TRY(sync_state(h, st));
         }
-        TRY(run_iteration(h, 0, key, iteration, st));
+        TRY(run_iteration(h, G_MASTER_D, key, iteration, st));
     }
     return VMAT_OK;
 }
@@ -234,9 +192,9 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
             }
             TRY(sync_state(h, st));
         }
-        const uint64_t key[6] = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)occ,
-                                 (uint64_t)(uintptr_t)h->ap->view, gamma_bits(h), 0, 0};
-        TRY(run_iteration(h, 1, key, iteration, st));
+        const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)occ, (uint64_t)(uintptr_t)h->ap->view,
+                              gamma_bits(h)};
+        TRY(run_iteration(h, G_MASTER_AP, key, iteration, st));
     }
     return VMAT_OK;
 }

@@ -17,6 +17,7 @@
 #include "vmat_block.h"
 #include "vmat_ctrl.h"
 #include "vmat_formats.h"
+#include "vmat_graph.h"
 #include "vmat_internal.h"
 #include "vmat_kernels.h"
 #include "vmat_rows.h"
@@ -751,48 +752,69 @@ struct BatchArgs {
 };
 
 // One lockstep master iteration over the variants whose master is running
-// (the others keep their state: zero direction, no step).  Returns with the
-// states read back; *any_active = false when no master was running.
+// (the others keep their state: zero direction, no step), as two captured
+// sequences: [direction, its fluence and dose SpMM, three line-search
+// evaluations] and, after the state read and any further line-search rounds,
+// [step, dose update, adjoint SpMM, beam gradients].  Returns with the states
+// read back; *any_active = false when no master was running (the second
+// sequence is then skipped).
 vmat_status batch_iteration(vmat_ctx* h, const BatchArgs& a, const int32_t* l, const int32_t* r,
                             const uint8_t* occ, double* y, int64_t* n_spmm, bool* any_active, hipStream_t st) {
     BatchState& bs = *h->bs;
     const int B = a.B, np = h->n_part;
     const MasterPtrs m = batch_ptrs(h, y, occ, l, r);
     const int64_t nbB = h->nb * B;
-    k_bmaster_dir<<<B, CTRL, 0, st>>>(m);
-    VMAT_LAUNCH_CHECK();
+    const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)l, (uint64_t)(uintptr_t)r,
+                          (uint64_t)(uintptr_t)occ, (uint64_t)(uintptr_t)a.label, (uint64_t)(uintptr_t)a.table,
+                          (uint64_t)B | ((uint64_t)a.S << 8) | ((uint64_t)(uint32_t)h->tune_fwd[B] << 16) |
+                              ((uint64_t)(uint32_t)h->tune_adj[B] << 32),
+                          gamma_bits(h), (uint64_t)(uintptr_t)bs.X};
+    auto ls_round = [&](hipStream_t s) -> vmat_status {
+        for (int i = 0; i < 3; ++i) {
+            k_bls_eval<<<np, BT, 0, s>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.pp, bs.qq);
+            VMAT_LAUNCH_CHECK();
+            k_bls_ctrl<<<B, CTRL, 0, s>>>(bs.ms, bs.pp, bs.qq, np);
+            VMAT_LAUNCH_CHECK();
+        }
+        return VMAT_OK;
+    };
+    auto direction = [&](hipStream_t s) -> vmat_status {
+        k_bmaster_dir<<<B, CTRL, 0, s>>>(m);
+        VMAT_LAUNCH_CHECK();
+        k_bfluence<<<(unsigned)((nbB + BT - 1) / BT), BT, 0, s>>>(h->nb, h->N, h->R, h->C, B, bs.d, l, r, occ,
+                                                                  bs.ms, bs.X);
+        VMAT_LAUNCH_CHECK();
+        BTRY(launch_spmm(h, true, B, bs.X, bs.dZ, s, 0));
+        return ls_round(s);
+    };
+    auto step = [&](hipStream_t s) -> vmat_status {
+        k_bmaster_step<<<B, CTRL, 0, s>>>(m);
+        VMAT_LAUNCH_CHECK();
+        k_bupdate<<<np, BT, 0, s>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.RZ, bs.pf);
+        VMAT_LAUNCH_CHECK();
+        BTRY(launch_spmm(h, false, B, bs.RZ, bs.G, s, 0));
+        k_bbeam_sums<<<h->N, BT, 0, s>>>(h->N, h->R, h->C, B, bs.G, l, r, occ, bs.gF);
+        VMAT_LAUNCH_CHECK();
+        k_bmaster_grad<<<B, CTRL, 0, s>>>(m, bs.pf, np, 0, nullptr);
+        VMAT_LAUNCH_CHECK();
+        return VMAT_OK;
+    };
+    BTRY(run_iteration(h, G_BATCH_DIR, key, direction, st));
+    n_spmm[0] += 1;
     BTRY(sync_batch(h, B, st));
     bool active = false;
     for (int b = 0; b < B; ++b) active = active || !bs.ms_host[b].done;
     *any_active = active;
     if (!active) return VMAT_OK;
-    k_bfluence<<<(unsigned)((nbB + BT - 1) / BT), BT, 0, st>>>(h->nb, h->N, h->R, h->C, B, bs.d, l, r, occ, bs.ms,
-                                                               bs.X);
-    VMAT_LAUNCH_CHECK();
-    BTRY(launch_spmm(h, true, B, bs.X, bs.dZ, st, 0));
-    n_spmm[0] += 1;
     for (;;) {
-        for (int i = 0; i < 3; ++i) {
-            k_bls_eval<<<np, BT, 0, st>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.pp, bs.qq);
-            VMAT_LAUNCH_CHECK();
-            k_bls_ctrl<<<B, CTRL, 0, st>>>(bs.ms, bs.pp, bs.qq, np);
-            VMAT_LAUNCH_CHECK();
-        }
-        BTRY(sync_batch(h, B, st));
         bool searching = false;
         for (int b = 0; b < B; ++b) searching = searching || (!bs.ms_host[b].done && !bs.ms_host[b].ls_done);
         if (!searching) break;
+        BTRY(ls_round(st));
+        BTRY(sync_batch(h, B, st));
     }
-    k_bmaster_step<<<B, CTRL, 0, st>>>(m);
-    VMAT_LAUNCH_CHECK();
-    k_bupdate<<<np, BT, 0, st>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.RZ, bs.pf);
-    VMAT_LAUNCH_CHECK();
-    BTRY(launch_spmm(h, false, B, bs.RZ, bs.G, st, 0));
+    BTRY(run_iteration(h, G_BATCH_STEP, key, step, st));
     n_spmm[1] += 1;
-    k_bbeam_sums<<<h->N, BT, 0, st>>>(h->N, h->R, h->C, B, bs.G, l, r, occ, bs.gF);
-    VMAT_LAUNCH_CHECK();
-    k_bmaster_grad<<<B, CTRL, 0, st>>>(m, bs.pf, np, 0, nullptr);
-    VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
 

@@ -172,6 +172,8 @@ struct BatchState {
 }  // namespace vmat
 
 namespace vmat {
+constexpr int GRAPH_KEY_LEN = 10;  // words identifying a captured sequence
+
 // Device-side view of the aperture-dose store, read by the master's kernels,
 // so that a captured master iteration stays valid while the store grows.
 struct ApView {
@@ -243,8 +245,8 @@ struct vmat_ctx {
     // one master iteration's kernels as a replayable graph, per master kind;
     // captured on cap_stream, keyed by the plan pointers its kernels take
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t iter_graph[2] = {nullptr, nullptr};
-    uint64_t iter_key[2][6] = {};
+    hipGraphExec_t iter_graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t iter_key[4][vmat::GRAPH_KEY_LEN] = {};
     // master vectors [N]
     double *my = nullptr, *mgrad = nullptr, *mgrad_prev = nullptr, *md = nullptr, *md_prev = nullptr,
            *mgF = nullptr;

@@ -211,3 +211,32 @@ def test_batched_solve_prostate_first_iterations():
                 assert tr1["margin"][t] <= eps or tr1["row_margin"][t] <= eps, (b, t)
                 break
             np.testing.assert_allclose(trs[b]["cost"][t + 1], tr1["cost"][t + 1], rtol=1e-6)
+
+
+def test_batched_solve_graph_replay_matches_direct_launches(monkeypatch):
+    """The captured lockstep iterations give the same bits as the same kernels
+    launched one by one."""
+    c = dict(CASES)["tiny36"]()
+    B = 4
+    tab = casegen.variant_table(c, B, seed=21)
+    prob = P.Problem.from_case(c)
+    try:
+        prob.reserve_batched(B)
+        out = []
+        for no_graph in (False, True):
+            if no_graph:
+                monkeypatch.setenv("VMAT_NO_GRAPH", "1")
+            else:
+                monkeypatch.delenv("VMAT_NO_GRAPH", raising=False)
+            (l, r, occ, y), reps, trs, cnt = prob.solve_batched(T(c.label, torch.uint8), T(tab, torch.float32))
+            out.append((y.cpu().numpy(), l.cpu().numpy(), r.cpu().numpy(), trs, cnt))
+    finally:
+        prob.close()
+    (y0, l0, r0, t0, c0), (y1, l1, r1, t1, c1) = out
+    assert c0 == c1
+    np.testing.assert_array_equal(y0, y1)
+    np.testing.assert_array_equal(l0, l1)
+    np.testing.assert_array_equal(r0, r1)
+    for a, b in zip(t0, t1):
+        np.testing.assert_array_equal(a["cost"], b["cost"])
+        np.testing.assert_array_equal(a["beam"], b["beam"])
