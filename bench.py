@@ -414,7 +414,20 @@ def precision_study(workload, torch, P, reps, log):
                     "forward_GBs": round(lay["fwd_bytes"] / f_ms / 1e6, 1),
                     "adjoint_GBs": round(lay["adj_bytes"] / a_ms / 1e6, 1),
                     "dose_rel_l2": err_l2, "dose_rel_inf": err_inf}
-        log(f"[bench] {fmt}: fwd {f_ms:.4f} ms adj {a_ms:.4f} ms dose err l2 {err_l2:.2e} inf {err_inf:.2e}")
+        # one full plan on this case (aperture-dose master)
+        o = P.vmat.SolveOpts()
+        o.max_cg_iter = 0
+        o.master_mode = 1
+        o.master = P.master_opts()
+        lp, rp, op, yp = prob.empty_plan()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep, _ = prob.solve(lp, rp, op, yp, o, want_trace=False)
+        torch.cuda.synchronize()
+        res[fmt]["plan_s"] = round(time.perf_counter() - t0, 4)
+        res[fmt]["plan_cost"] = rep.F + rep.gG
+        log(f"[bench] {fmt}: fwd {f_ms:.4f} ms adj {a_ms:.4f} ms dose err l2 {err_l2:.2e} inf {err_inf:.2e} "
+            f"plan {res[fmt]['plan_s']:.3f} s cost {rep.F + rep.gG:.6g}")
         prob.close()
     for fmt in ("bf16", "fp8"):
         res[fmt]["speedup_vs_f32"] = round((res["f32"]["forward_ms"] + res["f32"]["adjoint_ms"]) /

@@ -152,3 +152,28 @@ def test_graph_replay_matches_direct_launches(mode, name, monkeypatch):
         np.testing.assert_array_equal(y, out[0][1])
         np.testing.assert_array_equal(l, out[0][2])
         np.testing.assert_array_equal(r, out[0][3])
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_reduced_precision_plan_matches_oracle_on_stored_d(fmt, mode):
+    """A plan computed with D stored in BF16 / FP8 matches the FP64 reference
+    plan of the same rounded D (the plan is exact for what is stored)."""
+    c = preset_case("tiny36")
+    if fmt == "bf16":
+        vals = O.bf16_round(c.val)
+    else:
+        s_, q_ = O.fp8_quantise(c.row_ptr, c.val)
+        vals = O.fp8_dequantise(c.row_ptr, s_, q_)
+    D = oracle_D(c, vals)
+    ref = O.solve(D, c.alpha, c.beta, c.T, c.theta_deg, c.gamma, c.circular, c.n_rows, c.n_cols,
+                  c.max_leaf_step)
+    prob = P.Problem.from_case(c, d_store=fmt)
+    try:
+        l, r, occ, y = prob.empty_plan()
+        rep, tr = prob.solve(l, r, occ, y, _opts(mode))
+        matched = compare_plan(c, ref, tr, l.cpu().numpy(), r.cpu().numpy(), rep)
+    finally:
+        prob.close()
+    print(f"{fmt}/mode {mode}: matched {matched} of {c.n_beams}")
+    assert matched >= 10
