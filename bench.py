@@ -244,6 +244,7 @@ def batched_study(case, prob, torch, B, reps, log):
     tab = casegen.variant_table(case, B, seed=1)
     rng = np.random.default_rng(5)
     X = rng.random((case.n_beamlets, B)).astype(np.float32)
+    prob.reserve_batched(B)            # enables the tiled 64-wide adjoint
     t0 = time.perf_counter()
     fw, aw, times = prob.tune_batched(B, reps=3)
     log(f"[bench] tuned B={B}: forward tile {fw}, adjoint tile {aw} ({time.perf_counter() - t0:.1f}s) {times}")

@@ -178,7 +178,9 @@ vmat_status vmat_adjoint(vmat_handle h, const float* w, double* g, hipStream_t s
  *   vmat_set_batched_tile: sets the tile widths used at B right-hand sides
  *       (0 = default; otherwise 1, 2, 4, ..., 64), e.g. from an earlier tuning.
  * 1 <= B <= 64, 1 <= n_struct <= 16, FP64 accumulation, any storage format.
- * Results are deterministic (no atomics); a tile width changes no result.  */
+ * Results are deterministic (no atomics).  Tile widths change no result,
+ * except that after vmat_reserve_batched the 64-wide adjoint (tiled layout)
+ * sums each beamlet per voxel block first: rounding-level differences.     */
 vmat_status vmat_forward_batched(vmat_handle h, int32_t B, const float* X, double* Z,
                                  hipStream_t stream);
 vmat_status vmat_adjoint_batched(vmat_handle h, int32_t B, const float* W, double* G,

@@ -221,6 +221,77 @@ __global__ __launch_bounds__(SPMM_THREADS) void k_spmm_rows_w64(const uint32_t* 
     if (b < B) Z[row * B + b] = rscale ? acc * (double)rscale[row] : acc;
 }
 
+// Adjoint over the tiled slot rows (one beamlet's entries within one voxel
+// block, 16-bit voxel offsets): the W rows a block gathers belong to its
+// voxel range and stay in the L2 of the XCD its work items run on.  One slot
+// row per wave at a time; sums go to part[slot][b].
+template <int FMT>
+__global__ __launch_bounds__(SPMM_THREADS) void k_spmm_adj_slots_w64(const int4* __restrict__ work,
+                                                                    const int32_t* __restrict__ bounds,
+                                                                    const uint32_t* __restrict__ aqptr,
+                                                                    const uint16_t* __restrict__ acol,
+                                                                    const void* __restrict__ aval, int B,
+                                                                    const float* __restrict__ W,
+                                                                    double* __restrict__ part) {
+    const int4 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    const uint32_t j0 = (uint32_t)bounds[wk.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int b = lane;
+    const int bb = b < B ? b : B - 1;
+    const float* __restrict__ Wb = W + (int64_t)j0 * B;
+    const u16x4* __restrict__ c4 = reinterpret_cast<const u16x4*>(acol);
+    for (int row = wk.y + wave; row < wk.z; row += SPMM_THREADS / 64) {
+        const uint32_t q0 = aqptr[row], q1 = aqptr[row + 1];
+        double acc = 0.0;
+        for (uint32_t base = q0; base < q1; base += 64) {
+            const uint32_t n = min(64u, q1 - base);
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+            if ((uint32_t)lane < n) {
+                v = Quad<FMT>::load(aval, base + lane);
+                const u16x4 c = c4[base + lane];
+                c0 = c.x;
+                c1 = c.y;
+                c2 = c.z;
+                c3 = c.w;
+            }
+            for (uint32_t k = 0; k < n; k += 8) {
+                double xs[8][4];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    xs[u][0] = (double)Wb[(int64_t)bcast(c0, k + u) * B + bb];
+                    xs[u][1] = (double)Wb[(int64_t)bcast(c1, k + u) * B + bb];
+                    xs[u][2] = (double)Wb[(int64_t)bcast(c2, k + u) * B + bb];
+                    xs[u][3] = (double)Wb[(int64_t)bcast(c3, k + u) * B + bb];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    acc = fma((double)bcastf(v.x, k + u), xs[u][0], acc);
+                    acc = fma((double)bcastf(v.y, k + u), xs[u][1], acc);
+                    acc = fma((double)bcastf(v.z, k + u), xs[u][2], acc);
+                    acc = fma((double)bcastf(v.w, k + u), xs[u][3], acc);
+                }
+            }
+        }
+        if (b < B) part[(int64_t)row * B + b] = acc;
+    }
+}
+
+// G[i][b] = scale_i * sum of beamlet i's slot sums (block order).
+__global__ __launch_bounds__(256) void k_spmm_adj_reduce(int64_t nb, int B, const uint32_t* __restrict__ red_ptr,
+                                                         const uint32_t* __restrict__ red_slot,
+                                                         const double* __restrict__ part,
+                                                         const float* __restrict__ scale, double* __restrict__ G) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nb * B) return;
+    const int64_t i = e / B;
+    const int b = (int)(e - i * B);
+    double s = 0.0;
+    for (uint32_t k = red_ptr[i]; k < red_ptr[i + 1]; ++k) s += part[(int64_t)red_slot[k] * B + b];
+    G[e] = scale ? s * (double)scale[i] : s;
+}
+
 // Blocks for nrows rows at rpb rows per block, rounded up to a multiple of 8.
 static unsigned xcd_grid(int64_t nrows, int64_t rpb) {
     const int64_t n = (nrows + rpb - 1) / rpb;
@@ -257,6 +328,15 @@ template <int FMT, int TB>
 static void spmm_adj_t(const vmat_ctx* h, int B, const float* W, double* G, hipStream_t st) {
     const unsigned tiles = (unsigned)((B + TB - 1) / TB);
     if constexpr (TB == 64) {
+        const BatchState* bs = h->bs;
+        if (h->tl.on && bs && bs->spart && B <= bs->cap && h->tl.n_awork > 0) {
+            const Tiled& t = h->tl;
+            k_spmm_adj_slots_w64<FMT><<<(unsigned)t.n_awork, SPMM_THREADS, 0, st>>>(t.awork, t.bounds, t.aqptr,
+                                                                                   t.acol, t.aval, B, W, bs->spart);
+            k_spmm_adj_reduce<<<(unsigned)((h->nb * B + 255) / 256), 256, 0, st>>>(h->nb, B, t.red_ptr, t.red_slot,
+                                                                                   bs->spart, h->bm.scale, G);
+            return;
+        }
         const int64_t rpb = SPMM_THREADS / 64;
         k_spmm_rows_w64<FMT, false><<<dim3(xcd_grid(h->nb, rpb), tiles), SPMM_THREADS, 0, st>>>(
             h->bm.qptr, h->bm.col, h->bm.val, nullptr, h->bm.scale, h->nb, B, W, G);
@@ -699,6 +779,7 @@ void free_batch(vmat_ctx* h) {
     F(b->ms); F(b->pp); F(b->qq); F(b->pf);
     F(b->rowS); F(b->rowm); F(b->rowl); F(b->rowr); F(b->bprice); F(b->pbeam); F(b->pscore); F(b->kref);
     F(b->cost); F(b->tr.beam); F(b->tr.price); F(b->tr.margin); F(b->tr.row_margin); F(b->vmask); F(b->viter);
+    F(b->spart);
     if (b->ms_host) (void)hipHostFree(b->ms_host);
     if (b->mask_host) (void)hipHostFree(b->mask_host);
     if (b->iter_host) (void)hipHostFree(b->iter_host);
@@ -845,6 +926,7 @@ extern "C" vmat_status vmat_reserve_batched(vmat_handle h, int32_t max_variants)
     A(&b->cost, B);
     A(&b->tr.beam, B * N); A(&b->tr.price, B * N); A(&b->tr.margin, B * N); A(&b->tr.row_margin, B * N);
     A(&b->vmask, B); A(&b->viter, B);
+    if (h->tl.on) A(&b->spart, (size_t)h->tl.S * B);
     if (rc == VMAT_OK && (hipHostMalloc((void**)&b->ms_host, sizeof(MasterState) * B) != hipSuccess ||
                           hipHostMalloc((void**)&b->mask_host, B) != hipSuccess ||
                           hipHostMalloc((void**)&b->iter_host, sizeof(int32_t) * B) != hipSuccess))

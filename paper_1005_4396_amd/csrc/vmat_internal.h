@@ -162,6 +162,7 @@ struct BatchState {
     double* pscore = nullptr;                            // [cap][3]
     double* kref = nullptr;                              // [cap]
     double* cost = nullptr;                              // [cap]
+    double* spart = nullptr;                             // [S][cap] slot sums of the 64-wide tiled adjoint
     uint8_t* vmask = nullptr;                            // [cap] variants opening an aperture now
     int32_t* viter = nullptr;                            // [cap] their aperture counts
     uint8_t* mask_host = nullptr;                        // [cap], pinned

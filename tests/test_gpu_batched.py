@@ -240,3 +240,30 @@ def test_batched_solve_graph_replay_matches_direct_launches(monkeypatch):
     for a, b in zip(t0, t1):
         np.testing.assert_array_equal(a["cost"], b["cost"])
         np.testing.assert_array_equal(a["beam"], b["beam"])
+
+
+@pytest.mark.parametrize("fmt", ["f32", "fp8"])
+def test_batched_tiled_adjoint_after_reserve(fmt):
+    """With the batched state reserved, the 64-wide adjoint runs over the tiled
+    slot rows: same result as the reference product up to rounding."""
+    c = dict(CASES)["tiny36"]()
+    if fmt == "fp8":
+        s_, q_ = O.fp8_quantise(c.row_ptr, c.val)
+        D = oracle_D(c, O.fp8_dequantise(c.row_ptr, s_, q_))
+    else:
+        D = oracle_D(c)
+    B = 64
+    W = np.random.default_rng(31).standard_normal((c.n_voxels, B)).astype(np.float32)
+    prob = P.Problem.from_case(c, d_store=fmt)
+    try:
+        prob.set_batched_tile(B, 64, 64)
+        G_plain = prob.adjoint_batched(T(W, torch.float32)).cpu().numpy()
+        prob.reserve_batched(B)
+        G_tiled = prob.adjoint_batched(T(W, torch.float32)).cpu().numpy()
+        G_again = prob.adjoint_batched(T(W, torch.float32)).cpu().numpy()
+    finally:
+        prob.close()
+    ref = D @ W.astype(np.float64)
+    assert rel_inf(G_tiled, ref) <= 1e-12
+    assert rel_inf(G_tiled, G_plain) <= 1e-13
+    assert np.array_equal(G_tiled, G_again)
