@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--workload", default="prostate180")
     ap.add_argument("--d-store", default="f32", choices=["f32", "bf16", "f16", "fp8"])
     ap.add_argument("--kernel-reps", type=int, default=50)
-    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--precision-workload", default="headneck180")
@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--no-batched-solve", action="store_true")
     ap.add_argument("--no-aperture-master", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--products-only", action="store_true",
                     help="no plans and no side studies: only the per-kernel product timing (for profiling)")
     ap.add_argument("--sequential-variants", type=int, default=64,
@@ -216,6 +217,9 @@ def main():
     if not args.no_mixed and args.steps:
         out["mixed_resolution"] = mixed_resolution_study(case, prob, P, torch, log)
 
+    if not args.no_autograd and args.steps:
+        out["autograd"] = autograd_study(case, prob, P, torch, args.kernel_reps, log)
+
     if not args.no_batched:
         out["batched"] = batched_study(case, prob, torch, args.variants, max(3, args.kernel_reps // 10), log)
     if not args.no_batched_solve:
@@ -295,6 +299,32 @@ def aperture_master_study(prob, P, torch, steps, ms_stream, rep_stream, log):
             "cost_rel_diff_vs_streaming": abs(rep.F + rep.gG - (rep_stream.F + rep_stream.gG)) /
             (rep_stream.F + rep_stream.gG),
             "master_iters": rep.master_iters, "d_products": [rep.n_forward, rep.n_adjoint]}
+
+
+def autograd_study(case, prob, P, torch, reps, log):
+    """Differentiable dose + cost: one forward + backward of the fluence form
+    (d cost / d x, 288,000 beamlets) and of the aperture form (d cost / d y,
+    180 apertures, every aperture fully open), FP32 D."""
+    rng = np.random.default_rng(9)
+    N, R, C = case.n_beams, case.n_rows, case.n_cols
+    x = torch.tensor(rng.random(case.n_beamlets) + 0.5, dtype=torch.float64, device="cuda", requires_grad=True)
+    y = torch.tensor(rng.random(N) + 0.5, dtype=torch.float64, device="cuda", requires_grad=True)
+    l = torch.zeros(N * R, dtype=torch.int32, device="cuda")
+    r = torch.full((N * R,), C, dtype=torch.int32, device="cuda")
+    occ = torch.ones(N, dtype=torch.uint8, device="cuda")
+
+    def fx():
+        x.grad = None
+        P.fluence_cost(prob, x).backward()
+
+    def fy():
+        y.grad = None
+        P.aperture_cost(prob, y, l, r, occ).backward()
+    n = max(5, reps // 5)
+    tx = time_kernel(fx, n, torch)
+    ty = time_kernel(fy, n, torch)
+    log(f"[bench] autograd: fluence form {tx:.3f} ms, aperture form {ty:.3f} ms (forward + backward)")
+    return {"fluence_fwd_bwd_ms": round(tx, 4), "aperture_fwd_bwd_ms": round(ty, 4)}
 
 
 def mixed_resolution_study(case, prob_full, P, torch, log):
