@@ -112,10 +112,7 @@ vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, co
         TRY(launch_master_dir(h, y, occ, s));
         TRY(launch_fluence(h, h->md, l, r, occ, h->bm.scale, h->x, done, s));
         TRY(launch_fwd(h, h->x, h->dz, done, s));
-        for (int i = 0; i < 3; ++i) {
-            TRY(launch_ls_eval(h, s));
-            TRY(launch_ls_ctrl(h, s));
-        }
+        TRY(launch_ls_chain(h, 3, s));
         return VMAT_OK;
     };
     auto iteration = [&](hipStream_t s) -> vmat_status {
@@ -139,10 +136,7 @@ vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, co
         TRY(sync_state(h, st));
         if (h->ms_host->done) break;
         while (!h->ms_host->ls_done) {
-            for (int i = 0; i < 4; ++i) {
-                TRY(launch_ls_eval(h, st));
-                TRY(launch_ls_ctrl(h, st));
-            }
+            TRY(launch_ls_chain(h, 4, st));
             TRY(sync_state(h, st));
         }
         TRY(run_iteration(h, G_MASTER_D, key, iteration, st));
@@ -161,10 +155,7 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
     auto dir_and_search = [&](hipStream_t s) -> vmat_status {
         TRY(launch_master_dir(h, y, occ, s));
         TRY(ap_dose(h, h->md, h->dz, done, s));
-        for (int i = 0; i < 3; ++i) {
-            TRY(launch_ls_eval(h, s));
-            TRY(launch_ls_ctrl(h, s));
-        }
+        TRY(launch_ls_chain(h, 3, s));
         return VMAT_OK;
     };
     // the kernels reach the stored doses through the store's device view, so
@@ -186,10 +177,7 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
         TRY(sync_state(h, st));
         if (h->ms_host->done) break;
         while (!h->ms_host->ls_done) {
-            for (int i = 0; i < 4; ++i) {
-                TRY(launch_ls_eval(h, st));
-                TRY(launch_ls_ctrl(h, st));
-            }
+            TRY(launch_ls_chain(h, 4, st));
             TRY(sync_state(h, st));
         }
         const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)occ, (uint64_t)(uintptr_t)h->ap->view,

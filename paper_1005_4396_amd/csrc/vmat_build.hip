@@ -448,6 +448,7 @@ static void free_all(vmat_ctx* h) {
     F(h->abT); F(h->x); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->part); F(h->part_b);
     F(h->my); F(h->mgrad); F(h->mgrad_prev); F(h->md); F(h->md_prev); F(h->mgF); F(h->mW); F(h->mW_prev);
     F(h->ms);
+    F(h->ms2);
     if (h->ms_host) (void)hipHostFree(h->ms_host);
     free_tiled(h);
     F(h->row_S); F(h->row_l); F(h->row_r); F(h->row_m); F(h->bprice); F(h->pbeam); F(h->pscore); F(h->cost2);
@@ -549,6 +550,7 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     if ((rc = dalloc(h, &h->mW, N)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->mW_prev, N)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->ms, 1)) != VMAT_OK) return bail(rc);
+    if ((rc = dalloc(h, &h->ms2, 1)) != VMAT_OK) return bail(rc);
     if (hipHostMalloc((void**)&h->ms_host, sizeof(MasterState), hipHostMallocDefault) != hipSuccess)
         return bail(fail(VMAT_ERR_ALLOC, "hipHostMalloc failed"));
     if ((rc = dalloc(h, &h->row_S, NR)) != VMAT_OK) return bail(rc);

@@ -253,6 +253,7 @@ struct vmat_ctx {
            *mgF = nullptr;
     uint8_t *mW = nullptr, *mW_prev = nullptr;
     vmat::MasterState* ms = nullptr;      // device
+    vmat::MasterState* ms2 = nullptr;     // device, second buffer of the line-search chain
     vmat::MasterState* ms_host = nullptr; // pinned host mirror
     // pricing
     double* row_S = nullptr;       // [N*R]

@@ -72,6 +72,9 @@ vmat_status launch_master_grad(const vmat_ctx* h, const double* y, const uint8_t
 vmat_status launch_master_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, hipStream_t st);
 vmat_status launch_ls_eval(const vmat_ctx* h, hipStream_t st);
 vmat_status launch_ls_ctrl(const vmat_ctx* h, hipStream_t st);
+// n evaluations and their control steps in n + 1 launches (same arithmetic
+// as n alternating launch_ls_eval / launch_ls_ctrl pairs)
+vmat_status launch_ls_chain(const vmat_ctx* h, int n, hipStream_t st);
 vmat_status launch_master_step(const vmat_ctx* h, double* y, hipStream_t st);
 vmat_status launch_update(const vmat_ctx* h, hipStream_t st);
 

@@ -357,6 +357,72 @@ vmat_status launch_ls_eval(const vmat_ctx* h, hipStream_t st) {
     return VMAT_OK;
 }
 
+// A chain of line-search evaluations in which each evaluation first completes
+// the previous one: every block reduces the previous partial sums in the same
+// fixed order and applies the safeguarded-Newton step to its own copy of the
+// state read from src (identical in all blocks); block 0 writes that state to
+// dst, the other buffer of the pair, so no block reads what another writes.
+// The same arithmetic as alternating evaluation and control launches.
+__global__ __launch_bounds__(BLOCK) void k_ls_fused(int64_t nv, const double* __restrict__ z,
+                                                    const double* __restrict__ dz, const float4* __restrict__ abT,
+                                                    const MasterState* __restrict__ src, MasterState* __restrict__ dst,
+                                                    int consume, const double* __restrict__ part_in,
+                                                    double* __restrict__ part_out, int n_part) {
+    __shared__ double sh[4];
+    __shared__ MasterState s;
+    __shared__ int run;
+    const double pF = consume ? reduce_part(part_in, n_part, sh) : 0.0;
+    const double hF = consume ? reduce_part(part_in + n_part, n_part, sh) : 0.0;
+    if (threadIdx.x == 0) {
+        s = *src;
+        if (consume && !(s.done || s.ls_done)) ctrl_ls_step(s, pF, hF);
+        if (blockIdx.x == 0) *dst = s;
+        run = !(s.done || s.ls_done);
+    }
+    __syncthreads();
+    if (!run) return;
+    const double t = s.t_eval;
+    double p = 0.0, q = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < nv; j += (int64_t)gridDim.x * BLOCK) {
+        const double dzj = dz[j];
+        const Pen pn = penalty_at(z[j] + t * dzj, abT[j]);
+        p += dzj * pn.dF;
+        q += dzj * dzj * pn.curv;
+    }
+    p = block_sum(p, sh);
+    q = block_sum(q, sh);
+    if (threadIdx.x == 0) {
+        part_out[blockIdx.x] = p;
+        part_out[n_part + blockIdx.x] = q;
+    }
+}
+
+// Completes the last evaluation of a chain: state src -> dst (may alias).
+__global__ __launch_bounds__(BLOCK) void k_ls_finish(const MasterState* src, MasterState* dst,
+                                                     const double* __restrict__ part, int n_part) {
+    __shared__ double sh[4];
+    const double pF = reduce_part(part, n_part, sh);
+    const double hF = reduce_part(part + n_part, n_part, sh);
+    if (threadIdx.x == 0) {
+        MasterState s = *src;
+        if (!(s.done || s.ls_done)) ctrl_ls_step(s, pF, hF);
+        *dst = s;
+    }
+}
+
+vmat_status launch_ls_chain(const vmat_ctx* h, int n, hipStream_t st) {
+    MasterState* bufs[2] = {h->ms, h->ms2};
+    double* parts[2] = {h->part, h->part + 2 * (int64_t)h->n_part};
+    for (int i = 1; i <= n; ++i) {
+        k_ls_fused<<<h->n_part, BLOCK, 0, st>>>(h->nv, h->z, h->dz, h->abT, bufs[(i - 1) % 2], bufs[i % 2], i > 1,
+                                               parts[(i - 1) % 2], parts[i % 2], h->n_part);
+        VMAT_LAUNCH_CHECK();
+    }
+    k_ls_finish<<<1, BLOCK, 0, st>>>(bufs[n % 2], bufs[0], parts[n % 2], h->n_part);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
 // Safeguarded Newton on the piecewise-linear, non-decreasing phi' inside a bracket.
 __global__ __launch_bounds__(BLOCK) void k_ls_ctrl(MasterState* ms, const double* __restrict__ part, int n_part) {
     __shared__ double sh[4];
