@@ -101,27 +101,30 @@ vmat_status sync_state(vmat_ctx* h, hipStream_t st) {
 // Master solve with separate kernels and one state read per iteration (used
 // with the plain layout).
 // Master solve with separate kernels and one state read per iteration.  The
-// kernels between two reads (step, dose update, adjoint, gradient, next
-// direction, its dose product, three line-search evaluations) form one graph.
+// kernels between two reads (step with the dose update, adjoint, gradient
+// with the next direction, its dose product, three line-search evaluations)
+// form one graph.
 vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
                              const vmat_master_opts& o, int fresh, hipStream_t st) {
     Gate done;  // open while the solve is not done
     done.p = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(h->ms) + offsetof(MasterState, done));
     done.mask = 1u;
-    auto dir_and_search = [&](hipStream_t s) -> vmat_status {
-        TRY(launch_master_dir(h, y, occ, s));
+    auto search = [&](hipStream_t s) -> vmat_status {
         TRY(launch_fluence(h, h->md, l, r, occ, h->bm.scale, h->x, done, s));
         TRY(launch_fwd(h, h->x, h->dz, done, s));
         TRY(launch_ls_chain(h, 3, s));
         return VMAT_OK;
     };
+    auto dir_and_search = [&](hipStream_t s) -> vmat_status {
+        TRY(launch_master_dir(h, y, occ, s));
+        return search(s);
+    };
     auto iteration = [&](hipStream_t s) -> vmat_status {
-        TRY(launch_master_step(h, y, s));
-        TRY(launch_update(h, s));
+        TRY(launch_step_update(h, y, s));
         TRY(launch_adj(h, h->rz, h->g, done, s));
         TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, done, s));
-        TRY(launch_master_grad(h, y, occ, 0, s));
-        return dir_and_search(s);
+        TRY(launch_grad_dir(h, y, occ, s));
+        return search(s);
     };
     const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)l, (uint64_t)(uintptr_t)r,
                           (uint64_t)(uintptr_t)occ, gamma_bits(h)};
@@ -152,20 +155,22 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
     Gate done;
     done.p = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(h->ms) + offsetof(MasterState, done));
     done.mask = 1u;
-    auto dir_and_search = [&](hipStream_t s) -> vmat_status {
-        TRY(launch_master_dir(h, y, occ, s));
+    auto search = [&](hipStream_t s) -> vmat_status {
         TRY(ap_dose(h, h->md, h->dz, done, s));
         TRY(launch_ls_chain(h, 3, s));
         return VMAT_OK;
     };
+    auto dir_and_search = [&](hipStream_t s) -> vmat_status {
+        TRY(launch_master_dir(h, y, occ, s));
+        return search(s);
+    };
     // the kernels reach the stored doses through the store's device view, so
     // the captured iteration stays valid as apertures are added
     auto iteration = [&](hipStream_t s) -> vmat_status {
-        TRY(launch_master_step(h, y, s));
-        TRY(launch_update(h, s));
+        TRY(launch_step_update(h, y, s));
         TRY(ap_grad(h, h->rz, h->mgF, done, s));
-        TRY(launch_master_grad(h, y, occ, 0, s));
-        return dir_and_search(s);
+        TRY(launch_grad_dir(h, y, occ, s));
+        return search(s);
     };
     TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, fresh, st));
     if (fresh) TRY(ap_dose(h, y, h->z, Gate{}, st));

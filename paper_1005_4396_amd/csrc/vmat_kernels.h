@@ -77,6 +77,10 @@ vmat_status launch_ls_ctrl(const vmat_ctx* h, hipStream_t st);
 vmat_status launch_ls_chain(const vmat_ctx* h, int n, hipStream_t st);
 vmat_status launch_master_step(const vmat_ctx* h, double* y, hipStream_t st);
 vmat_status launch_update(const vmat_ctx* h, hipStream_t st);
+// launch_master_step + launch_update in one launch
+vmat_status launch_step_update(const vmat_ctx* h, double* y, hipStream_t st);
+// launch_master_grad(first = 0) + launch_master_dir in one launch
+vmat_status launch_grad_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, hipStream_t st);
 
 // max over eq. 2 pairs of |y_b - y_a| / (theta_b - theta_a) -> out[0]; G(y) -> out[1]
 vmat_status launch_max_rate(const vmat_ctx* h, const double* y, double* out, hipStream_t st);

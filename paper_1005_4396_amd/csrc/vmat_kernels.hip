@@ -475,4 +475,54 @@ vmat_status launch_update(const vmat_ctx* h, hipStream_t st) {
     return VMAT_OK;
 }
 
+// The step and the dose update in one launch: block 0 also moves y (and the
+// previous direction, gradient and face) as k_master_step does; the update
+// reads only t* and the dose vectors, which the step does not touch.
+__global__ __launch_bounds__(BLOCK) void k_update_step(MasterPtrs m, int64_t nv, double* __restrict__ z,
+                                                       const double* __restrict__ dz,
+                                                       const float4* __restrict__ abT, float* __restrict__ rz,
+                                                       double* __restrict__ part) {
+    __shared__ double sh[4];
+    const MasterState* ms = m.ms;
+    if (ms->done) return;
+    const double t = ms->t_star;
+    double F = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < nv; j += (int64_t)gridDim.x * BLOCK) {
+        const double zj = z[j] + t * dz[j];
+        z[j] = zj;
+        const Pen p = penalty_at(zj, abT[j]);
+        F += p.F;
+        rz[j] = (float)p.dF;
+    }
+    F = block_sum(F, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = F;
+    if (blockIdx.x == 0) ctrl_step(m);
+}
+
+vmat_status launch_step_update(const vmat_ctx* h, double* y, hipStream_t st) {
+    k_update_step<<<h->n_part, BLOCK, 0, st>>>(master_ptrs(h, y, nullptr, nullptr, nullptr), h->nv, h->z, h->dz,
+                                               h->abT, h->rz, h->part);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
+// Gradient after a step, then the KKT test and the next direction, in one
+// single-block launch (k_master_grad followed by k_master_dir).
+__global__ __launch_bounds__(CTRL) void k_grad_dir(MasterPtrs m, const double* __restrict__ part, int n_part) {
+    __shared__ double sh[4];
+    __shared__ int shi[4];
+    if (m.ms->done) return;
+    const double F = reduce_part(part, n_part, sh);
+    ctrl_grad(m, F, 0, sh);
+    __syncthreads();
+    ctrl_dir(m, sh, shi);
+}
+
+vmat_status launch_grad_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, hipStream_t st) {
+    k_grad_dir<<<1, CTRL, 0, st>>>(master_ptrs(h, const_cast<double*>(y), occ, nullptr, nullptr), h->part,
+                                   h->n_part);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
 }  // namespace vmat
