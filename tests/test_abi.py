@@ -66,3 +66,30 @@ def test_product_path_has_no_fallback(monkeypatch):
     with pytest.raises(RuntimeError):
         V.lib()
     assert not hasattr(P, "oracle")
+
+
+def test_create_without_a_device_reports_an_error():
+    """Without a GPU every device step fails: vmat_create must return an error
+    status with a message (never crash or abort).  Skipped where a GPU is
+    present, since the arrays here are host memory."""
+    import numpy as np
+    torch = pytest.importorskip("torch")
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    L = _lib()
+    N, R, C, nv = 2, 1, 2, 3
+    theta = np.array([0.0, 180.0])
+    row_ptr = np.array([0, 1, 1, 2, 2], np.int64)
+    col = np.array([0, 2], np.int32)
+    val = np.array([1.0, 0.5], np.float32)
+    ab = np.ones(nv, np.float32)
+    p = V._Problem()
+    p.n_beams, p.n_rows, p.n_cols, p.n_voxels, p.nnz = N, R, C, nv, 2
+    p.theta_deg = theta.ctypes.data
+    p.row_ptr, p.col, p.val = row_ptr.ctypes.data, col.ctypes.data, val.ctypes.data
+    p.alpha = p.beta = p.T = ab.ctypes.data
+    h = ctypes.c_void_p()
+    rc = L.vmat_create(ctypes.byref(p), None, ctypes.byref(h))
+    assert rc in (V.VMAT_ERR_ALLOC, V.VMAT_ERR_DEVICE)
+    assert V.last_error()
+    assert not h.value
