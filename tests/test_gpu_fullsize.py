@@ -69,3 +69,41 @@ def test_prostate_full_plan(prostate_ref, mode):
         assert np.all(np.abs(Rr[a] - Rr[b]) <= c.max_leaf_step)
     print(f"mode {mode}: cost {rep.F + rep.gG:.9g}, reference re-evaluation {F + gG:.9g}, KKT {kkt:.3g} "
           f"(tolerance {1e-5 * rep.kkt_ref:.3g})")
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_headneck_full_plan(fmt):
+    """Head-and-neck-shaped plan (432,000 beamlets, 3,538,944 voxels, 3.7e8
+    non-zeros), FP32 and BF16 storage: the first aperture against the
+    reference on the same stored D, the final cost and KKT conditions
+    re-evaluated by the reference, and the invariants."""
+    c = preset_case("headneck180")
+    vals = c.val if fmt == "f32" else O.bf16_round(c.val)
+    D = oracle_D(c, vals)
+    ref = O.solve(D, c.alpha, c.beta, c.T, c.theta_deg, c.gamma, c.circular, c.n_rows, c.n_cols,
+                  c.max_leaf_step, max_cg_iter=1)
+    o = P.vmat.SolveOpts()
+    o.max_cg_iter = 0
+    o.master_mode = 1
+    o.master = P.master_opts()
+    prob = P.Problem.from_case(c, d_store=fmt)
+    try:
+        l, r, occ, y = prob.empty_plan()
+        rep, tr = prob.solve(l, r, occ, y, o)
+        lg, rg, og, yg = l.cpu().numpy(), r.cpu().numpy(), occ.cpu().numpy(), y.cpu().numpy()
+    finally:
+        prob.close()
+    N, R = c.n_beams, c.n_rows
+    k = ref.order[0]
+    assert tr["beam"][0] == k
+    np.testing.assert_array_equal(lg[k * R:(k + 1) * R], ref.apertures[0][0])
+    np.testing.assert_array_equal(rg[k * R:(k + 1) * R], ref.apertures[0][1])
+    np.testing.assert_allclose(tr["cost"][:2], ref.costs[:2], rtol=1e-6)
+    assert rep.cg_iters == N and og.all()
+    F, gG, z, dF, g, grad = O.objective(D, (c.alpha, c.beta, c.T), yg, lg, rg, og, c.gamma, c.theta_deg,
+                                        c.circular, R, c.n_cols)
+    assert rep.F + rep.gG == pytest.approx(F + gG, rel=1e-6)
+    assert np.abs(np.minimum(yg, grad)).max() <= 2e-5 * rep.kkt_ref
+    cost = tr["cost"]
+    assert np.all(cost[1:] <= cost[:-1] * (1 + 1e-12))
+    print(f"head-and-neck {fmt}: cost {rep.F + rep.gG:.9g}, reference re-evaluation {F + gG:.9g}")
