@@ -177,7 +177,7 @@ __device__ __forceinline__ double row_w64(uint32_t q0, uint32_t q1, const void* 
 }
 
 template <int FMT>
-__global__ __launch_bounds__(SPMM_THREADS) void k_spmm_fwd_tiled_w64(const int4* __restrict__ work,
+__global__ __launch_bounds__(SPMM_THREADS) void k_spmm_fwd_tiled_w64(const int4* __restrict__ work, int n_items,
                                                                     const uint32_t* __restrict__ loff,
                                                                     const uint32_t* __restrict__ list,
                                                                     const uint32_t* __restrict__ qptr,
@@ -187,16 +187,22 @@ __global__ __launch_bounds__(SPMM_THREADS) void k_spmm_fwd_tiled_w64(const int4*
                                                                     const float* __restrict__ X,
                                                                     double* __restrict__ Z) {
     __shared__ uint32_t ls[TILE_LIST];
-    const int4 wk = work[blockIdx.x];
-    if (wk.x < 0) return;
-    const uint32_t l0 = loff[wk.x], ln = loff[wk.x + 1] - l0;
-    for (uint32_t u = threadIdx.x; u < ln; u += SPMM_THREADS) ls[u] = list[l0 + u];
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int b = blockIdx.y * 64 + lane;
-    for (int row = wk.y + wave; row < wk.z; row += SPMM_THREADS / 64) {
-        const double acc = row_w64<FMT, 0, FMT == FMT_FP8>(qptr[row], qptr[row + 1], val, col16, ls, cscale, B, b, X);
-        if (b < B) Z[(int64_t)row * B + b] = acc;
+    // persistent: a fixed grid (a multiple of 8 workgroups, so item i keeps
+    // running on XCD i mod 8) walks the work items
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 wk = work[it];
+        if (wk.x < 0) continue;
+        const uint32_t l0 = loff[wk.x], ln = loff[wk.x + 1] - l0;
+        for (uint32_t u = threadIdx.x; u < ln; u += SPMM_THREADS) ls[u] = list[l0 + u];
+        __syncthreads();
+        for (int row = wk.y + wave; row < wk.z; row += SPMM_THREADS / 64) {
+            const double acc =
+                row_w64<FMT, 0, FMT == FMT_FP8>(qptr[row], qptr[row + 1], val, col16, ls, cscale, B, b, X);
+            if (b < B) Z[(int64_t)row * B + b] = acc;
+        }
+        __syncthreads();
     }
 }
 
@@ -226,55 +232,56 @@ __global__ __launch_bounds__(SPMM_THREADS) void k_spmm_rows_w64(const uint32_t* 
 // voxel range and stay in the L2 of the XCD its work items run on.  One slot
 // row per wave at a time; sums go to part[slot][b].
 template <int FMT>
-__global__ __launch_bounds__(SPMM_THREADS) void k_spmm_adj_slots_w64(const int4* __restrict__ work,
+__global__ __launch_bounds__(SPMM_THREADS) void k_spmm_adj_slots_w64(const int4* __restrict__ work, int n_items,
                                                                     const int32_t* __restrict__ bounds,
                                                                     const uint32_t* __restrict__ aqptr,
                                                                     const uint16_t* __restrict__ acol,
                                                                     const void* __restrict__ aval, int B,
                                                                     const float* __restrict__ W,
                                                                     double* __restrict__ part) {
-    const int4 wk = work[blockIdx.x];
-    if (wk.x < 0) return;
-    const uint32_t j0 = (uint32_t)bounds[wk.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int b = lane;
     const int bb = b < B ? b : B - 1;
-    const float* __restrict__ Wb = W + (int64_t)j0 * B;
     const u16x4* __restrict__ c4 = reinterpret_cast<const u16x4*>(acol);
-    for (int row = wk.y + wave; row < wk.z; row += SPMM_THREADS / 64) {
-        const uint32_t q0 = aqptr[row], q1 = aqptr[row + 1];
-        double acc = 0.0;
-        for (uint32_t base = q0; base < q1; base += 64) {
-            const uint32_t n = min(64u, q1 - base);
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-            if ((uint32_t)lane < n) {
-                v = Quad<FMT>::load(aval, base + lane);
-                const u16x4 c = c4[base + lane];
-                c0 = c.x;
-                c1 = c.y;
-                c2 = c.z;
-                c3 = c.w;
-            }
-            for (uint32_t k = 0; k < n; k += 8) {
-                double xs[8][4];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    xs[u][0] = (double)Wb[(int64_t)bcast(c0, k + u) * B + bb];
-                    xs[u][1] = (double)Wb[(int64_t)bcast(c1, k + u) * B + bb];
-                    xs[u][2] = (double)Wb[(int64_t)bcast(c2, k + u) * B + bb];
-                    xs[u][3] = (double)Wb[(int64_t)bcast(c3, k + u) * B + bb];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {  // persistent, as the forward
+        const int4 wk = work[it];
+        if (wk.x < 0) continue;
+        const float* __restrict__ Wb = W + (int64_t)bounds[wk.x] * B;
+        for (int row = wk.y + wave; row < wk.z; row += SPMM_THREADS / 64) {
+            const uint32_t q0 = aqptr[row], q1 = aqptr[row + 1];
+            double acc = 0.0;
+            for (uint32_t base = q0; base < q1; base += 64) {
+                const uint32_t n = min(64u, q1 - base);
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+                if ((uint32_t)lane < n) {
+                    v = Quad<FMT>::load(aval, base + lane);
+                    const u16x4 c = c4[base + lane];
+                    c0 = c.x;
+                    c1 = c.y;
+                    c2 = c.z;
+                    c3 = c.w;
                 }
+                for (uint32_t k = 0; k < n; k += 8) {
+                    double xs[8][4];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    acc = fma((double)bcastf(v.x, k + u), xs[u][0], acc);
-                    acc = fma((double)bcastf(v.y, k + u), xs[u][1], acc);
-                    acc = fma((double)bcastf(v.z, k + u), xs[u][2], acc);
-                    acc = fma((double)bcastf(v.w, k + u), xs[u][3], acc);
+                    for (int u = 0; u < 8; ++u) {
+                        xs[u][0] = (double)Wb[(int64_t)bcast(c0, k + u) * B + bb];
+                        xs[u][1] = (double)Wb[(int64_t)bcast(c1, k + u) * B + bb];
+                        xs[u][2] = (double)Wb[(int64_t)bcast(c2, k + u) * B + bb];
+                        xs[u][3] = (double)Wb[(int64_t)bcast(c3, k + u) * B + bb];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        acc = fma((double)bcastf(v.x, k + u), xs[u][0], acc);
+                        acc = fma((double)bcastf(v.y, k + u), xs[u][1], acc);
+                        acc = fma((double)bcastf(v.z, k + u), xs[u][2], acc);
+                        acc = fma((double)bcastf(v.w, k + u), xs[u][3], acc);
+                    }
                 }
             }
+            if (b < B) part[(int64_t)row * B + b] = acc;
         }
-        if (b < B) part[(int64_t)row * B + b] = acc;
     }
 }
 
@@ -292,6 +299,15 @@ __global__ __launch_bounds__(256) void k_spmm_adj_reduce(int64_t nb, int B, cons
     G[e] = scale ? s * (double)scale[i] : s;
 }
 
+// Workgroups of the persistent 64-wide kernels: at most per_cu per compute
+// unit (256 CUs), a multiple of 8 (work items are placed round-robin on the
+// XCDs).  Measured on the prostate case: the adjoint is fastest with 2 per
+// CU, the forward (whose LDS list limits residency) with 4.
+static unsigned persistent_grid(int n_items, int per_cu) {
+    const int g = std::min(n_items, per_cu * 256);
+    return (unsigned)std::max(8, (g + 7) / 8 * 8);
+}
+
 // Blocks for nrows rows at rpb rows per block, rounded up to a multiple of 8.
 static unsigned xcd_grid(int64_t nrows, int64_t rpb) {
     const int64_t n = (nrows + rpb - 1) / rpb;
@@ -304,8 +320,8 @@ static void spmm_fwd_t(const vmat_ctx* h, int B, const float* X, double* Z, hipS
     if constexpr (TB == 64) {
         if (h->tl.on) {
             const Tiled& t = h->tl;
-            k_spmm_fwd_tiled_w64<FMT><<<dim3((unsigned)t.n_fwork, tiles), SPMM_THREADS, 0, st>>>(
-                t.fwork, t.loff, t.list, h->vm.qptr, t.fcol, h->vm.val, h->bm.scale, B, X, Z);
+            k_spmm_fwd_tiled_w64<FMT><<<dim3(persistent_grid(t.n_fwork, 4), tiles), SPMM_THREADS, 0, st>>>(
+                t.fwork, t.n_fwork, t.loff, t.list, h->vm.qptr, t.fcol, h->vm.val, h->bm.scale, B, X, Z);
         } else {
             const int64_t rpb = SPMM_THREADS / 64;
             k_spmm_rows_w64<FMT, FMT == FMT_FP8><<<dim3(xcd_grid(h->nv, rpb), tiles), SPMM_THREADS, 0, st>>>(
@@ -331,8 +347,8 @@ static void spmm_adj_t(const vmat_ctx* h, int B, const float* W, double* G, hipS
         const BatchState* bs = h->bs;
         if (h->tl.on && bs && bs->spart && B <= bs->cap && h->tl.n_awork > 0) {
             const Tiled& t = h->tl;
-            k_spmm_adj_slots_w64<FMT><<<(unsigned)t.n_awork, SPMM_THREADS, 0, st>>>(t.awork, t.bounds, t.aqptr,
-                                                                                   t.acol, t.aval, B, W, bs->spart);
+            k_spmm_adj_slots_w64<FMT><<<persistent_grid(t.n_awork, 2), SPMM_THREADS, 0, st>>>(
+                t.awork, t.n_awork, t.bounds, t.aqptr, t.acol, t.aval, B, W, bs->spart);
             k_spmm_adj_reduce<<<(unsigned)((h->nb * B + 255) / 256), 256, 0, st>>>(h->nb, B, t.red_ptr, t.red_slot,
                                                                                    bs->spart, h->bm.scale, G);
             return;
