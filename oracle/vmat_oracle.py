@@ -10,7 +10,7 @@ of C beamlets; beamlet i = (k*R + rho)*C + c.  D is beamlet-major:
 aperture A_k is one open interval [l_{k,rho}, r_{k,rho}) per leaf row
 (l == r: closed row); y_k >= 0 is its intensity.
 
-Readings of points the paper leaves open (each one also in the design doc):
+Readings of points the paper leaves open:
   * Apertures are row-convex leaf intervals; rows are independent (no
     interdigitation or minimum-gap rule).  Closed rows are allowed.
   * eq. 2 smoothing: ``circular=0`` is the literal open chain k=1..N-1;
