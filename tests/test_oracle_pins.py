@@ -551,3 +551,69 @@ def test_rate_continuation_on_generated_case():
     occ = sol.occ.astype(bool)
     kkt = np.abs(np.minimum(res.y, grad))[occ].max()
     assert kkt <= 1e-8 * abs(sol.prices[0])
+
+
+# ---------------------------------------------------------------- property tests (Hypothesis)
+
+try:
+    from hypothesis import given, settings, strategies as st
+except ImportError:  # pragma: no cover
+    given = None
+
+if given is not None:
+    def _brute_row_prefix(g, Llo, Lhi, Rlo, Rhi):
+        # every feasible pair; S from prefix sums accumulated in column order
+        P = [0.0]
+        for v in g:
+            P.append(P[-1] + v)
+        best = None
+        for l in range(Llo, Lhi + 1):
+            for r in range(max(l, Rlo), Rhi + 1):
+                key = (P[r] - P[l], r - l, l)
+                if best is None or key < best[0]:
+                    best = (key, l, r)
+        return best
+
+    @settings(max_examples=400, deadline=None, derandomize=True)
+    @given(st.lists(st.floats(min_value=-50, max_value=50, allow_nan=False, width=32), min_size=1, max_size=12),
+           st.data())
+    def test_price_row_property_vs_bruteforce(g, data):
+        """Any real-valued row and any window: the one-pass search finds the
+        least S over every feasible pair, with the (S, r-l, l) tie rule."""
+        C = len(g)
+        a = data.draw(st.integers(0, C))
+        b = data.draw(st.integers(a, C))
+        c = data.draw(st.integers(0, C))
+        d = data.draw(st.integers(c, C))
+        S, l, r = O.price_row(np.asarray(g, float), a, b, c, d)
+        if a > d:
+            assert (l, r) == (-1, -1)
+            return
+        br = _brute_row_prefix(list(map(float, g)), a, b, c, d)
+        assert (l, r) == (br[1], br[2])
+        assert S == br[0][0]
+
+    @settings(max_examples=200, deadline=None, derandomize=True)
+    @given(st.lists(st.floats(min_value=0, max_value=100, allow_nan=False), min_size=1, max_size=20),
+           st.floats(min_value=0, max_value=5), st.floats(min_value=0, max_value=5),
+           st.floats(min_value=0, max_value=100))
+    def test_penalty_property_convex_and_derivative(z, alpha, beta, T):
+        """eq. 1 per voxel: F >= 0, F = 0 exactly at z = T, F' matches a central
+        difference away from the kink, and F is convex along any segment."""
+        z = np.asarray(z, float)
+        n = len(z)
+        a, b, t = np.full(n, alpha), np.full(n, beta), np.full(n, T)
+        F, dF = O.penalty(z, a, b, t)
+        assert F >= 0
+        F0, d0 = O.penalty(t, a, b, t)
+        assert F0 == 0 and not d0.any()
+        h = 1e-4
+        away = np.abs(z - T) > 2 * h
+        Fp = np.array([O.penalty(np.array([v + h]), a[:1], b[:1], t[:1])[0] for v in z])
+        Fm = np.array([O.penalty(np.array([v - h]), a[:1], b[:1], t[:1])[0] for v in z])
+        fd = (Fp - Fm) / (2 * h)
+        assert np.allclose(fd[away], dF[away], rtol=1e-6, atol=1e-6)
+        mid, _ = O.penalty(0.5 * (z + t[::-1]), a, b, t)
+        e1, _ = O.penalty(z, a, b, t)
+        e2, _ = O.penalty(t[::-1], a, b, t)
+        assert mid <= 0.5 * (e1 + e2) + 1e-9 * (1 + e1 + e2)
