@@ -575,11 +575,14 @@ if given is not None:
         return best
 
     @settings(max_examples=400, deadline=None, derandomize=True)
-    @given(st.lists(st.floats(min_value=-50, max_value=50, allow_nan=False, width=32), min_size=1, max_size=12),
-           st.data())
-    def test_price_row_property_vs_bruteforce(g, data):
-        """Any real-valued row and any window: the one-pass search finds the
-        least S over every feasible pair, with the (S, r-l, l) tie rule."""
+    @given(st.lists(st.integers(-400, 400), min_size=1, max_size=12), st.data())
+    def test_price_row_property_vs_bruteforce(gi, data):
+        """Rows of multiples of 1/8 (every prefix sum exact in FP64, so exact
+        ties stay ties) and any window: the one-pass search finds the least S
+        over every feasible pair, with the (S, r-l, l) tie rule.  (With
+        arbitrary reals, rounding can make two different sums equal; the
+        one-pass rule then keeps the exactly smaller one.)"""
+        g = [v / 8.0 for v in gi]
         C = len(g)
         a = data.draw(st.integers(0, C))
         b = data.draw(st.integers(a, C))
@@ -589,7 +592,7 @@ if given is not None:
         if a > d:
             assert (l, r) == (-1, -1)
             return
-        br = _brute_row_prefix(list(map(float, g)), a, b, c, d)
+        br = _brute_row_prefix(g, a, b, c, d)
         assert (l, r) == (br[1], br[2])
         assert S == br[0][0]
 
