@@ -195,6 +195,9 @@ def main():
                    "layout": "tiled" if lay["tiled"] else "plain",
                    "step": "one full column-generation plan"},
         "plan_s": round(ms_per_step / 1e3, 4) if ms_per_step else None,
+        # the paper's own plan times (clinical cases of 1.8e7-5.5e7 non-zeros,
+        # other hardware): context only, not the same workload
+        "context": {"paper_plan_s_matlab_xeon_2_27ghz": [265, 512], "paper_plan_s_cuda_tesla_c1060": [18, 31]},
         "plan": {"cg_iters": reps[-1].cg_iters, "master_iters": reps[-1].master_iters,
                  "n_forward": reps[-1].n_forward, "n_adjoint": reps[-1].n_adjoint,
                  "n_ls_evals": reps[-1].n_ls_evals, "cost": reps[-1].F + reps[-1].gG} if reps else None,
