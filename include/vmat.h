@@ -25,9 +25,13 @@
  *     checked before any launch, so VMAT_ERR_INVALID_ARG leaves outputs
  *     untouched.  vmat_last_error() gives a text for the last failure on the
  *     calling thread.
- *   - A handle is not thread-safe; distinct handles are independent.  All
- *     device memory a handle needs is allocated by vmat_create and released
- *     by vmat_destroy; no other call allocates.
+ *   - A handle is not thread-safe; distinct handles are independent.  Device
+ *     memory is allocated by vmat_create (D's layouts and work buffers), by
+ *     vmat_reserve_batched (batched state), and once, on first use, by
+ *     vmat_solve with master_mode 1 (aperture-dose store, grown by doubling if
+ *     needed) and by the captured master iterations (graphs); vmat_destroy
+ *     releases all of it.  The dose, gradient, pricing and product calls
+ *     allocate nothing.
  */
 #ifndef VMAT_H
 #define VMAT_H
@@ -87,8 +91,9 @@ typedef struct vmat_problem {
 } vmat_problem;
 
 /* Copies D, alpha, beta, T into the library's own device layouts (beamlet-major
- * and voxel-major, in d_store precision) and validates them (one pass; invalid
- * data gives VMAT_ERR_INVALID_ARG).  The caller may free its arrays afterwards. */
+ * and voxel-major quad CSR, and the tiled and sliced forms of both products,
+ * in d_store precision) and validates them (one pass; invalid data gives
+ * VMAT_ERR_INVALID_ARG).  The caller may free its arrays afterwards.          */
 vmat_status vmat_create(const vmat_problem* prob, hipStream_t stream, vmat_handle* out);
 vmat_status vmat_destroy(vmat_handle h);
 const char* vmat_last_error(void);
@@ -103,8 +108,9 @@ vmat_status vmat_device_bytes(vmat_handle h, int64_t* bytes);
 typedef struct vmat_layout_info {
     int32_t tiled;          /* 1: tiled layout (LDS-staged gathers), 0: plain quad CSR   */
     int32_t n_blocks;       /* voxel blocks of the tiled layout                          */
-    int32_t fwd_lanes;      /* lanes per row of the forward kernel                        */
-    int32_t adj_lanes;      /* lanes per row of the adjoint kernel                        */
+    int32_t fwd_lanes;      /* lanes per row of the CSR-shaped tiled forward (the sliced  */
+                            /* kernels, used by default, give every row one lane)         */
+    int32_t adj_lanes;      /* lanes per row of the CSR-shaped tiled adjoint              */
     int64_t fwd_entries;    /* stored entries of the forward layout, padding included     */
     int64_t adj_entries;    /* stored entries of the adjoint layout, padding included     */
     int64_t slots;          /* (block, beamlet) pairs of the tiled layout                 */
@@ -116,9 +122,10 @@ vmat_status vmat_layout(vmat_handle h, vmat_layout_info* out);
 /* Dose of a plan (Sec. 2.1; the constraint of eq. 3):
  *   z_j = sum_k y_k sum_{i in A_k} D_ij, accumulated in FP64, stored as FP32.
  * y: DEVICE double [N]; l, r: DEVICE int32 [N*R]; occ: DEVICE uint8 [N];
- * z: DEVICE float [nv] (out).  Leaf pairs must satisfy 0 <= l <= r <= C for
- * occupied beams (checked on the device; a violation makes the call return
- * nothing useful, so check on the host when the data is untrusted).           */
+ * z: DEVICE float [nv] (out).  Leaf pairs are meant to satisfy
+ * 0 <= l <= r <= C; other values are not rejected: a row then exposes the
+ * columns c in [0, C) with l <= c < r (no memory is touched outside the
+ * arrays).                                                                   */
 vmat_status vmat_dose(vmat_handle h, const double* y, const int32_t* l, const int32_t* r,
                       const uint8_t* occ, float* z, hipStream_t stream);
 
@@ -149,7 +156,8 @@ vmat_status vmat_dose_fluence(vmat_handle h, const double* x, float* z, hipStrea
 vmat_status vmat_grad_fluence(vmat_handle h, const double* x, double* cost, float* z,
                               float* dFdz, double* g, hipStream_t stream);
 
-/* Raw products, one kernel each (FP32/BF16/FP16 storage; FP8 adds a scaling pass):
+/* Raw products (the adjoint of the tiled layout adds a per-beamlet reduction;
+ * FP8 storage adds a scaling pass to the forward):
  *   vmat_forward:  z = D^T x      x: DEVICE double [nb],  z: DEVICE double [nv]
  *   vmat_adjoint:  g = D w        w: DEVICE float  [nv],  g: DEVICE double [nb]
  * FP64 accumulation; the forward is the dose of eq. 3 for beamlet
@@ -157,7 +165,7 @@ vmat_status vmat_grad_fluence(vmat_handle h, const double* x, double* cost, floa
 vmat_status vmat_forward(vmat_handle h, const double* x, double* z, hipStream_t stream);
 vmat_status vmat_adjoint(vmat_handle h, const float* w, double* g, hipStream_t stream);
 
-/* Plan variants sharing one D (many right-hand sides, one launch per product).
+/* Plan variants sharing one D (many right-hand sides, one SpMM per product).
  * The variants differ in the voxel weights and thresholds of eq. 1; the dose
  * of eq. 3 and the beamlet prices of Sec. 2.2 are the same linear maps applied
  * to B columns at once.  RHS-contiguous layout: element (row, b) at row*B + b.
