@@ -14,6 +14,7 @@
 namespace vmat {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
@@ -98,11 +99,14 @@ template <> struct Quad<FMT_F16> {
     }
 };
 
+// The hardware conversion (two codes per instruction) gives the same bits as
+// e4m3_to_f32 on every finite code; stored codes never exceed 0x7E.
 template <> struct Quad<FMT_FP8> {
     __device__ __forceinline__ static float4 load(const void* base, int64_t q) {
-        uint32_t u = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base) + q);
-        return make_float4(e4m3_to_f32(u & 0xFF), e4m3_to_f32((u >> 8) & 0xFF),
-                           e4m3_to_f32((u >> 16) & 0xFF), e4m3_to_f32(u >> 24));
+        const uint32_t u = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base) + q);
+        const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)u, false);
+        const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)u, true);
+        return make_float4(lo.x, lo.y, hi.x, hi.y);
     }
 };
 

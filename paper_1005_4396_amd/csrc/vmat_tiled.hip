@@ -321,9 +321,15 @@ static vmat_status adj_fmt(const vmat_ctx* h, const float* w, double* g, Gate ga
     const Tiled& t = h->tl;
     static const bool acsr = getenv("VMAT_ADJ_CSR") != nullptr;
     if (t.n_awork > 0 && t.as_val && !acsr) {
-        k_adj_sell<FMT, SELL_U><<<(unsigned)t.n_awork, TILE_THREADS, 0, st>>>(t.awork, t.bounds, t.as_off, t.as_len,
-                                                                           t.as_row, t.as_col, t.as_val, w, t.part,
-                                                                           gate);
+        static const int su = getenv("VMAT_SELL_U") ? atoi(getenv("VMAT_SELL_U")) : SELL_U;
+#define ASELL(UU) k_adj_sell<FMT, UU><<<(unsigned)t.n_awork, TILE_THREADS, 0, st>>>( \
+    t.awork, t.bounds, t.as_off, t.as_len, t.as_row, t.as_col, t.as_val, w, t.part, gate)
+        switch (su) {
+            case 2: ASELL(2); break;
+            case 8: ASELL(8); break;
+            default: ASELL(4); break;
+        }
+#undef ASELL
         VMAT_LAUNCH_CHECK();
     } else if (t.n_awork > 0) {
 #define ADJ(GG) k_adj_tiled<FMT, GG, 4><<<(unsigned)t.n_awork, TILE_THREADS, 0, st>>>(t.awork, t.bounds, \
