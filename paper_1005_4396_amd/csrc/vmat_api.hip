@@ -90,20 +90,43 @@ vmat_status check_opts(const vmat_master_opts& o) {
     return VMAT_OK;
 }
 
-vmat_status sync_state(vmat_ctx* h, hipStream_t st) {
-    VMAT_HIP(hipMemcpyAsync(h->ms_host, h->ms, sizeof(MasterState), hipMemcpyDeviceToHost, st));
-    VMAT_HIP(hipStreamSynchronize(st));
+// Snapshot k of the master state: copied after everything enqueued so far
+// into pinned slot k % 2, signalled by event k % 2.
+vmat_status publish_state(vmat_ctx* h, int k, hipStream_t st) {
+    VMAT_HIP(hipMemcpyAsync(h->ms_slot + (k & 1), h->ms, sizeof(MasterState), hipMemcpyDeviceToHost, st));
+    VMAT_HIP(hipEventRecord(h->ms_ev[k & 1], st));
     return VMAT_OK;
 }
 
-// One master solve (Sec. 2.2) on the device; the host only enqueues and reads
-// the done / line-search flags once per iteration.
-// Master solve with separate kernels and one state read per iteration (used
-// with the plain layout).
-// Master solve with separate kernels and one state read per iteration.  The
-// kernels between two reads (step with the dose update, adjoint, gradient
-// with the next direction, its dose product, three line-search evaluations)
-// form one graph.
+vmat_status read_state(vmat_ctx* h, int k) {
+    VMAT_HIP(hipEventSynchronize(h->ms_ev[k & 1]));
+    *h->ms_host = h->ms_slot[k & 1];
+    return VMAT_OK;
+}
+
+// The master iterations after the first direction and its line search: each
+// replay of the captured iteration is enqueued before the host has read the
+// state the previous one left, so the device never waits for the host.  A
+// replay enqueued after the solve has ended, or while a line search is
+// unfinished, does no work beyond the line search (the done flag gates every
+// kernel), so the arithmetic is that of one read per iteration.  The pending
+// replay at exit finds done == 1 and leaves the state as it is.
+template <class It>
+vmat_status master_loop(vmat_ctx* h, int kind, const GraphKey key, It iteration, hipStream_t st) {
+    TRY(publish_state(h, 0, st));
+    for (int k = 0;; ++k) {
+        TRY(run_iteration(h, kind, key, iteration, st));
+        TRY(publish_state(h, k + 1, st));
+        TRY(read_state(h, k));
+        if (h->ms_host->done == 1) break;
+    }
+    return VMAT_OK;
+}
+
+// One master solve (Sec. 2.2) on the device with separate kernels.  The
+// kernels of one iteration (step with the dose update, adjoint, gradient with
+// the next direction, its dose product, three line-search evaluations) form
+// one graph; the host reads the state once per iteration, one behind.
 vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
                              const vmat_master_opts& o, int fresh, hipStream_t st) {
     Gate done;  // open while the solve is not done
@@ -135,16 +158,7 @@ vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, co
     TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, Gate{}, st));
     TRY(launch_master_grad(h, y, occ, fresh ? 1 : 2, st));
     TRY(dir_and_search(st));
-    for (;;) {
-        TRY(sync_state(h, st));
-        if (h->ms_host->done) break;
-        while (!h->ms_host->ls_done) {
-            TRY(launch_ls_chain(h, 4, st));
-            TRY(sync_state(h, st));
-        }
-        TRY(run_iteration(h, G_MASTER_D, key, iteration, st));
-    }
-    return VMAT_OK;
+    return master_loop(h, G_MASTER_D, key, iteration, st);
 }
 
 // The same iterations over the stored aperture doses: the dose of a direction
@@ -178,18 +192,9 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
     TRY(ap_grad(h, h->rz, h->mgF, Gate{}, st));
     TRY(launch_master_grad(h, y, occ, fresh ? 1 : 2, st));
     TRY(dir_and_search(st));
-    for (;;) {
-        TRY(sync_state(h, st));
-        if (h->ms_host->done) break;
-        while (!h->ms_host->ls_done) {
-            TRY(launch_ls_chain(h, 4, st));
-            TRY(sync_state(h, st));
-        }
-        const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)occ, (uint64_t)(uintptr_t)h->ap->view,
-                              gamma_bits(h)};
-        TRY(run_iteration(h, G_MASTER_AP, key, iteration, st));
-    }
-    return VMAT_OK;
+    const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)occ, (uint64_t)(uintptr_t)h->ap->view,
+                          gamma_bits(h)};
+    return master_loop(h, G_MASTER_AP, key, iteration, st);
 }
 
 // fresh == 0: the handle's z, F'(z) and g already belong to y (the column-

@@ -450,6 +450,9 @@ static void free_all(vmat_ctx* h) {
     F(h->ms);
     F(h->ms2);
     if (h->ms_host) (void)hipHostFree(h->ms_host);
+    if (h->ms_slot) (void)hipHostFree(h->ms_slot);
+    for (hipEvent_t& e : h->ms_ev)
+        if (e) (void)hipEventDestroy(e);
     free_tiled(h);
     F(h->row_S); F(h->row_l); F(h->row_r); F(h->row_m); F(h->bprice); F(h->pbeam); F(h->pscore); F(h->cost2);
     F(h->tr.beam); F(h->tr.price); F(h->tr.margin); F(h->tr.row_margin); F(h->tr.cost); F(h->tr.miters);
@@ -551,8 +554,12 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     if ((rc = dalloc(h, &h->mW_prev, N)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->ms, 1)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->ms2, 1)) != VMAT_OK) return bail(rc);
-    if (hipHostMalloc((void**)&h->ms_host, sizeof(MasterState), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void**)&h->ms_host, sizeof(MasterState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->ms_slot, 2 * sizeof(MasterState), hipHostMallocDefault) != hipSuccess)
         return bail(fail(VMAT_ERR_ALLOC, "hipHostMalloc failed"));
+    for (hipEvent_t& e : h->ms_ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(VMAT_ERR_DEVICE, "hipEventCreateWithFlags failed"));
     if ((rc = dalloc(h, &h->row_S, NR)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->row_l, NR)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->row_r, NR)) != VMAT_OK) return bail(rc);

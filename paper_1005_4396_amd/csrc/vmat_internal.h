@@ -116,6 +116,9 @@ struct MasterState {
     double t_max, t_eval, t, lo, hi, p0, h0, p, h, t_star, slope0, curv;
     // master
     double kkt, kkt_ref, tol, F, gG, beta_cg;
+    // done: 0 while iterating, 1 when the solve has ended, 2 while an
+    // iteration waits for its line search (the step found it unfinished: the
+    // kernels of that iteration skip, the line-search evaluations go on)
     int32_t it, max_iter, done, converged;
     int32_t ls_phase, ls_steps, ls_max, ls_done;
     int32_t n_fwd, n_adj, n_ls, have_prev;
@@ -255,6 +258,11 @@ struct vmat_ctx {
     vmat::MasterState* ms = nullptr;      // device
     vmat::MasterState* ms2 = nullptr;     // device, second buffer of the line-search chain
     vmat::MasterState* ms_host = nullptr; // pinned host mirror
+    // two pinned snapshots of the state, each written by a copy enqueued after
+    // an iteration and signalled by its event, so that the host reads one
+    // iteration behind while the next is already queued
+    vmat::MasterState* ms_slot = nullptr;
+    hipEvent_t ms_ev[2] = {nullptr, nullptr};
     // pricing
     double* row_S = nullptr;       // [N*R]
     int32_t* row_l = nullptr;      // [N*R]

@@ -334,7 +334,7 @@ __global__ __launch_bounds__(BLOCK) void k_ls_eval(int64_t nv, const double* __r
                                                    const MasterState* __restrict__ ms, double* __restrict__ part,
                                                    int n_part) {
     __shared__ double sh[4];
-    if (ms->done || ms->ls_done) return;
+    if (ms->done == 1 || ms->ls_done) return;
     const double t = ms->t_eval;
     double p = 0.0, q = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < nv; j += (int64_t)gridDim.x * BLOCK) {
@@ -375,9 +375,9 @@ __global__ __launch_bounds__(BLOCK) void k_ls_fused(int64_t nv, const double* __
     const double hF = consume ? reduce_part(part_in + n_part, n_part, sh) : 0.0;
     if (threadIdx.x == 0) {
         s = *src;
-        if (consume && !(s.done || s.ls_done)) ctrl_ls_step(s, pF, hF);
+        if (consume && !(s.done == 1 || s.ls_done)) ctrl_ls_step(s, pF, hF);
         if (blockIdx.x == 0) *dst = s;
-        run = !(s.done || s.ls_done);
+        run = !(s.done == 1 || s.ls_done);
     }
     __syncthreads();
     if (!run) return;
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(BLOCK) void k_ls_finish(const MasterState* src, Mas
     const double hF = reduce_part(part + n_part, n_part, sh);
     if (threadIdx.x == 0) {
         MasterState s = *src;
-        if (!(s.done || s.ls_done)) ctrl_ls_step(s, pF, hF);
+        if (!(s.done == 1 || s.ls_done)) ctrl_ls_step(s, pF, hF);
         *dst = s;
     }
 }
@@ -426,7 +426,7 @@ vmat_status launch_ls_chain(const vmat_ctx* h, int n, hipStream_t st) {
 // Safeguarded Newton on the piecewise-linear, non-decreasing phi' inside a bracket.
 __global__ __launch_bounds__(BLOCK) void k_ls_ctrl(MasterState* ms, const double* __restrict__ part, int n_part) {
     __shared__ double sh[4];
-    if (ms->done || ms->ls_done) return;
+    if (ms->done == 1 || ms->ls_done) return;
     const double pF = reduce_part(part, n_part, sh);
     const double hF = reduce_part(part + n_part, n_part, sh);
     if (threadIdx.x == 0) ctrl_ls_step(*ms, pF, hF);
@@ -477,14 +477,23 @@ vmat_status launch_update(const vmat_ctx* h, hipStream_t st) {
 
 // The step and the dose update in one launch: block 0 also moves y (and the
 // previous direction, gradient and face) as k_master_step does; the update
-// reads only t* and the dose vectors, which the step does not touch.
+// reads only t* and the dose vectors, which the step does not touch.  An
+// unfinished line search stalls the iteration (done = 2: the kernels after
+// this one skip, the line-search evaluations continue); a finished one
+// releases it.  Every block takes the same decision: done == 1 and ls_done
+// are not written here, and the value block 0 writes is never 1.
 __global__ __launch_bounds__(BLOCK) void k_update_step(MasterPtrs m, int64_t nv, double* __restrict__ z,
                                                        const double* __restrict__ dz,
                                                        const float4* __restrict__ abT, float* __restrict__ rz,
                                                        double* __restrict__ part) {
     __shared__ double sh[4];
-    const MasterState* ms = m.ms;
-    if (ms->done) return;
+    MasterState* ms = m.ms;
+    if (ms->done == 1) return;
+    if (!ms->ls_done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) ms->done = 2;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ms->done = 0;
     const double t = ms->t_star;
     double F = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < nv; j += (int64_t)gridDim.x * BLOCK) {
