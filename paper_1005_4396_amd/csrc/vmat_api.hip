@@ -135,7 +135,7 @@ vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, co
     auto search = [&](hipStream_t s) -> vmat_status {
         TRY(launch_fluence(h, h->md, l, r, occ, h->bm.scale, h->x, done, s));
         TRY(launch_fwd(h, h->x, h->dz, done, s));
-        TRY(launch_ls_chain(h, 3, s));
+        TRY(launch_ls_passes(h, s));
         return VMAT_OK;
     };
     auto dir_and_search = [&](hipStream_t s) -> vmat_status {
@@ -171,7 +171,7 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
     done.mask = 1u;
     auto search = [&](hipStream_t s) -> vmat_status {
         TRY(ap_dose(h, h->md, h->dz, done, s));
-        TRY(launch_ls_chain(h, 3, s));
+        TRY(launch_ls_passes(h, s));
         return VMAT_OK;
     };
     auto dir_and_search = [&](hipStream_t s) -> vmat_status {

@@ -170,6 +170,8 @@ __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi, bool 
     s.t_max = tmax;
     s.ls_phase = 0;
     s.t_eval = 0.0;
+    s.t_eval2 = tmax;
+    s.n_eval = isfinite(tmax) ? 2 : 1;
     s.ls_steps = 0;
     s.ls_done = 0;
     s.n_fwd += 1;
@@ -233,10 +235,85 @@ __device__ inline void ctrl_ls_step(MasterState& s, double pF, double hF) {
     }
 }
 
+// One pass of the exact line search that evaluated phi' and phi'' at one or
+// two points (thread 0); pa, ha (pb, hb): the voxel sums at t_eval (t_eval2),
+// the smoothing part is added here.  The first pass takes t = 0 and the first
+// blocking bound t_max.  phi' is piecewise linear and non-decreasing; the
+// bracket [lo, hi] keeps phi'(lo) <= 0 < phi'(hi) with phi', phi'' at both
+// ends, and each later pass evaluates the Newton points from both ends (a
+// Newton step from an end is exact when no breakpoint of phi' lies between it
+// and the root), or one Newton point and the midpoint, or the midpoint alone,
+// or doubling while no upper end is known.  The stopping tests are those of
+// the one-point search: |phi'| <= 1e-12 |phi'(0)| at an evaluated point, a
+// bracket narrower than 1e-15 hi, or ls_max passes after the first.
+__device__ inline void ctrl_ls_pass(MasterState& s, double pa, double ha, double pb, double hb) {
+    const int ne = s.n_eval;
+    const double tv[2] = {s.t_eval, s.t_eval2};
+    const double pv[2] = {pa + s.slope0 + s.t_eval * s.curv, pb + s.slope0 + s.t_eval2 * s.curv};
+    const double hv[2] = {ha + s.curv, hb + s.curv};
+    s.n_ls += 1;
+    bool fin = false;
+    double ts = 0.0;
+    if (s.ls_phase == 0) {
+        s.p0 = pv[0];
+        s.h0 = hv[0];
+        if (!(pv[0] < 0.0)) {
+            fin = true;
+            ts = 0.0;
+        } else if (ne == 2 && pv[1] <= 0.0) {
+            fin = true;
+            ts = s.t_max;
+        } else {
+            s.lo = 0.0; s.plo = pv[0]; s.hlo = hv[0];
+            if (ne == 2) { s.hi = s.t_max; s.phi = pv[1]; s.hhi = hv[1]; }
+            else { s.hi = INFINITY; s.phi = 0.0; s.hhi = 0.0; }
+            s.ls_phase = 2;
+            s.ls_steps = 0;
+        }
+    } else {
+        s.ls_steps += 1;
+        for (int i = 0; i < ne && !fin; ++i)
+            if (fabs(pv[i]) <= 1e-12 * fabs(s.p0)) { fin = true; ts = tv[i]; }
+        if (!fin) {
+            for (int i = 0; i < ne; ++i) {
+                if (pv[i] <= 0.0) {
+                    if (tv[i] > s.lo) { s.lo = tv[i]; s.plo = pv[i]; s.hlo = hv[i]; }
+                } else if (tv[i] < s.hi) {
+                    s.hi = tv[i]; s.phi = pv[i]; s.hhi = hv[i];
+                }
+            }
+            if (isfinite(s.hi) && s.hi - s.lo <= 1e-15 * s.hi) { fin = true; ts = s.lo; }
+            else if (s.ls_steps >= s.ls_max) { fin = true; ts = s.lo; }
+        }
+    }
+    if (fin) {
+        s.t_star = ts;
+        s.ls_done = 1;
+        s.phase = PH_LS_DONE;
+        return;
+    }
+    s.phase = PH_LS;
+    const bool bounded = isfinite(s.hi);
+    double ta = s.hlo > 0.0 ? s.lo - s.plo / s.hlo : NAN;
+    if (!(s.lo < ta && ta < s.hi)) ta = NAN;
+    double tb = NAN;
+    if (bounded && s.hhi > 0.0) {
+        tb = s.hi - s.phi / s.hhi;
+        if (!(s.lo < tb && tb < s.hi)) tb = NAN;
+    }
+    if (isnan(ta)) { ta = tb; tb = NAN; }
+    const double mid = bounded ? 0.5 * (s.lo + s.hi) : (s.lo > 0.0 ? 2.0 * s.lo : 1.0);
+    if (isnan(ta)) ta = mid;
+    else if (isnan(tb) || tb == ta) tb = bounded ? mid : 2.0 * ta;
+    if (tb == ta) tb = NAN;
+    s.t_eval = ta;
+    s.t_eval2 = isnan(tb) ? 0.0 : tb;
+    s.n_eval = isnan(tb) ? 1 : 2;
+}
+
 // y <- max(0, y + t* d); bounds that block at t* = t_max become exactly 0;
 // the direction, gradient and face become the previous ones.
-__device__ inline void ctrl_step(const MasterPtrs& m) {
-    const double t = m.ms->t_star, tmax = m.ms->t_max;
+__device__ inline void ctrl_step_vec(const MasterPtrs& m, double t, double tmax) {
     for (int k = threadIdx.x; k < m.N; k += CTRL) {
         const double yo = m.y[k], dk = m.d[k];
         double yn = fmax(0.0, yo + t * dk);
@@ -246,6 +323,10 @@ __device__ inline void ctrl_step(const MasterPtrs& m) {
         m.grad_prev[k] = m.grad[k];
         m.W_prev[k] = m.W[k];
     }
+}
+
+__device__ inline void ctrl_step(const MasterPtrs& m) {
+    ctrl_step_vec(m, m.ms->t_star, m.ms->t_max);
     if (threadIdx.x == 0) m.ms->have_prev = 1;
 }
 

@@ -114,6 +114,8 @@ struct Gate {
 struct MasterState {
     // line search
     double t_max, t_eval, t, lo, hi, p0, h0, p, h, t_star, slope0, curv;
+    // two-point passes: second point, and phi', phi'' at the bracket ends
+    double t_eval2, plo, hlo, phi, hhi;
     // master
     double kkt, kkt_ref, tol, F, gG, beta_cg;
     // done: 0 while iterating, 1 when the solve has ended, 2 while an
@@ -124,6 +126,7 @@ struct MasterState {
     int32_t n_fwd, n_adj, n_ls, have_prev;
     int32_t phase;                // pipeline phase of the fused master iteration
     uint32_t cnt_a, cnt_b, cnt_c; // arrival counters of the last-block reductions
+    int32_t n_eval;               // points in the next line-search pass (1 or 2)
 };
 
 // Phases of the fused master iteration: every kernel of an iteration runs only
@@ -239,7 +242,7 @@ struct vmat_ctx {
     double* dz = nullptr;          // [nv] dose of the search direction
     float* rz = nullptr;           // [nv] F'(z) for the adjoint gather
     double* g = nullptr;           // [nb] beamlet prices
-    double* part = nullptr;        // [n_part * 4] block partial sums
+    double* part = nullptr;        // [n_part * 8] block partial sums
     int n_part = 0;
     double* part_b = nullptr;      // [64 * n_part] per-variant partial sums (batched cost)
     int32_t tune_fwd[65] = {};     // tuned RHS tile width of the batched products, by B (0: default)

@@ -70,14 +70,12 @@ vmat_status launch_master_begin(const vmat_ctx* h, double* y, const uint8_t* occ
 vmat_status launch_master_grad(const vmat_ctx* h, const double* y, const uint8_t* occ, int first,
                                hipStream_t st);
 vmat_status launch_master_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, hipStream_t st);
-vmat_status launch_ls_eval(const vmat_ctx* h, hipStream_t st);
-vmat_status launch_ls_ctrl(const vmat_ctx* h, hipStream_t st);
-// n evaluations and their control steps in n + 1 launches (same arithmetic
-// as n alternating launch_ls_eval / launch_ls_ctrl pairs)
-vmat_status launch_ls_chain(const vmat_ctx* h, int n, hipStream_t st);
-vmat_status launch_master_step(const vmat_ctx* h, double* y, hipStream_t st);
-vmat_status launch_update(const vmat_ctx* h, hipStream_t st);
-// launch_master_step + launch_update in one launch
+// a chain of line-search passes, each completing the previous one; the last
+// is completed by launch_step_update
+vmat_status launch_ls_passes(const vmat_ctx* h, hipStream_t st);
+// completes the line search, then the master step (y, previous direction,
+// gradient and face) and the dose update with F'(z) and the partial sums of
+// F, in one launch; stalls the iteration while the line search is unfinished
 vmat_status launch_step_update(const vmat_ctx* h, double* y, hipStream_t st);
 // launch_master_grad(first = 0) + launch_master_dir in one launch
 vmat_status launch_grad_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, hipStream_t st);

@@ -18,6 +18,8 @@
 namespace vmat {
 
 constexpr int BLOCK = 256;
+// line-search passes per master iteration (captured with the iteration)
+constexpr int LS_PASSES = 3;
 
 // ---------------------------------------------------------------- reductions
 
@@ -328,41 +330,59 @@ vmat_status launch_master_dir(const vmat_ctx* h, const double* y, const uint8_t*
     return VMAT_OK;
 }
 
-// phi'(t) and phi''(t) partial sums over voxels at t = t_eval.
-__global__ __launch_bounds__(BLOCK) void k_ls_eval(int64_t nv, const double* __restrict__ z,
-                                                   const double* __restrict__ dz, const float4* __restrict__ abT,
-                                                   const MasterState* __restrict__ ms, double* __restrict__ part,
-                                                   int n_part) {
-    __shared__ double sh[4];
-    if (ms->done == 1 || ms->ls_done) return;
-    const double t = ms->t_eval;
-    double p = 0.0, q = 0.0;
-    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < nv; j += (int64_t)gridDim.x * BLOCK) {
-        const double dzj = dz[j];
-        const Pen pn = penalty_at(z[j] + t * dzj, abT[j]);
-        p += dzj * pn.dF;
-        q += dzj * dzj * pn.curv;
-    }
-    p = block_sum(p, sh);
-    q = block_sum(q, sh);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = p;
-        part[n_part + blockIdx.x] = q;
+// Sums of a[i] over n entries for NA arrays a = part + q n, q < NA, each in
+// the fixed order of reduce_part; valid on thread 0.
+template <int NA>
+__device__ __forceinline__ void reduce_parts(const double* part, int n, double* out, double* sh) {
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+    for (int i = threadIdx.x; i < n; i += BLOCK)
+#pragma unroll
+        for (int q = 0; q < NA; ++q) acc[q] += part[(int64_t)q * n + i];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) out[q] = block_sum(acc[q], sh);
+}
+
+// phi'(t), phi''(t) voxel sums at one or two points.  Each thread's voxels
+// (a grid stride apart) are loaded U at a time before any arithmetic, so a
+// grid of a few hundred blocks keeps enough loads in flight.
+template <int U>
+__device__ __forceinline__ void ls_sums(int64_t nv, const double* __restrict__ z, const double* __restrict__ dz,
+                                        const float4* __restrict__ abT, double ta, double tb, bool two,
+                                        double acc[4]) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t j0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j0 < nv; j0 += U * stride) {
+        double zv[U], dv[U];
+        float4 wv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = j0 + u * stride;
+            const bool in = j < nv;
+            zv[u] = in ? z[j] : 0.0;
+            dv[u] = in ? dz[j] : 0.0;
+            wv[u] = in ? abT[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const Pen a = penalty_at(zv[u] + ta * dv[u], wv[u]);
+            acc[0] += dv[u] * a.dF;
+            acc[1] += dv[u] * dv[u] * a.curv;
+            if (two) {
+                const Pen b = penalty_at(zv[u] + tb * dv[u], wv[u]);
+                acc[2] += dv[u] * b.dF;
+                acc[3] += dv[u] * dv[u] * b.curv;
+            }
+        }
     }
 }
 
-vmat_status launch_ls_eval(const vmat_ctx* h, hipStream_t st) {
-    k_ls_eval<<<h->n_part, BLOCK, 0, st>>>(h->nv, h->z, h->dz, h->abT, h->ms, h->part, h->n_part);
-    VMAT_LAUNCH_CHECK();
-    return VMAT_OK;
-}
-
-// A chain of line-search evaluations in which each evaluation first completes
-// the previous one: every block reduces the previous partial sums in the same
-// fixed order and applies the safeguarded-Newton step to its own copy of the
-// state read from src (identical in all blocks); block 0 writes that state to
-// dst, the other buffer of the pair, so no block reads what another writes.
-// The same arithmetic as alternating evaluation and control launches.
+// A chain of line-search passes in which each pass first completes the
+// previous one: every block reduces the previous partial sums in the same
+// fixed order and takes the control step on its own copy of the state read
+// from src (identical in all blocks); block 0 writes that state to dst, the
+// other buffer of the pair, so no block reads what another writes.  Padding
+// voxels (zero dz, zero weights) add exact zeros.
 __global__ __launch_bounds__(BLOCK) void k_ls_fused(int64_t nv, const double* __restrict__ z,
                                                     const double* __restrict__ dz, const float4* __restrict__ abT,
                                                     const MasterState* __restrict__ src, MasterState* __restrict__ dst,
@@ -371,146 +391,121 @@ __global__ __launch_bounds__(BLOCK) void k_ls_fused(int64_t nv, const double* __
     __shared__ double sh[4];
     __shared__ MasterState s;
     __shared__ int run;
-    const double pF = consume ? reduce_part(part_in, n_part, sh) : 0.0;
-    const double hF = consume ? reduce_part(part_in + n_part, n_part, sh) : 0.0;
+    if (threadIdx.x == 0) s = *src;
+    __syncthreads();
+    const bool active = !(s.done == 1 || s.ls_done);
+    if (consume && active) {
+        double r[4];
+        reduce_parts<4>(part_in, n_part, r, sh);
+        if (threadIdx.x == 0) ctrl_ls_pass(s, r[0], r[1], r[2], r[3]);
+    }
     if (threadIdx.x == 0) {
-        s = *src;
-        if (consume && !(s.done == 1 || s.ls_done)) ctrl_ls_step(s, pF, hF);
         if (blockIdx.x == 0) *dst = s;
         run = !(s.done == 1 || s.ls_done);
     }
     __syncthreads();
     if (!run) return;
-    const double t = s.t_eval;
-    double p = 0.0, q = 0.0;
-    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < nv; j += (int64_t)gridDim.x * BLOCK) {
-        const double dzj = dz[j];
-        const Pen pn = penalty_at(z[j] + t * dzj, abT[j]);
-        p += dzj * pn.dF;
-        q += dzj * dzj * pn.curv;
-    }
-    p = block_sum(p, sh);
-    q = block_sum(q, sh);
-    if (threadIdx.x == 0) {
-        part_out[blockIdx.x] = p;
-        part_out[n_part + blockIdx.x] = q;
-    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    ls_sums<4>(nv, z, dz, abT, s.t_eval, s.t_eval2, s.n_eval == 2, acc);
+    double r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = block_sum(acc[q], sh);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) part_out[(int64_t)q * n_part + blockIdx.x] = r[q];
 }
 
-// Completes the last evaluation of a chain: state src -> dst (may alias).
-__global__ __launch_bounds__(BLOCK) void k_ls_finish(const MasterState* src, MasterState* dst,
-                                                     const double* __restrict__ part, int n_part) {
-    __shared__ double sh[4];
-    const double pF = reduce_part(part, n_part, sh);
-    const double hF = reduce_part(part + n_part, n_part, sh);
-    if (threadIdx.x == 0) {
-        MasterState s = *src;
-        if (!(s.done == 1 || s.ls_done)) ctrl_ls_step(s, pF, hF);
-        *dst = s;
-    }
+// The buffers of pass i of a chain: it reads the state from bufs[(i-1) % 2]
+// and the previous partials from parts[(i-1) % 2], writes bufs[i % 2] and
+// parts[i % 2].  The last pass's sums are consumed by the next step.
+static void ls_buffers(const vmat_ctx* h, MasterState* bufs[2], double* parts[2]) {
+    bufs[0] = h->ms;
+    bufs[1] = h->ms2;
+    parts[0] = h->part;
+    parts[1] = h->part + 4 * (int64_t)h->n_part;
 }
 
-vmat_status launch_ls_chain(const vmat_ctx* h, int n, hipStream_t st) {
-    MasterState* bufs[2] = {h->ms, h->ms2};
-    double* parts[2] = {h->part, h->part + 2 * (int64_t)h->n_part};
-    for (int i = 1; i <= n; ++i) {
+vmat_status launch_ls_passes(const vmat_ctx* h, hipStream_t st) {
+    MasterState* bufs[2];
+    double* parts[2];
+    ls_buffers(h, bufs, parts);
+    for (int i = 1; i <= LS_PASSES; ++i) {
         k_ls_fused<<<h->n_part, BLOCK, 0, st>>>(h->nv, h->z, h->dz, h->abT, bufs[(i - 1) % 2], bufs[i % 2], i > 1,
                                                parts[(i - 1) % 2], parts[i % 2], h->n_part);
         VMAT_LAUNCH_CHECK();
     }
-    k_ls_finish<<<1, BLOCK, 0, st>>>(bufs[n % 2], bufs[0], parts[n % 2], h->n_part);
-    VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
 
-// Safeguarded Newton on the piecewise-linear, non-decreasing phi' inside a bracket.
-__global__ __launch_bounds__(BLOCK) void k_ls_ctrl(MasterState* ms, const double* __restrict__ part, int n_part) {
-    __shared__ double sh[4];
-    if (ms->done == 1 || ms->ls_done) return;
-    const double pF = reduce_part(part, n_part, sh);
-    const double hF = reduce_part(part + n_part, n_part, sh);
-    if (threadIdx.x == 0) ctrl_ls_step(*ms, pF, hF);
-}
-
-vmat_status launch_ls_ctrl(const vmat_ctx* h, hipStream_t st) {
-    k_ls_ctrl<<<1, BLOCK, 0, st>>>(h->ms, h->part, h->n_part);
-    VMAT_LAUNCH_CHECK();
-    return VMAT_OK;
-}
-
-// y <- max(0, y + t* d); bounds that block at t* = t_max become exactly 0.
-__global__ __launch_bounds__(CTRL) void k_master_step(MasterPtrs m) {
-    if (m.ms->done) return;
-    ctrl_step(m);
-}
-
-vmat_status launch_master_step(const vmat_ctx* h, double* y, hipStream_t st) {
-    k_master_step<<<1, CTRL, 0, st>>>(master_ptrs(h, y, nullptr, nullptr, nullptr));
-    VMAT_LAUNCH_CHECK();
-    return VMAT_OK;
-}
-
-// z <- z + t* dz, then F'(z) for the adjoint and the partial sums of F.
-__global__ __launch_bounds__(BLOCK) void k_update(int64_t nv, double* __restrict__ z, const double* __restrict__ dz,
-                                                  const float4* __restrict__ abT, float* __restrict__ rz,
-                                                  const MasterState* __restrict__ ms, double* __restrict__ part) {
-    __shared__ double sh[4];
-    if (ms->done) return;
-    const double t = ms->t_star;
-    double F = 0.0;
-    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < nv; j += (int64_t)gridDim.x * BLOCK) {
-        const double zj = z[j] + t * dz[j];
-        z[j] = zj;
-        const Pen p = penalty_at(zj, abT[j]);
-        F += p.F;
-        rz[j] = (float)p.dF;
-    }
-    F = block_sum(F, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = F;
-}
-
-vmat_status launch_update(const vmat_ctx* h, hipStream_t st) {
-    k_update<<<h->n_part, BLOCK, 0, st>>>(h->nv, h->z, h->dz, h->abT, h->rz, h->ms, h->part);
-    VMAT_LAUNCH_CHECK();
-    return VMAT_OK;
-}
-
-// The step and the dose update in one launch: block 0 also moves y (and the
-// previous direction, gradient and face) as k_master_step does; the update
-// reads only t* and the dose vectors, which the step does not touch.  An
-// unfinished line search stalls the iteration (done = 2: the kernels after
-// this one skip, the line-search evaluations continue); a finished one
-// releases it.  Every block takes the same decision: done == 1 and ls_done
-// are not written here, and the value block 0 writes is never 1.
-__global__ __launch_bounds__(BLOCK) void k_update_step(MasterPtrs m, int64_t nv, double* __restrict__ z,
-                                                       const double* __restrict__ dz,
+// The step and the dose update in one launch, after a chain of line-search
+// passes.  Every block first completes the chain's last pass on its own copy
+// of the state (the same fixed-order reduction and control step in all
+// blocks); block 0 writes the result to the master state.  If the line search
+// is still unfinished the iteration stalls (done = 2: the kernels after this
+// one skip, the next chain continues the search); otherwise the stall is
+// released, block 0 moves y (and the previous direction, gradient and face),
+// and all blocks update the dose, F'(z) and the partial sums of F.
+__global__ __launch_bounds__(BLOCK) void k_update_step(MasterPtrs m, const MasterState* __restrict__ src,
+                                                       const double* __restrict__ part_ls, int64_t nv,
+                                                       double* __restrict__ z, const double* __restrict__ dz,
                                                        const float4* __restrict__ abT, float* __restrict__ rz,
-                                                       double* __restrict__ part) {
+                                                       double* __restrict__ part, int n_part) {
     __shared__ double sh[4];
-    MasterState* ms = m.ms;
-    if (ms->done == 1) return;
-    if (!ms->ls_done) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) ms->done = 2;
-        return;
+    __shared__ MasterState s;
+    if (threadIdx.x == 0) s = *src;
+    __syncthreads();
+    if (s.done != 1 && !s.ls_done) {
+        double r[4];
+        reduce_parts<4>(part_ls, n_part, r, sh);
+        if (threadIdx.x == 0) {
+            ctrl_ls_pass(s, r[0], r[1], r[2], r[3]);
+            if (!s.ls_done) s.done = 2;
+        }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) ms->done = 0;
-    const double t = ms->t_star;
+    if (threadIdx.x == 0 && s.done == 2 && s.ls_done) s.done = 0;
+    if (threadIdx.x == 0 && s.done == 0) s.have_prev = 1;
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) *m.ms = s;
+    if (s.done != 0) return;
+    const double t = s.t_star;
+    if (blockIdx.x == 0) ctrl_step_vec(m, t, s.t_max);
     double F = 0.0;
-    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < nv; j += (int64_t)gridDim.x * BLOCK) {
-        const double zj = z[j] + t * dz[j];
-        z[j] = zj;
-        const Pen p = penalty_at(zj, abT[j]);
-        F += p.F;
-        rz[j] = (float)p.dF;
+    constexpr int U = 4;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t j0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j0 < nv; j0 += U * stride) {
+        double zv[U], dv[U];
+        float4 wv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = j0 + u * stride;
+            const bool in = j < nv;
+            zv[u] = in ? z[j] : 0.0;
+            dv[u] = in ? dz[j] : 0.0;
+            wv[u] = in ? abT[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = j0 + u * stride;
+            const double zj = zv[u] + t * dv[u];
+            const Pen p = penalty_at(zj, wv[u]);
+            if (j < nv) {
+                z[j] = zj;
+                rz[j] = (float)p.dF;
+                F += p.F;
+            }
+        }
     }
     F = block_sum(F, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = F;
-    if (blockIdx.x == 0) ctrl_step(m);
 }
 
 vmat_status launch_step_update(const vmat_ctx* h, double* y, hipStream_t st) {
-    k_update_step<<<h->n_part, BLOCK, 0, st>>>(master_ptrs(h, y, nullptr, nullptr, nullptr), h->nv, h->z, h->dz,
-                                               h->abT, h->rz, h->part);
+    MasterState* bufs[2];
+    double* parts[2];
+    ls_buffers(h, bufs, parts);
+    k_update_step<<<h->n_part, BLOCK, 0, st>>>(master_ptrs(h, y, nullptr, nullptr, nullptr), bufs[LS_PASSES % 2],
+                                               parts[LS_PASSES % 2], h->nv, h->z, h->dz, h->abT, h->rz, h->part,
+                                               h->n_part);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
