@@ -116,6 +116,11 @@ typedef struct vmat_layout_info {
     int64_t slots;          /* (block, beamlet) pairs of the tiled layout                 */
     int64_t fwd_bytes;      /* algorithmic HBM bytes of one vmat_forward                  */
     int64_t adj_bytes;      /* algorithmic HBM bytes of one vmat_adjoint                  */
+    int32_t weight_labels;  /* distinct (alpha, beta, T) held as one-byte voxel labels    */
+                            /* for the master's voxel passes (at most 256); 0: per-voxel  */
+                            /* weights (more than 256 distinct, or VMAT_NO_WEIGHT_LABELS  */
+                            /* set in the environment at vmat_create)                     */
+    int32_t reserved;
 } vmat_layout_info;
 vmat_status vmat_layout(vmat_handle h, vmat_layout_info* out);
 

@@ -318,6 +318,7 @@ extern "C" vmat_status vmat_layout(vmat_handle h, vmat_layout_info* out) {
     const int64_t nb = h->nb, nv = h->nv, sc = h->d_store == VMAT_FP8_E4M3 ? 4 * nb : 0;
     vmat_layout_info L = {};
     L.tiled = h->tl.on ? 1 : 0;
+    L.weight_labels = h->n_wtab;
     L.fwd_entries = h->vm.n_quads * 4;
     if (h->tl.on) {
         const Tiled& t = h->tl;

@@ -6,10 +6,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "vmat_formats.h"
 #include "vmat_internal.h"
@@ -445,7 +447,7 @@ static void free_all(vmat_ctx* h) {
     F(h->d_theta);
     F(h->bm.qptr); F(h->bm.col); F(h->bm.val); F(h->bm.scale);
     F(h->vm.qptr); F(h->vm.col); F(h->vm.val); F(h->vm.scale);
-    F(h->abT); F(h->x); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->part); F(h->part_b);
+    F(h->abT); F(h->wlab); F(h->wtab); F(h->x); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->part); F(h->part_b);
     F(h->my); F(h->mgrad); F(h->mgrad_prev); F(h->md); F(h->md_prev); F(h->mgF); F(h->mW); F(h->mW_prev);
     F(h->ms);
     F(h->ms2);
@@ -456,6 +458,45 @@ static void free_all(vmat_ctx* h) {
     free_tiled(h);
     F(h->row_S); F(h->row_l); F(h->row_r); F(h->row_m); F(h->bprice); F(h->pbeam); F(h->pscore); F(h->cost2);
     F(h->tr.beam); F(h->tr.price); F(h->tr.margin); F(h->tr.row_margin); F(h->tr.cost); F(h->tr.miters);
+}
+
+// Labels of the voxel weights: the distinct (alpha, beta, T) triples, compared
+// bit for bit, in order of first appearance.  More than 256 of them: no labels
+// (the kernels read abT).  VMAT_NO_WEIGHT_LABELS in the environment at
+// creation also keeps abT only.
+static vmat_status build_weight_labels(vmat_ctx* h, hipStream_t st) {
+    if (getenv("VMAT_NO_WEIGHT_LABELS")) return VMAT_OK;
+    const int64_t nv = h->nv;
+    std::vector<float4> w((size_t)nv);
+    if (hipMemcpyAsync(w.data(), h->abT, (size_t)nv * sizeof(float4), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(VMAT_ERR_DEVICE, "copy of the voxel weights failed");
+    auto same = [](const float4& a, const float4& b) { return std::memcmp(&a, &b, 3 * sizeof(float)) == 0; };
+    std::vector<float4> tab;
+    std::vector<uint8_t> lab((size_t)nv);
+    int last = -1;
+    for (int64_t j = 0; j < nv; ++j) {
+        if (last < 0 || !same(w[j], tab[last])) {
+            last = -1;
+            for (int q = 0; q < (int)tab.size(); ++q)
+                if (same(w[j], tab[q])) { last = q; break; }
+            if (last < 0) {
+                if (tab.size() == 256) return VMAT_OK;
+                tab.push_back(make_float4(w[j].x, w[j].y, w[j].z, 0.0f));
+                last = (int)tab.size() - 1;
+            }
+        }
+        lab[j] = (uint8_t)last;
+    }
+    vmat_status rc;
+    if ((rc = dalloc(h, &h->wlab, nv)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->wtab, (int64_t)tab.size())) != VMAT_OK) return rc;
+    if (hipMemcpyAsync(h->wlab, lab.data(), (size_t)nv, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h->wtab, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(VMAT_ERR_DEVICE, "upload of the weight labels failed");
+    h->n_wtab = (int)tab.size();
+    return VMAT_OK;
 }
 
 }  // namespace vmat
@@ -526,6 +567,7 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
         if (flag & BAD_T) m += " T";
         return bail(fail(VMAT_ERR_INVALID_ARG, m));
     }
+    if ((rc = build_weight_labels(h, st)) != VMAT_OK) return bail(rc);
     switch (h->d_store) {
         case VMAT_F32: rc = build_layouts<FMT_F32>(h, p, st, dflag); break;
         case VMAT_F16: rc = build_layouts<FMT_F16>(h, p, st, dflag); break;

@@ -235,6 +235,12 @@ struct vmat_ctx {
     vmat::Tiled tl;                // tiled forms of both (used when tl.on)
     int32_t layout_req = 0;
     float4* abT = nullptr;         // [nv] (alpha, beta, T, 0)
+    // the same weights as a one-byte label per voxel into a table of the
+    // distinct (alpha, beta, T), kept when there are at most 256 of them (one
+    // per structure in the usual case); n_wtab == 0: none
+    uint8_t* wlab = nullptr;       // [nv]
+    float4* wtab = nullptr;        // [n_wtab]
+    int n_wtab = 0;
 
     // work buffers
     double* x = nullptr;           // [nb] fluence

@@ -344,34 +344,66 @@ __device__ __forceinline__ void reduce_parts(const double* part, int n, double* 
     for (int q = 0; q < NA; ++q) out[q] = block_sum(acc[q], sh);
 }
 
-// phi'(t), phi''(t) voxel sums at one or two points.  Each thread's voxels
-// (a grid stride apart) are loaded U at a time before any arithmetic, so a
-// grid of a few hundred blocks keeps enough loads in flight.
-template <int U>
-__device__ __forceinline__ void ls_sums(int64_t nv, const double* __restrict__ z, const double* __restrict__ dz,
-                                        const float4* __restrict__ abT, double ta, double tb, bool two,
-                                        double acc[4]) {
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t j0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j0 < nv; j0 += U * stride) {
-        double zv[U], dv[U];
-        float4 wv[U];
+// Penalty weights of the voxels: abT per voxel, or (LAB) a one-byte label per
+// voxel into a table staged in LDS.  Both give the same float4.
+struct VoxW {
+    const float4* abT;
+    const uint8_t* lab;
+    const float4* tab;
+    int n_tab;
+};
+
+inline VoxW voxw(const vmat_ctx* h) { return VoxW{h->abT, h->wlab, h->wtab, h->n_wtab}; }
+
+template <bool LAB>
+__device__ __forceinline__ void stage_tab(const VoxW& vw, float4* stab) {
+    if (LAB)
+        for (int i = threadIdx.x; i < vw.n_tab; i += BLOCK) stab[i] = vw.tab[i];
+}
+
+// U voxels a grid stride apart, loaded before any arithmetic so that a grid
+// of a few hundred blocks keeps enough loads in flight.  Voxels past nv read
+// as z = dz = 0 with finite weights and add exact zeros.
+template <int U, bool LAB>
+struct VoxLoad {
+    double z[U], dz[U];
+    float4 w[U];
+    __device__ __forceinline__ void load(int64_t j0, int64_t stride, int64_t nv, const double* __restrict__ zp,
+                                         const double* __restrict__ dzp, const VoxW& vw, const float4* stab) {
+        uint32_t lv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t j = j0 + u * stride;
             const bool in = j < nv;
-            zv[u] = in ? z[j] : 0.0;
-            dv[u] = in ? dz[j] : 0.0;
-            wv[u] = in ? abT[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            z[u] = in ? zp[j] : 0.0;
+            dz[u] = in ? dzp[j] : 0.0;
+            if (LAB) lv[u] = in ? vw.lab[j] : 0u;
+            else w[u] = in ? vw.abT[j] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
+        if (LAB)
+#pragma unroll
+            for (int u = 0; u < U; ++u) w[u] = stab[lv[u]];
+    }
+};
+
+// phi'(t), phi''(t) voxel sums at one or two points.
+template <int U, bool LAB>
+__device__ __forceinline__ void ls_sums(int64_t nv, const double* __restrict__ z, const double* __restrict__ dz,
+                                        const VoxW& vw, const float4* stab, double ta, double tb, bool two,
+                                        double acc[4]) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t j0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j0 < nv; j0 += U * stride) {
+        VoxLoad<U, LAB> v;
+        v.load(j0, stride, nv, z, dz, vw, stab);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const Pen a = penalty_at(zv[u] + ta * dv[u], wv[u]);
-            acc[0] += dv[u] * a.dF;
-            acc[1] += dv[u] * dv[u] * a.curv;
+            const Pen a = penalty_at(v.z[u] + ta * v.dz[u], v.w[u]);
+            acc[0] += v.dz[u] * a.dF;
+            acc[1] += v.dz[u] * v.dz[u] * a.curv;
             if (two) {
-                const Pen b = penalty_at(zv[u] + tb * dv[u], wv[u]);
-                acc[2] += dv[u] * b.dF;
-                acc[3] += dv[u] * dv[u] * b.curv;
+                const Pen b = penalty_at(v.z[u] + tb * v.dz[u], v.w[u]);
+                acc[2] += v.dz[u] * b.dF;
+                acc[3] += v.dz[u] * v.dz[u] * b.curv;
             }
         }
     }
@@ -383,15 +415,18 @@ __device__ __forceinline__ void ls_sums(int64_t nv, const double* __restrict__ z
 // from src (identical in all blocks); block 0 writes that state to dst, the
 // other buffer of the pair, so no block reads what another writes.  Padding
 // voxels (zero dz, zero weights) add exact zeros.
+template <bool LAB>
 __global__ __launch_bounds__(BLOCK) void k_ls_fused(int64_t nv, const double* __restrict__ z,
-                                                    const double* __restrict__ dz, const float4* __restrict__ abT,
+                                                    const double* __restrict__ dz, VoxW vw,
                                                     const MasterState* __restrict__ src, MasterState* __restrict__ dst,
                                                     int consume, const double* __restrict__ part_in,
                                                     double* __restrict__ part_out, int n_part) {
     __shared__ double sh[4];
     __shared__ MasterState s;
     __shared__ int run;
+    __shared__ float4 stab[LAB ? 256 : 1];
     if (threadIdx.x == 0) s = *src;
+    stage_tab<LAB>(vw, stab);
     __syncthreads();
     const bool active = !(s.done == 1 || s.ls_done);
     if (consume && active) {
@@ -406,7 +441,7 @@ __global__ __launch_bounds__(BLOCK) void k_ls_fused(int64_t nv, const double* __
     __syncthreads();
     if (!run) return;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    ls_sums<4>(nv, z, dz, abT, s.t_eval, s.t_eval2, s.n_eval == 2, acc);
+    ls_sums<4, LAB>(nv, z, dz, vw, stab, s.t_eval, s.t_eval2, s.n_eval == 2, acc);
     double r[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) r[q] = block_sum(acc[q], sh);
@@ -429,9 +464,14 @@ vmat_status launch_ls_passes(const vmat_ctx* h, hipStream_t st) {
     MasterState* bufs[2];
     double* parts[2];
     ls_buffers(h, bufs, parts);
+    const VoxW vw = voxw(h);
     for (int i = 1; i <= LS_PASSES; ++i) {
-        k_ls_fused<<<h->n_part, BLOCK, 0, st>>>(h->nv, h->z, h->dz, h->abT, bufs[(i - 1) % 2], bufs[i % 2], i > 1,
-                                               parts[(i - 1) % 2], parts[i % 2], h->n_part);
+        if (vw.n_tab > 0)
+            k_ls_fused<true><<<h->n_part, BLOCK, 0, st>>>(h->nv, h->z, h->dz, vw, bufs[(i - 1) % 2], bufs[i % 2],
+                                                         i > 1, parts[(i - 1) % 2], parts[i % 2], h->n_part);
+        else
+            k_ls_fused<false><<<h->n_part, BLOCK, 0, st>>>(h->nv, h->z, h->dz, vw, bufs[(i - 1) % 2], bufs[i % 2],
+                                                          i > 1, parts[(i - 1) % 2], parts[i % 2], h->n_part);
         VMAT_LAUNCH_CHECK();
     }
     return VMAT_OK;
@@ -445,14 +485,17 @@ vmat_status launch_ls_passes(const vmat_ctx* h, hipStream_t st) {
 // one skip, the next chain continues the search); otherwise the stall is
 // released, block 0 moves y (and the previous direction, gradient and face),
 // and all blocks update the dose, F'(z) and the partial sums of F.
+template <bool LAB>
 __global__ __launch_bounds__(BLOCK) void k_update_step(MasterPtrs m, const MasterState* __restrict__ src,
                                                        const double* __restrict__ part_ls, int64_t nv,
                                                        double* __restrict__ z, const double* __restrict__ dz,
-                                                       const float4* __restrict__ abT, float* __restrict__ rz,
-                                                       double* __restrict__ part, int n_part) {
+                                                       VoxW vw, float* __restrict__ rz, double* __restrict__ part,
+                                                       int n_part) {
     __shared__ double sh[4];
     __shared__ MasterState s;
+    __shared__ float4 stab[LAB ? 256 : 1];
     if (threadIdx.x == 0) s = *src;
+    stage_tab<LAB>(vw, stab);
     __syncthreads();
     if (s.done != 1 && !s.ls_done) {
         double r[4];
@@ -473,21 +516,13 @@ __global__ __launch_bounds__(BLOCK) void k_update_step(MasterPtrs m, const Maste
     constexpr int U = 4;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t j0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j0 < nv; j0 += U * stride) {
-        double zv[U], dv[U];
-        float4 wv[U];
+        VoxLoad<U, LAB> v;
+        v.load(j0, stride, nv, z, dz, vw, stab);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t j = j0 + u * stride;
-            const bool in = j < nv;
-            zv[u] = in ? z[j] : 0.0;
-            dv[u] = in ? dz[j] : 0.0;
-            wv[u] = in ? abT[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t j = j0 + u * stride;
-            const double zj = zv[u] + t * dv[u];
-            const Pen p = penalty_at(zj, wv[u]);
+            const double zj = v.z[u] + t * v.dz[u];
+            const Pen p = penalty_at(zj, v.w[u]);
             if (j < nv) {
                 z[j] = zj;
                 rz[j] = (float)p.dF;
@@ -503,9 +538,14 @@ vmat_status launch_step_update(const vmat_ctx* h, double* y, hipStream_t st) {
     MasterState* bufs[2];
     double* parts[2];
     ls_buffers(h, bufs, parts);
-    k_update_step<<<h->n_part, BLOCK, 0, st>>>(master_ptrs(h, y, nullptr, nullptr, nullptr), bufs[LS_PASSES % 2],
-                                               parts[LS_PASSES % 2], h->nv, h->z, h->dz, h->abT, h->rz, h->part,
-                                               h->n_part);
+    const VoxW vw = voxw(h);
+    const MasterPtrs m = master_ptrs(h, y, nullptr, nullptr, nullptr);
+    if (vw.n_tab > 0)
+        k_update_step<true><<<h->n_part, BLOCK, 0, st>>>(m, bufs[LS_PASSES % 2], parts[LS_PASSES % 2], h->nv, h->z,
+                                                        h->dz, vw, h->rz, h->part, h->n_part);
+    else
+        k_update_step<false><<<h->n_part, BLOCK, 0, st>>>(m, bufs[LS_PASSES % 2], parts[LS_PASSES % 2], h->nv, h->z,
+                                                         h->dz, vw, h->rz, h->part, h->n_part);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }

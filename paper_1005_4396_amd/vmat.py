@@ -45,7 +45,8 @@ class _Problem(ctypes.Structure):
 class LayoutInfo(ctypes.Structure):
     _fields_ = [("tiled", ctypes.c_int32), ("n_blocks", ctypes.c_int32), ("fwd_lanes", ctypes.c_int32),
                 ("adj_lanes", ctypes.c_int32), ("fwd_entries", ctypes.c_int64), ("adj_entries", ctypes.c_int64),
-                ("slots", ctypes.c_int64), ("fwd_bytes", ctypes.c_int64), ("adj_bytes", ctypes.c_int64)]
+                ("slots", ctypes.c_int64), ("fwd_bytes", ctypes.c_int64), ("adj_bytes", ctypes.c_int64),
+                ("weight_labels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class MasterOpts(ctypes.Structure):
@@ -225,7 +226,7 @@ class Problem:
     def layout(self) -> dict:
         info = LayoutInfo()
         _check(lib().vmat_layout(self._h, ctypes.byref(info)))
-        return {k: getattr(info, k) for k, _ in LayoutInfo._fields_}
+        return {k: getattr(info, k) for k, _ in LayoutInfo._fields_ if k != "reserved"}
 
     # ------------------------------------------------------------ helpers
     def empty_plan(self):
