@@ -142,11 +142,11 @@ vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, co
         TRY(launch_master_dir(h, y, occ, s));
         return search(s);
     };
+    const int Q = beam_parts(h);
     auto iteration = [&](hipStream_t s) -> vmat_status {
         TRY(launch_step_update(h, y, s));
-        TRY(launch_adj(h, h->rz, h->g, done, s));
-        TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, done, s));
-        TRY(launch_grad_dir(h, y, occ, s));
+        TRY(launch_adj_beams(h, h->rz, h->g, l, r, occ, Q > 0 ? h->bpart : h->mgF, done, s));
+        TRY(launch_grad_dir(h, y, occ, h->bpart, Q, s));
         return search(s);
     };
     const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)l, (uint64_t)(uintptr_t)r,
@@ -183,7 +183,7 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
     auto iteration = [&](hipStream_t s) -> vmat_status {
         TRY(launch_step_update(h, y, s));
         TRY(ap_grad(h, h->rz, h->mgF, done, s));
-        TRY(launch_grad_dir(h, y, occ, s));
+        TRY(launch_grad_dir(h, y, occ, nullptr, 0, s));
         return search(s);
     };
     TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, fresh, st));

@@ -447,7 +447,7 @@ static void free_all(vmat_ctx* h) {
     F(h->d_theta);
     F(h->bm.qptr); F(h->bm.col); F(h->bm.val); F(h->bm.scale);
     F(h->vm.qptr); F(h->vm.col); F(h->vm.val); F(h->vm.scale);
-    F(h->abT); F(h->wlab); F(h->wtab); F(h->x); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->part); F(h->part_b);
+    F(h->abT); F(h->wlab); F(h->wtab); F(h->x); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->bpart); F(h->part); F(h->part_b);
     F(h->my); F(h->mgrad); F(h->mgrad_prev); F(h->md); F(h->md_prev); F(h->mgF); F(h->mW); F(h->mW_prev);
     F(h->ms);
     F(h->ms2);
@@ -587,6 +587,7 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     if ((rc = dalloc(h, &h->dz, h->nv)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->rz, h->nv)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->g, h->nb)) != VMAT_OK) return bail(rc);
+    if ((rc = dalloc(h, &h->bpart, (size_t)N * ((h->R * h->C + 255) / 256))) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->part, (size_t)h->n_part * 8)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->part_b, (size_t)h->n_part * 64)) != VMAT_OK) return bail(rc);
     double** vecs[] = {&h->my, &h->mgrad, &h->mgrad_prev, &h->md, &h->md_prev, &h->mgF};

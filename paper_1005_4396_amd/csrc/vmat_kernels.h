@@ -27,6 +27,14 @@ vmat_status launch_fwd(const vmat_ctx* h, const double* x, double* out, Gate gat
 vmat_status launch_adj(const vmat_ctx* h, const float* w, double* g, Gate gate, hipStream_t st);
 // Tiled adjoint up to the slot sums (h->tl.part).
 vmat_status launch_adj_slots(const vmat_ctx* h, const float* w, Gate gate, hipStream_t st);
+// Partial beam sums per beam in the tiled layout (0: the plain layout, where
+// the beam sums are whole).
+int beam_parts(const vmat_ctx* h);
+// launch_adj followed by the sums of g over the exposed beamlets of each
+// occupied beam: bpart[N * max(1, beam_parts(h))], beam k's parts at
+// k * beam_parts(h) (the whole sums at k when beam_parts(h) == 0)
+vmat_status launch_adj_beams(const vmat_ctx* h, const float* w, double* g, const int32_t* l, const int32_t* r,
+                             const uint8_t* occ, double* bpart, Gate gate, hipStream_t st);
 vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st);
 // Fused master solve over the tiled layout (see vmat_master.hip).
 vmat_status run_master_fused(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
@@ -78,7 +86,9 @@ vmat_status launch_ls_passes(const vmat_ctx* h, hipStream_t st);
 // F, in one launch; stalls the iteration while the line search is unfinished
 vmat_status launch_step_update(const vmat_ctx* h, double* y, hipStream_t st);
 // launch_master_grad(first = 0) + launch_master_dir in one launch
-vmat_status launch_grad_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, hipStream_t st);
+// bpart, Q: the beam gradient in parts (launch_adj_beams); Q == 0: gF is whole
+vmat_status launch_grad_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, const double* bpart, int Q,
+                            hipStream_t st);
 
 // max over eq. 2 pairs of |y_b - y_a| / (theta_b - theta_a) -> out[0]; G(y) -> out[1]
 vmat_status launch_max_rate(const vmat_ctx* h, const double* y, double* out, hipStream_t st);

@@ -552,19 +552,31 @@ vmat_status launch_step_update(const vmat_ctx* h, double* y, hipStream_t st) {
 
 // Gradient after a step, then the KKT test and the next direction, in one
 // single-block launch (k_master_grad followed by k_master_dir).
-__global__ __launch_bounds__(CTRL) void k_grad_dir(MasterPtrs m, const double* __restrict__ part, int n_part) {
+// bpart (nullable): the beam gradient in Q parts per beam (gF_k = sum of
+// bpart[k*Q .. k*Q+Q-1] in order), written to gF first.
+__global__ __launch_bounds__(CTRL) void k_grad_dir(MasterPtrs m, const double* __restrict__ part, int n_part,
+                                                   const double* __restrict__ bpart, int Q) {
     __shared__ double sh[4];
     __shared__ int shi[4];
     if (m.ms->done) return;
+    if (bpart) {
+        for (int k = threadIdx.x; k < m.N; k += CTRL) {
+            double s = 0.0;
+            for (int q = 0; q < Q; ++q) s += bpart[(int64_t)k * Q + q];
+            m.gF[k] = s;
+        }
+        __syncthreads();
+    }
     const double F = reduce_part(part, n_part, sh);
     ctrl_grad(m, F, 0, sh);
     __syncthreads();
     ctrl_dir(m, sh, shi);
 }
 
-vmat_status launch_grad_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, hipStream_t st) {
+vmat_status launch_grad_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, const double* bpart, int Q,
+                            hipStream_t st) {
     k_grad_dir<<<1, CTRL, 0, st>>>(master_ptrs(h, const_cast<double*>(y), occ, nullptr, nullptr), h->part,
-                                   h->n_part);
+                                   h->n_part, Q > 0 ? bpart : nullptr, Q);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }

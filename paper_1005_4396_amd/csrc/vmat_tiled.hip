@@ -279,6 +279,39 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int64_t nb, const uint32_t* 
     g[i] = scale ? s * (double)scale[i] : s;
 }
 
+// g as k_adj_reduce, and the sum of g over the exposed beamlets of each
+// occupied beam in parts: block (k, q) takes the beamlets q*256 .. q*256+255
+// of beam k and writes its block sum (fixed tree) to bpart[k*Q + q].
+__global__ __launch_bounds__(256) void k_adj_reduce_beams(int R, int C, int Q, const uint32_t* __restrict__ red_ptr,
+                                                          const uint32_t* __restrict__ red_slot,
+                                                          const double* __restrict__ part,
+                                                          const float* __restrict__ scale, double* __restrict__ g,
+                                                          const int32_t* __restrict__ l, const int32_t* __restrict__ r,
+                                                          const uint8_t* __restrict__ occ, double* __restrict__ bpart,
+                                                          Gate gate) {
+    __shared__ double sh[4];
+    if (gate.closed()) return;
+    const int k = blockIdx.x / Q, q = blockIdx.x - k * Q;
+    const int RC = R * C;
+    const int e = q * 256 + threadIdx.x;
+    double ex = 0.0;
+    if (e < RC) {
+        const int64_t i = (int64_t)k * RC + e;
+        double s = 0.0;
+        for (uint32_t p = red_ptr[i]; p < red_ptr[i + 1]; ++p) s += part[red_slot[p]];
+        const double gi = scale ? s * (double)scale[i] : s;
+        g[i] = gi;
+        const int rho = e / C, c = e - rho * C;
+        const int64_t kr = (int64_t)k * R + rho;
+        if (occ[k] && c >= l[kr] && c < r[kr]) ex = gi;
+    }
+    double v = ex;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) bpart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
 // ---------------------------------------------------------------- launchers
 
 template <int FMT>
@@ -369,6 +402,24 @@ vmat_status launch_adj_slots(const vmat_ctx* h, const float* w, Gate gate, hipSt
         case VMAT_BF16: return adj_fmt<FMT_BF16>(h, w, nullptr, gate, st, true);
         default: return adj_fmt<FMT_FP8>(h, w, nullptr, gate, st, true);
     }
+}
+
+int beam_parts(const vmat_ctx* h) { return h->tl.on ? (h->R * h->C + 255) / 256 : 0; }
+
+vmat_status launch_adj_beams(const vmat_ctx* h, const float* w, double* g, const int32_t* l, const int32_t* r,
+                             const uint8_t* occ, double* bpart, Gate gate, hipStream_t st) {
+    const int Q = beam_parts(h);
+    vmat_status rc;
+    if (Q == 0) {
+        if ((rc = launch_adj(h, w, g, gate, st)) != VMAT_OK) return rc;
+        return launch_beam_sums(h, g, l, r, occ, bpart, gate, st);
+    }
+    if ((rc = launch_adj_slots(h, w, gate, st)) != VMAT_OK) return rc;
+    const Tiled& t = h->tl;
+    k_adj_reduce_beams<<<(unsigned)(h->N * Q), 256, 0, st>>>(h->R, h->C, Q, t.red_ptr, t.red_slot, t.part,
+                                                              h->bm.scale, g, l, r, occ, bpart, gate);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
 }
 
 vmat_status launch_adj(const vmat_ctx* h, const float* w, double* g, Gate gate, hipStream_t st) {
