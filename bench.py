@@ -175,7 +175,15 @@ def main():
     big2 = torch.empty_like(big)
     cp_ms = time_kernel(lambda: big2.copy_(big), 20, torch)
     copy_gbs = 2 * big.numel() * 4 / cp_ms / 1e6
-    del big, big2
+    # streaming-read ceiling (context): 1 GiB read by the library's read kernel
+    del big2
+    big = torch.empty(1024 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    big.zero_()
+    rs_part = torch.empty(8192, dtype=torch.float32, device="cuda")
+    rd_ms = time_kernel(lambda: P.vmat.read_stream(big, rs_part, 8192), 20, torch)
+    read_gbs = big.numel() * 4 / rd_ms / 1e6
+    del big, rs_part
+    log(f"[bench] device copy {copy_gbs:.0f} GB/s, streaming read {read_gbs:.0f} GB/s")
 
     out = {
         "metric": METRIC,
@@ -208,7 +216,9 @@ def main():
                      "adjoint_ms": round(adj_ms, 5), "adjoint_GBs": round(adj_gbs, 1), "adjoint_bytes": adj_b,
                      "nnz_per_s_fwd": round(case.nnz / fwd_ms / 1e6, 1), "nnz_per_s_adj": round(case.nnz / adj_ms / 1e6, 1),
                      "csr_fp32_equiv_GBs_fwd": round(8 * case.nnz / fwd_ms / 1e6, 1),
-                     "device_copy_GBs": round(copy_gbs, 1), "layout": lay},
+                     "device_copy_GBs": round(copy_gbs, 1), "read_stream_GBs": round(read_gbs, 1),
+                     "fwd_frac_of_read_stream": round(fwd_gbs / read_gbs, 3),
+                     "adj_frac_of_read_stream": round(adj_gbs / read_gbs, 3), "layout": lay},
     }
 
     if not args.no_precision and args.d_store == "f32":

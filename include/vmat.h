@@ -345,6 +345,14 @@ vmat_status vmat_solve_batched(vmat_handle h, const vmat_solve_opts* opts, int32
                                uint8_t* occ, double* y, vmat_solve_report* rep,
                                vmat_solve_trace* trace, int64_t* n_spmm, hipStream_t stream);
 
+/* Measurement aid, not a step of the method: one streaming read of a device
+ * buffer (non-temporal 16-byte loads, eight in flight per lane), timed by the
+ * caller as the practical HBM read ceiling beside the products' rates.
+ * buf: DEVICE [bytes], bytes a positive multiple of 16; partials: DEVICE
+ * float [grid] (out: per-block sums that keep the loads live); grid in
+ * [1, 65536] blocks of 256 lanes.  Asynchronous; allocates nothing.        */
+vmat_status vmat_read_stream(const void* buf, int64_t bytes, float* partials, int32_t grid, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -120,6 +120,7 @@ def lib():
             "vmat_tune_batched": [P, I32, P, P, P, P, I32, P, P, P],
             "vmat_set_batched_tile": [P, I32, I32, I32],
             "vmat_reserve_batched": [P, I32],
+            "vmat_read_stream": [P, ctypes.c_int64, P, I32, P],
             "vmat_enforce_rate": [P, ctypes.POINTER(RateOpts), P, P, P, P, ctypes.POINTER(RateReport), P],
             "vmat_solve_batched": [P, ctypes.POINTER(SolveOpts), I32, I32, P, P, P, P, P, P,
                                    ctypes.POINTER(SolveReport), ctypes.POINTER(SolveTrace), P, P],
@@ -154,6 +155,13 @@ def _ptr(t):
 def _stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def read_stream(buf, partials, grid: int) -> None:
+    """One streaming read of the device tensor buf (a measurement aid: the
+    HBM read ceiling); partials: float32 device tensor of at least grid."""
+    assert partials.numel() >= grid and partials.dtype.itemsize == 4
+    _check(lib().vmat_read_stream(_ptr(buf), buf.numel() * buf.element_size(), _ptr(partials), grid, _stream()))
 
 
 def master_opts(max_iter=200, ls_max_steps=50, tol_rel=1e-5, kkt_ref=0.0) -> MasterOpts:
