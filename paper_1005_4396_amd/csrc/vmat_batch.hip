@@ -476,7 +476,9 @@ __global__ __launch_bounds__(BT) void k_bfluence(int64_t nb, int N, int R, int C
 struct VarTables {
     float tb[64 * 16 * 3];
     double t[64];
+    double t2[64];
     int on[64];
+    int two[64];
     double sh[BT];
     double sh2[BT];
 };
@@ -503,32 +505,46 @@ __device__ __forceinline__ void variant_sums(VarTables& S_, int B, double a, dou
     }
 }
 
-// phi'(t_b) and phi''(t_b) voxel sums along dZ for every variant still searching.
+// phi' and phi'' voxel sums along dZ at each searching variant's one or two
+// line-search points (t_eval, and t_eval2 when n_eval == 2): one pass over
+// the variants' doses serves both points.
 __global__ __launch_bounds__(BT) void k_bls_eval(int64_t nv, int B, int S, const uint8_t* __restrict__ label,
                                                  const float* __restrict__ table, const double* __restrict__ Z,
                                                  const double* __restrict__ dZ, const MasterState* __restrict__ ms,
-                                                 double* __restrict__ pp, double* __restrict__ qq) {
+                                                 double* __restrict__ pp, double* __restrict__ qq,
+                                                 double* __restrict__ pp2, double* __restrict__ qq2) {
     __shared__ VarTables S_;
     stage_table(S_, table, B, S);
     for (int u = threadIdx.x; u < B; u += BT) {
         S_.on[u] = !(ms[u].done || ms[u].ls_done);
         S_.t[u] = ms[u].t_eval;
+        S_.t2[u] = ms[u].t_eval2;
+        S_.two[u] = ms[u].n_eval == 2;
     }
     __syncthreads();
     const int per = BT / B, t = threadIdx.x;
-    double p = 0.0, q = 0.0;
+    double p = 0.0, q = 0.0, p2 = 0.0, q2 = 0.0;
     if (t < per * B && S_.on[t % B]) {
         const int b = t % B;
-        const double tb = S_.t[b];
+        const double tb = S_.t[b], tb2 = S_.t2[b];
+        const bool two = S_.two[b];
         for (int64_t j = (int64_t)blockIdx.x * per + t / B; j < nv; j += (int64_t)gridDim.x * per) {
             const float* w = S_.tb + (b * S + min((int)label[j], S - 1)) * 3;
-            const double dz = dZ[j * B + b];
-            const Pen pn = penalty_at(Z[j * B + b] + tb * dz, make_float4(w[0], w[1], w[2], 0.f));
+            const float4 wv = make_float4(w[0], w[1], w[2], 0.f);
+            const double dz = dZ[j * B + b], z = Z[j * B + b];
+            const Pen pn = penalty_at(z + tb * dz, wv);
             p += dz * pn.dF;
             q += dz * dz * pn.curv;
+            if (two) {
+                const Pen pm = penalty_at(z + tb2 * dz, wv);
+                p2 += dz * pm.dF;
+                q2 += dz * dz * pm.curv;
+            }
         }
     }
     variant_sums(S_, B, p, q, pp, qq);
+    __syncthreads();
+    variant_sums(S_, B, p2, q2, pp2, qq2);
 }
 
 // z <- z + t*_b dz for every variant still iterating; F'(z) and F partial sums.
@@ -649,13 +665,17 @@ __global__ __launch_bounds__(CTRL) void k_bmaster_dir(MasterPtrs m0) {
 }
 
 __global__ __launch_bounds__(CTRL) void k_bls_ctrl(MasterState* ms, const double* __restrict__ pp,
-                                                   const double* __restrict__ qq, int n_part) {
+                                                   const double* __restrict__ qq, const double* __restrict__ pp2,
+                                                   const double* __restrict__ qq2, int n_part) {
     __shared__ double sh[4];
     MasterState& s = ms[blockIdx.x];
     if (s.done || s.ls_done) return;
     const double pF = reduce_row(pp + (int64_t)blockIdx.x * n_part, n_part, sh);
     const double hF = reduce_row(qq + (int64_t)blockIdx.x * n_part, n_part, sh);
-    if (threadIdx.x == 0) ctrl_ls_step(s, pF, hF);
+    const bool two = s.n_eval == 2;
+    const double pF2 = two ? reduce_row(pp2 + (int64_t)blockIdx.x * n_part, n_part, sh) : 0.0;
+    const double hF2 = two ? reduce_row(qq2 + (int64_t)blockIdx.x * n_part, n_part, sh) : 0.0;
+    if (threadIdx.x == 0) ctrl_ls_pass(s, pF, hF, pF2, hF2);
 }
 
 __global__ __launch_bounds__(CTRL) void k_bmaster_step(MasterPtrs m0) {
@@ -792,7 +812,7 @@ void free_batch(vmat_ctx* h) {
     auto F = [](void* p) { if (p) (void)hipFree(p); };
     F(b->X); F(b->Z); F(b->dZ); F(b->RZ); F(b->G);
     F(b->grad); F(b->grad_prev); F(b->d); F(b->d_prev); F(b->gF); F(b->W); F(b->W_prev);
-    F(b->ms); F(b->pp); F(b->qq); F(b->pf);
+    F(b->ms); F(b->pp); F(b->qq); F(b->pp2); F(b->qq2); F(b->pf);
     F(b->rowS); F(b->rowm); F(b->rowl); F(b->rowr); F(b->bprice); F(b->pbeam); F(b->pscore); F(b->kref);
     F(b->cost); F(b->tr.beam); F(b->tr.price); F(b->tr.margin); F(b->tr.row_margin); F(b->vmask); F(b->viter);
     F(b->spart);
@@ -868,9 +888,10 @@ vmat_status batch_iteration(vmat_ctx* h, const BatchArgs& a, const int32_t* l, c
                           gamma_bits(h), (uint64_t)(uintptr_t)bs.X};
     auto ls_round = [&](hipStream_t s) -> vmat_status {
         for (int i = 0; i < 3; ++i) {
-            k_bls_eval<<<np, BT, 0, s>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.pp, bs.qq);
+            k_bls_eval<<<np, BT, 0, s>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.pp, bs.qq,
+                                         bs.pp2, bs.qq2);
             VMAT_LAUNCH_CHECK();
-            k_bls_ctrl<<<B, CTRL, 0, s>>>(bs.ms, bs.pp, bs.qq, np);
+            k_bls_ctrl<<<B, CTRL, 0, s>>>(bs.ms, bs.pp, bs.qq, bs.pp2, bs.qq2, np);
             VMAT_LAUNCH_CHECK();
         }
         return VMAT_OK;
@@ -936,7 +957,7 @@ extern "C" vmat_status vmat_reserve_batched(vmat_handle h, int32_t max_variants)
     A(&b->X, nb * B); A(&b->Z, nv * B); A(&b->dZ, nv * B); A(&b->RZ, nv * B); A(&b->G, nb * B);
     A(&b->grad, B * N); A(&b->grad_prev, B * N); A(&b->d, B * N); A(&b->d_prev, B * N); A(&b->gF, B * N);
     A(&b->W, B * N); A(&b->W_prev, B * N); A(&b->ms, B);
-    A(&b->pp, B * np); A(&b->qq, B * np); A(&b->pf, B * np);
+    A(&b->pp, B * np); A(&b->qq, B * np); A(&b->pp2, B * np); A(&b->qq2, B * np); A(&b->pf, B * np);
     A(&b->rowS, B * NR); A(&b->rowm, B * NR); A(&b->rowl, B * NR); A(&b->rowr, B * NR);
     A(&b->bprice, B * N); A(&b->pbeam, B * (1 + 2 * (size_t)h->R)); A(&b->pscore, B * 3); A(&b->kref, B);
     A(&b->cost, B);

@@ -161,6 +161,7 @@ struct BatchState {
     MasterState* ms = nullptr;       // [cap]
     MasterState* ms_host = nullptr;  // [cap], pinned
     double *pp = nullptr, *qq = nullptr, *pf = nullptr;  // [cap][n_part] partial sums
+    double *pp2 = nullptr, *qq2 = nullptr;               // [cap][n_part] second line-search point
     double *rowS = nullptr, *rowm = nullptr;             // [cap][N*R]
     int32_t *rowl = nullptr, *rowr = nullptr;            // [cap][N*R]
     double* bprice = nullptr;                            // [cap][N]
