@@ -158,22 +158,26 @@ __global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, int N, const ApVie
     out[j] = s;
 }
 
-// gF_k = <d_k, w> (0 without a stored aperture): one block of AP_GT threads
-// per beam; thread t takes entries t, t + AP_GT, ... with four loads in flight,
-// then a fixed reduction tree.
-constexpr int AP_GT = 1024;
+// gF_k = <d_k, w> (0 without a stored aperture) in Q parts: block (k, q)
+// takes the q-th of Q equal contiguous shares of aperture k's entries; thread
+// t takes entries t, t + AP_GT, ... of the share with four loads in flight,
+// then a fixed reduction tree; out[k*Q + q] = the share's sum.
+constexpr int AP_GT = 256;
 
 __global__ __launch_bounds__(AP_GT) void k_ap_grad(const ApView* __restrict__ view, const float* __restrict__ w,
-                                                   double* __restrict__ gF, Gate gate) {
+                                                   int Q, double* __restrict__ out, Gate gate) {
     __shared__ double sh[AP_GT / 64];
     if (gate.closed()) return;
-    const int k = blockIdx.x;
+    const int k = blockIdx.x / Q, q = blockIdx.x - k * Q;
     const int s = view->beam_slot[k];
     double acc = 0.0;
     if (s >= 0) {
         const uint32_t* __restrict__ vox = view->col_vox;
         const double* __restrict__ val = view->col_val;
-        const uint32_t e0 = view->col_ptr[s], e1 = view->col_ptr[s + 1];
+        const uint32_t a0 = view->col_ptr[s], a1 = view->col_ptr[s + 1];
+        const uint32_t share = (a1 - a0 + Q - 1) / Q;
+        const uint32_t e0 = a0 + min(a1 - a0, (uint32_t)q * share);
+        const uint32_t e1 = a0 + min(a1 - a0, (uint32_t)(q + 1) * share);
         uint32_t e = e0 + threadIdx.x;
         for (; e + 3 * AP_GT < e1; e += 4 * AP_GT) {
             const uint32_t j0 = vox[e], j1 = vox[e + AP_GT], j2 = vox[e + 2 * AP_GT], j3 = vox[e + 3 * AP_GT];
@@ -192,7 +196,7 @@ __global__ __launch_bounds__(AP_GT) void k_ap_grad(const ApView* __restrict__ vi
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int i = 0; i < AP_GT / 64; ++i) t += sh[i];
-        gF[k] = t;
+        out[blockIdx.x] = t;
     }
 }
 
@@ -364,8 +368,8 @@ vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate
     return VMAT_OK;
 }
 
-vmat_status ap_grad(const vmat_ctx* h, const float* w, double* gF, Gate gate, hipStream_t st) {
-    k_ap_grad<<<h->N, AP_GT, 0, st>>>(h->ap->view, w, gF, gate);
+vmat_status ap_grad(const vmat_ctx* h, const float* w, double* out, int Q, Gate gate, hipStream_t st) {
+    k_ap_grad<<<(unsigned)(h->N * Q), AP_GT, 0, st>>>(h->ap->view, w, Q, out, gate);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }

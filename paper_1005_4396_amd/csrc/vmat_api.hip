@@ -182,14 +182,14 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
     // the captured iteration stays valid as apertures are added
     auto iteration = [&](hipStream_t s) -> vmat_status {
         TRY(launch_step_update(h, y, s));
-        TRY(ap_grad(h, h->rz, h->mgF, done, s));
-        TRY(launch_grad_dir(h, y, occ, nullptr, 0, s));
+        TRY(ap_grad(h, h->rz, h->bpart, AP_GRAD_PARTS, done, s));
+        TRY(launch_grad_dir(h, y, occ, h->bpart, AP_GRAD_PARTS, s));
         return search(s);
     };
     TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, fresh, st));
     if (fresh) TRY(ap_dose(h, y, h->z, Gate{}, st));
     TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
-    TRY(ap_grad(h, h->rz, h->mgF, Gate{}, st));
+    TRY(ap_grad(h, h->rz, h->mgF, 1, Gate{}, st));
     TRY(launch_master_grad(h, y, occ, fresh ? 1 : 2, st));
     TRY(dir_and_search(st));
     const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)occ, (uint64_t)(uintptr_t)h->ap->view,

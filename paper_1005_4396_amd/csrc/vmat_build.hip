@@ -587,7 +587,8 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     if ((rc = dalloc(h, &h->dz, h->nv)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->rz, h->nv)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->g, h->nb)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->bpart, (size_t)N * ((h->R * h->C + 255) / 256))) != VMAT_OK) return bail(rc);
+    if ((rc = dalloc(h, &h->bpart, (size_t)N * std::max(AP_GRAD_PARTS, (h->R * h->C + 255) / 256))) != VMAT_OK)
+        return bail(rc);
     if ((rc = dalloc(h, &h->part, (size_t)h->n_part * 8)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->part_b, (size_t)h->n_part * 64)) != VMAT_OK) return bail(rc);
     double** vecs[] = {&h->my, &h->mgrad, &h->mgrad_prev, &h->md, &h->md_prev, &h->mgF};

@@ -249,7 +249,7 @@ struct vmat_ctx {
     double* dz = nullptr;          // [nv] dose of the search direction
     float* rz = nullptr;           // [nv] F'(z) for the adjoint gather
     double* g = nullptr;           // [nb] beamlet prices
-    double* bpart = nullptr;       // [N * ceil(R*C/256)] beam gradient in parts (tiled adjoint)
+    double* bpart = nullptr;       // [N * max(8, ceil(R*C/256))] beam gradient in parts
     double* part = nullptr;        // [n_part * 8] block partial sums
     int n_part = 0;
     double* part_b = nullptr;      // [64 * n_part] per-variant partial sums (batched cost)

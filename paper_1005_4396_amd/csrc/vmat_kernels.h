@@ -52,7 +52,10 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
 // out = sum_k vec_k d_k over the stored apertures
 vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate, hipStream_t st);
 // gF_k = <d_k, w> (0 for beams without a stored aperture)
-vmat_status ap_grad(const vmat_ctx* h, const float* w, double* gF, Gate gate, hipStream_t st);
+// the beam gradient from the stored aperture doses in Q parts per beam:
+// out[k*Q + q] (Q = 1: out = gF); Q <= AP_GRAD_PARTS
+constexpr int AP_GRAD_PARTS = 8;
+vmat_status ap_grad(const vmat_ctx* h, const float* w, double* out, int Q, Gate gate, hipStream_t st);
 vmat_status scan_u32_dev(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t st);
 
 // F'(z) into rz (FP32, for the adjoint gather), optional FP32 copies of z and
