@@ -148,13 +148,15 @@ __global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, int N, const ApVie
     double s = 0.0;
     const uint32_t e1 = ptr[j + 1];
     uint32_t e = ptr[j];
-    for (; e + 1 < e1; e += 2) {
-        const double v0 = val[e], v1 = val[e + 1];
-        const uint16_t b0 = beam[e], b1 = beam[e + 1];
+    for (; e + 3 < e1; e += 4) {
+        const double v0 = val[e], v1 = val[e + 1], v2 = val[e + 2], v3 = val[e + 3];
+        const uint16_t b0 = beam[e], b1 = beam[e + 1], b2 = beam[e + 2], b3 = beam[e + 3];
         s = fma(v0, vs[b0], s);
         s = fma(v1, vs[b1], s);
+        s = fma(v2, vs[b2], s);
+        s = fma(v3, vs[b3], s);
     }
-    if (e < e1) s = fma(val[e], vs[beam[e]], s);
+    for (; e < e1; ++e) s = fma(val[e], vs[beam[e]], s);
     out[j] = s;
 }
 
