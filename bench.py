@@ -62,11 +62,15 @@ def cpu_baseline(case, n_iter):
     """The FP64 reference, unmodified, on the first column-generation iterations
     of the same plan.  Returns (bytes-weighted product counts, seconds, result)."""
     import oracle as O
+    from threadpoolctl import threadpool_limits
     D = O.dose_matrix(case.row_ptr, case.col, case.val, case.n_voxels)
-    t0 = time.perf_counter()
-    res = O.solve(D, case.alpha, case.beta, case.T, case.theta_deg, case.gamma, case.circular,
-                  case.n_rows, case.n_cols, case.max_leaf_step, max_cg_iter=n_iter, with_margins=False)
-    dt = time.perf_counter() - t0
+    # one host core: scipy's sparse products are single-threaded, and numpy's
+    # BLAS pool is held to one thread
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        res = O.solve(D, case.alpha, case.beta, case.T, case.theta_deg, case.gamma, case.circular,
+                      case.n_rows, case.n_cols, case.max_leaf_step, max_cg_iter=n_iter, with_margins=False)
+        dt = time.perf_counter() - t0
     n_it = len(res.order)
     # one adjoint for the empty plan, then one forward + one adjoint per master iteration
     nf = sum(res.master_iters)
