@@ -110,7 +110,15 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
         const uint32_t o0 = optr[j], o1 = optr[j + 1];
         const uint32_t n0 = o0 + p;
         nptr[j] = n0;
-        for (uint32_t e = o0; e < o1; ++e) {
+        uint32_t e = o0;
+        for (; e + 3 < o1; e += 4) {
+            const uint16_t b0 = obeam[e], b1 = obeam[e + 1], b2 = obeam[e + 2], b3 = obeam[e + 3];
+            const double v0 = oval[e], v1 = oval[e + 1], v2 = oval[e + 2], v3 = oval[e + 3];
+            const uint32_t d = n0 + (e - o0);
+            nbeam[d] = b0; nbeam[d + 1] = b1; nbeam[d + 2] = b2; nbeam[d + 3] = b3;
+            nval[d] = v0; nval[d + 1] = v1; nval[d + 2] = v2; nval[d + 3] = v3;
+        }
+        for (; e < o1; ++e) {
             nbeam[n0 + (e - o0)] = obeam[e];
             nval[n0 + (e - o0)] = oval[e];
         }
