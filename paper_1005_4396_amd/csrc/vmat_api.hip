@@ -347,7 +347,11 @@ extern "C" vmat_status vmat_master(vmat_handle h, const int32_t* l, const int32_
     TRY(check_plan(y, l, r, occ));
     const vmat_master_opts o = defaults(opts);
     TRY(check_opts(o));
-    return run_master(h, l, r, occ, y, o, rep, st);
+    const vmat_status rc = run_master(h, l, r, occ, y, o, rep, st);
+    // the replay enqueued after the last iteration does nothing, but the call
+    // returns with the stream drained
+    VMAT_HIP(hipStreamSynchronize(st));
+    return rc;
 }
 
 extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, int32_t* l, int32_t* r, uint8_t* occ,

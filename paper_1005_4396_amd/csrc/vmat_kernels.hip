@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 
 #include "vmat_block.h"
 #include "vmat_ctrl.h"
@@ -551,19 +552,70 @@ vmat_status launch_step_update(const vmat_ctx* h, double* y, hipStream_t st) {
 }
 
 // Gradient after a step, then the KKT test and the next direction, in one
-// single-block launch (k_master_grad followed by k_master_dir).
-// bpart (nullable): the beam gradient in Q parts per beam (gF_k = sum of
-// bpart[k*Q .. k*Q+Q-1] in order), written to gF first.
+// single-block launch (k_master_grad followed by k_master_dir).  bpart
+// (nullable): the beam gradient in Q parts per beam (gF_k = sum of
+// bpart[k*Q .. k*Q+Q-1] in order), written to gF first.  With lds, the
+// per-beam vectors and the state are copied to LDS with one round of loads,
+// the same control code runs on the copies, and the outputs (gradient, face,
+// direction, gF, state) are written back once: the same arithmetic without a
+// global round trip between its phases.
 __global__ __launch_bounds__(CTRL) void k_grad_dir(MasterPtrs m, const double* __restrict__ part, int n_part,
-                                                   const double* __restrict__ bpart, int Q) {
+                                                   const double* __restrict__ bpart, int Q, int lds) {
     __shared__ double sh[4];
     __shared__ int shi[4];
+    __shared__ MasterState s_ms;
+    extern __shared__ double dyn[];
     if (m.ms->done) return;
+    const int N = m.N;
+    if (lds) {
+        double* y = dyn;
+        double* gF = y + N;
+        double* grad = gF + N;
+        double* grad_prev = grad + N;
+        double* d = grad_prev + N;
+        double* d_prev = d + N;
+        double* th = d_prev + N;
+        uint8_t* occ = reinterpret_cast<uint8_t*>(th + N);
+        uint8_t* W = occ + N;
+        uint8_t* W_prev = W + N;
+        for (int k = threadIdx.x; k < N; k += CTRL) {
+            double g = 0.0;
+            if (bpart)
+                for (int q = 0; q < Q; ++q) g += bpart[(int64_t)k * Q + q];
+            else
+                g = m.gF[k];
+            gF[k] = g;
+            y[k] = m.y[k];
+            grad_prev[k] = m.grad_prev[k];
+            d_prev[k] = m.d_prev[k];
+            th[k] = m.th[k];
+            occ[k] = m.occ[k];
+            W_prev[k] = m.W_prev[k];
+        }
+        if (threadIdx.x == 0) s_ms = *m.ms;
+        __syncthreads();
+        MasterPtrs L = m;
+        L.y = y; L.gF = gF; L.grad = grad; L.grad_prev = grad_prev; L.d = d; L.d_prev = d_prev; L.th = th;
+        L.occ = occ; L.W = W; L.W_prev = W_prev; L.ms = &s_ms;
+        const double F = reduce_part(part, n_part, sh);
+        ctrl_grad(L, F, 0, sh);
+        __syncthreads();
+        ctrl_dir(L, sh, shi);
+        __syncthreads();
+        for (int k = threadIdx.x; k < N; k += CTRL) {
+            m.grad[k] = grad[k];
+            m.d[k] = d[k];
+            m.W[k] = W[k];
+            if (bpart) m.gF[k] = gF[k];
+        }
+        if (threadIdx.x == 0) *m.ms = s_ms;
+        return;
+    }
     if (bpart) {
-        for (int k = threadIdx.x; k < m.N; k += CTRL) {
-            double s = 0.0;
-            for (int q = 0; q < Q; ++q) s += bpart[(int64_t)k * Q + q];
-            m.gF[k] = s;
+        for (int k = threadIdx.x; k < N; k += CTRL) {
+            double g = 0.0;
+            for (int q = 0; q < Q; ++q) g += bpart[(int64_t)k * Q + q];
+            m.gF[k] = g;
         }
         __syncthreads();
     }
@@ -575,8 +627,12 @@ __global__ __launch_bounds__(CTRL) void k_grad_dir(MasterPtrs m, const double* _
 
 vmat_status launch_grad_dir(const vmat_ctx* h, const double* y, const uint8_t* occ, const double* bpart, int Q,
                             hipStream_t st) {
-    k_grad_dir<<<1, CTRL, 0, st>>>(master_ptrs(h, const_cast<double*>(y), occ, nullptr, nullptr), h->part,
-                                   h->n_part, Q > 0 ? bpart : nullptr, Q);
+    // VMAT_GRAD_DIR_GLOBAL: the global-memory form (read when an iteration is
+    // captured or launched directly)
+    const size_t dyn = (size_t)h->N * (7 * sizeof(double) + 3);
+    const int lds = dyn <= 48 * 1024 && !getenv("VMAT_GRAD_DIR_GLOBAL") ? 1 : 0;
+    k_grad_dir<<<1, CTRL, lds ? dyn : 0, st>>>(master_ptrs(h, const_cast<double*>(y), occ, nullptr, nullptr), h->part,
+                                               h->n_part, Q > 0 ? bpart : nullptr, Q, lds);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
