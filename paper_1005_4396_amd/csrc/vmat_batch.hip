@@ -155,17 +155,17 @@ __device__ __forceinline__ double row_w64(uint32_t q0, uint32_t q1, const void* 
         // nothing; quads past the row's end (lanes >= n) hold zeros and index 0
         const int bb = b < B ? b : B - 1;
         constexpr int XF = CS ? FMT : FMT_F32;
-        for (uint32_t k = 0; k < n; k += 8) {
-            double xs[8][4];
+        for (uint32_t k = 0; k < n; k += 4) {
+            double xs[4][4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 4; ++u) {
                 xs[u][0] = xval<XF>(X, cscale, bcast(c0, k + u), B, bb);
                 xs[u][1] = xval<XF>(X, cscale, bcast(c1, k + u), B, bb);
                 xs[u][2] = xval<XF>(X, cscale, bcast(c2, k + u), B, bb);
                 xs[u][3] = xval<XF>(X, cscale, bcast(c3, k + u), B, bb);
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 4; ++u) {
                 acc = fma((double)bcastf(v.x, k + u), xs[u][0], acc);
                 acc = fma((double)bcastf(v.y, k + u), xs[u][1], acc);
                 acc = fma((double)bcastf(v.z, k + u), xs[u][2], acc);
