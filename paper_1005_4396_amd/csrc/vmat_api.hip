@@ -124,9 +124,10 @@ vmat_status master_loop(vmat_ctx* h, int kind, const GraphKey key, It iteration,
 }
 
 // One master solve (Sec. 2.2) on the device with separate kernels.  The
-// kernels of one iteration (step with the dose update, adjoint, gradient with
-// the next direction, its dose product, three line-search evaluations) form
-// one graph; the host reads the state once per iteration, one behind.
+// kernels of one iteration (completion of the line search with the step and
+// the dose update, adjoint with the beam sums, gradient with the next
+// direction, its dose product, three line-search passes) form one graph; the
+// host reads the state once per iteration, one behind.
 vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
                              const vmat_master_opts& o, int fresh, hipStream_t st) {
     Gate done;  // open while the solve is not done

@@ -870,8 +870,9 @@ struct BatchArgs {
 
 // One lockstep master iteration over the variants whose master is running
 // (the others keep their state: zero direction, no step), as two captured
-// sequences: [direction, its fluence and dose SpMM, three line-search
-// evaluations] and, after the state read and any further line-search rounds,
+// sequences: [direction, its fluence and dose SpMM, three line-search passes
+// (one or two points each)] and, after the state read and any further
+// line-search rounds,
 // [step, dose update, adjoint SpMM, beam gradients].  Returns with the states
 // read back; *any_active = false when no master was running (the second
 // sequence is then skipped).
