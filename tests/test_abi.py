@@ -93,3 +93,17 @@ def test_create_without_a_device_reports_an_error():
     assert rc in (V.VMAT_ERR_ALLOC, V.VMAT_ERR_DEVICE)
     assert V.last_error()
     assert not h.value
+
+
+def test_read_stream_rejects_bad_arguments_before_launch():
+    """The measurement aid checks its arguments on the host: nothing is
+    launched for a null buffer, a size that is not a positive multiple of
+    16, or a grid outside [1, 65536] (the pointers below are never touched)."""
+    L = _lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.vmat_read_stream(None, 1024, fake, 8, None) == V.VMAT_ERR_INVALID_ARG
+    assert L.vmat_read_stream(fake, 1000, fake, 8, None) == V.VMAT_ERR_INVALID_ARG
+    assert L.vmat_read_stream(fake, 0, fake, 8, None) == V.VMAT_ERR_INVALID_ARG
+    assert L.vmat_read_stream(fake, 1024, fake, 0, None) == V.VMAT_ERR_INVALID_ARG
+    assert L.vmat_read_stream(fake, 1024, fake, 65537, None) == V.VMAT_ERR_INVALID_ARG
+    assert "grid" in V.last_error()
