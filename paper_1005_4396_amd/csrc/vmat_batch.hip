@@ -320,8 +320,8 @@ static void spmm_fwd_t(const vmat_ctx* h, int B, const float* X, double* Z, hipS
     if constexpr (TB == 64) {
         if (h->tl.on) {
             const Tiled& t = h->tl;
-            k_spmm_fwd_tiled_w64<FMT><<<dim3(persistent_grid(t.n_fwork, 4), tiles), SPMM_THREADS, 0, st>>>(
-                t.fwork, t.n_fwork, t.loff, t.list, h->vm.qptr, t.fcol, h->vm.val, h->bm.scale, B, X, Z);
+            k_spmm_fwd_tiled_w64<FMT><<<dim3(persistent_grid(t.n_fwork_half, 8), tiles), SPMM_THREADS, 0, st>>>(
+                t.fwork_half, t.n_fwork_half, t.loff, t.list, h->vm.qptr, t.fcol, h->vm.val, h->bm.scale, B, X, Z);
         } else {
             const int64_t rpb = SPMM_THREADS / 64;
             k_spmm_rows_w64<FMT, FMT == FMT_FP8><<<dim3(xcd_grid(h->nv, rpb), tiles), SPMM_THREADS, 0, st>>>(

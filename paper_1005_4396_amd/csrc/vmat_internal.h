@@ -72,6 +72,8 @@ struct Tiled {
     uint16_t* fcol = nullptr;     // [4 * vm.n_quads]
     int4* fwork = nullptr;        // (block, first row, end row, first slice)
     int n_fwork = 0;
+    int4* fwork_half = nullptr;   // fwork with each item's rows split in two halves (batched forward)
+    int n_fwork_half = 0;
     int fG = 8;
     // forward, sliced: each work item's rows sorted by length (longest first)
     // and cut into slices of 64 rows; a slice stores its quads column-major

@@ -876,6 +876,22 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     t.n_fwork = (int)fw.size();
     t.n_awork = (int)aw.size();
     {
+        // entry i = pos * 8 + xcd of fw becomes entries (2 pos + h) * 8 + xcd,
+        // h = 0, 1: both halves stay on the item's XCD
+        std::vector<int4> fh(fw.size() * 2, make_int4(-1, 0, 0, 0));
+        for (size_t i = 0; i < fw.size(); ++i) {
+            const int4 w = fw[i];
+            const size_t pos = i / 8, xcd = i % 8;
+            if (w.x < 0) continue;
+            const int mid = w.y + (w.z - w.y) / 2;
+            fh[(2 * pos) * 8 + xcd] = make_int4(w.x, w.y, mid, w.w);
+            fh[(2 * pos + 1) * 8 + xcd] = make_int4(w.x, mid, w.z, w.w);
+        }
+        A(t.fwork_half, fh.size() * sizeof(int4));
+        VMAT_HIP(hipMemcpyAsync(t.fwork_half, fh.data(), fh.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+        t.n_fwork_half = (int)fh.size();
+    }
+    {
         const int vb = h->d_store == VMAT_F32 ? 4 : (h->d_store == VMAT_FP8_E4M3 ? 1 : 2);
         auto sliced = [&](int64_t n_sl, int64_t quads, const std::vector<uint32_t>& so,
                           const std::vector<uint32_t>& sn, const std::vector<uint32_t>& sr, const uint32_t* qp,
@@ -927,7 +943,7 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
 
 void free_tiled(vmat_ctx* h) {
     Tiled& t = h->tl;
-    void* ps[] = {t.bounds, t.loff, t.list, t.lpack, t.fcol, t.fwork, t.aqptr, t.acol, t.aval, t.awork, t.part, t.red_ptr,
+    void* ps[] = {t.bounds, t.loff, t.list, t.lpack, t.fcol, t.fwork, t.fwork_half, t.aqptr, t.acol, t.aval, t.awork, t.part, t.red_ptr,
                   t.red_slot, t.s_off, t.s_len, t.s_row, t.s_col, t.s_val, t.as_off, t.as_len, t.as_row, t.as_col,
                   t.as_val};
     for (void* q : ps)
