@@ -214,7 +214,7 @@ static vmat_status enqueue_iteration(vmat_ctx* h, const MasterPtrs& m, int n_ls,
                                                            offsetof(MasterState, phase));
     ready.mask = M_READY;
     ls_done.mask = M_LS_DONE;
-    if (h->tl.on) {
+    if (h->tl.on && h->tl.lpack) {
         switch (h->d_store) {
             case VMAT_F32: launch_mfwd<FMT_F32>(h, m, st); break;
             case VMAT_F16: launch_mfwd<FMT_F16>(h, m, st); break;

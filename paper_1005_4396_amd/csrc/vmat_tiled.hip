@@ -767,11 +767,16 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     k_blk_list<<<nblk, 256, 0, st>>>(W, d_bits.as<uint32_t>(), t.loff, d_wpref.as<uint32_t>(), t.list);
     VMAT_LAUNCH_CHECK();
 
-    A(t.lpack, t.S * 4);
-    if (t.S > 0) {
-        k_list_pack<<<(unsigned)((t.S + 255) / 256), 256, 0, st>>>(t.S, t.list, (uint32_t)h->R, (uint32_t)h->C,
-                                                                   t.lpack);
-        VMAT_LAUNCH_CHECK();
+    // the packed (beam, leaf row, column) of every list entry: 12, 12 and 8
+    // bits, so only when the leaf rows fit (beams are at most 4096, columns 64);
+    // without it the forms that use it launch the fluence kernel instead
+    if (h->R <= 4096) {
+        A(t.lpack, t.S * 4);
+        if (t.S > 0) {
+            k_list_pack<<<(unsigned)((t.S + 255) / 256), 256, 0, st>>>(t.S, t.list, (uint32_t)h->R,
+                                                                       (uint32_t)h->C, t.lpack);
+            VMAT_LAUNCH_CHECK();
+        }
     }
 
     // forward indices
