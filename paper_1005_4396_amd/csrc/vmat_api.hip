@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "vmat_internal.h"
@@ -90,35 +92,53 @@ vmat_status check_opts(const vmat_master_opts& o) {
     return VMAT_OK;
 }
 
-// Snapshot k of the master state: copied after everything enqueued so far
-// into pinned slot k % 2, signalled by event k % 2.
-vmat_status publish_state(vmat_ctx* h, int k, hipStream_t st) {
-    VMAT_HIP(hipMemcpyAsync(h->ms_slot + (k & 1), h->ms, sizeof(MasterState), hipMemcpyDeviceToHost, st));
-    VMAT_HIP(hipEventRecord(h->ms_ev[k & 1], st));
-    return VMAT_OK;
-}
-
-vmat_status read_state(vmat_ctx* h, int k) {
-    VMAT_HIP(hipEventSynchronize(h->ms_ev[k & 1]));
-    *h->ms_host = h->ms_slot[k & 1];
+// Waits until the device has completed line-search chain `want` of this
+// handle (the mirror's count), spinning on the pinned mirror; after about two
+// seconds without progress it drains the stream and looks once more.  Then
+// copies the mirrored state to ms_host.
+vmat_status wait_chain(vmat_ctx* h, uint32_t want, hipStream_t st) {
+    const MasterMirror* mir = h->mirror;
+    auto reached = [&]() {
+        return (int32_t)(__atomic_load_n(&mir->seq, __ATOMIC_ACQUIRE) - want) >= 0;
+    };
+    if (!reached()) {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (uint32_t spin = 0; !reached(); ++spin) {
+            if ((spin & 1023u) == 1023u) {
+                if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+                    VMAT_HIP(hipStreamSynchronize(st));
+                    if (!reached()) return fail(VMAT_ERR_DEVICE, "master state not signalled by the device");
+                    break;
+                }
+                std::this_thread::yield();
+            }
+        }
+    }
+    std::memcpy((void*)h->ms_host, (const void*)&mir->s, sizeof(MasterState));
     return VMAT_OK;
 }
 
 // The master iterations after the first direction and its line search: each
 // replay of the captured iteration is enqueued before the host has read the
-// state the previous one left, so the device never waits for the host.  A
+// state the previous one left, so the device never waits for the host.  The
+// last line-search pass of every chain writes the state and a sequence
+// number to pinned host memory, so no copy is enqueued for the host.  A
 // replay enqueued after the solve has ended, or while a line search is
 // unfinished, does no work beyond the line search (the done flag gates every
 // kernel), so the arithmetic is that of one read per iteration.  The pending
-// replay at exit finds done == 1 and leaves the state as it is.
+// replay at exit finds done == 1 and leaves the state as it is.  h->chains
+// counts the chains enqueued; the device's count starts from it at every
+// master start, so a value left in the mirror by an earlier master is
+// always behind the one waited for.
 template <class It>
 vmat_status master_loop(vmat_ctx* h, int kind, const GraphKey key, It iteration, hipStream_t st) {
-    TRY(publish_state(h, 0, st));
-    for (int k = 0;; ++k) {
+    uint32_t want = h->chains;  // the first search's chain
+    for (;;) {
         TRY(run_iteration(h, kind, key, iteration, st));
-        TRY(publish_state(h, k + 1, st));
-        TRY(read_state(h, k));
+        h->chains += 1;
+        TRY(wait_chain(h, want, st));
         if (h->ms_host->done == 1) break;
+        want += 1;
     }
     return VMAT_OK;
 }
@@ -159,6 +179,7 @@ vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, co
     TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, Gate{}, st));
     TRY(launch_master_grad(h, y, occ, fresh ? 1 : 2, st));
     TRY(dir_and_search(st));
+    h->chains += 1;
     return master_loop(h, G_MASTER_D, key, iteration, st);
 }
 
@@ -193,6 +214,7 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
     TRY(ap_grad(h, h->rz, h->mgF, 1, Gate{}, st));
     TRY(launch_master_grad(h, y, occ, fresh ? 1 : 2, st));
     TRY(dir_and_search(st));
+    h->chains += 1;
     const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)occ, (uint64_t)(uintptr_t)h->ap->view,
                           gamma_bits(h)};
     return master_loop(h, G_MASTER_AP, key, iteration, st);

@@ -452,9 +452,7 @@ static void free_all(vmat_ctx* h) {
     F(h->ms);
     F(h->ms2);
     if (h->ms_host) (void)hipHostFree(h->ms_host);
-    if (h->ms_slot) (void)hipHostFree(h->ms_slot);
-    for (hipEvent_t& e : h->ms_ev)
-        if (e) (void)hipEventDestroy(e);
+    if (h->mirror) (void)hipHostFree(h->mirror);
     free_tiled(h);
     F(h->row_S); F(h->row_l); F(h->row_r); F(h->row_m); F(h->bprice); F(h->pbeam); F(h->pscore); F(h->cost2);
     F(h->tr.beam); F(h->tr.price); F(h->tr.margin); F(h->tr.row_margin); F(h->tr.cost); F(h->tr.miters);
@@ -599,11 +597,12 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     if ((rc = dalloc(h, &h->ms, 1)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->ms2, 1)) != VMAT_OK) return bail(rc);
     if (hipHostMalloc((void**)&h->ms_host, sizeof(MasterState), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&h->ms_slot, 2 * sizeof(MasterState), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void**)&h->mirror, sizeof(MasterMirror), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess)
         return bail(fail(VMAT_ERR_ALLOC, "hipHostMalloc failed"));
-    for (hipEvent_t& e : h->ms_ev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-            return bail(fail(VMAT_ERR_DEVICE, "hipEventCreateWithFlags failed"));
+    std::memset((void*)h->mirror, 0, sizeof(MasterMirror));
+    if (hipHostGetDevicePointer((void**)&h->mirror_dev, h->mirror, 0) != hipSuccess)
+        return bail(fail(VMAT_ERR_DEVICE, "hipHostGetDevicePointer failed"));
     if ((rc = dalloc(h, &h->row_S, NR)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->row_l, NR)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->row_r, NR)) != VMAT_OK) return bail(rc);

@@ -129,6 +129,15 @@ struct MasterState {
     int32_t phase;                // pipeline phase of the fused master iteration
     uint32_t cnt_a, cnt_b, cnt_c; // arrival counters of the last-block reductions
     int32_t n_eval;               // points in the next line-search pass (1 or 2)
+    uint32_t seq;                 // line-search chains completed since the master began
+};
+
+// Host-visible copy of the master state (pinned host memory): the last
+// line-search pass of every chain stores the state, then seq (release at
+// system scope), so a host that sees seq sees that state.
+struct MasterMirror {
+    MasterState s;
+    uint32_t seq;
 };
 
 // Phases of the fused master iteration: every kernel of an iteration runs only
@@ -271,11 +280,13 @@ struct vmat_ctx {
     vmat::MasterState* ms = nullptr;      // device
     vmat::MasterState* ms2 = nullptr;     // device, second buffer of the line-search chain
     vmat::MasterState* ms_host = nullptr; // pinned host mirror
-    // two pinned snapshots of the state, each written by a copy enqueued after
-    // an iteration and signalled by its event, so that the host reads one
-    // iteration behind while the next is already queued
-    vmat::MasterState* ms_slot = nullptr;
-    hipEvent_t ms_ev[2] = {nullptr, nullptr};
+    // pinned host copy of the state written by the device after every
+    // line-search chain, read by the host one iteration behind
+    vmat::MasterMirror* mirror = nullptr;
+    vmat::MasterMirror* mirror_dev = nullptr;  // its device address
+    // line-search chains enqueued on this handle; every master start sets the
+    // device's chain count to it, and each chain's last pass advances both
+    uint32_t chains = 0;
     // pricing
     double* row_S = nullptr;       // [N*R]
     int32_t* row_l = nullptr;      // [N*R]

@@ -280,11 +280,12 @@ vmat_status launch_max_rate(const vmat_ctx* h, const double* y, double* out, hip
 __global__ __launch_bounds__(CTRL) void k_master_begin(int N, double* __restrict__ y,
                                                        const uint8_t* __restrict__ occ, MasterState* ms,
                                                        int max_iter, int ls_max, double tol, double kkt_ref,
-                                                       int fresh) {
+                                                       int fresh, uint32_t seq) {
     for (int k = threadIdx.x; k < N; k += CTRL)
         if (!occ[k]) y[k] = 0.0;
     if (threadIdx.x == 0) {
         MasterState s = {};
+        s.seq = seq;
         s.max_iter = max_iter;
         s.ls_max = ls_max;
         s.tol = tol;
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(CTRL) void k_master_begin(int N, double* __restrict
 
 vmat_status launch_master_begin(const vmat_ctx* h, double* y, const uint8_t* occ, int max_iter, int ls_max,
                                 double tol, double kkt_ref, int fresh, hipStream_t st) {
-    k_master_begin<<<1, CTRL, 0, st>>>(h->N, y, occ, h->ms, max_iter, ls_max, tol, kkt_ref, fresh);
+    k_master_begin<<<1, CTRL, 0, st>>>(h->N, y, occ, h->ms, max_iter, ls_max, tol, kkt_ref, fresh, h->chains);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
@@ -421,7 +422,8 @@ __global__ __launch_bounds__(BLOCK) void k_ls_fused(int64_t nv, const double* __
                                                     const double* __restrict__ dz, VoxW vw,
                                                     const MasterState* __restrict__ src, MasterState* __restrict__ dst,
                                                     int consume, const double* __restrict__ part_in,
-                                                    double* __restrict__ part_out, int n_part) {
+                                                    double* __restrict__ part_out, int n_part,
+                                                    MasterMirror* mirror) {
     __shared__ double sh[4];
     __shared__ MasterState s;
     __shared__ int run;
@@ -436,7 +438,16 @@ __global__ __launch_bounds__(BLOCK) void k_ls_fused(int64_t nv, const double* __
         if (threadIdx.x == 0) ctrl_ls_pass(s, r[0], r[1], r[2], r[3]);
     }
     if (threadIdx.x == 0) {
-        if (blockIdx.x == 0) *dst = s;
+        // the last pass of a chain (mirror set) counts the chain and shows the
+        // state to the host
+        if (mirror) s.seq += 1;
+        if (blockIdx.x == 0) {
+            *dst = s;
+            if (mirror) {
+                mirror->s = s;
+                __hip_atomic_store(&mirror->seq, s.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
         run = !(s.done == 1 || s.ls_done);
     }
     __syncthreads();
@@ -467,12 +478,13 @@ vmat_status launch_ls_passes(const vmat_ctx* h, hipStream_t st) {
     ls_buffers(h, bufs, parts);
     const VoxW vw = voxw(h);
     for (int i = 1; i <= LS_PASSES; ++i) {
+        MasterMirror* mir = i == LS_PASSES ? h->mirror_dev : nullptr;
         if (vw.n_tab > 0)
             k_ls_fused<true><<<h->n_part, BLOCK, 0, st>>>(h->nv, h->z, h->dz, vw, bufs[(i - 1) % 2], bufs[i % 2],
-                                                         i > 1, parts[(i - 1) % 2], parts[i % 2], h->n_part);
+                                                         i > 1, parts[(i - 1) % 2], parts[i % 2], h->n_part, mir);
         else
             k_ls_fused<false><<<h->n_part, BLOCK, 0, st>>>(h->nv, h->z, h->dz, vw, bufs[(i - 1) % 2], bufs[i % 2],
-                                                          i > 1, parts[(i - 1) % 2], parts[i % 2], h->n_part);
+                                                          i > 1, parts[(i - 1) % 2], parts[i % 2], h->n_part, mir);
         VMAT_LAUNCH_CHECK();
     }
     return VMAT_OK;
