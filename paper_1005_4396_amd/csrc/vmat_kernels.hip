@@ -40,6 +40,22 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
+// Four block sums at once: each value takes block_sum's tree (wave tree,
+// then (w0 + w1) + (w2 + w3)), so the results are those of four block_sum
+// calls, with one barrier round instead of four.  Valid on thread 0.
+__device__ __forceinline__ void block_sum4(double v[4], double* sh16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = wave_sum(v[q]);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh16[q * 4 + (threadIdx.x >> 6)] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = (sh16[q * 4 + 0] + sh16[q * 4 + 1]) + (sh16[q * 4 + 2] + sh16[q * 4 + 3]);
+    __syncthreads();
+}
+
 __device__ __forceinline__ double reduce_part(const double* part, int n, double* sh) {
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += BLOCK) s += part[i];
@@ -342,8 +358,15 @@ __device__ __forceinline__ void reduce_parts(const double* part, int n, double* 
     for (int i = threadIdx.x; i < n; i += BLOCK)
 #pragma unroll
         for (int q = 0; q < NA; ++q) acc[q] += part[(int64_t)q * n + i];
+    if constexpr (NA == 4) {
+        __shared__ double sh16[16];
+        block_sum4(acc, sh16);
 #pragma unroll
-    for (int q = 0; q < NA; ++q) out[q] = block_sum(acc[q], sh);
+        for (int q = 0; q < 4; ++q) out[q] = acc[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < NA; ++q) out[q] = block_sum(acc[q], sh);
+    }
 }
 
 // Penalty weights of the voxels: abT per voxel, or (LAB) a one-byte label per
@@ -453,13 +476,12 @@ __global__ __launch_bounds__(BLOCK) void k_ls_fused(int64_t nv, const double* __
     __syncthreads();
     if (!run) return;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    ls_sums<4, LAB>(nv, z, dz, vw, stab, s.t_eval, s.t_eval2, s.n_eval == 2, acc);
-    double r[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = block_sum(acc[q], sh);
+    ls_sums<8, LAB>(nv, z, dz, vw, stab, s.t_eval, s.t_eval2, s.n_eval == 2, acc);
+    __shared__ double sh16[16];
+    block_sum4(acc, sh16);
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) part_out[(int64_t)q * n_part + blockIdx.x] = r[q];
+        for (int q = 0; q < 4; ++q) part_out[(int64_t)q * n_part + blockIdx.x] = acc[q];
 }
 
 // The buffers of pass i of a chain: it reads the state from bufs[(i-1) % 2]
