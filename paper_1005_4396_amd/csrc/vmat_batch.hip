@@ -749,9 +749,16 @@ extern "C" vmat_status vmat_tune_batched(vmat_handle h, int32_t B, const float* 
     vmat_status rc = check_batch(h, B);
     if (rc != VMAT_OK) return rc;
     if (!X || !Z || !W || !G || reps < 1) return fail(VMAT_ERR_INVALID_ARG, "null buffer or reps < 1");
-    hipEvent_t e0, e1;
-    VMAT_HIP(hipEventCreate(&e0));
-    VMAT_HIP(hipEventCreate(&e1));
+    // the timing events are released on every path out
+    struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    VMAT_HIP(hipEventCreate(&ev.e[0]));
+    VMAT_HIP(hipEventCreate(&ev.e[1]));
     int bt[2] = {0, 0};
     float bm[2] = {INFINITY, INFINITY};
     int idx = 0;
@@ -762,13 +769,13 @@ extern "C" vmat_status vmat_tune_batched(vmat_handle h, int32_t B, const float* 
                 const bool fwd = dir == 0;
                 const float* in = fwd ? X : W;
                 double* out = fwd ? Z : G;
-                if ((rc = launch_spmm(h, fwd, B, in, out, st, TB)) != VMAT_OK) break;
-                VMAT_HIP(hipEventRecord(e0, st));
+                if ((rc = launch_spmm(h, fwd, B, in, out, st, TB)) != VMAT_OK) return rc;
+                VMAT_HIP(hipEventRecord(ev.e[0], st));
                 for (int k = 0; k < reps; ++k)
-                    if ((rc = launch_spmm(h, fwd, B, in, out, st, TB)) != VMAT_OK) break;
-                VMAT_HIP(hipEventRecord(e1, st));
-                VMAT_HIP(hipEventSynchronize(e1));
-                VMAT_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if ((rc = launch_spmm(h, fwd, B, in, out, st, TB)) != VMAT_OK) return rc;
+                VMAT_HIP(hipEventRecord(ev.e[1], st));
+                VMAT_HIP(hipEventSynchronize(ev.e[1]));
+                VMAT_HIP(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
                 ms /= (float)reps;
                 if (ms < bm[dir]) {
                     bm[dir] = ms;
@@ -779,8 +786,6 @@ extern "C" vmat_status vmat_tune_batched(vmat_handle h, int32_t B, const float* 
             ++idx;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc != VMAT_OK) return rc;
     h->tune_fwd[B] = bt[0];
     h->tune_adj[B] = bt[1];
