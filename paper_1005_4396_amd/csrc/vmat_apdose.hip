@@ -84,7 +84,12 @@ __global__ __launch_bounds__(AP_T) void k_ap_scan(int n, uint32_t* __restrict__ 
 
 // Appends the non-zeros of d (voxels ascending) to the aperture-major copy at
 // offset top, and merges them into the voxel-major copy (old -> new):
-// new_ptr[j] = old_ptr[j] + (non-zeros before voxel j).
+// new_ptr[j] = old_ptr[j] + (non-zeros before voxel j), voxel j's old entries
+// keep their order and its new entry follows them.  Each block takes
+// AP_CHUNK voxels: every thread places its voxels' pointers and new entries,
+// then the block copies the chunk's old entries as one contiguous range
+// (coalesced), each entry moved by its voxel's count of new entries before
+// it, the voxel found by binary search over the chunk's pointers in LDS.
 __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, const double* __restrict__ d,
                                                   const uint32_t* __restrict__ chunk,
                                                   const int32_t* __restrict__ beam, uint32_t top,
@@ -94,7 +99,11 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
                                                   const double* __restrict__ oval, uint32_t* __restrict__ nptr,
                                                   uint16_t* __restrict__ nbeam, double* __restrict__ nval) {
     __shared__ uint32_t sh[AP_T + 1];
-    const int64_t j0 = (int64_t)blockIdx.x * AP_CHUNK + threadIdx.x * 4;
+    __shared__ uint32_t ps[AP_CHUNK + 1];   // old pointers of the chunk's voxels (and the end)
+    __shared__ uint32_t shift[AP_CHUNK];    // new entries before each voxel
+    const int64_t c0 = (int64_t)blockIdx.x * AP_CHUNK;
+    const int64_t j0 = c0 + threadIdx.x * 4;
+    const int nvc = (int)min((int64_t)AP_CHUNK, nv - c0);  // voxels in this chunk
     double v[4];
     uint32_t c = 0;
     for (int u = 0; u < 4; ++u) {
@@ -107,21 +116,13 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
     for (int u = 0; u < 4; ++u) {
         const int64_t j = j0 + u;
         if (j >= nv) break;
+        const int jj = threadIdx.x * 4 + u;
         const uint32_t o0 = optr[j], o1 = optr[j + 1];
+        ps[jj] = o0;
+        if (jj == nvc - 1) ps[nvc] = o1;
+        shift[jj] = p;
         const uint32_t n0 = o0 + p;
         nptr[j] = n0;
-        uint32_t e = o0;
-        for (; e + 3 < o1; e += 4) {
-            const uint16_t b0 = obeam[e], b1 = obeam[e + 1], b2 = obeam[e + 2], b3 = obeam[e + 3];
-            const double v0 = oval[e], v1 = oval[e + 1], v2 = oval[e + 2], v3 = oval[e + 3];
-            const uint32_t d = n0 + (e - o0);
-            nbeam[d] = b0; nbeam[d + 1] = b1; nbeam[d + 2] = b2; nbeam[d + 3] = b3;
-            nval[d] = v0; nval[d + 1] = v1; nval[d + 2] = v2; nval[d + 3] = v3;
-        }
-        for (; e < o1; ++e) {
-            nbeam[n0 + (e - o0)] = obeam[e];
-            nval[n0 + (e - o0)] = oval[e];
-        }
         if (v[u] != 0.0) {
             nbeam[n0 + (o1 - o0)] = kb;
             nval[n0 + (o1 - o0)] = v[u];
@@ -130,6 +131,19 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
             ++p;
         }
         if (j == nv - 1) nptr[nv] = optr[nv] + chunk[n_chunks];
+    }
+    __syncthreads();
+    const uint32_t e_begin = ps[0], e_end = ps[nvc];
+    for (uint32_t e = e_begin + threadIdx.x; e < e_end; e += AP_T) {
+        // the chunk voxel whose entries hold e: the last jj with ps[jj] <= e
+        int lo = 0, hi = nvc;  // ps[lo] <= e < ps[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (ps[mid] <= e) lo = mid; else hi = mid;
+        }
+        const uint32_t dst = e + shift[lo];
+        nbeam[dst] = obeam[e];
+        nval[dst] = oval[e];
     }
 }
 
