@@ -620,6 +620,7 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     if (hipMemcpyAsync(h->d_theta, h->theta.data(), N * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return bail(fail(VMAT_ERR_DEVICE, "copy of theta failed"));
+    if ((rc = tune_sell(h, st)) != VMAT_OK) return bail(rc);
     *out = h;
     return VMAT_OK;
 }

@@ -246,6 +246,9 @@ struct vmat_ctx {
     vmat::QuadCsr vm;              // voxel-major (rows = voxels): forward z = D^T x
     vmat::Tiled tl;                // tiled forms of both (used when tl.on)
     int32_t layout_req = 0;
+    // quads in flight per lane of the sliced forward and adjoint (4 or 8),
+    // the faster of the two as timed on this handle at creation
+    int sell_u_fwd = 4, sell_u_adj = 4;
     float4* abT = nullptr;         // [nv] (alpha, beta, T, 0)
     // the same weights as a one-byte label per voxel into a table of the
     // distinct (alpha, beta, T), kept when there are at most 256 of them (one

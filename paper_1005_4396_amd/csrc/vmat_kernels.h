@@ -24,6 +24,8 @@ vmat_status launch_spmv(const vmat_ctx* h, const QuadCsr& A, const float* x, dou
 // Dispatch to the tiled or the plain layout.
 // forward: out = D^T x (x: fluence, FP8 scale already folded in); adjoint: g = D w.
 vmat_status launch_fwd(const vmat_ctx* h, const double* x, double* out, Gate gate, hipStream_t st);
+// picks the quads in flight of the sliced products by timing (at creation)
+vmat_status tune_sell(vmat_ctx* h, hipStream_t st);
 vmat_status launch_adj(const vmat_ctx* h, const float* w, double* g, Gate gate, hipStream_t st);
 // Tiled adjoint up to the slot sums (h->tl.part).
 vmat_status launch_adj_slots(const vmat_ctx* h, const float* w, Gate gate, hipStream_t st);

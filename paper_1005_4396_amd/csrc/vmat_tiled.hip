@@ -314,6 +314,15 @@ __global__ __launch_bounds__(256) void k_adj_reduce_beams(int R, int C, int Q, c
 
 // ---------------------------------------------------------------- launchers
 
+// Quads in flight per lane of the sliced products: VMAT_SELL_U (2, 4 or 8)
+// when set, else the handle's choice.
+static int sell_u(const vmat_ctx* h, bool fwd) {
+    const char* e = getenv("VMAT_SELL_U");
+    const int env = e ? atoi(e) : 0;
+    if (env == 2 || env == 4 || env == 8) return env;
+    return fwd ? h->sell_u_fwd : h->sell_u_adj;
+}
+
 template <int FMT>
 static vmat_status fwd_fmt(const vmat_ctx* h, const double* x, double* out, Gate gate, hipStream_t st) {
     const Tiled& t = h->tl;
@@ -321,7 +330,7 @@ static vmat_status fwd_fmt(const vmat_ctx* h, const double* x, double* out, Gate
     if (grid == 0) return VMAT_OK;
     static const bool csr = getenv("VMAT_FWD_CSR") != nullptr;
     if (t.s_val && !csr) {
-        static const int su = getenv("VMAT_SELL_U") ? atoi(getenv("VMAT_SELL_U")) : SELL_U;
+        const int su = sell_u(h, true);
 #define SELL(UU) k_fwd_sell<FMT, UU><<<grid, TILE_THREADS, 0, st>>>(t.fwork, t.loff, t.list, t.s_off, t.s_len, \
                                                                   t.s_row, t.s_col, t.s_val, x, out, gate)
         switch (su) {
@@ -354,7 +363,7 @@ static vmat_status adj_fmt(const vmat_ctx* h, const float* w, double* g, Gate ga
     const Tiled& t = h->tl;
     static const bool acsr = getenv("VMAT_ADJ_CSR") != nullptr;
     if (t.n_awork > 0 && t.as_val && !acsr) {
-        static const int su = getenv("VMAT_SELL_U") ? atoi(getenv("VMAT_SELL_U")) : SELL_U;
+        const int su = sell_u(h, false);
 #define ASELL(UU) k_adj_sell<FMT, UU><<<(unsigned)t.n_awork, TILE_THREADS, 0, st>>>( \
     t.awork, t.bounds, t.as_off, t.as_len, t.as_row, t.as_col, t.as_val, w, t.part, gate)
         switch (su) {
@@ -402,6 +411,45 @@ vmat_status launch_adj_slots(const vmat_ctx* h, const float* w, Gate gate, hipSt
         case VMAT_BF16: return adj_fmt<FMT_BF16>(h, w, nullptr, gate, st, true);
         default: return adj_fmt<FMT_FP8>(h, w, nullptr, gate, st, true);
     }
+}
+
+// Times the sliced forward and adjoint with 4 and 8 quads in flight on the
+// handle's own layout (zero operands; the time does not depend on the values)
+// and keeps the faster of each.  Either choice gives the same bits: every
+// lane sums its quads in order.
+vmat_status tune_sell(vmat_ctx* h, hipStream_t st) {
+    const Tiled& t = h->tl;
+    if (!t.on || !t.s_val || !t.as_val) return VMAT_OK;
+    VMAT_HIP(hipMemsetAsync(h->x, 0, (size_t)h->nb * sizeof(double), st));
+    VMAT_HIP(hipMemsetAsync(h->rz, 0, (size_t)h->nv * sizeof(float), st));
+    struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    VMAT_HIP(hipEventCreate(&ev.e[0]));
+    VMAT_HIP(hipEventCreate(&ev.e[1]));
+    constexpr int reps = 3;
+    float best[2][2];
+    for (int fwd = 0; fwd < 2; ++fwd)
+        for (int ui = 0; ui < 2; ++ui) {
+            const int u = ui ? 8 : 4;
+            (fwd ? h->sell_u_fwd : h->sell_u_adj) = u;
+            for (int r = -1; r < reps; ++r) {
+                if (r == 0) VMAT_HIP(hipEventRecord(ev.e[0], st));
+                const vmat_status rc = fwd ? launch_fwd(h, h->x, h->dz, Gate{}, st)
+                                           : launch_adj(h, h->rz, h->g, Gate{}, st);
+                if (rc != VMAT_OK) return rc;
+            }
+            VMAT_HIP(hipEventRecord(ev.e[1], st));
+            VMAT_HIP(hipEventSynchronize(ev.e[1]));
+            VMAT_HIP(hipEventElapsedTime(&best[fwd][ui], ev.e[0], ev.e[1]));
+        }
+    h->sell_u_adj = best[0][1] < best[0][0] ? 8 : 4;
+    h->sell_u_fwd = best[1][1] < best[1][0] ? 8 : 4;
+    return VMAT_OK;
 }
 
 int beam_parts(const vmat_ctx* h) { return h->tl.on ? (h->R * h->C + 255) / 256 : 0; }
