@@ -93,7 +93,10 @@ typedef struct vmat_problem {
 /* Copies D, alpha, beta, T into the library's own device layouts (beamlet-major
  * and voxel-major quad CSR, and the tiled and sliced forms of both products,
  * in d_store precision) and validates them (one pass; invalid data gives
- * VMAT_ERR_INVALID_ARG).  The caller may free its arrays afterwards.          */
+ * VMAT_ERR_INVALID_ARG).  With the sliced forms it also times each product
+ * with 4 and 8 quads in flight per lane (a few launches on zero operands) and
+ * keeps the faster; the choice changes no result.  The caller may free its
+ * arrays afterwards.                                                          */
 vmat_status vmat_create(const vmat_problem* prob, hipStream_t stream, vmat_handle* out);
 vmat_status vmat_destroy(vmat_handle h);
 const char* vmat_last_error(void);
