@@ -19,8 +19,15 @@
 namespace vmat {
 
 constexpr int BLOCK = 256;
-// line-search passes per master iteration (captured with the iteration)
-constexpr int LS_PASSES = 3;
+// Line-search passes per master iteration (captured with the iteration): 3,
+// or VMAT_LS_PASSES (1..8) as read when an iteration is captured or launched.
+// The grouping of passes into replays changes no result: a search that needs
+// more passes than a replay holds stalls that replay and goes on in the next.
+static int ls_passes() {
+    const char* e = getenv("VMAT_LS_PASSES");
+    const int n = e ? atoi(e) : 3;
+    return n >= 1 && n <= 8 ? n : 3;
+}
 
 // ---------------------------------------------------------------- reductions
 
@@ -499,8 +506,9 @@ vmat_status launch_ls_passes(const vmat_ctx* h, hipStream_t st) {
     double* parts[2];
     ls_buffers(h, bufs, parts);
     const VoxW vw = voxw(h);
-    for (int i = 1; i <= LS_PASSES; ++i) {
-        MasterMirror* mir = i == LS_PASSES ? h->mirror_dev : nullptr;
+    const int np = ls_passes();
+    for (int i = 1; i <= np; ++i) {
+        MasterMirror* mir = i == np ? h->mirror_dev : nullptr;
         if (vw.n_tab > 0)
             k_ls_fused<true><<<h->n_part, BLOCK, 0, st>>>(h->nv, h->z, h->dz, vw, bufs[(i - 1) % 2], bufs[i % 2],
                                                          i > 1, parts[(i - 1) % 2], parts[i % 2], h->n_part, mir);
@@ -573,13 +581,14 @@ vmat_status launch_step_update(const vmat_ctx* h, double* y, hipStream_t st) {
     MasterState* bufs[2];
     double* parts[2];
     ls_buffers(h, bufs, parts);
+    const int np = ls_passes();  // the last pass of the chain wrote bufs[np % 2], parts[np % 2]
     const VoxW vw = voxw(h);
     const MasterPtrs m = master_ptrs(h, y, nullptr, nullptr, nullptr);
     if (vw.n_tab > 0)
-        k_update_step<true><<<h->n_part, BLOCK, 0, st>>>(m, bufs[LS_PASSES % 2], parts[LS_PASSES % 2], h->nv, h->z,
+        k_update_step<true><<<h->n_part, BLOCK, 0, st>>>(m, bufs[np % 2], parts[np % 2], h->nv, h->z,
                                                         h->dz, vw, h->rz, h->part, h->n_part);
     else
-        k_update_step<false><<<h->n_part, BLOCK, 0, st>>>(m, bufs[LS_PASSES % 2], parts[LS_PASSES % 2], h->nv, h->z,
+        k_update_step<false><<<h->n_part, BLOCK, 0, st>>>(m, bufs[np % 2], parts[np % 2], h->nv, h->z,
                                                          h->dz, vw, h->rz, h->part, h->n_part);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
