@@ -83,7 +83,7 @@ __global__ __launch_bounds__(AP_T) void k_ap_scan(int n, uint32_t* __restrict__ 
 }
 
 // Appends the non-zeros of d (voxels ascending) to the aperture-major copy at
-// offset top, and merges them into the voxel-major copy (old -> new):
+// offset col_ptr[slot] (the entries of the apertures stored before), and merges them into the voxel-major copy (old -> new):
 // new_ptr[j] = old_ptr[j] + (non-zeros before voxel j), voxel j's old entries
 // keep their order and its new entry follows them.  Each block takes
 // AP_CHUNK voxels: every thread places its voxels' pointers and new entries,
@@ -92,7 +92,8 @@ __global__ __launch_bounds__(AP_T) void k_ap_scan(int n, uint32_t* __restrict__ 
 // it, the voxel found by binary search over the chunk's pointers in LDS.
 __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, const double* __restrict__ d,
                                                   const uint32_t* __restrict__ chunk,
-                                                  const int32_t* __restrict__ beam, uint32_t top,
+                                                  const int32_t* __restrict__ beam,
+                                                  const uint32_t* __restrict__ col_ptr, int slot,
                                                   uint32_t* __restrict__ col_vox, double* __restrict__ col_val,
                                                   const uint32_t* __restrict__ optr,
                                                   const uint16_t* __restrict__ obeam,
@@ -113,6 +114,7 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
     uint32_t tot;
     uint32_t p = chunk[blockIdx.x] + block_excl_scan_u32(c, sh, &tot);
     const uint16_t kb = (uint16_t)beam[0];
+    const uint32_t top = col_ptr[slot];  // entries of the apertures stored before
     for (int u = 0; u < 4; ++u) {
         const int64_t j = j0 + u;
         if (j >= nv) break;
@@ -268,6 +270,7 @@ void free_apdose(vmat_ctx* h) {
     ap_free_entries(a);
     F(a->col_ptr); F(a->beam_slot); F(a->vx_ptr[0]); F(a->vx_ptr[1]); F(a->chunk); F(a->unit); F(a->view);
     if (a->total_host) (void)hipHostFree(a->total_host);
+    if (a->counted) (void)hipEventDestroy(a->counted);
     h->bytes -= a->bytes;
     delete a;
     h->ap = nullptr;
@@ -303,6 +306,10 @@ vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
             a->total_host = nullptr;
             rc = fail(VMAT_ERR_ALLOC, "pinned host allocation failed");
         }
+        if (rc == VMAT_OK && hipEventCreateWithFlags(&a->counted, hipEventDisableTiming) != hipSuccess) {
+            a->counted = nullptr;
+            rc = fail(VMAT_ERR_DEVICE, "event creation failed");
+        }
         h->bytes += a->bytes;
         if (rc != VMAT_OK) {
             free_apdose(h);
@@ -310,7 +317,9 @@ vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
         }
     }
     ApDose* a = h->ap;
+    if (a->pending) VMAT_HIP(hipEventSynchronize(a->counted));
     a->top = 0;
+    a->pending = 0;
     a->n_slots = 0;
     a->cur = 0;
     VMAT_HIP(hipMemsetAsync(a->col_ptr, 0, sizeof(uint32_t) * (h->N + 1), st));
@@ -352,16 +361,28 @@ static vmat_status ap_grow(vmat_ctx* h, int64_t need, hipStream_t st) {
 
 // Stores the dose of the aperture of one beam: beam_dev (device, e.g. the
 // pricing result) or, if null, beam_h.  One dose product plus compaction.
+// Nothing waits for the device: the aperture's place in the store comes from
+// the device-side aperture pointers, its non-zero count reaches the host one
+// append later (through pinned memory and an event that, between two
+// column-generation iterations, has long completed), and the store is kept
+// at least one dose vector (nv entries) ahead of the counted entries, so no
+// aperture can overflow it before its count is known.
 vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ,
                       const int32_t* beam_dev, int beam_h, hipStream_t st) {
     ApDose* a = h->ap;
     if (!a) return fail(VMAT_ERR_INVALID_ARG, "aperture doses not initialised");
     if (a->n_slots >= h->N) return fail(VMAT_ERR_INVALID_ARG, "more apertures than beams");
+    if (a->pending) {
+        VMAT_HIP(hipEventSynchronize(a->counted));
+        a->top += *a->total_host;
+        a->pending = 0;
+    }
+    vmat_status rc;
+    if (a->top + h->nv > a->cap && (rc = ap_grow(h, a->top + h->nv, st)) != VMAT_OK) return rc;
     int32_t* kb = reinterpret_cast<int32_t*>(a->unit + h->N);
     k_ap_unit<<<1, AP_T, 0, st>>>(h->N, beam_dev, beam_h, a->unit, kb);
     VMAT_LAUNCH_CHECK();
-    vmat_status rc = launch_fluence(h, a->unit, l, r, occ, h->bm.scale, h->x, Gate{}, st);
-    if (rc != VMAT_OK) return rc;
+    if ((rc = launch_fluence(h, a->unit, l, r, occ, h->bm.scale, h->x, Gate{}, st)) != VMAT_OK) return rc;
     if ((rc = launch_fwd(h, h->x, h->dz, Gate{}, st)) != VMAT_OK) return rc;
     const int nch = n_chunks_of(h->nv);
     k_ap_count<<<nch, AP_T, 0, st>>>(h->nv, h->dz, a->chunk);
@@ -369,17 +390,15 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
     k_ap_scan<<<1, AP_T, 0, st>>>(nch, a->chunk);
     VMAT_LAUNCH_CHECK();
     VMAT_HIP(hipMemcpyAsync(a->total_host, a->chunk + nch, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    VMAT_HIP(hipStreamSynchronize(st));
-    const int64_t total = *a->total_host;
-    if (a->top + total > a->cap && (rc = ap_grow(h, a->top + total, st)) != VMAT_OK) return rc;
+    VMAT_HIP(hipEventRecord(a->counted, st));
+    a->pending = 1;
     const int c = a->cur, n = 1 - c;
-    k_ap_emit<<<nch, AP_T, 0, st>>>(h->nv, nch, h->dz, a->chunk, kb, (uint32_t)a->top, a->col_vox, a->col_val,
-                                    a->vx_ptr[c], a->vx_beam[c], a->vx_val[c], a->vx_ptr[n], a->vx_beam[n],
-                                    a->vx_val[n]);
+    k_ap_emit<<<nch, AP_T, 0, st>>>(h->nv, nch, h->dz, a->chunk, kb, a->col_ptr, a->n_slots, a->col_vox,
+                                    a->col_val, a->vx_ptr[c], a->vx_beam[c], a->vx_val[c], a->vx_ptr[n],
+                                    a->vx_beam[n], a->vx_val[n]);
     VMAT_LAUNCH_CHECK();
     k_ap_slot<<<1, 1, 0, st>>>(a->n_slots, kb, a->chunk, nch, a->col_ptr, a->beam_slot);
     VMAT_LAUNCH_CHECK();
-    a->top += total;
     a->n_slots += 1;
     a->cur = n;
     return ap_publish(h, st);

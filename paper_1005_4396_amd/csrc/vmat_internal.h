@@ -213,7 +213,8 @@ struct ApView {
 // voxel in opening order) for the dose of an intensity vector.
 struct ApDose {
     int64_t cap = 0;               // entries each array can hold
-    int64_t top = 0;               // entries in use
+    int64_t top = 0;               // entries in use, up to the last counted aperture
+    int pending = 0;               // 1: the last aperture's count is still in total_host
     int n_slots = 0;               // apertures stored
     int cur = 0;                   // voxel-major copy in use (0/1)
     uint32_t* col_vox = nullptr;   // [cap]
@@ -226,7 +227,8 @@ struct ApDose {
     uint32_t* chunk = nullptr;     // [n_chunks + 1] non-zero counts, then offsets; [n_chunks+1] = total
     double* unit = nullptr;        // [N] unit intensity vector of the aperture being stored
     ApView* view = nullptr;        // device copy of the current pointers
-    uint32_t* total_host = nullptr;// pinned
+    uint32_t* total_host = nullptr;// pinned: non-zeros of the last stored aperture
+    hipEvent_t counted = nullptr;  // recorded after that count's copy
     int64_t bytes = 0;
 };
 }  // namespace vmat
