@@ -83,28 +83,21 @@ __global__ __launch_bounds__(AP_T) void k_ap_scan(int n, uint32_t* __restrict__ 
 }
 
 // Appends the non-zeros of d (voxels ascending) to the aperture-major copy at
-// offset col_ptr[slot] (the entries of the apertures stored before), and merges them into the voxel-major copy (old -> new):
-// new_ptr[j] = old_ptr[j] + (non-zeros before voxel j), voxel j's old entries
-// keep their order and its new entry follows them.  Each block takes
-// AP_CHUNK voxels: every thread places its voxels' pointers and new entries,
-// then the block copies the chunk's old entries as one contiguous range
-// (coalesced), each entry moved by its voxel's count of new entries before
-// it, the voxel found by binary search over the chunk's pointers in LDS.
+// offset col_ptr[slot] (the entries of the apertures stored before) and
+// places them in the voxel-major copy (old -> new): new_ptr[j] = old_ptr[j] +
+// (non-zeros before voxel j) = old_ptr[j] + shift[j]; voxel j's new entry
+// follows its old entries, which k_ap_copy moves.  Each block takes AP_CHUNK
+// voxels, four per thread.
 __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, const double* __restrict__ d,
                                                   const uint32_t* __restrict__ chunk,
                                                   const int32_t* __restrict__ beam,
                                                   const uint32_t* __restrict__ col_ptr, int slot,
                                                   uint32_t* __restrict__ col_vox, double* __restrict__ col_val,
                                                   const uint32_t* __restrict__ optr,
-                                                  const uint16_t* __restrict__ obeam,
-                                                  const double* __restrict__ oval, uint32_t* __restrict__ nptr,
+                                                  uint32_t* __restrict__ nptr, uint32_t* __restrict__ shift,
                                                   uint16_t* __restrict__ nbeam, double* __restrict__ nval) {
     __shared__ uint32_t sh[AP_T + 1];
-    __shared__ uint32_t ps[AP_CHUNK + 1];   // old pointers of the chunk's voxels (and the end)
-    __shared__ uint32_t shift[AP_CHUNK];    // new entries before each voxel
-    const int64_t c0 = (int64_t)blockIdx.x * AP_CHUNK;
-    const int64_t j0 = c0 + threadIdx.x * 4;
-    const int nvc = (int)min((int64_t)AP_CHUNK, nv - c0);  // voxels in this chunk
+    const int64_t j0 = (int64_t)blockIdx.x * AP_CHUNK + threadIdx.x * 4;
     double v[4];
     uint32_t c = 0;
     for (int u = 0; u < 4; ++u) {
@@ -118,11 +111,8 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
     for (int u = 0; u < 4; ++u) {
         const int64_t j = j0 + u;
         if (j >= nv) break;
-        const int jj = threadIdx.x * 4 + u;
         const uint32_t o0 = optr[j], o1 = optr[j + 1];
-        ps[jj] = o0;
-        if (jj == nvc - 1) ps[nvc] = o1;
-        shift[jj] = p;
+        shift[j] = p;
         const uint32_t n0 = o0 + p;
         nptr[j] = n0;
         if (v[u] != 0.0) {
@@ -134,19 +124,28 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
         }
         if (j == nv - 1) nptr[nv] = optr[nv] + chunk[n_chunks];
     }
-    __syncthreads();
-    const uint32_t e_begin = ps[0], e_end = ps[nvc];
-    for (uint32_t e = e_begin + threadIdx.x; e < e_end; e += AP_T) {
-        // the chunk voxel whose entries hold e: the last jj with ps[jj] <= e
-        int lo = 0, hi = nvc;  // ps[lo] <= e < ps[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (ps[mid] <= e) lo = mid; else hi = mid;
-        }
-        const uint32_t dst = e + shift[lo];
-        nbeam[dst] = obeam[e];
-        nval[dst] = oval[e];
+}
+
+// Moves every old entry of the voxel-major copy to its new place: entry e of
+// voxel j (old_ptr[j] <= e < old_ptr[j+1], found by binary search) goes to
+// e + shift[j].  One entry per thread, so the work does not depend on how the
+// entries are spread over the voxels; consecutive entries move to
+// consecutive places.
+__global__ __launch_bounds__(AP_T) void k_ap_copy(uint32_t n_old, int64_t nv, const uint32_t* __restrict__ optr,
+                                                  const uint32_t* __restrict__ shift,
+                                                  const uint16_t* __restrict__ obeam,
+                                                  const double* __restrict__ oval, uint16_t* __restrict__ nbeam,
+                                                  double* __restrict__ nval) {
+    const uint32_t e = blockIdx.x * AP_T + threadIdx.x;
+    if (e >= n_old) return;
+    int64_t lo = 0, hi = nv;  // optr[lo] <= e < optr[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (optr[mid] <= e) lo = mid; else hi = mid;
     }
+    const uint32_t dst = e + shift[lo];
+    nbeam[dst] = obeam[e];
+    nval[dst] = oval[e];
 }
 
 __global__ void k_ap_slot(int slot, const int32_t* __restrict__ beam, const uint32_t* __restrict__ chunk,
@@ -268,7 +267,8 @@ void free_apdose(vmat_ctx* h) {
     if (!a) return;
     auto F = [](void* p) { if (p) (void)hipFree(p); };
     ap_free_entries(a);
-    F(a->col_ptr); F(a->beam_slot); F(a->vx_ptr[0]); F(a->vx_ptr[1]); F(a->chunk); F(a->unit); F(a->view);
+    F(a->col_ptr); F(a->beam_slot); F(a->vx_ptr[0]); F(a->vx_ptr[1]); F(a->chunk); F(a->shift); F(a->unit);
+    F(a->view);
     if (a->total_host) (void)hipHostFree(a->total_host);
     if (a->counted) (void)hipEventDestroy(a->counted);
     h->bytes -= a->bytes;
@@ -299,6 +299,7 @@ vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
         A(&a->vx_ptr[0], (size_t)h->nv + 1);
         A(&a->vx_ptr[1], (size_t)h->nv + 1);
         A(&a->chunk, (size_t)nch + 2);
+        A(&a->shift, (size_t)h->nv);
         A(&a->unit, (size_t)h->N + 1);  // unit[N] keeps the beam index being stored
         A(&a->view, 1);
         if (rc == VMAT_OK) rc = ap_alloc_entries(a, std::max<int64_t>(1 << 20, 4 * h->nv));
@@ -394,9 +395,15 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
     a->pending = 1;
     const int c = a->cur, n = 1 - c;
     k_ap_emit<<<nch, AP_T, 0, st>>>(h->nv, nch, h->dz, a->chunk, kb, a->col_ptr, a->n_slots, a->col_vox,
-                                    a->col_val, a->vx_ptr[c], a->vx_beam[c], a->vx_val[c], a->vx_ptr[n],
-                                    a->vx_beam[n], a->vx_val[n]);
+                                    a->col_val, a->vx_ptr[c], a->vx_ptr[n], a->shift, a->vx_beam[n],
+                                    a->vx_val[n]);
     VMAT_LAUNCH_CHECK();
+    if (a->top > 0) {
+        k_ap_copy<<<(unsigned)((a->top + AP_T - 1) / AP_T), AP_T, 0, st>>>((uint32_t)a->top, h->nv, a->vx_ptr[c],
+                                                                          a->shift, a->vx_beam[c], a->vx_val[c],
+                                                                          a->vx_beam[n], a->vx_val[n]);
+        VMAT_LAUNCH_CHECK();
+    }
     k_ap_slot<<<1, 1, 0, st>>>(a->n_slots, kb, a->chunk, nch, a->col_ptr, a->beam_slot);
     VMAT_LAUNCH_CHECK();
     a->n_slots += 1;

@@ -225,6 +225,7 @@ struct ApDose {
     uint16_t* vx_beam[2] = {nullptr, nullptr}; // [cap]
     double* vx_val[2] = {nullptr, nullptr};    // [cap]
     uint32_t* chunk = nullptr;     // [n_chunks + 1] non-zero counts, then offsets; [n_chunks+1] = total
+    uint32_t* shift = nullptr;     // [nv] new entries before each voxel in the last merge
     double* unit = nullptr;        // [N] unit intensity vector of the aperture being stored
     ApView* view = nullptr;        // device copy of the current pointers
     uint32_t* total_host = nullptr;// pinned: non-zeros of the last stored aperture
