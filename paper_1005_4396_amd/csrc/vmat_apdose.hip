@@ -154,8 +154,13 @@ __global__ void k_ap_slot(int slot, const int32_t* __restrict__ beam, const uint
     beam_slot[beam[0]] = slot;
 }
 
-// out_j = sum over voxel j's entries (opening order) of val * vec[beam]; the
-// per-beam vector is staged in LDS.
+// out_j = sum over voxel j's entries of val * vec[beam]; the per-beam vector
+// is staged in LDS.  G lanes share a voxel: lane t of the group takes the
+// voxel's entries t, t + G, ... in order, two at a time, and the group sums
+// with a fixed shuffle tree, so a voxel with an entry from every aperture
+// (the target's) costs its group 1/G of the serial walk.
+constexpr int AP_DG = 4;
+
 __global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, int N, const ApView* __restrict__ view,
                                                   const double* __restrict__ vec, double* __restrict__ out,
                                                   Gate gate) {
@@ -163,24 +168,25 @@ __global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, int N, const ApVie
     if (gate.closed()) return;
     for (int k = threadIdx.x; k < N; k += AP_T) vs[k] = vec[k];
     __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * AP_T + threadIdx.x;
-    if (j >= nv) return;
+    const int64_t j = ((int64_t)blockIdx.x * AP_T + threadIdx.x) / AP_DG;
+    const int t = threadIdx.x % AP_DG;
     const uint32_t* __restrict__ ptr = view->vx_ptr;
     const uint16_t* __restrict__ beam = view->vx_beam;
     const double* __restrict__ val = view->vx_val;
     double s = 0.0;
-    const uint32_t e1 = ptr[j + 1];
-    uint32_t e = ptr[j];
-    for (; e + 3 < e1; e += 4) {
-        const double v0 = val[e], v1 = val[e + 1], v2 = val[e + 2], v3 = val[e + 3];
-        const uint16_t b0 = beam[e], b1 = beam[e + 1], b2 = beam[e + 2], b3 = beam[e + 3];
-        s = fma(v0, vs[b0], s);
-        s = fma(v1, vs[b1], s);
-        s = fma(v2, vs[b2], s);
-        s = fma(v3, vs[b3], s);
+    if (j < nv) {
+        const uint32_t e1 = ptr[j + 1];
+        uint32_t e = ptr[j] + t;
+        for (; e + AP_DG < e1; e += 2 * AP_DG) {
+            const double v0 = val[e], v1 = val[e + AP_DG];
+            const uint16_t b0 = beam[e], b1 = beam[e + AP_DG];
+            s = fma(v0, vs[b0], s);
+            s = fma(v1, vs[b1], s);
+        }
+        if (e < e1) s = fma(val[e], vs[beam[e]], s);
     }
-    for (; e < e1; ++e) s = fma(val[e], vs[beam[e]], s);
-    out[j] = s;
+    for (int off = AP_DG / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, AP_DG);
+    if (j < nv && t == 0) out[j] = s;
 }
 
 // gF_k = <d_k, w> (0 without a stored aperture) in Q parts: block (k, q)
@@ -412,8 +418,10 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
 }
 
 vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate, hipStream_t st) {
-    k_ap_dose<<<(unsigned)((h->nv + AP_T - 1) / AP_T), AP_T, sizeof(double) * h->N, st>>>(h->nv, h->N, h->ap->view,
-                                                                                       vec, out, gate);
+    const int64_t threads = h->nv * AP_DG;
+    k_ap_dose<<<(unsigned)((threads + AP_T - 1) / AP_T), AP_T, sizeof(double) * h->N, st>>>(h->nv, h->N,
+                                                                                          h->ap->view, vec, out,
+                                                                                          gate);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
