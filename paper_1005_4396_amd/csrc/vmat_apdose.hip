@@ -10,7 +10,10 @@
 // Storage (ApDose in vmat_internal.h): an aperture-major copy, appended per
 // aperture with voxels ascending, for the per-aperture sums; a voxel-major
 // copy, rebuilt by merging each new aperture into the previous one, for the
-// dose.  Every sum runs in a fixed order: deterministic results.
+// dose.  Values are stored in FP32: each d_k entry (a sum of FP32 D values
+// formed in FP64) is rounded once, to 2^-24 relative, and every product with
+// them accumulates in FP64.  Every sum runs in a fixed order: deterministic
+// results.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -92,10 +95,10 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
                                                   const uint32_t* __restrict__ chunk,
                                                   const int32_t* __restrict__ beam,
                                                   const uint32_t* __restrict__ col_ptr, int slot,
-                                                  uint32_t* __restrict__ col_vox, double* __restrict__ col_val,
+                                                  uint32_t* __restrict__ col_vox, float* __restrict__ col_val,
                                                   const uint32_t* __restrict__ optr,
                                                   uint32_t* __restrict__ nptr, uint32_t* __restrict__ shift,
-                                                  uint16_t* __restrict__ nbeam, double* __restrict__ nval) {
+                                                  uint16_t* __restrict__ nbeam, float* __restrict__ nval) {
     __shared__ uint32_t sh[AP_T + 1];
     const int64_t j0 = (int64_t)blockIdx.x * AP_CHUNK + threadIdx.x * 4;
     double v[4];
@@ -117,9 +120,10 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
         nptr[j] = n0;
         if (v[u] != 0.0) {
             nbeam[n0 + (o1 - o0)] = kb;
-            nval[n0 + (o1 - o0)] = v[u];
+            const float vf = (float)v[u];
+            nval[n0 + (o1 - o0)] = vf;
             col_vox[top + p] = (uint32_t)j;
-            col_val[top + p] = v[u];
+            col_val[top + p] = vf;
             ++p;
         }
         if (j == nv - 1) nptr[nv] = optr[nv] + chunk[n_chunks];
@@ -134,8 +138,8 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
 __global__ __launch_bounds__(AP_T) void k_ap_copy(uint32_t n_old, int64_t nv, const uint32_t* __restrict__ optr,
                                                   const uint32_t* __restrict__ shift,
                                                   const uint16_t* __restrict__ obeam,
-                                                  const double* __restrict__ oval, uint16_t* __restrict__ nbeam,
-                                                  double* __restrict__ nval) {
+                                                  const float* __restrict__ oval, uint16_t* __restrict__ nbeam,
+                                                  float* __restrict__ nval) {
     const uint32_t e = blockIdx.x * AP_T + threadIdx.x;
     if (e >= n_old) return;
     int64_t lo = 0, hi = nv;  // optr[lo] <= e < optr[hi]
@@ -172,18 +176,18 @@ __global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, int N, const ApVie
     const int t = threadIdx.x % AP_DG;
     const uint32_t* __restrict__ ptr = view->vx_ptr;
     const uint16_t* __restrict__ beam = view->vx_beam;
-    const double* __restrict__ val = view->vx_val;
+    const float* __restrict__ val = view->vx_val;
     double s = 0.0;
     if (j < nv) {
         const uint32_t e1 = ptr[j + 1];
         uint32_t e = ptr[j] + t;
         for (; e + AP_DG < e1; e += 2 * AP_DG) {
-            const double v0 = val[e], v1 = val[e + AP_DG];
+            const float v0 = val[e], v1 = val[e + AP_DG];
             const uint16_t b0 = beam[e], b1 = beam[e + AP_DG];
-            s = fma(v0, vs[b0], s);
-            s = fma(v1, vs[b1], s);
+            s = fma((double)v0, vs[b0], s);
+            s = fma((double)v1, vs[b1], s);
         }
-        if (e < e1) s = fma(val[e], vs[beam[e]], s);
+        if (e < e1) s = fma((double)val[e], vs[beam[e]], s);
     }
     for (int off = AP_DG / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, AP_DG);
     if (j < nv && t == 0) out[j] = s;
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(AP_GT) void k_ap_grad(const ApView* __restrict__ vi
     double acc = 0.0;
     if (s >= 0) {
         const uint32_t* __restrict__ vox = view->col_vox;
-        const double* __restrict__ val = view->col_val;
+        const float* __restrict__ val = view->col_val;
         const uint32_t a0 = view->col_ptr[s], a1 = view->col_ptr[s + 1];
         const uint32_t share = (a1 - a0 + Q - 1) / Q;
         const uint32_t e0 = a0 + min(a1 - a0, (uint32_t)q * share);
@@ -212,14 +216,14 @@ __global__ __launch_bounds__(AP_GT) void k_ap_grad(const ApView* __restrict__ vi
         uint32_t e = e0 + threadIdx.x;
         for (; e + 3 * AP_GT < e1; e += 4 * AP_GT) {
             const uint32_t j0 = vox[e], j1 = vox[e + AP_GT], j2 = vox[e + 2 * AP_GT], j3 = vox[e + 3 * AP_GT];
-            const double v0 = val[e], v1 = val[e + AP_GT], v2 = val[e + 2 * AP_GT], v3 = val[e + 3 * AP_GT];
+            const float v0 = val[e], v1 = val[e + AP_GT], v2 = val[e + 2 * AP_GT], v3 = val[e + 3 * AP_GT];
             const float w0 = w[j0], w1 = w[j1], w2 = w[j2], w3 = w[j3];
-            acc = fma(v0, (double)w0, acc);
-            acc = fma(v1, (double)w1, acc);
-            acc = fma(v2, (double)w2, acc);
-            acc = fma(v3, (double)w3, acc);
+            acc = fma((double)v0, (double)w0, acc);
+            acc = fma((double)v1, (double)w1, acc);
+            acc = fma((double)v2, (double)w2, acc);
+            acc = fma((double)v3, (double)w3, acc);
         }
-        for (; e < e1; e += AP_GT) acc = fma(val[e], (double)w[vox[e]], acc);
+        for (; e < e1; e += AP_GT) acc = fma((double)val[e], (double)w[vox[e]], acc);
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
@@ -255,7 +259,7 @@ static void ap_free_entries(ApDose* a) {
     a->col_vox = nullptr; a->col_val = nullptr;
     a->vx_beam[0] = a->vx_beam[1] = nullptr;
     a->vx_val[0] = a->vx_val[1] = nullptr;
-    a->bytes -= a->cap * (int64_t)(4 + 8 + 2 * (2 + 8));
+    a->bytes -= a->cap * (int64_t)(4 + 4 + 2 * (2 + 4));
     a->cap = 0;
 }
 
@@ -349,9 +353,9 @@ static vmat_status ap_grow(vmat_ctx* h, int64_t need, hipStream_t st) {
     const size_t n = (size_t)a->top;
     const int c = a->cur;
     VMAT_HIP(hipMemcpyAsync(fresh.col_vox, a->col_vox, n * 4, hipMemcpyDeviceToDevice, st));
-    VMAT_HIP(hipMemcpyAsync(fresh.col_val, a->col_val, n * 8, hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(fresh.col_val, a->col_val, n * 4, hipMemcpyDeviceToDevice, st));
     VMAT_HIP(hipMemcpyAsync(fresh.vx_beam[c], a->vx_beam[c], n * 2, hipMemcpyDeviceToDevice, st));
-    VMAT_HIP(hipMemcpyAsync(fresh.vx_val[c], a->vx_val[c], n * 8, hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(fresh.vx_val[c], a->vx_val[c], n * 4, hipMemcpyDeviceToDevice, st));
     VMAT_HIP(hipStreamSynchronize(st));
     h->bytes -= a->bytes;
     ap_free_entries(a);

@@ -198,10 +198,10 @@ constexpr int GRAPH_KEY_LEN = 10;  // words identifying a captured sequence
 struct ApView {
     const uint32_t* vx_ptr;
     const uint16_t* vx_beam;
-    const double* vx_val;
+    const float* vx_val;
     const uint32_t* col_ptr;
     const uint32_t* col_vox;
-    const double* col_val;
+    const float* col_val;
     const int32_t* beam_slot;
 };
 
@@ -218,12 +218,12 @@ struct ApDose {
     int n_slots = 0;               // apertures stored
     int cur = 0;                   // voxel-major copy in use (0/1)
     uint32_t* col_vox = nullptr;   // [cap]
-    double* col_val = nullptr;     // [cap]
+    float* col_val = nullptr;      // [cap]
     uint32_t* col_ptr = nullptr;   // [N+1]
     int32_t* beam_slot = nullptr;  // [N], -1 for beams without a stored aperture
     uint32_t* vx_ptr[2] = {nullptr, nullptr};  // [nv+1]
     uint16_t* vx_beam[2] = {nullptr, nullptr}; // [cap]
-    double* vx_val[2] = {nullptr, nullptr};    // [cap]
+    float* vx_val[2] = {nullptr, nullptr};     // [cap]
     uint32_t* chunk = nullptr;     // [n_chunks + 1] non-zero counts, then offsets; [n_chunks+1] = total
     uint32_t* shift = nullptr;     // [nv] new entries before each voxel in the last merge
     double* unit = nullptr;        // [N] unit intensity vector of the aperture being stored
