@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "vmat_block.h"
@@ -312,7 +313,11 @@ vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
         A(&a->shift, (size_t)h->nv);
         A(&a->unit, (size_t)h->N + 1);  // unit[N] keeps the beam index being stored
         A(&a->view, 1);
-        if (rc == VMAT_OK) rc = ap_alloc_entries(a, std::max<int64_t>(1 << 20, 4 * h->nv));
+        // VMAT_AP_MIN_CAP: start at the smallest capacity (one dose vector),
+        // so that the store grows during a plan (read when the store is first
+        // allocated)
+        const int64_t cap0 = getenv("VMAT_AP_MIN_CAP") ? h->nv : std::max<int64_t>(1 << 20, 4 * h->nv);
+        if (rc == VMAT_OK) rc = ap_alloc_entries(a, cap0);
         if (rc == VMAT_OK && hipHostMalloc((void**)&a->total_host, sizeof(uint32_t)) != hipSuccess) {
             a->total_host = nullptr;
             rc = fail(VMAT_ERR_ALLOC, "pinned host allocation failed");

@@ -177,3 +177,36 @@ def test_reduced_precision_plan_matches_oracle_on_stored_d(fmt, mode):
         prob.close()
     print(f"{fmt}/mode {mode}: matched {matched} of {c.n_beams}")
     assert matched >= 10
+
+
+def test_aperture_store_growth_keeps_results(monkeypatch):
+    """A store that starts at its smallest capacity (one dose vector) has to
+    grow during the plan, each time copying the stored entries to larger
+    arrays; the plan is the same, bit for bit, as with the default capacity."""
+    c = small_case(n_beams=8, n_rows=4, n_cols=6, grid=(12, 12, 8))
+    out = []
+    for small in (False, True):
+        if small:
+            monkeypatch.setenv("VMAT_AP_MIN_CAP", "1")
+        else:
+            monkeypatch.delenv("VMAT_AP_MIN_CAP", raising=False)
+        prob = P.Problem.from_case(c)
+        try:
+            b0 = prob.device_bytes()
+            l, r, occ, y = prob.empty_plan()
+            rep, tr = prob.solve(l, r, occ, y, _opts(1))
+            b1 = prob.device_bytes()
+            out.append((tr, y.cpu().numpy(), l.cpu().numpy(), r.cpu().numpy(), rep.F + rep.gG, b1 - b0))
+        finally:
+            prob.close()
+    (t0, y0, l0, r0, f0, s0), (t1, y1, l1, r1, f1, s1) = out
+    # the smaller store: the hook took effect, so the appends after the first
+    # found it full (one dose vector ahead of the stored entries) and grew it
+    assert s1 < s0
+    assert len(t1["beam"]) == c.n_beams > 1
+    np.testing.assert_array_equal(t1["beam"], t0["beam"])
+    np.testing.assert_array_equal(t1["cost"], t0["cost"])
+    np.testing.assert_array_equal(y1, y0)
+    np.testing.assert_array_equal(l1, l0)
+    np.testing.assert_array_equal(r1, r0)
+    assert f1 == f0
