@@ -99,7 +99,8 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
                                                   uint32_t* __restrict__ col_vox, float* __restrict__ col_val,
                                                   const uint32_t* __restrict__ optr,
                                                   uint32_t* __restrict__ nptr, uint32_t* __restrict__ shift,
-                                                  uint16_t* __restrict__ nbeam, float* __restrict__ nval) {
+                                                  uint16_t* __restrict__ nbeam, float* __restrict__ nval,
+                                                  uint32_t* __restrict__ nvox) {
     __shared__ uint32_t sh[AP_T + 1];
     const int64_t j0 = (int64_t)blockIdx.x * AP_CHUNK + threadIdx.x * 4;
     double v[4];
@@ -123,6 +124,7 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
             nbeam[n0 + (o1 - o0)] = kb;
             const float vf = (float)v[u];
             nval[n0 + (o1 - o0)] = vf;
+            nvox[n0 + (o1 - o0)] = (uint32_t)j;
             col_vox[top + p] = (uint32_t)j;
             col_val[top + p] = vf;
             ++p;
@@ -131,26 +133,23 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
     }
 }
 
-// Moves every old entry of the voxel-major copy to its new place: entry e of
-// voxel j (old_ptr[j] <= e < old_ptr[j+1], found by binary search) goes to
-// e + shift[j].  One entry per thread, so the work does not depend on how the
-// entries are spread over the voxels; consecutive entries move to
-// consecutive places.
-__global__ __launch_bounds__(AP_T) void k_ap_copy(uint32_t n_old, int64_t nv, const uint32_t* __restrict__ optr,
-                                                  const uint32_t* __restrict__ shift,
+// Moves every old entry of the voxel-major copy to its new place: entry e
+// of voxel j = vox[e] goes to e + shift[j].  One entry per thread, so the
+// work does not depend on how the entries are spread over the voxels; reads
+// and writes stream (consecutive entries move to consecutive places, shift is
+// gathered through the cache).
+__global__ __launch_bounds__(AP_T) void k_ap_copy(uint32_t n_old, const uint32_t* __restrict__ shift,
                                                   const uint16_t* __restrict__ obeam,
-                                                  const float* __restrict__ oval, uint16_t* __restrict__ nbeam,
-                                                  float* __restrict__ nval) {
+                                                  const float* __restrict__ oval, const uint32_t* __restrict__ ovox,
+                                                  uint16_t* __restrict__ nbeam, float* __restrict__ nval,
+                                                  uint32_t* __restrict__ nvox) {
     const uint32_t e = blockIdx.x * AP_T + threadIdx.x;
     if (e >= n_old) return;
-    int64_t lo = 0, hi = nv;  // optr[lo] <= e < optr[hi]
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (optr[mid] <= e) lo = mid; else hi = mid;
-    }
-    const uint32_t dst = e + shift[lo];
+    const uint32_t j = ovox[e];
+    const uint32_t dst = e + shift[j];
     nbeam[dst] = obeam[e];
     nval[dst] = oval[e];
+    nvox[dst] = j;
 }
 
 __global__ void k_ap_slot(int slot, const int32_t* __restrict__ beam, const uint32_t* __restrict__ chunk,
@@ -256,11 +255,12 @@ static vmat_status ap_alloc(ApDose* a, T** p, size_t count) {
 static void ap_free_entries(ApDose* a) {
     auto F = [](void* p) { if (p) (void)hipFree(p); };
     F(a->col_vox); F(a->col_val);
-    F(a->vx_beam[0]); F(a->vx_beam[1]); F(a->vx_val[0]); F(a->vx_val[1]);
+    F(a->vx_beam[0]); F(a->vx_beam[1]); F(a->vx_val[0]); F(a->vx_val[1]); F(a->vx_vox[0]); F(a->vx_vox[1]);
     a->col_vox = nullptr; a->col_val = nullptr;
     a->vx_beam[0] = a->vx_beam[1] = nullptr;
     a->vx_val[0] = a->vx_val[1] = nullptr;
-    a->bytes -= a->cap * (int64_t)(4 + 4 + 2 * (2 + 4));
+    a->vx_vox[0] = a->vx_vox[1] = nullptr;
+    a->bytes -= a->cap * (int64_t)(4 + 4 + 2 * (2 + 4 + 4));
     a->cap = 0;
 }
 
@@ -268,7 +268,7 @@ static vmat_status ap_alloc_entries(ApDose* a, int64_t cap) {
     vmat_status rc = VMAT_OK;
     auto A = [&](auto** p) { if (rc == VMAT_OK) rc = ap_alloc(a, p, (size_t)cap); };
     A(&a->col_vox); A(&a->col_val);
-    A(&a->vx_beam[0]); A(&a->vx_beam[1]); A(&a->vx_val[0]); A(&a->vx_val[1]);
+    A(&a->vx_beam[0]); A(&a->vx_beam[1]); A(&a->vx_val[0]); A(&a->vx_val[1]); A(&a->vx_vox[0]); A(&a->vx_vox[1]);
     a->cap = cap;
     return rc;
 }
@@ -361,6 +361,7 @@ static vmat_status ap_grow(vmat_ctx* h, int64_t need, hipStream_t st) {
     VMAT_HIP(hipMemcpyAsync(fresh.col_val, a->col_val, n * 4, hipMemcpyDeviceToDevice, st));
     VMAT_HIP(hipMemcpyAsync(fresh.vx_beam[c], a->vx_beam[c], n * 2, hipMemcpyDeviceToDevice, st));
     VMAT_HIP(hipMemcpyAsync(fresh.vx_val[c], a->vx_val[c], n * 4, hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(fresh.vx_vox[c], a->vx_vox[c], n * 4, hipMemcpyDeviceToDevice, st));
     VMAT_HIP(hipStreamSynchronize(st));
     h->bytes -= a->bytes;
     ap_free_entries(a);
@@ -368,6 +369,7 @@ static vmat_status ap_grow(vmat_ctx* h, int64_t need, hipStream_t st) {
     for (int i = 0; i < 2; ++i) {
         a->vx_beam[i] = fresh.vx_beam[i];
         a->vx_val[i] = fresh.vx_val[i];
+        a->vx_vox[i] = fresh.vx_vox[i];
     }
     a->cap = fresh.cap;
     a->bytes += fresh.bytes;
@@ -411,12 +413,13 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
     const int c = a->cur, n = 1 - c;
     k_ap_emit<<<nch, AP_T, 0, st>>>(h->nv, nch, h->dz, a->chunk, kb, a->col_ptr, a->n_slots, a->col_vox,
                                     a->col_val, a->vx_ptr[c], a->vx_ptr[n], a->shift, a->vx_beam[n],
-                                    a->vx_val[n]);
+                                    a->vx_val[n], a->vx_vox[n]);
     VMAT_LAUNCH_CHECK();
     if (a->top > 0) {
-        k_ap_copy<<<(unsigned)((a->top + AP_T - 1) / AP_T), AP_T, 0, st>>>((uint32_t)a->top, h->nv, a->vx_ptr[c],
-                                                                          a->shift, a->vx_beam[c], a->vx_val[c],
-                                                                          a->vx_beam[n], a->vx_val[n]);
+        k_ap_copy<<<(unsigned)((a->top + AP_T - 1) / AP_T), AP_T, 0, st>>>((uint32_t)a->top, a->shift,
+                                                                          a->vx_beam[c], a->vx_val[c],
+                                                                          a->vx_vox[c], a->vx_beam[n],
+                                                                          a->vx_val[n], a->vx_vox[n]);
         VMAT_LAUNCH_CHECK();
     }
     k_ap_slot<<<1, 1, 0, st>>>(a->n_slots, kb, a->chunk, nch, a->col_ptr, a->beam_slot);

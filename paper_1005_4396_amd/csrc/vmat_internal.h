@@ -224,6 +224,7 @@ struct ApDose {
     uint32_t* vx_ptr[2] = {nullptr, nullptr};  // [nv+1]
     uint16_t* vx_beam[2] = {nullptr, nullptr}; // [cap]
     float* vx_val[2] = {nullptr, nullptr};     // [cap]
+    uint32_t* vx_vox[2] = {nullptr, nullptr};  // [cap] voxel of each entry (read only by the merge)
     uint32_t* chunk = nullptr;     // [n_chunks + 1] non-zero counts, then offsets; [n_chunks+1] = total
     uint32_t* shift = nullptr;     // [nv] new entries before each voxel in the last merge
     double* unit = nullptr;        // [N] unit intensity vector of the aperture being stored
