@@ -58,14 +58,15 @@ inline MasterPtrs master_ptrs(const vmat_ctx* h, double* y, const uint8_t* occ, 
 // 1 at a fresh start, 2 at a carried-over start.
 __device__ inline void ctrl_grad(const MasterPtrs& m, double F, int first, double* sh) {
     const int N = m.N;
-    const double G = smoothing_G(m.y, m.th, N, m.circ, sh);
+    double G = smoothing_G_part(m.y, m.th, N, m.circ);
     double ref = 0.0;
     for (int k = threadIdx.x; k < N; k += CTRL) {
         const double gk = m.gF[k] + m.gamma * dG_at(k, m.y, m.th, N, m.circ);
         m.grad[k] = gk;
         if (m.occ[k]) ref = fmax(ref, fabs(gk));
     }
-    ref = bmax(ref, sh);
+    bred2<RED_SUM, RED_MAX>(G, ref);
+    (void)sh;
     if (threadIdx.x != 0) return;
     MasterState& s = *m.ms;
     s.F = F;
@@ -85,6 +86,7 @@ __device__ inline void ctrl_grad(const MasterPtrs& m, double F, int first, doubl
 // direction is rounded to FP32, the precision in which the batched products
 // take it, so that y and the carried dose move by the same step.
 __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi, bool f32_dir = false) {
+    (void)shi;
     auto rnd = [f32_dir](double v) { return f32_dir ? (double)(float)v : v; };
     const int N = m.N;
     MasterState& s0 = *m.ms;
@@ -110,8 +112,9 @@ __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi, bool 
         if (w != W_prev[k]) changed = 1;
         d[k] = w ? rnd(-grad[k]) : 0.0;
     }
-    kkt = bmax(kkt, sh);
-    changed = bor(changed, shi);
+    double chg = __any(changed) ? 1.0 : 0.0;
+    bred2<RED_MAX, RED_MAX>(kkt, chg);
+    changed = chg != 0.0;
     const double tol_abs = s0.tol * s0.kkt_ref;
     if (kkt <= tol_abs || s0.it >= s0.max_iter) {
         __syncthreads();
@@ -131,8 +134,7 @@ __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi, bool 
             den += gp * gp;
             num += gw * (gw - gp);
         }
-        den = bsum(den, sh);
-        num = bsum(num, sh);
+        bred2<RED_SUM, RED_SUM>(den, num);
         b_cg = den > 0.0 ? fmax(0.0, num / den) : 0.0;
         double slope = 0.0;
         for (int k = threadIdx.x; k < N; k += CTRL) {
@@ -152,10 +154,10 @@ __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi, bool 
         if (dk != 0.0) any = 1;
         sl += dG_at(k, y, th, N, circ) * dk;
     }
-    tmax = bmin(tmax, sh);
-    any = bor(any, shi);
-    sl = bsum(sl, sh);
-    const double curv = smoothing_dHd(d, th, N, circ, sh);
+    double curv = smoothing_dHd_part(d, th, N, circ);
+    double anyd = __any(any) ? 1.0 : 0.0;
+    bred4<RED_MIN, RED_MAX, RED_SUM, RED_SUM>(tmax, anyd, sl, curv);
+    any = anyd != 0.0;
     if (threadIdx.x != 0) return;
     MasterState& s = s0;
     s.kkt = kkt;
