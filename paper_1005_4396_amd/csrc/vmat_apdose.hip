@@ -38,23 +38,25 @@ __global__ __launch_bounds__(AP_T) void k_ap_unit(int N, const int32_t* __restri
 }
 
 __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t* sh, uint32_t* total) {
-    // sh: AP_T + 1 entries; fixed sequential scan by thread 0 over the block
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int t = 0; t < AP_T; ++t) {
-            const uint32_t c = sh[t];
-            sh[t] = run;
-            run += c;
-        }
-        sh[AP_T] = run;
+    // sh: at least AP_T / 64 entries.  Inclusive scan within each wave
+    // (shuffles), then the wave totals in order; exact integer sums.
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
     }
+    if (lane == 63) sh[wid] = x;
     __syncthreads();
-    const uint32_t r = sh[threadIdx.x];
-    *total = sh[AP_T];
+    uint32_t base = 0, tot = 0;
+    for (int w = 0; w < AP_T / 64; ++w) {
+        const uint32_t t = sh[w];
+        if (w < wid) base += t;
+        tot += t;
+    }
+    *total = tot;
     __syncthreads();
-    return r;
+    return base + x - v;
 }
 
 // Non-zeros of d per chunk of AP_CHUNK voxels.
