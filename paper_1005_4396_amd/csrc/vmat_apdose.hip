@@ -27,7 +27,7 @@
 namespace vmat {
 
 constexpr int AP_CHUNK = 1024;  // voxels per chunk of the compaction
-constexpr int AP_T = 256;       // threads per block (4 voxels each)
+constexpr int AP_T = 256;       // threads per block
 
 // Unit intensity on the aperture being stored: beam = *src if src, else beam_h.
 __global__ __launch_bounds__(AP_T) void k_ap_unit(int N, const int32_t* __restrict__ src, int beam_h,
@@ -164,9 +164,12 @@ __global__ void k_ap_slot(int slot, const int32_t* __restrict__ beam, const uint
 // is staged in LDS.  G lanes share a voxel: lane t of the group takes the
 // voxel's entries t, t + G, ... in order, two at a time, and the group sums
 // with a fixed shuffle tree, so a voxel with an entry from every aperture
-// (the target's) costs its group 1/G of the serial walk.
-constexpr int AP_DG = 4;
-
+// (the target's) costs its group 1/G of the serial walk.  G = 2 measured
+// fastest on the prostate plan (1, 4 and 8 slower: a lone lane walks the
+// target voxels serially, wider groups idle on the many voxels with few
+// entries); a grid with fewer voxels than it takes to fill the chip's wave
+// slots at G = 2 uses G = 4 (more loads in flight).
+template <int AP_DG>
 __global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, int N, const ApView* __restrict__ view,
                                                   const double* __restrict__ vec, double* __restrict__ out,
                                                   Gate gate) {
@@ -432,10 +435,15 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
 }
 
 vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate, hipStream_t st) {
-    const int64_t threads = h->nv * AP_DG;
-    k_ap_dose<<<(unsigned)((threads + AP_T - 1) / AP_T), AP_T, sizeof(double) * h->N, st>>>(h->nv, h->N,
-                                                                                          h->ap->view, vec, out,
-                                                                                          gate);
+    // wave slots of the chip: 256 CUs x 4 SIMDs x 8 waves x 64 lanes
+    constexpr int64_t LANE_SLOTS = 256 * 4 * 8 * 64;
+    const size_t lds = sizeof(double) * h->N;
+    if (2 * h->nv >= LANE_SLOTS)
+        k_ap_dose<2><<<(unsigned)((2 * h->nv + AP_T - 1) / AP_T), AP_T, lds, st>>>(h->nv, h->N, h->ap->view, vec,
+                                                                                 out, gate);
+    else
+        k_ap_dose<4><<<(unsigned)((4 * h->nv + AP_T - 1) / AP_T), AP_T, lds, st>>>(h->nv, h->N, h->ap->view, vec,
+                                                                                 out, gate);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
