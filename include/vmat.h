@@ -256,8 +256,10 @@ typedef struct vmat_solve_opts {
                               *    aperture opens (one forward each) and the master works
                               *    on them alone; one adjoint per column-generation
                               *    iteration gives the prices.  Same iterates up to
-                              *    rounding; the store (about 32 B per non-zero of the
-                              *    aperture doses) is allocated on first use.          */
+                              *    rounding (values stored in FP32, sums in FP64); the
+                              *    store (28 B per non-zero of the aperture doses, with
+                              *    room for one dose vector more) is allocated on first
+                              *    use.                                                */
     vmat_master_opts master; /* master.kkt_ref <= 0: |p| of the first priced aperture       */
 } vmat_solve_opts;
 
