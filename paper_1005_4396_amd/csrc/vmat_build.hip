@@ -578,7 +578,10 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
 
     // work buffers
     const int64_t N = h->N, NR = (int64_t)h->N * h->R;
-    h->n_part = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (h->nv + 2047) / 2048));
+    // partial-sum workgroups of the voxel passes: one per 2048 voxels, at
+    // least 256 (a small grid leaves CUs idle on these latency-bound passes)
+    // and at most 1024 (every pass reduces all partials of the previous one)
+    h->n_part = (int)std::min<int64_t>(1024, std::max<int64_t>(256, (h->nv + 2047) / 2048));
     if ((rc = dalloc(h, &h->d_theta, N)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->x, h->nb)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->z, h->nv)) != VMAT_OK) return bail(rc);
