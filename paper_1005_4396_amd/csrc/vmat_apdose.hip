@@ -98,7 +98,7 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
                                                   const uint32_t* __restrict__ chunk,
                                                   const int32_t* __restrict__ beam,
                                                   const uint32_t* __restrict__ col_ptr, int slot,
-                                                  uint32_t* __restrict__ col_vox, float* __restrict__ col_val,
+                                                  ApEntry* __restrict__ col,
                                                   const uint32_t* __restrict__ optr,
                                                   uint32_t* __restrict__ nptr, uint32_t* __restrict__ shift,
                                                   uint16_t* __restrict__ nbeam, float* __restrict__ nval,
@@ -127,8 +127,7 @@ __global__ __launch_bounds__(AP_T) void k_ap_emit(int64_t nv, int n_chunks, cons
             const float vf = (float)v[u];
             nval[n0 + (o1 - o0)] = vf;
             nvox[n0 + (o1 - o0)] = (uint32_t)j;
-            col_vox[top + p] = (uint32_t)j;
-            col_val[top + p] = vf;
+            col[top + p] = ApEntry{(uint32_t)j, vf};
             ++p;
         }
         if (j == nv - 1) nptr[nv] = optr[nv] + chunk[n_chunks];
@@ -212,23 +211,24 @@ __global__ __launch_bounds__(AP_GT) void k_ap_grad(const ApView* __restrict__ vi
     const int s = view->beam_slot[k];
     double acc = 0.0;
     if (s >= 0) {
-        const uint32_t* __restrict__ vox = view->col_vox;
-        const float* __restrict__ val = view->col_val;
+        const ApEntry* __restrict__ col = view->col;
         const uint32_t a0 = view->col_ptr[s], a1 = view->col_ptr[s + 1];
         const uint32_t share = (a1 - a0 + Q - 1) / Q;
         const uint32_t e0 = a0 + min(a1 - a0, (uint32_t)q * share);
         const uint32_t e1 = a0 + min(a1 - a0, (uint32_t)(q + 1) * share);
         uint32_t e = e0 + threadIdx.x;
         for (; e + 3 * AP_GT < e1; e += 4 * AP_GT) {
-            const uint32_t j0 = vox[e], j1 = vox[e + AP_GT], j2 = vox[e + 2 * AP_GT], j3 = vox[e + 3 * AP_GT];
-            const float v0 = val[e], v1 = val[e + AP_GT], v2 = val[e + 2 * AP_GT], v3 = val[e + 3 * AP_GT];
-            const float w0 = w[j0], w1 = w[j1], w2 = w[j2], w3 = w[j3];
-            acc = fma((double)v0, (double)w0, acc);
-            acc = fma((double)v1, (double)w1, acc);
-            acc = fma((double)v2, (double)w2, acc);
-            acc = fma((double)v3, (double)w3, acc);
+            const ApEntry c0 = col[e], c1 = col[e + AP_GT], c2 = col[e + 2 * AP_GT], c3 = col[e + 3 * AP_GT];
+            const float w0 = w[c0.vox], w1 = w[c1.vox], w2 = w[c2.vox], w3 = w[c3.vox];
+            acc = fma((double)c0.val, (double)w0, acc);
+            acc = fma((double)c1.val, (double)w1, acc);
+            acc = fma((double)c2.val, (double)w2, acc);
+            acc = fma((double)c3.val, (double)w3, acc);
         }
-        for (; e < e1; e += AP_GT) acc = fma((double)val[e], (double)w[vox[e]], acc);
+        for (; e < e1; e += AP_GT) {
+            const ApEntry c = col[e];
+            acc = fma((double)c.val, (double)w[c.vox], acc);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
@@ -259,9 +259,9 @@ static vmat_status ap_alloc(ApDose* a, T** p, size_t count) {
 
 static void ap_free_entries(ApDose* a) {
     auto F = [](void* p) { if (p) (void)hipFree(p); };
-    F(a->col_vox); F(a->col_val);
+    F(a->col);
     F(a->vx_beam[0]); F(a->vx_beam[1]); F(a->vx_val[0]); F(a->vx_val[1]); F(a->vx_vox[0]); F(a->vx_vox[1]);
-    a->col_vox = nullptr; a->col_val = nullptr;
+    a->col = nullptr;
     a->vx_beam[0] = a->vx_beam[1] = nullptr;
     a->vx_val[0] = a->vx_val[1] = nullptr;
     a->vx_vox[0] = a->vx_vox[1] = nullptr;
@@ -272,7 +272,7 @@ static void ap_free_entries(ApDose* a) {
 static vmat_status ap_alloc_entries(ApDose* a, int64_t cap) {
     vmat_status rc = VMAT_OK;
     auto A = [&](auto** p) { if (rc == VMAT_OK) rc = ap_alloc(a, p, (size_t)cap); };
-    A(&a->col_vox); A(&a->col_val);
+    A(&a->col);
     A(&a->vx_beam[0]); A(&a->vx_beam[1]); A(&a->vx_val[0]); A(&a->vx_val[1]); A(&a->vx_vox[0]); A(&a->vx_vox[1]);
     a->cap = cap;
     return rc;
@@ -296,7 +296,7 @@ void free_apdose(vmat_ctx* h) {
 static vmat_status ap_publish(vmat_ctx* h, hipStream_t st) {
     const ApDose* a = h->ap;
     const int c = a->cur;
-    ApView v{a->vx_ptr[c], a->vx_beam[c], a->vx_val[c], a->col_ptr, a->col_vox, a->col_val, a->beam_slot};
+    ApView v{a->vx_ptr[c], a->vx_beam[c], a->vx_val[c], a->col_ptr, a->col, a->beam_slot};
     k_ap_view<<<1, 1, 0, st>>>(a->view, v);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
@@ -362,15 +362,14 @@ static vmat_status ap_grow(vmat_ctx* h, int64_t need, hipStream_t st) {
     }
     const size_t n = (size_t)a->top;
     const int c = a->cur;
-    VMAT_HIP(hipMemcpyAsync(fresh.col_vox, a->col_vox, n * 4, hipMemcpyDeviceToDevice, st));
-    VMAT_HIP(hipMemcpyAsync(fresh.col_val, a->col_val, n * 4, hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(fresh.col, a->col, n * sizeof(ApEntry), hipMemcpyDeviceToDevice, st));
     VMAT_HIP(hipMemcpyAsync(fresh.vx_beam[c], a->vx_beam[c], n * 2, hipMemcpyDeviceToDevice, st));
     VMAT_HIP(hipMemcpyAsync(fresh.vx_val[c], a->vx_val[c], n * 4, hipMemcpyDeviceToDevice, st));
     VMAT_HIP(hipMemcpyAsync(fresh.vx_vox[c], a->vx_vox[c], n * 4, hipMemcpyDeviceToDevice, st));
     VMAT_HIP(hipStreamSynchronize(st));
     h->bytes -= a->bytes;
     ap_free_entries(a);
-    a->col_vox = fresh.col_vox; a->col_val = fresh.col_val;
+    a->col = fresh.col;
     for (int i = 0; i < 2; ++i) {
         a->vx_beam[i] = fresh.vx_beam[i];
         a->vx_val[i] = fresh.vx_val[i];
@@ -416,8 +415,8 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
     VMAT_HIP(hipEventRecord(a->counted, st));
     a->pending = 1;
     const int c = a->cur, n = 1 - c;
-    k_ap_emit<<<nch, AP_T, 0, st>>>(h->nv, nch, h->dz, a->chunk, kb, a->col_ptr, a->n_slots, a->col_vox,
-                                    a->col_val, a->vx_ptr[c], a->vx_ptr[n], a->shift, a->vx_beam[n],
+    k_ap_emit<<<nch, AP_T, 0, st>>>(h->nv, nch, h->dz, a->chunk, kb, a->col_ptr, a->n_slots, a->col,
+                                    a->vx_ptr[c], a->vx_ptr[n], a->shift, a->vx_beam[n],
                                     a->vx_val[n], a->vx_vox[n]);
     VMAT_LAUNCH_CHECK();
     if (a->top > 0) {

@@ -195,13 +195,19 @@ constexpr int GRAPH_KEY_LEN = 10;  // words identifying a captured sequence
 
 // Device-side view of the aperture-dose store, read by the master's kernels,
 // so that a captured master iteration stays valid while the store grows.
+// One aperture-major entry of the aperture doses: voxel and value, loaded
+// as one 8-byte word.
+struct alignas(8) ApEntry {
+    uint32_t vox;
+    float val;
+};
+
 struct ApView {
     const uint32_t* vx_ptr;
     const uint16_t* vx_beam;
     const float* vx_val;
     const uint32_t* col_ptr;
-    const uint32_t* col_vox;
-    const float* col_val;
+    const ApEntry* col;
     const int32_t* beam_slot;
 };
 
@@ -217,8 +223,7 @@ struct ApDose {
     int pending = 0;               // 1: the last aperture's count is still in total_host
     int n_slots = 0;               // apertures stored
     int cur = 0;                   // voxel-major copy in use (0/1)
-    uint32_t* col_vox = nullptr;   // [cap]
-    float* col_val = nullptr;      // [cap]
+    ApEntry* col = nullptr;        // [cap]
     uint32_t* col_ptr = nullptr;   // [N+1]
     int32_t* beam_slot = nullptr;  // [N], -1 for beams without a stored aperture
     uint32_t* vx_ptr[2] = {nullptr, nullptr};  // [nv+1]
