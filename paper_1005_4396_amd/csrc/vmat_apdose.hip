@@ -153,10 +153,14 @@ __global__ __launch_bounds__(AP_T) void k_ap_copy(uint32_t n_old, const uint32_t
     nvox[dst] = j;
 }
 
+// Closes an append: the new aperture's slot, then the device view of the
+// store's current pointers.
 __global__ void k_ap_slot(int slot, const int32_t* __restrict__ beam, const uint32_t* __restrict__ chunk,
-                          int n_chunks, uint32_t* __restrict__ col_ptr, int32_t* __restrict__ beam_slot) {
+                          int n_chunks, uint32_t* __restrict__ col_ptr, int32_t* __restrict__ beam_slot,
+                          ApView* view, ApView v) {
     col_ptr[slot + 1] = col_ptr[slot] + chunk[n_chunks];
     beam_slot[beam[0]] = slot;
+    *view = v;
 }
 
 // out_j = sum over voxel j's entries of val * vec[beam]; the per-beam vector
@@ -292,12 +296,14 @@ void free_apdose(vmat_ctx* h) {
     h->ap = nullptr;
 }
 
+// The store's pointers with voxel-major copy c.
+static ApView view_of(const ApDose* a, int c) {
+    return ApView{a->vx_ptr[c], a->vx_beam[c], a->vx_val[c], a->col_ptr, a->col, a->beam_slot};
+}
+
 // Writes the current pointers to the device view.
 static vmat_status ap_publish(vmat_ctx* h, hipStream_t st) {
-    const ApDose* a = h->ap;
-    const int c = a->cur;
-    ApView v{a->vx_ptr[c], a->vx_beam[c], a->vx_val[c], a->col_ptr, a->col, a->beam_slot};
-    k_ap_view<<<1, 1, 0, st>>>(a->view, v);
+    k_ap_view<<<1, 1, 0, st>>>(h->ap->view, view_of(h->ap, h->ap->cur));
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
@@ -426,11 +432,11 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
                                                                           a->vx_val[n], a->vx_vox[n]);
         VMAT_LAUNCH_CHECK();
     }
-    k_ap_slot<<<1, 1, 0, st>>>(a->n_slots, kb, a->chunk, nch, a->col_ptr, a->beam_slot);
+    k_ap_slot<<<1, 1, 0, st>>>(a->n_slots, kb, a->chunk, nch, a->col_ptr, a->beam_slot, a->view, view_of(a, n));
     VMAT_LAUNCH_CHECK();
     a->n_slots += 1;
     a->cur = n;
-    return ap_publish(h, st);
+    return VMAT_OK;
 }
 
 vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate, hipStream_t st) {
