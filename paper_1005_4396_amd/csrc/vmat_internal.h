@@ -213,7 +213,7 @@ struct ApView {
 
 // Aperture doses (master over the generated apertures): d_k = D^T 1_{A_k} for
 // every occupied beam, built once when the aperture is opened.  Two copies:
-// aperture-major (col_*: entries of slot s in [col_ptr[s], col_ptr[s+1]),
+// aperture-major (col, col_ptr: entries of slot s in [col_ptr[s], col_ptr[s+1]),
 // voxels ascending) for the per-aperture sums of F'(z), and voxel-major
 // (vx_*: ping-pong pair rebuilt by merging each new aperture, entries of a
 // voxel in opening order) for the dose of an intensity vector.
