@@ -204,9 +204,11 @@ __global__ __launch_bounds__(AP_T) void k_ap_dose(int64_t nv, int N, const ApVie
 // gF_k = <d_k, w> (0 without a stored aperture) in Q parts: block (k, q)
 // takes the q-th of Q equal contiguous shares of aperture k's entries; thread
 // t takes entries t, t + AP_GT, ... of the share with four loads in flight,
-// then a fixed reduction tree; out[k*Q + q] = the share's sum.
-constexpr int AP_GT = 256;
-
+// then a fixed reduction tree; out[k*Q + q] = the share's sum.  AP_GT = 512
+// on grids that fill the chip at two lanes per voxel (their apertures hold
+// more entries per share: 1% faster on the prostate plan), else 256 (512 is
+// 1.5% slower on the mixed-resolution plan's coarse grid).
+template <int AP_GT>
 __global__ __launch_bounds__(AP_GT) void k_ap_grad(const ApView* __restrict__ view, const float* __restrict__ w,
                                                    int Q, double* __restrict__ out, Gate gate) {
     __shared__ double sh[AP_GT / 64];
@@ -439,11 +441,16 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
     return VMAT_OK;
 }
 
-vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate, hipStream_t st) {
-    // wave slots of the chip: 256 CUs x 4 SIMDs x 8 waves x 64 lanes
+// A voxel grid that fills the chip's wave slots (256 CUs x 4 SIMDs x 8 waves
+// x 64 lanes) at two lanes per voxel.
+static bool ap_large_grid(const vmat_ctx* h) {
     constexpr int64_t LANE_SLOTS = 256 * 4 * 8 * 64;
+    return 2 * h->nv >= LANE_SLOTS;
+}
+
+vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate, hipStream_t st) {
     const size_t lds = sizeof(double) * h->N;
-    if (2 * h->nv >= LANE_SLOTS)
+    if (ap_large_grid(h))
         k_ap_dose<2><<<(unsigned)((2 * h->nv + AP_T - 1) / AP_T), AP_T, lds, st>>>(h->nv, h->N, h->ap->view, vec,
                                                                                  out, gate);
     else
@@ -454,7 +461,10 @@ vmat_status ap_dose(const vmat_ctx* h, const double* vec, double* out, Gate gate
 }
 
 vmat_status ap_grad(const vmat_ctx* h, const float* w, double* out, int Q, Gate gate, hipStream_t st) {
-    k_ap_grad<<<(unsigned)(h->N * Q), AP_GT, 0, st>>>(h->ap->view, w, Q, out, gate);
+    if (ap_large_grid(h))
+        k_ap_grad<512><<<(unsigned)(h->N * Q), 512, 0, st>>>(h->ap->view, w, Q, out, gate);
+    else
+        k_ap_grad<256><<<(unsigned)(h->N * Q), 256, 0, st>>>(h->ap->view, w, Q, out, gate);
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
