@@ -32,10 +32,28 @@ def _rows(name):
 # ---------------------------------------------------------------- eq. 1 / eq. 2
 
 def test_eq1_penalty_golden():
-    for a, b, T, z, F, dF in _rows("eq1_penalty.txt"):
+    for a, b, T, z, F, dF, d2F in _rows("eq1_penalty.txt"):
         Fo, dFo = O.penalty(np.array([z]), np.array([a]), np.array([b]), np.array([T]))
         assert Fo == F
         assert dFo[0] == dF
+        assert O.curvature(np.array([z]), np.array([a]), np.array([b]), np.array([T]))[0] == d2F
+
+
+def test_eq1_curvature_is_second_difference():
+    """Away from the threshold F is a quadratic on each side, so the second
+    difference of eq. 1 is exact: it must equal the curvature on both sides."""
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        a, b = rng.integers(0, 5, 2).astype(float)
+        a, b = (a, b) if a != b else (a, b + 1.0)
+        T = float(rng.integers(5, 50))
+        for z in (T - 2.0 - rng.random(), T + 2.0 + rng.random()):
+            h = 0.5
+            Fz = [O.penalty(np.array([v]), np.array([a]), np.array([b]), np.array([T]))[0]
+                  for v in (z - h, z, z + h)]
+            d2 = (Fz[0] - 2 * Fz[1] + Fz[2]) / (h * h)
+            assert O.curvature(np.array([z]), np.array([a]), np.array([b]), np.array([T]))[0] == \
+                pytest.approx(d2, rel=1e-9, abs=1e-9)
 
 
 def test_eq1_zero_dose_cost():
@@ -250,6 +268,106 @@ def test_leaf_bounds_deliverable_against_all_occupied():
             assert np.all(pr.l <= pr.r)
             occ[k] = 1
             l[k * R:(k + 1) * R], r[k * R:(k + 1) * R] = pr.l, pr.r
+
+
+def _leaf_window_cases():
+    cases, cur = [], None
+    with open(os.path.join(GOLDEN, "leaf_window.txt")) as f:
+        for line in f:
+            w = line.split("#")[0].split()
+            if not w:
+                continue
+            if w[0] == "setup":
+                N, R, C, delta, circ = (int(v) for v in w[2:])
+                cur = dict(name=w[1], N=N, R=R, C=C, delta=delta, circ=circ, occ=np.zeros(N, np.uint8),
+                           l=np.zeros(N * R, np.int64), r=np.zeros(N * R, np.int64), win=[])
+                cases.append(cur)
+            elif w[0] == "occ":
+                k, lr = int(w[1]), [int(v) for v in w[2:]]
+                cur["occ"][k] = 1
+                cur["l"][k * cur["R"]:(k + 1) * cur["R"]] = lr[0::2]
+                cur["r"][k * cur["R"]:(k + 1) * cur["R"]] = lr[1::2]
+            elif w[0] == "win":
+                cur["win"].append(tuple(int(v) for v in w[1:]))
+    return cases
+
+
+def test_leaf_bounds_golden_windows():
+    """Hand-worked leaf windows (tests/golden/leaf_window.txt): neighbours at
+    distances 1 to 4, open and circular chains, delta 1 and 2, unconstrained,
+    and no occupied beam."""
+    n = 0
+    for cs in _leaf_window_cases():
+        for k, rho, Llo, Lhi, Rlo, Rhi in cs["win"]:
+            w = O.leaf_bounds(k, cs["l"], cs["r"], cs["occ"], cs["R"], cs["C"], cs["delta"], cs["circ"])
+            assert tuple(int(v[rho]) for v in w) == (Llo, Lhi, Rlo, Rhi), (cs["name"], k, rho)
+            n += 1
+    assert n == 19
+
+
+def test_leaf_bounds_window_is_every_deliverable_position():
+    """Brute force: a leaf position is in the window exactly when, for every
+    occupied beam a, it is within delta * d(a) of beam a's leaf, where d(a)
+    is the number of beam steps from k to a along the chain in the direction
+    in which a is the first occupied beam (every occupied beam is reached from
+    k through the nearest one on that side, so this is the reading's rule
+    written out over all beams)."""
+    rng = np.random.default_rng(15)
+    for circ in (0, 1):
+        for _ in range(40):
+            N, R, C, delta = int(rng.integers(3, 9)), 2, int(rng.integers(3, 9)), int(rng.integers(0, 3))
+            occ = np.zeros(N, np.uint8)
+            l = np.zeros(N * R, np.int64)
+            r = np.zeros(N * R, np.int64)
+            for _ in range(int(rng.integers(1, N))):
+                g = rng.standard_normal(N * R * C)
+                pr = O.price(g, np.zeros(N), l, r, occ, np.arange(N) * (360.0 / N), 0.0, R, C, delta, circ,
+                             with_margins=False)
+                occ[pr.beam] = 1
+                l[pr.beam * R:(pr.beam + 1) * R], r[pr.beam * R:(pr.beam + 1) * R] = pr.l, pr.r
+            for k in np.flatnonzero(occ == 0):
+                Llo, Lhi, Rlo, Rhi = O.leaf_bounds(k, l, r, occ, R, C, delta, circ)
+                # the first occupied beam met walking each way from k, with its step count
+                walks = []
+                for step in (-1, 1):
+                    for dist in range(1, N):
+                        kk = k + step * dist
+                        if not circ and not 0 <= kk < N:
+                            break
+                        if occ[kk % N]:
+                            walks.append((kk % N, dist))
+                            break
+                for rho in range(R):
+                    for leaf, lo, hi in ((l, Llo, Lhi), (r, Rlo, Rhi)):
+                        ok = [p for p in range(C + 1)
+                              if all(abs(p - leaf[a * R + rho]) <= delta * dist for a, dist in walks)]
+                        if ok:
+                            assert (lo[rho], hi[rho]) == (ok[0], ok[-1])
+                            assert ok == list(range(ok[0], ok[-1] + 1))
+                        else:
+                            assert lo[rho] > hi[rho]
+
+
+def test_beam_price_exact_tie_goes_to_smaller_beam():
+    """Two unoccupied beams with identical rows and identical neighbours have
+    the same price to the last bit; the smaller beam index is chosen and the
+    beam margin is zero."""
+    N, R, C = 4, 2, 3
+    th = np.array([0.0, 90.0, 180.0, 270.0])
+    g = np.zeros((N, R, C))
+    g[1] = g[3] = [[-1.0, -2.0, 0.5], [0.25, -0.75, -0.5]]
+    g[0] = g[2] = [[-0.5, 0.0, 0.0], [0.0, 0.0, -0.25]]
+    for gamma, occ, y in ((0.0, np.zeros(N, np.uint8), np.zeros(N)),
+                          (0.3, np.array([1, 0, 1, 0], np.uint8), np.array([1.5, 0.0, 1.5, 0.0]))):
+        l = np.zeros(N * R, np.int64)
+        r = np.where(np.repeat(occ, R) == 1, C, 0).astype(np.int64)
+        gg = g.copy()
+        gg[occ == 1] = 0.0
+        pr = O.price(gg.reshape(-1), y, l, r, occ, th, gamma, R, C, -1, 1)
+        assert pr.beam_prices[1] == pr.beam_prices[3]
+        assert pr.beam == 1
+        assert pr.margin == 0.0
+        assert list(pr.l) == [0, 1] and list(pr.r) == [2, 3]
 
 
 def test_beam_price_includes_smoothing_derivative():
