@@ -270,14 +270,20 @@ typedef struct vmat_solve_report {
 } vmat_solve_report;
 
 /* Per-iteration record (HOST arrays, each nullable, length max iterations;
- * cost has one more entry: cost[0] is the cost before the first aperture).     */
+ * cost has one more entry: cost[0] is the cost before the first aperture).
+ * y holds N entries per iteration: the intensities the pricing of that
+ * iteration saw (the solution of the previous master, before the new
+ * aperture opened at 0).  With the beam order and the final leaf pairs
+ * (apertures never change once opened) it gives the plan state at every
+ * iteration, so a reference can re-price each decision from the same state. */
 typedef struct vmat_solve_trace {
     int32_t* beam;
-    double* price;
-    double* margin;
-    double* row_margin;
-    double* cost;
+    double* price;          /* p_k* of the chosen beam                        */
+    double* margin;         /* second-best beam price minus p_k*             */
+    double* row_margin;     /* least gap to a different row sum in beam k*   */
+    double* cost;           /* F + gamma G after each master                 */
     int32_t* master_iters;
+    double* y;              /* [iterations * N]                               */
 } vmat_solve_trace;
 
 /* Column generation (abstract; Sec. 2.2): repeat pricing -> add the aperture

@@ -497,6 +497,7 @@ class SolveResult:
     costs: list          # cost_0 (no apertures), then after each master solve
     master_iters: list
     apertures: list      # (l[R], r[R]) chosen at each iteration
+    priced_y: list = dataclasses.field(default_factory=list)  # intensities each pricing saw
 
 
 def solve(D, alpha, beta, T, theta_deg, gamma, circular, R, C, delta, max_cg_iter=None,
@@ -517,6 +518,7 @@ def solve(D, alpha, beta, T, theta_deg, gamma, circular, R, C, delta, max_cg_ite
     ref = None
     iters = N if max_cg_iter is None else min(N, max_cg_iter)
     for _ in range(iters):
+        out.priced_y.append(np.array(y, dtype=np.float64))
         pr = price(g, y, l, r, occ, theta_deg, gamma, R, C, delta, circular, with_margins)
         if pr.beam < 0:
             break

@@ -263,24 +263,29 @@ static vmat_status ap_alloc(ApDose* a, T** p, size_t count) {
     return VMAT_OK;
 }
 
+// Frees the entry arrays (those allocated: after a failed allocation some are
+// null) and takes exactly their bytes off the count.
 static void ap_free_entries(ApDose* a) {
-    auto F = [](void* p) { if (p) (void)hipFree(p); };
+    const int64_t cap = std::max<int64_t>(a->cap, 1);
+    auto F = [&](auto*& p) {
+        if (!p) return;
+        (void)hipFree(p);
+        a->bytes -= cap * (int64_t)sizeof(*p);
+        p = nullptr;
+    };
     F(a->col);
     F(a->vx_beam[0]); F(a->vx_beam[1]); F(a->vx_val[0]); F(a->vx_val[1]); F(a->vx_vox[0]); F(a->vx_vox[1]);
-    a->col = nullptr;
-    a->vx_beam[0] = a->vx_beam[1] = nullptr;
-    a->vx_val[0] = a->vx_val[1] = nullptr;
-    a->vx_vox[0] = a->vx_vox[1] = nullptr;
-    a->bytes -= a->cap * (int64_t)(4 + 4 + 2 * (2 + 4 + 4));
     a->cap = 0;
 }
 
+// The entry arrays at capacity cap; on failure the ones allocated stay for
+// ap_free_entries.
 static vmat_status ap_alloc_entries(ApDose* a, int64_t cap) {
     vmat_status rc = VMAT_OK;
+    a->cap = cap;
     auto A = [&](auto** p) { if (rc == VMAT_OK) rc = ap_alloc(a, p, (size_t)cap); };
     A(&a->col);
     A(&a->vx_beam[0]); A(&a->vx_beam[1]); A(&a->vx_val[0]); A(&a->vx_val[1]); A(&a->vx_vox[0]); A(&a->vx_vox[1]);
-    a->cap = cap;
     return rc;
 }
 

@@ -95,7 +95,8 @@ vmat_status check_opts(const vmat_master_opts& o) {
 // Waits until the device has completed line-search chain `want` of this
 // handle (the mirror's count), spinning on the pinned mirror; after about two
 // seconds without progress it drains the stream and looks once more.  Then
-// copies the mirrored state to ms_host.
+// copies chain `want`'s state (its mirror slot, which no chain enqueued so far
+// writes again) to ms_host.
 vmat_status wait_chain(vmat_ctx* h, uint32_t want, hipStream_t st) {
     const MasterMirror* mir = h->mirror;
     auto reached = [&]() {
@@ -114,7 +115,7 @@ vmat_status wait_chain(vmat_ctx* h, uint32_t want, hipStream_t st) {
             }
         }
     }
-    std::memcpy((void*)h->ms_host, (const void*)&mir->s, sizeof(MasterState));
+    std::memcpy((void*)h->ms_host, (const void*)&mir->s[want & 1u], sizeof(MasterState));
     return VMAT_OK;
 }
 
@@ -225,13 +226,8 @@ vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const
 vmat_status run_master(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
                        const vmat_master_opts& o, vmat_master_report* rep, hipStream_t st, int fresh = 1,
                        int mode = 0) {
-    // The gated pipeline (one state read per chunk of iterations) measured no
-    // faster than one read per iteration on the prostate case; the separate-
-    // kernel driver stays the default and the pipeline is selectable.
     if (mode == 1) {
         TRY(run_master_ap(h, l, r, occ, y, o, fresh, st));
-    } else if (getenv("VMAT_PIPELINED_MASTER")) {
-        TRY(run_master_fused(h, l, r, occ, y, o, fresh, st));
     } else {
         TRY(run_master_plain(h, l, r, occ, y, o, fresh, st));
     }
@@ -488,6 +484,8 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
         if (trace->margin && n) VMAT_HIP(hipMemcpyAsync(trace->margin, h->tr.margin, n * sizeof(double), hipMemcpyDeviceToHost, st));
         if (trace->row_margin && n)
             VMAT_HIP(hipMemcpyAsync(trace->row_margin, h->tr.row_margin, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (trace->y && n)
+            VMAT_HIP(hipMemcpyAsync(trace->y, h->tr.y, (size_t)n * N * sizeof(double), hipMemcpyDeviceToHost, st));
         VMAT_HIP(hipStreamSynchronize(st));
         if (trace->cost) std::copy(costs.begin(), costs.begin() + n + 1, trace->cost);
         if (trace->master_iters) std::copy(miters.begin(), miters.begin() + n, trace->master_iters);

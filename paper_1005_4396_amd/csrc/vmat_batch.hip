@@ -819,7 +819,7 @@ void free_batch(vmat_ctx* h) {
     F(b->grad); F(b->grad_prev); F(b->d); F(b->d_prev); F(b->gF); F(b->W); F(b->W_prev);
     F(b->ms); F(b->pp); F(b->qq); F(b->pp2); F(b->qq2); F(b->pf);
     F(b->rowS); F(b->rowm); F(b->rowl); F(b->rowr); F(b->bprice); F(b->pbeam); F(b->pscore); F(b->kref);
-    F(b->cost); F(b->tr.beam); F(b->tr.price); F(b->tr.margin); F(b->tr.row_margin); F(b->vmask); F(b->viter);
+    F(b->cost); F(b->tr.beam); F(b->tr.price); F(b->tr.margin); F(b->tr.row_margin); F(b->tr.y); F(b->vmask); F(b->viter);
     F(b->spart);
     if (b->ms_host) (void)hipHostFree(b->ms_host);
     if (b->mask_host) (void)hipHostFree(b->mask_host);
@@ -968,6 +968,7 @@ extern "C" vmat_status vmat_reserve_batched(vmat_handle h, int32_t max_variants)
     A(&b->bprice, B * N); A(&b->pbeam, B * (1 + 2 * (size_t)h->R)); A(&b->pscore, B * 3); A(&b->kref, B);
     A(&b->cost, B);
     A(&b->tr.beam, B * N); A(&b->tr.price, B * N); A(&b->tr.margin, B * N); A(&b->tr.row_margin, B * N);
+    A(&b->tr.y, B * N * N);
     A(&b->vmask, B); A(&b->viter, B);
     if (h->tl.on) A(&b->spart, (size_t)h->tl.S * B);
     if (rc == VMAT_OK && (hipHostMalloc((void**)&b->ms_host, sizeof(MasterState) * B) != hipSuccess ||
@@ -1114,6 +1115,9 @@ extern "C" vmat_status vmat_solve_batched(vmat_handle h, const vmat_solve_opts* 
             if (T.price && n) VMAT_HIP(hipMemcpyAsync(T.price, bs.tr.price + (int64_t)b * N, n * sizeof(double), hipMemcpyDeviceToHost, st));
             if (T.margin && n) VMAT_HIP(hipMemcpyAsync(T.margin, bs.tr.margin + (int64_t)b * N, n * sizeof(double), hipMemcpyDeviceToHost, st));
             if (T.row_margin && n) VMAT_HIP(hipMemcpyAsync(T.row_margin, bs.tr.row_margin + (int64_t)b * N, n * sizeof(double), hipMemcpyDeviceToHost, st));
+            if (T.y && n)
+                VMAT_HIP(hipMemcpyAsync(T.y, bs.tr.y + (int64_t)b * N * N, (size_t)n * N * sizeof(double),
+                                        hipMemcpyDeviceToHost, st));
         }
         VMAT_HIP(hipStreamSynchronize(st));
         for (int b = 0; b < B; ++b) {

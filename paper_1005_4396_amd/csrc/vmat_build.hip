@@ -455,7 +455,7 @@ static void free_all(vmat_ctx* h) {
     if (h->mirror) (void)hipHostFree(h->mirror);
     free_tiled(h);
     F(h->row_S); F(h->row_l); F(h->row_r); F(h->row_m); F(h->bprice); F(h->pbeam); F(h->pscore); F(h->cost2);
-    F(h->tr.beam); F(h->tr.price); F(h->tr.margin); F(h->tr.row_margin); F(h->tr.cost); F(h->tr.miters);
+    F(h->tr.beam); F(h->tr.price); F(h->tr.margin); F(h->tr.row_margin); F(h->tr.cost); F(h->tr.miters); F(h->tr.y);
 }
 
 // Labels of the voxel weights: the distinct (alpha, beta, T) triples, compared
@@ -620,6 +620,7 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     if ((rc = dalloc(h, &h->tr.row_margin, N)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->tr.cost, N + 1)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->tr.miters, N)) != VMAT_OK) return bail(rc);
+    if ((rc = dalloc(h, &h->tr.y, N * N)) != VMAT_OK) return bail(rc);
     if (hipMemcpyAsync(h->d_theta, h->theta.data(), N * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return bail(fail(VMAT_ERR_DEVICE, "copy of theta failed"));

@@ -82,7 +82,7 @@ __device__ inline void ctrl_grad(const MasterPtrs& m, double F, int first, doubl
 
 // KKT test; if not converged, the direction on the free face (steepest
 // descent after a face change, else Polak-Ribiere(+)), the first blocking
-// bound and the line-search set-up.  Sets the pipeline phase.  f32_dir: the
+// bound and the line-search set-up.  f32_dir: the
 // direction is rounded to FP32, the precision in which the batched products
 // take it, so that y and the carried dose move by the same step.
 __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi, bool f32_dir = false) {
@@ -122,7 +122,6 @@ __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi, bool 
             s0.kkt = kkt;
             s0.converged = kkt <= tol_abs;
             s0.done = 1;
-            s0.phase = PH_DONE;
         }
         return;
     }
@@ -163,7 +162,6 @@ __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi, bool 
     s.kkt = kkt;
     if (!any) {
         s.done = 1;
-        s.phase = PH_DONE;
         return;
     }
     s.beta_cg = b_cg;
@@ -177,64 +175,6 @@ __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi, bool 
     s.ls_steps = 0;
     s.ls_done = 0;
     s.n_fwd += 1;
-    s.phase = PH_READY;
-}
-
-// One step of the exact line search: safeguarded Newton on the piecewise-
-// linear, non-decreasing phi' inside a bracket (thread 0).  pF, hF: the voxel
-// sums of phi'(t_eval) and phi''(t_eval); the smoothing part is added here.
-__device__ inline void ctrl_ls_step(MasterState& s, double pF, double hF) {
-    const double t = s.t_eval;
-    const double p = pF + s.slope0 + t * s.curv;
-    const double hh = hF + s.curv;
-    s.n_ls += 1;
-    bool fin = false;
-    double ts = 0.0;
-    bool prop = false;
-    if (s.ls_phase == 0) {
-        s.p0 = p;
-        s.h0 = hh;
-        if (!(p < 0.0)) {
-            fin = true;
-            ts = 0.0;
-        } else if (isfinite(s.t_max)) {
-            s.ls_phase = 1;
-            s.t_eval = s.t_max;
-        } else {
-            s.lo = 0.0; s.hi = INFINITY; s.t = 0.0; s.p = p; s.h = hh;
-            s.ls_phase = 2; s.ls_steps = 0;
-            prop = true;
-        }
-    } else if (s.ls_phase == 1) {
-        if (p <= 0.0) {
-            fin = true;
-            ts = s.t_max;
-        } else {
-            s.lo = 0.0; s.hi = s.t_max; s.t = 0.0; s.p = s.p0; s.h = s.h0;
-            s.ls_phase = 2; s.ls_steps = 0;
-            prop = true;
-        }
-    } else {
-        s.t = t; s.p = p; s.h = hh;
-        s.ls_steps += 1;
-        if (p <= 0.0) s.lo = t; else s.hi = t;
-        if (fabs(p) <= 1e-12 * fabs(s.p0)) { fin = true; ts = t; }
-        else if (isfinite(s.hi) && s.hi - s.lo <= 1e-15 * s.hi) { fin = true; ts = s.lo; }
-        else if (s.ls_steps >= s.ls_max) { fin = true; ts = s.lo; }
-        else prop = true;
-    }
-    if (fin) {
-        s.t_star = ts;
-        s.ls_done = 1;
-        s.phase = PH_LS_DONE;
-    } else {
-        s.phase = PH_LS;
-        if (prop) {
-            double tn = s.h > 0.0 ? s.t - s.p / s.h : NAN;
-            if (!(s.lo < tn && tn < s.hi)) tn = isfinite(s.hi) ? 0.5 * (s.lo + s.hi) : (s.lo > 0.0 ? 2.0 * s.lo : 1.0);
-            s.t_eval = tn;
-        }
-    }
 }
 
 // One pass of the exact line search that evaluated phi' and phi'' at one or
@@ -291,10 +231,8 @@ __device__ inline void ctrl_ls_pass(MasterState& s, double pa, double ha, double
     if (fin) {
         s.t_star = ts;
         s.ls_done = 1;
-        s.phase = PH_LS_DONE;
         return;
     }
-    s.phase = PH_LS;
     const bool bounded = isfinite(s.hi);
     double ta = s.hlo > 0.0 ? s.lo - s.plo / s.hlo : NAN;
     if (!(s.lo < ta && ta < s.hi)) ta = NAN;

@@ -67,7 +67,6 @@ struct Tiled {
     int32_t* bounds = nullptr;    // [nblk+1] voxel boundaries
     uint32_t* loff = nullptr;     // [nblk+1] list offsets
     uint32_t* list = nullptr;     // [S] beamlet of each slot
-    uint32_t* lpack = nullptr;    // [S] (beam << 20) | (leaf row << 8) | column of each slot
     // forward
     uint16_t* fcol = nullptr;     // [4 * vm.n_quads]
     int4* fwork = nullptr;        // (block, first row, end row, first slice)
@@ -126,23 +125,20 @@ struct MasterState {
     int32_t it, max_iter, done, converged;
     int32_t ls_phase, ls_steps, ls_max, ls_done;
     int32_t n_fwd, n_adj, n_ls, have_prev;
-    int32_t phase;                // pipeline phase of the fused master iteration
-    uint32_t cnt_a, cnt_b, cnt_c; // arrival counters of the last-block reductions
     int32_t n_eval;               // points in the next line-search pass (1 or 2)
     uint32_t seq;                 // line-search chains completed since the master began
 };
 
 // Host-visible copy of the master state (pinned host memory): the last
-// line-search pass of every chain stores the state, then seq (release at
-// system scope), so a host that sees seq sees that state.
+// line-search pass of the chain with count v stores the state in slot v % 2,
+// then seq = v (release at system scope), so a host that sees seq >= v finds
+// chain v's state in slot v % 2.  The host waits for chain v with at most chain
+// v + 1 enqueued after it, so no chain writes that slot while the host copies
+// it (chain v + 2, the next writer of the slot, is enqueued after the copy).
 struct MasterMirror {
-    MasterState s;
+    MasterState s[2];
     uint32_t seq;
 };
-
-// Phases of the fused master iteration: every kernel of an iteration runs only
-// in its phase, and the last workgroup of a kernel moves the phase on.
-enum : int32_t { PH_READY = 1, PH_LS = 2, PH_LS_DONE = 3, PH_UPDATED = 4, PH_DONE = 6 };
 
 // Per-iteration record of vmat_solve, resident on the device.
 struct SolveTraceDev {
@@ -152,6 +148,7 @@ struct SolveTraceDev {
     double* row_margin;  // [N]
     double* cost;        // [N+1]
     int32_t* miters;     // [N]
+    double* y;           // [N*N] intensities each pricing saw (the previous master's solution)
 };
 
 }  // namespace vmat

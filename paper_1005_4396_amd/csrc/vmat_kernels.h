@@ -39,8 +39,6 @@ vmat_status launch_adj_beams(const vmat_ctx* h, const float* w, double* g, const
                              const uint8_t* occ, double* bpart, Gate gate, hipStream_t st);
 vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st);
 // Fused master solve over the tiled layout (see vmat_master.hip).
-vmat_status run_master_fused(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
-                             const vmat_master_opts& o, int fresh, hipStream_t st);
 void free_tiled(vmat_ctx* h);
 void free_batch(vmat_ctx* h);  // batched-solve state (vmat_batch.hip)
 

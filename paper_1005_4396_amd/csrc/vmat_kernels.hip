@@ -20,13 +20,18 @@ namespace vmat {
 
 constexpr int BLOCK = 256;
 // Line-search passes per master iteration (captured with the iteration): 3,
-// or VMAT_LS_PASSES (1..8) as read when an iteration is captured or launched.
-// The grouping of passes into replays changes no result: a search that needs
-// more passes than a replay holds stalls that replay and goes on in the next.
+// or VMAT_LS_PASSES (1, 3, 5 or 7) as read when an iteration is captured or
+// launched.  The grouping of passes into replays changes no result: a search
+// that needs more passes than a replay holds stalls that replay and goes on in
+// the next.  The count must be odd: pass i writes state buffer i % 2 and
+// partial-sum buffer i % 2, so after an odd chain the step kernel reads ms2
+// and the second partial-sum half while it writes ms and the first half; an
+// even chain would have it read what its own blocks write.  Other values
+// take the default.
 static int ls_passes() {
     const char* e = getenv("VMAT_LS_PASSES");
     const int n = e ? atoi(e) : 3;
-    return n >= 1 && n <= 8 ? n : 3;
+    return n >= 1 && n <= 7 && (n & 1) ? n : 3;
 }
 
 // ---------------------------------------------------------------- reductions
@@ -474,7 +479,7 @@ __global__ __launch_bounds__(BLOCK) void k_ls_fused(int64_t nv, const double* __
         if (blockIdx.x == 0) {
             *dst = s;
             if (mirror) {
-                mirror->s = s;
+                mirror->s[s.seq & 1u] = s;
                 __hip_atomic_store(&mirror->seq, s.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }

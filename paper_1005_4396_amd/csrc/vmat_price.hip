@@ -189,6 +189,7 @@ __global__ __launch_bounds__(CTRL) void k_price_beams(int N, int R, double gamma
             tr.price += (int64_t)b * N;
             tr.margin += (int64_t)b * N;
             tr.row_margin += (int64_t)b * N;
+            tr.y += (int64_t)b * N * N;
         }
     }
     __shared__ double shp[4];
@@ -220,6 +221,7 @@ __global__ __launch_bounds__(CTRL) void k_price_beams(int N, int R, double gamma
         }
         bprice[k] = p;
         if (user_bp) user_bp[k] = p;
+        if (apply) tr.y[(int64_t)iter * N + k] = y[k];
     }
     // block argmin with ties to the smallest k
     for (int off = 32; off > 0; off >>= 1) {

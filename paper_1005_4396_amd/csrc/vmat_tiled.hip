@@ -617,14 +617,6 @@ __global__ void k_adj_fill(int64_t S, int nblk, const uint32_t* __restrict__ lof
     }
 }
 
-__global__ void k_list_pack(int64_t S, const uint32_t* __restrict__ list, uint32_t R, uint32_t C,
-                            uint32_t* __restrict__ lpack) {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= S) return;
-    const uint32_t i = list[s], c = i % C, kr = i / C, rho = kr % R, k = kr / R;
-    lpack[s] = (k << 20) | (rho << 8) | c;
-}
-
 __global__ void k_red_count(int64_t S, const uint32_t* __restrict__ list, uint32_t* __restrict__ cnt) {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s < S) atomicAdd(&cnt[list[s]], 1u);
@@ -815,18 +807,6 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     k_blk_list<<<nblk, 256, 0, st>>>(W, d_bits.as<uint32_t>(), t.loff, d_wpref.as<uint32_t>(), t.list);
     VMAT_LAUNCH_CHECK();
 
-    // the packed (beam, leaf row, column) of every list entry: 12, 12 and 8
-    // bits, so only when the leaf rows fit (beams are at most 4096, columns 64);
-    // without it the forms that use it launch the fluence kernel instead
-    if (h->R <= 4096) {
-        A(t.lpack, t.S * 4);
-        if (t.S > 0) {
-            k_list_pack<<<(unsigned)((t.S + 255) / 256), 256, 0, st>>>(t.S, t.list, (uint32_t)h->R,
-                                                                       (uint32_t)h->C, t.lpack);
-            VMAT_LAUNCH_CHECK();
-        }
-    }
-
     // forward indices
     A(t.fcol, (size_t)h->vm.n_quads * 4 * 2);
     k_fw_col16<<<dim3(64, nblk), 256, 0, st>>>(nblk, t.bounds, h->vm.qptr, h->vm.col, W, d_bits.as<uint32_t>(),
@@ -996,7 +976,7 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
 
 void free_tiled(vmat_ctx* h) {
     Tiled& t = h->tl;
-    void* ps[] = {t.bounds, t.loff, t.list, t.lpack, t.fcol, t.fwork, t.fwork_half, t.aqptr, t.acol, t.aval, t.awork, t.part, t.red_ptr,
+    void* ps[] = {t.bounds, t.loff, t.list, t.fcol, t.fwork, t.fwork_half, t.aqptr, t.acol, t.aval, t.awork, t.part, t.red_ptr,
                   t.red_slot, t.s_off, t.s_len, t.s_row, t.s_col, t.s_val, t.as_off, t.as_len, t.as_row, t.as_col,
                   t.as_val};
     for (void* q : ps)

@@ -73,7 +73,18 @@ class SolveReport(ctypes.Structure):
 
 class SolveTrace(ctypes.Structure):
     _fields_ = [("beam", ctypes.c_void_p), ("price", ctypes.c_void_p), ("margin", ctypes.c_void_p),
-                ("row_margin", ctypes.c_void_p), ("cost", ctypes.c_void_p), ("master_iters", ctypes.c_void_p)]
+                ("row_margin", ctypes.c_void_p), ("cost", ctypes.c_void_p), ("master_iters", ctypes.c_void_p),
+                ("y", ctypes.c_void_p)]
+
+
+_TRACE_FIELDS = ("beam", "price", "margin", "row_margin", "cost", "master_iters", "y")
+
+
+def _trace_arrays(n):
+    """Host arrays of one plan's trace (n beams); y is [iterations, n]."""
+    return {"beam": np.zeros(n, np.int32), "price": np.zeros(n), "margin": np.zeros(n),
+            "row_margin": np.zeros(n), "cost": np.zeros(n + 1), "master_iters": np.zeros(n, np.int32),
+            "y": np.zeros((n, n))}
 
 
 class RateOpts(ctypes.Structure):
@@ -337,12 +348,8 @@ class Problem:
         reps = (SolveReport * B)()
         trs, tr_c = None, None
         if want_trace:
-            trs = [{"beam": np.zeros(N, np.int32), "price": np.zeros(N), "margin": np.zeros(N),
-                    "row_margin": np.zeros(N), "cost": np.zeros(N + 1), "master_iters": np.zeros(N, np.int32)}
-                   for _ in range(B)]
-            tr_c = (SolveTrace * B)(*[SolveTrace(*(t[k].ctypes.data for k in
-                                                   ("beam", "price", "margin", "row_margin", "cost",
-                                                    "master_iters"))) for t in trs])
+            trs = [_trace_arrays(N) for _ in range(B)]
+            tr_c = (SolveTrace * B)(*[SolveTrace(*(t[k].ctypes.data for k in _TRACE_FIELDS)) for t in trs])
         cnt = (ctypes.c_int64 * 2)()
         _check(lib().vmat_solve_batched(self._h, ctypes.byref(opts) if opts is not None else None, B, S,
                                         _ptr(label), _ptr(table), _ptr(l), _ptr(r), _ptr(occ), _ptr(y), reps,
@@ -430,10 +437,8 @@ class Problem:
         tr_arrays = None
         tr = None
         if want_trace:
-            tr_arrays = {"beam": np.zeros(n, np.int32), "price": np.zeros(n), "margin": np.zeros(n),
-                         "row_margin": np.zeros(n), "cost": np.zeros(n + 1), "master_iters": np.zeros(n, np.int32)}
-            tr = SolveTrace(*(tr_arrays[k].ctypes.data for k in
-                              ("beam", "price", "margin", "row_margin", "cost", "master_iters")))
+            tr_arrays = _trace_arrays(n)
+            tr = SolveTrace(*(tr_arrays[k].ctypes.data for k in _TRACE_FIELDS))
         _check(lib().vmat_solve(self._h, ctypes.byref(opts) if opts is not None else None, _ptr(l), _ptr(r),
                                 _ptr(occ), _ptr(y), _ptr(z), ctypes.byref(rep),
                                 ctypes.byref(tr) if tr is not None else None, _stream()))

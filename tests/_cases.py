@@ -7,7 +7,6 @@ from __future__ import annotations
 import functools
 
 import numpy as np
-import pytest
 
 import casegen
 import oracle as O
@@ -93,38 +92,3 @@ def scatter_case(nb_rows=30, n_cols=40, n_beams=10, nv=300, per_row=3, seed=0):
     T = (rng.random(nv) * 50 + 10).astype(np.float32)
     theta = np.arange(N, dtype=np.float64) * (360.0 / N)
     return casegen.Case(spec, N, R, C, nv, theta, row_ptr, col, val, alpha, beta, T, np.zeros(nv, np.uint8))
-
-
-def compare_plan(c, ref, tr, lk, rk, rep, eps_rel=1e-5, cost_rel=1e-6):
-    """Iteration by iteration the chosen beam and its leaf pairs must equal the
-    reference's; the first difference is excused only where the reference's
-    beam or row margin is at most eps_rel * |price|."""
-    R = c.n_rows
-    assert rep.cg_iters == len(ref.order)
-    matched = 0
-    for t in range(len(ref.order)):
-        k = ref.order[t]
-        same = (tr["beam"][t] == k and np.array_equal(lk[k * R:(k + 1) * R], ref.apertures[t][0])
-                and np.array_equal(rk[k * R:(k + 1) * R], ref.apertures[t][1]))
-        if not same:
-            eps = eps_rel * abs(ref.prices[t])
-            assert ref.margins[t] <= eps or ref.row_margins[t] <= eps, \
-                f"iteration {t}: beam {tr['beam'][t]} vs {k}, margins {ref.margins[t]}, {ref.row_margins[t]}"
-            break
-        assert abs(tr["price"][t] - ref.prices[t]) <= 1e-4 * abs(ref.prices[0])
-        matched += 1
-    if matched == len(ref.order):
-        assert rep.F + rep.gG == pytest.approx(ref.costs[-1], rel=cost_rel)
-        np.testing.assert_allclose(tr["cost"], ref.costs, rtol=cost_rel)
-    cost = tr["cost"]
-    assert np.all(cost[1:] <= cost[:-1] * (1 + 1e-12))
-    assert sorted(tr["beam"].tolist()) == list(range(c.n_beams))
-    L, Rr = lk.reshape(c.n_beams, R), rk.reshape(c.n_beams, R)
-    assert np.all(L <= Rr)
-    N = c.n_beams
-    pairs = [(k, k + 1) for k in range(N - 1)] + ([(N - 1, 0)] if c.circular else [])
-    if c.max_leaf_step >= 0:
-        for a, b in pairs:
-            assert np.all(np.abs(L[a] - L[b]) <= c.max_leaf_step)
-            assert np.all(np.abs(Rr[a] - Rr[b]) <= c.max_leaf_step)
-    return matched

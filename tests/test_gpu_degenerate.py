@@ -8,7 +8,8 @@ import pytest
 
 import casegen
 import oracle as O
-from _cases import compare_plan, oracle_D, small_case
+from _cases import oracle_D, small_case
+from _lockstep import deliverable, lockstep
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -55,18 +56,18 @@ CASES = [("empty_d", _empty_d), ("single_beamlet", _single_beamlet), ("frozen_le
 def test_degenerate_plans_match_oracle(name, mode):
     c = dict(CASES)[name]()
     D = oracle_D(c)
-    ref = O.solve(D, c.alpha, c.beta, c.T, c.theta_deg, c.gamma, c.circular, c.n_rows, c.n_cols,
-                  c.max_leaf_step)
     prob = P.Problem.from_case(c)
     try:
         l, r, occ, y = prob.empty_plan()
         rep, tr = prob.solve(l, r, occ, y, _opts(mode))
         lg, rg, yg = l.cpu().numpy(), r.cpu().numpy(), y.cpu().numpy()
-        matched = compare_plan(c, ref, tr, lg, rg, rep)
         z = prob.dose(y, l, r, occ).cpu().numpy().astype(np.float64)
     finally:
         prob.close()
-    assert matched == c.n_beams
+    assert rep.cg_iters == c.n_beams
+    log = lockstep(c, D, tr, lg, rg, yg, master_every=1, name=f"{name}/mode {mode}")
+    assert log.checked == c.n_beams
+    deliverable(c, lg, rg)
     z_ref = O.dose(D, O.fluence(yg, lg, rg, np.ones(c.n_beams, np.uint8), c.n_rows, c.n_cols))
     assert np.abs(z - z_ref).max() <= 1e-6 * max(np.abs(z_ref).max(), 1e-300)
     if name in ("empty_d", "no_dose_wanted"):
