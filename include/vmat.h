@@ -26,12 +26,14 @@
  *     untouched.  vmat_last_error() gives a text for the last failure on the
  *     calling thread.
  *   - A handle is not thread-safe; distinct handles are independent.  Device
- *     memory is allocated by vmat_create (D's layouts and work buffers), by
- *     vmat_reserve_batched (batched state), and once, on first use, by
- *     vmat_solve with master_mode 1 (aperture-dose store, grown by doubling if
- *     needed) and by the captured master iterations (graphs); vmat_destroy
- *     releases all of it.  The dose, gradient, pricing and product calls
- *     allocate nothing.
+ *     memory is allocated by vmat_create (D's layouts, work buffers and the
+ *     captured iteration of the master that streams D), by vmat_reserve_solve
+ *     (the aperture-dose store at the size no plan exceeds, and the captured
+ *     iteration of the aperture-dose master) and by vmat_reserve_batched
+ *     (batched state); vmat_destroy releases all of it.  The dose, gradient,
+ *     pricing, product, master and column-generation calls allocate no device
+ *     memory: they work on the handle's own copy of the plan (copied in from
+ *     the caller's arrays and back out at the end).
  */
 #ifndef VMAT_H
 #define VMAT_H
@@ -256,10 +258,9 @@ typedef struct vmat_solve_opts {
                               *    aperture opens (one forward each) and the master works
                               *    on them alone; one adjoint per column-generation
                               *    iteration gives the prices.  Same iterates up to
-                              *    rounding (values stored in FP32, sums in FP64); the
-                              *    store (28 B per non-zero of the aperture doses, with
-                              *    room for one dose vector more) is allocated on first
-                              *    use.                                                */
+                              *    rounding (values stored in FP32, sums in FP64); needs
+                              *    the store of vmat_reserve_solve (else
+                              *    VMAT_ERR_UNSUPPORTED).                              */
     vmat_master_opts master; /* master.kkt_ref <= 0: |p| of the first priced aperture       */
 } vmat_solve_opts;
 
@@ -286,10 +287,24 @@ typedef struct vmat_solve_trace {
     double* y;              /* [iterations * N]                               */
 } vmat_solve_trace;
 
+/* Storage for master_mode 1 of vmat_solve (the master over the generated
+ * apertures, Sec. 2.2): allocates the aperture-dose store at its final size,
+ * 28 bytes per entry for U + nv entries, where U = sum over beams of the voxels
+ * a beam reaches (no set of one aperture per beam stores more), and captures
+ * the aperture-dose master's iteration.  Once per handle (later calls return
+ * VMAT_OK at once); synchronises the device.                                  */
+vmat_status vmat_reserve_solve(vmat_handle h);
+
 /* Column generation (abstract; Sec. 2.2): repeat pricing -> add the aperture
  * (y = 0) -> master, until every beam has an aperture or max_cg_iter.
  * l, r, occ, y: DEVICE, in: start state (occ all zero: empty plan; otherwise a
  * resumed plan whose y is re-optimised first), out: final plan.
+ * A resumed plan is checked before anything is launched (VMAT_ERR_INVALID_ARG,
+ * outputs untouched): every occupied beam has 0 <= l <= r <= C in each row and
+ * a finite y >= 0, and with max_leaf_step delta >= 0 every leaf of an occupied
+ * beam lies within delta * (index distance) of the same leaf of the next
+ * occupied beam (around the circle when circular; Sec. 2.2 leaf motion), as
+ * column generation leaves a plan.  Entries of unoccupied beams are ignored.
  * z (nullable): DEVICE float [nv] final dose.  opts, rep, trace: HOST, nullable.
  * Returns VMAT_OK even if some master solve hit its cap (rep->not_converged).   */
 vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, int32_t* l, int32_t* r,

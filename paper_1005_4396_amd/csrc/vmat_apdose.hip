@@ -19,8 +19,11 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <string>
+#include <vector>
 
 #include "vmat_block.h"
+#include "vmat_formats.h"
 #include "vmat_internal.h"
 #include "vmat_kernels.h"
 
@@ -315,42 +318,132 @@ static vmat_status ap_publish(vmat_ctx* h, hipStream_t st) {
     return VMAT_OK;
 }
 
-// Empty store (allocated on first use, kept until the handle is destroyed).
-vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
-    if (!h->ap) {
-        ApDose* a = new ApDose();
-        h->ap = a;
-        const int64_t nch = n_chunks_of(h->nv);
-        vmat_status rc = VMAT_OK;
-        auto A = [&](auto** p, size_t n) { if (rc == VMAT_OK) rc = ap_alloc(a, p, n); };
-        A(&a->col_ptr, (size_t)h->N + 1);
-        A(&a->beam_slot, (size_t)h->N);
-        A(&a->vx_ptr[0], (size_t)h->nv + 1);
-        A(&a->vx_ptr[1], (size_t)h->nv + 1);
-        A(&a->chunk, (size_t)nch + 2);
-        A(&a->shift, (size_t)h->nv);
-        A(&a->unit, (size_t)h->N + 1);  // unit[N] keeps the beam index being stored
-        A(&a->view, 1);
-        // VMAT_AP_MIN_CAP: start at the smallest capacity (one dose vector),
-        // so that the store grows during a plan (read when the store is first
-        // allocated)
-        const int64_t cap0 = getenv("VMAT_AP_MIN_CAP") ? h->nv : std::max<int64_t>(1 << 20, 4 * h->nv);
-        if (rc == VMAT_OK) rc = ap_alloc_entries(a, cap0);
-        if (rc == VMAT_OK && hipHostMalloc((void**)&a->total_host, sizeof(uint32_t)) != hipSuccess) {
-            a->total_host = nullptr;
-            rc = fail(VMAT_ERR_ALLOC, "pinned host allocation failed");
-        }
-        if (rc == VMAT_OK && hipEventCreateWithFlags(&a->counted, hipEventDisableTiming) != hipSuccess) {
-            a->counted = nullptr;
-            rc = fail(VMAT_ERR_DEVICE, "event creation failed");
-        }
-        h->bytes += a->bytes;
-        if (rc != VMAT_OK) {
-            free_apdose(h);
-            return rc;
-        }
+// Voxels each beam reaches: bit j % 32 of bits[k * words + j / 32] is set when
+// a stored entry of a beamlet row of beam k at voxel j is non-zero.  One wave
+// per beamlet row, lanes over its quads (padding entries hold zeros).
+// Integer atomics only; the result does not depend on their order.
+template <int FMT>
+__global__ __launch_bounds__(256) void k_beam_voxel_bits(int64_t nb, int RC, const uint32_t* __restrict__ qptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const void* __restrict__ val, int64_t words,
+                                                         uint32_t* __restrict__ bits) {
+    const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (row >= nb) return;
+    uint32_t* b = bits + (row / RC) * words;
+    const i32x4* c4 = reinterpret_cast<const i32x4*>(col);
+    const uint32_t q1 = qptr[row + 1];
+    for (uint32_t q = qptr[row] + lane; q < q1; q += 64) {
+        const float4 v = Quad<FMT>::load(val, q);
+        const i32x4 c = c4[q];
+        if (v.x != 0.f) atomicOr(b + (c.x >> 5), 1u << (c.x & 31));
+        if (v.y != 0.f) atomicOr(b + (c.y >> 5), 1u << (c.y & 31));
+        if (v.z != 0.f) atomicOr(b + (c.z >> 5), 1u << (c.z & 31));
+        if (v.w != 0.f) atomicOr(b + (c.w >> 5), 1u << (c.w & 31));
     }
+}
+
+// Set bits of n words, as one partial count per block.
+__global__ __launch_bounds__(AP_T) void k_popcount(int64_t n, const uint32_t* __restrict__ bits,
+                                                   unsigned long long* __restrict__ part) {
+    __shared__ unsigned long long sh[AP_T / 64];
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * AP_T + threadIdx.x; i < n; i += (int64_t)gridDim.x * AP_T)
+        c += (unsigned long long)__popc(bits[i]);
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < AP_T / 64; ++w) t += sh[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+// U = sum over beams of the voxels the beam reaches: no set of apertures (one
+// per beam) has more aperture-dose entries than U.
+static vmat_status beam_voxel_bound(vmat_ctx* h, int64_t* U) {
+    const int64_t words = (h->nv + 31) / 32, n = words * h->N;
+    constexpr int NPART = 1024;
+    uint32_t* bits = nullptr;
+    unsigned long long* part = nullptr;
+    if (hipMalloc((void**)&bits, (size_t)n * 4) != hipSuccess) return fail(VMAT_ERR_ALLOC, "device allocation failed (aperture-dose bound)");
+    if (hipMalloc((void**)&part, NPART * sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipFree(bits);
+        return fail(VMAT_ERR_ALLOC, "device allocation failed (aperture-dose bound)");
+    }
+    std::vector<unsigned long long> ph(NPART);
+    hipError_t e = hipMemset(bits, 0, (size_t)n * 4);
+    const unsigned grid = (unsigned)((h->nb * 64 + 255) / 256);
+    const int RC = h->R * h->C;
+    if (e == hipSuccess && grid > 0) {
+        switch (h->d_store) {
+            case VMAT_F32: k_beam_voxel_bits<FMT_F32><<<grid, 256>>>(h->nb, RC, h->bm.qptr, h->bm.col, h->bm.val, words, bits); break;
+            case VMAT_F16: k_beam_voxel_bits<FMT_F16><<<grid, 256>>>(h->nb, RC, h->bm.qptr, h->bm.col, h->bm.val, words, bits); break;
+            case VMAT_BF16: k_beam_voxel_bits<FMT_BF16><<<grid, 256>>>(h->nb, RC, h->bm.qptr, h->bm.col, h->bm.val, words, bits); break;
+            default: k_beam_voxel_bits<FMT_FP8><<<grid, 256>>>(h->nb, RC, h->bm.qptr, h->bm.col, h->bm.val, words, bits); break;
+        }
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        k_popcount<<<NPART, AP_T>>>(n, bits, part);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(ph.data(), part, NPART * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    (void)hipFree(bits);
+    (void)hipFree(part);
+    if (e != hipSuccess) return fail(VMAT_ERR_DEVICE, std::string("aperture-dose bound: ") + hipGetErrorString(e));
+    unsigned long long t = 0;
+    for (unsigned long long v : ph) t += v;
+    *U = (int64_t)t;
+    return VMAT_OK;
+}
+
+// The store at its final size: U + nv entries, where U bounds the entries of
+// any aperture set (beam_voxel_bound) and the extra dose vector is the room an
+// append needs before the previous aperture's count reaches the host.  So no
+// plan ever grows the store.
+vmat_status ap_reserve(vmat_ctx* h) {
+    if (h->ap) return VMAT_OK;
+    int64_t U = 0;
+    vmat_status rc = beam_voxel_bound(h, &U);
+    if (rc != VMAT_OK) return rc;
+    const int64_t cap = std::max<int64_t>(1, U + h->nv);
+    if (cap >= ((int64_t)1 << 32)) return fail(VMAT_ERR_UNSUPPORTED, "aperture doses would exceed 2^32 entries");
+    ApDose* a = new ApDose();
+    h->ap = a;
+    const int64_t nch = n_chunks_of(h->nv);
+    auto A = [&](auto** p, size_t n) { if (rc == VMAT_OK) rc = ap_alloc(a, p, n); };
+    A(&a->col_ptr, (size_t)h->N + 1);
+    A(&a->beam_slot, (size_t)h->N);
+    A(&a->vx_ptr[0], (size_t)h->nv + 1);
+    A(&a->vx_ptr[1], (size_t)h->nv + 1);
+    A(&a->chunk, (size_t)nch + 2);
+    A(&a->shift, (size_t)h->nv);
+    A(&a->unit, (size_t)h->N + 1);  // unit[N] keeps the beam index being stored
+    A(&a->view, 1);
+    if (rc == VMAT_OK) rc = ap_alloc_entries(a, cap);
+    if (rc == VMAT_OK && hipHostMalloc((void**)&a->total_host, sizeof(uint32_t)) != hipSuccess) {
+        a->total_host = nullptr;
+        rc = fail(VMAT_ERR_ALLOC, "pinned host allocation failed");
+    }
+    if (rc == VMAT_OK && hipEventCreateWithFlags(&a->counted, hipEventDisableTiming) != hipSuccess) {
+        a->counted = nullptr;
+        rc = fail(VMAT_ERR_DEVICE, "event creation failed");
+    }
+    h->bytes += a->bytes;
+    if (rc != VMAT_OK) {
+        free_apdose(h);
+        return rc;
+    }
+    // publish the (empty) store so the view holds valid pointers from the start
+    return ap_reset(h, nullptr);
+}
+
+// Empty store (reserved by ap_reserve).
+vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
     ApDose* a = h->ap;
+    if (!a) return fail(VMAT_ERR_UNSUPPORTED, "aperture-dose store not reserved");
     if (a->pending) VMAT_HIP(hipEventSynchronize(a->counted));
     a->top = 0;
     a->pending = 0;
@@ -360,38 +453,6 @@ vmat_status ap_reset(vmat_ctx* h, hipStream_t st) {
     VMAT_HIP(hipMemsetAsync(a->beam_slot, 0xFF, sizeof(int32_t) * h->N, st));
     VMAT_HIP(hipMemsetAsync(a->vx_ptr[0], 0, sizeof(uint32_t) * (h->nv + 1), st));
     return ap_publish(h, st);
-}
-
-// Grows the entry arrays to hold `need` entries, keeping the stored ones.
-static vmat_status ap_grow(vmat_ctx* h, int64_t need, hipStream_t st) {
-    ApDose* a = h->ap;
-    ApDose fresh;
-    const int64_t cap = std::max<int64_t>(need, 2 * a->cap);
-    if (cap >= ((int64_t)1 << 32)) return fail(VMAT_ERR_UNSUPPORTED, "aperture doses exceed 2^32 entries");
-    vmat_status rc = ap_alloc_entries(&fresh, cap);
-    if (rc != VMAT_OK) {
-        ap_free_entries(&fresh);
-        return rc;
-    }
-    const size_t n = (size_t)a->top;
-    const int c = a->cur;
-    VMAT_HIP(hipMemcpyAsync(fresh.col, a->col, n * sizeof(ApEntry), hipMemcpyDeviceToDevice, st));
-    VMAT_HIP(hipMemcpyAsync(fresh.vx_beam[c], a->vx_beam[c], n * 2, hipMemcpyDeviceToDevice, st));
-    VMAT_HIP(hipMemcpyAsync(fresh.vx_val[c], a->vx_val[c], n * 4, hipMemcpyDeviceToDevice, st));
-    VMAT_HIP(hipMemcpyAsync(fresh.vx_vox[c], a->vx_vox[c], n * 4, hipMemcpyDeviceToDevice, st));
-    VMAT_HIP(hipStreamSynchronize(st));
-    h->bytes -= a->bytes;
-    ap_free_entries(a);
-    a->col = fresh.col;
-    for (int i = 0; i < 2; ++i) {
-        a->vx_beam[i] = fresh.vx_beam[i];
-        a->vx_val[i] = fresh.vx_val[i];
-        a->vx_vox[i] = fresh.vx_vox[i];
-    }
-    a->cap = fresh.cap;
-    a->bytes += fresh.bytes;
-    h->bytes += a->bytes;
-    return VMAT_OK;
 }
 
 // Stores the dose of the aperture of one beam: beam_dev (device, e.g. the
@@ -413,7 +474,8 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
         a->pending = 0;
     }
     vmat_status rc;
-    if (a->top + h->nv > a->cap && (rc = ap_grow(h, a->top + h->nv, st)) != VMAT_OK) return rc;
+    // cannot happen: the reserved capacity bounds every plan
+    if (a->top + h->nv > a->cap) return fail(VMAT_ERR_DEVICE, "aperture-dose store full");
     int32_t* kb = reinterpret_cast<int32_t*>(a->unit + h->N);
     k_ap_unit<<<1, AP_T, 0, st>>>(h->N, beam_dev, beam_h, a->unit, kb);
     VMAT_LAUNCH_CHECK();

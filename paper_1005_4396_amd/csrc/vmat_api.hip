@@ -45,6 +45,8 @@ __global__ void k_to_float(int64_t n, const double* __restrict__ a, float* __res
     if (i < n) b[i] = (float)a[i];
 }
 
+__global__ void k_set_f64(double* p, double v) { *p = v; }
+
 __global__ void k_scale_copy(int64_t n, const double* __restrict__ x, const float* __restrict__ s,
                              double* __restrict__ o) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -119,6 +121,61 @@ vmat_status wait_chain(vmat_ctx* h, uint32_t want, hipStream_t st) {
     return VMAT_OK;
 }
 
+// The master state's done flag as a launch gate: open while the solve runs.
+Gate master_gate(const vmat_ctx* h) {
+    Gate done;
+    done.p = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(h->ms) + offsetof(MasterState, done));
+    done.mask = 1u;
+    return done;
+}
+
+// The master (Sec. 2.2) works on the handle's plan: leaf pairs pl/pr,
+// occupancy pocc and intensities my, copied in from the caller's arrays by
+// the entry points and copied back at the end.
+//
+// Line search of a direction: its dose (fluence expansion and forward product
+// for the master that streams D, the stored aperture doses otherwise), then a
+// chain of line-search passes.
+vmat_status search(vmat_ctx* h, int mode, hipStream_t s) {
+    const Gate done = master_gate(h);
+    if (mode == 1) {
+        TRY(ap_dose(h, h->md, h->dz, done, s));
+    } else {
+        TRY(launch_fluence(h, h->md, h->pl, h->pr, h->pocc, h->bm.scale, h->x, done, s));
+        TRY(launch_fwd(h, h->x, h->dz, done, s));
+    }
+    return launch_ls_passes(h, s);
+}
+
+// One master iteration: completion of the line search with the step and the
+// dose update, the beam gradient (adjoint with the exposed-beamlet sums, or
+// the aperture doses against F'(z)), the gradient with the next direction,
+// and the next line search.
+vmat_status iteration(vmat_ctx* h, int mode, hipStream_t s) {
+    TRY(launch_step_update(h, h->my, s));
+    if (mode == 1) {
+        TRY(ap_grad(h, h->rz, h->bpart, AP_GRAD_PARTS, master_gate(h), s));
+        TRY(launch_grad_dir(h, h->my, h->pocc, h->bpart, AP_GRAD_PARTS, s));
+    } else {
+        const int Q = beam_parts(h);
+        TRY(launch_adj_beams(h, h->rz, h->g, h->pl, h->pr, h->pocc, Q > 0 ? h->bpart : h->mgF, master_gate(h), s));
+        TRY(launch_grad_dir(h, h->my, h->pocc, h->bpart, Q, s));
+    }
+    return search(h, mode, s);
+}
+
+int master_kind(int mode) { return mode == 1 ? G_MASTER_AP : G_MASTER_D; }
+
+// Enqueues one master iteration: a replay of the captured graph, or the
+// kernels one by one when graphs are off.
+vmat_status enqueue_iteration(vmat_ctx* h, int mode, hipStream_t st) {
+    if (graphs_off()) return iteration(h, mode, st);
+    const hipGraphExec_t g = h->iter_graph[master_kind(mode)];
+    if (!g) return fail(VMAT_ERR_DEVICE, "master iteration graph not captured");
+    VMAT_HIP(hipGraphLaunch(g, st));
+    return VMAT_OK;
+}
+
 // The master iterations after the first direction and its line search: each
 // replay of the captured iteration is enqueued before the host has read the
 // state the previous one left, so the device never waits for the host.  The
@@ -131,11 +188,10 @@ vmat_status wait_chain(vmat_ctx* h, uint32_t want, hipStream_t st) {
 // counts the chains enqueued; the device's count starts from it at every
 // master start, so a value left in the mirror by an earlier master is
 // always behind the one waited for.
-template <class It>
-vmat_status master_loop(vmat_ctx* h, int kind, const GraphKey key, It iteration, hipStream_t st) {
+vmat_status master_loop(vmat_ctx* h, int mode, hipStream_t st) {
     uint32_t want = h->chains;  // the first search's chain
     for (;;) {
-        TRY(run_iteration(h, kind, key, iteration, st));
+        TRY(enqueue_iteration(h, mode, st));
         h->chains += 1;
         TRY(wait_chain(h, want, st));
         if (h->ms_host->done == 1) break;
@@ -144,93 +200,30 @@ vmat_status master_loop(vmat_ctx* h, int kind, const GraphKey key, It iteration,
     return VMAT_OK;
 }
 
-// One master solve (Sec. 2.2) on the device with separate kernels.  The
-// kernels of one iteration (completion of the line search with the step and
-// the dose update, adjoint with the beam sums, gradient with the next
-// direction, its dose product, three line-search passes) form one graph; the
-// host reads the state once per iteration, one behind.
-vmat_status run_master_plain(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
-                             const vmat_master_opts& o, int fresh, hipStream_t st) {
-    Gate done;  // open while the solve is not done
-    done.p = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(h->ms) + offsetof(MasterState, done));
-    done.mask = 1u;
-    auto search = [&](hipStream_t s) -> vmat_status {
-        TRY(launch_fluence(h, h->md, l, r, occ, h->bm.scale, h->x, done, s));
-        TRY(launch_fwd(h, h->x, h->dz, done, s));
-        TRY(launch_ls_passes(h, s));
-        return VMAT_OK;
-    };
-    auto dir_and_search = [&](hipStream_t s) -> vmat_status {
-        TRY(launch_master_dir(h, y, occ, s));
-        return search(s);
-    };
-    const int Q = beam_parts(h);
-    auto iteration = [&](hipStream_t s) -> vmat_status {
-        TRY(launch_step_update(h, y, s));
-        TRY(launch_adj_beams(h, h->rz, h->g, l, r, occ, Q > 0 ? h->bpart : h->mgF, done, s));
-        TRY(launch_grad_dir(h, y, occ, h->bpart, Q, s));
-        return search(s);
-    };
-    const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)l, (uint64_t)(uintptr_t)r,
-                          (uint64_t)(uintptr_t)occ, gamma_bits(h)};
-    TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, fresh, st));
-    if (fresh) TRY(forward_from_plan(h, y, l, r, occ, h->z, Gate{}, st));
-    TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
-    if (fresh) TRY(launch_adj(h, h->rz, h->g, Gate{}, st));
-    TRY(launch_beam_sums(h, h->g, l, r, occ, h->mgF, Gate{}, st));
-    TRY(launch_master_grad(h, y, occ, fresh ? 1 : 2, st));
-    TRY(dir_and_search(st));
-    h->chains += 1;
-    return master_loop(h, G_MASTER_D, key, iteration, st);
-}
-
-// The same iterations over the stored aperture doses: the dose of a direction
-// is sum_k d_k dir_k and the beam gradient <d_k, F'(z)>, so no product with D
-// runs inside the master.  The beamlet prices g are not maintained here.
-vmat_status run_master_ap(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
-                          const vmat_master_opts& o, int fresh, hipStream_t st) {
-    Gate done;
-    done.p = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(h->ms) + offsetof(MasterState, done));
-    done.mask = 1u;
-    auto search = [&](hipStream_t s) -> vmat_status {
-        TRY(ap_dose(h, h->md, h->dz, done, s));
-        TRY(launch_ls_passes(h, s));
-        return VMAT_OK;
-    };
-    auto dir_and_search = [&](hipStream_t s) -> vmat_status {
-        TRY(launch_master_dir(h, y, occ, s));
-        return search(s);
-    };
-    // the kernels reach the stored doses through the store's device view, so
-    // the captured iteration stays valid as apertures are added
-    auto iteration = [&](hipStream_t s) -> vmat_status {
-        TRY(launch_step_update(h, y, s));
-        TRY(ap_grad(h, h->rz, h->bpart, AP_GRAD_PARTS, done, s));
-        TRY(launch_grad_dir(h, y, occ, h->bpart, AP_GRAD_PARTS, s));
-        return search(s);
-    };
-    TRY(launch_master_begin(h, y, occ, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, fresh, st));
-    if (fresh) TRY(ap_dose(h, y, h->z, Gate{}, st));
-    TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
-    TRY(ap_grad(h, h->rz, h->mgF, 1, Gate{}, st));
-    TRY(launch_master_grad(h, y, occ, fresh ? 1 : 2, st));
-    TRY(dir_and_search(st));
-    h->chains += 1;
-    const GraphKey key = {(uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)occ, (uint64_t)(uintptr_t)h->ap->view,
-                          gamma_bits(h)};
-    return master_loop(h, G_MASTER_AP, key, iteration, st);
-}
-
-// fresh == 0: the handle's z, F'(z) and g already belong to y (the column-
-// generation driver adds apertures at y = 0), so no product is needed to start.
-vmat_status run_master(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ, double* y,
-                       const vmat_master_opts& o, vmat_master_report* rep, hipStream_t st, int fresh = 1,
-                       int mode = 0) {
+// One master solve on the handle's plan.  fresh == 0: the handle's z, F'(z)
+// and g already belong to my (column generation adds apertures at y = 0), so
+// no product is needed to start.  mode 1: the iterations run on the stored
+// aperture doses (the dose of a direction is sum_k d_k dir_k, the beam
+// gradient <d_k, F'(z)>), so no product with D runs inside the master and the
+// beamlet prices g are not maintained.
+vmat_status run_master(vmat_ctx* h, const vmat_master_opts& o, vmat_master_report* rep, hipStream_t st,
+                       int fresh = 1, int mode = 0) {
+    TRY(launch_master_begin(h, h->my, h->pocc, o.max_iter, o.ls_max_steps, o.tol_rel, o.kkt_ref, fresh, st));
     if (mode == 1) {
-        TRY(run_master_ap(h, l, r, occ, y, o, fresh, st));
+        if (fresh) TRY(ap_dose(h, h->my, h->z, Gate{}, st));
+        TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
+        TRY(ap_grad(h, h->rz, h->mgF, 1, Gate{}, st));
     } else {
-        TRY(run_master_plain(h, l, r, occ, y, o, fresh, st));
+        if (fresh) TRY(forward_from_plan(h, h->my, h->pl, h->pr, h->pocc, h->z, Gate{}, st));
+        TRY(launch_penalty(h, h->z, nullptr, nullptr, st));
+        if (fresh) TRY(launch_adj(h, h->rz, h->g, Gate{}, st));
+        TRY(launch_beam_sums(h, h->g, h->pl, h->pr, h->pocc, h->mgF, Gate{}, st));
     }
+    TRY(launch_master_grad(h, h->my, h->pocc, fresh ? 1 : 2, st));
+    TRY(launch_master_dir(h, h->my, h->pocc, st));
+    TRY(search(h, mode, st));
+    h->chains += 1;
+    TRY(master_loop(h, mode, st));
     const MasterState& s = *h->ms_host;
     if (rep) {
         rep->iters = s.it;
@@ -247,7 +240,84 @@ vmat_status run_master(vmat_ctx* h, const int32_t* l, const int32_t* r, const ui
     return s.converged ? VMAT_OK : VMAT_ERR_NOT_CONVERGED;
 }
 
+// The caller's plan into the handle's plan buffers (y may be null: not copied).
+vmat_status plan_in(vmat_ctx* h, const double* y, const int32_t* l, const int32_t* r, const uint8_t* occ,
+                    hipStream_t st) {
+    const size_t NR = (size_t)h->N * h->R;
+    VMAT_HIP(hipMemcpyAsync(h->pl, l, NR * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(h->pr, r, NR * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(h->pocc, occ, (size_t)h->N, hipMemcpyDeviceToDevice, st));
+    if (y) VMAT_HIP(hipMemcpyAsync(h->my, y, (size_t)h->N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return VMAT_OK;
+}
+
+// A plan the column-generation loop may resume from (Sec. 2.2): every
+// occupied beam has 0 <= l <= r <= C in each row and a finite y >= 0, and,
+// with a leaf-speed limit delta >= 0, each leaf of an occupied beam lies
+// within delta * (index distance) of the same leaf of the next occupied beam
+// (around the circle when circular), as column generation leaves it.
+vmat_status check_resume(const vmat_ctx* h, const std::vector<int32_t>& l, const std::vector<int32_t>& r,
+                         const std::vector<uint8_t>& occ, const std::vector<double>& y) {
+    const int N = h->N, R = h->R, C = h->C;
+    for (int k = 0; k < N; ++k) {
+        if (!occ[k]) continue;
+        if (!std::isfinite(y[k]) || y[k] < 0.0)
+            return fail(VMAT_ERR_INVALID_ARG, "resumed plan: y of occupied beam " + std::to_string(k) +
+                                                  " is negative or not finite");
+        for (int rho = 0; rho < R; ++rho) {
+            const int64_t a = (int64_t)k * R + rho;
+            if (l[a] < 0 || l[a] > r[a] || r[a] > C)
+                return fail(VMAT_ERR_INVALID_ARG, "resumed plan: beam " + std::to_string(k) + " row " +
+                                                      std::to_string(rho) + " violates 0 <= l <= r <= C");
+        }
+    }
+    if (h->delta < 0) return VMAT_OK;
+    for (int k = 0; k < N; ++k) {
+        if (!occ[k]) continue;
+        int k2 = -1, dist = 0;
+        for (int d = 1; d < N; ++d) {
+            int kk = k + d;
+            if (kk >= N) {
+                if (!h->circular) break;
+                kk -= N;
+            }
+            if (occ[kk]) {
+                k2 = kk;
+                dist = d;
+                break;
+            }
+        }
+        if (k2 < 0) continue;
+        const int64_t reach = (int64_t)h->delta * dist;
+        for (int rho = 0; rho < R; ++rho) {
+            const int64_t a = (int64_t)k * R + rho, b = (int64_t)k2 * R + rho;
+            if (std::llabs((int64_t)l[a] - l[b]) > reach || std::llabs((int64_t)r[a] - r[b]) > reach)
+                return fail(VMAT_ERR_INVALID_ARG, "resumed plan: beams " + std::to_string(k) + " and " +
+                                                      std::to_string(k2) + " row " + std::to_string(rho) +
+                                                      " exceed the leaf-speed limit");
+        }
+    }
+    return VMAT_OK;
+}
+
 }  // namespace
+
+namespace vmat {
+
+vmat_status set_gamma(vmat_ctx* h, double gamma, hipStream_t st) {
+    h->gamma = gamma;
+    k_set_f64<<<1, 1, 0, st>>>(h->d_gamma, gamma);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+
+vmat_status capture_master(vmat_ctx* h, int mode) {
+    const GraphKey key = {(uint64_t)mode + 1};
+    return capture_graph(h, master_kind(mode), key, [&](hipStream_t s) { return iteration(h, mode, s); });
+}
+
+}  // namespace vmat
+
 
 extern "C" vmat_status vmat_dose(vmat_handle h, const double* y, const int32_t* l, const int32_t* r,
                                  const uint8_t* occ, float* z, hipStream_t st) {
@@ -366,11 +436,28 @@ extern "C" vmat_status vmat_master(vmat_handle h, const int32_t* l, const int32_
     TRY(check_plan(y, l, r, occ));
     const vmat_master_opts o = defaults(opts);
     TRY(check_opts(o));
-    const vmat_status rc = run_master(h, l, r, occ, y, o, rep, st);
+    TRY(plan_in(h, y, l, r, occ, st));
+    const vmat_status rc = run_master(h, o, rep, st);
+    if (rc != VMAT_OK && rc != VMAT_ERR_NOT_CONVERGED) return rc;
+    VMAT_HIP(hipMemcpyAsync(y, h->my, (size_t)h->N * sizeof(double), hipMemcpyDeviceToDevice, st));
     // the replay enqueued after the last iteration does nothing, but the call
     // returns with the stream drained
     VMAT_HIP(hipStreamSynchronize(st));
     return rc;
+}
+
+extern "C" vmat_status vmat_reserve_solve(vmat_handle h) {
+    TRY(check_handle(h));
+    if (h->ap) return VMAT_OK;
+    VMAT_HIP(hipDeviceSynchronize());
+    TRY(ap_reserve(h));
+    vmat_status rc = capture_master(h, 1);
+    if (rc == VMAT_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(VMAT_ERR_DEVICE, "vmat_reserve_solve: device synchronisation failed");
+    if (rc != VMAT_OK) {
+        free_apdose(h);
+        return rc;
+    }
+    return VMAT_OK;
 }
 
 extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, int32_t* l, int32_t* r, uint8_t* occ,
@@ -386,14 +473,24 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
     TRY(check_opts(so.master));
     if (so.master_mode != 0 && so.master_mode != 1) return fail(VMAT_ERR_INVALID_ARG, "master_mode must be 0 or 1");
     const int mode = so.master_mode;
+    if (mode == 1 && !h->ap)
+        return fail(VMAT_ERR_UNSUPPORTED, "master_mode 1 needs the aperture-dose store: call vmat_reserve_solve first");
     const int N = h->N;
+    const size_t NR = (size_t)N * h->R;
     std::vector<uint8_t> occ_h(N);
+    std::vector<int32_t> l_h(NR), r_h(NR);
+    std::vector<double> y_h(N);
     VMAT_HIP(hipMemcpyAsync(occ_h.data(), occ, N, hipMemcpyDeviceToHost, st));
+    VMAT_HIP(hipMemcpyAsync(l_h.data(), l, NR * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    VMAT_HIP(hipMemcpyAsync(r_h.data(), r, NR * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    VMAT_HIP(hipMemcpyAsync(y_h.data(), y, N * sizeof(double), hipMemcpyDeviceToHost, st));
     VMAT_HIP(hipStreamSynchronize(st));
+    TRY(check_resume(h, l_h, r_h, occ_h, y_h));
     int n_occ = 0;
     for (uint8_t o : occ_h) n_occ += o ? 1 : 0;
     int iters = N - n_occ;
     if (so.max_cg_iter > 0) iters = std::min(iters, so.max_cg_iter);
+    TRY(plan_in(h, y, l, r, occ, st));
 
     vmat_solve_report R = {};
     std::vector<double> costs(iters + 1, 0.0);
@@ -416,12 +513,11 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
         if (mode == 1) {
             for (int k = 0; k < N; ++k)
                 if (occ_h[k]) {
-                    TRY(ap_append(h, l, r, occ, nullptr, k, st));
+                    TRY(ap_append(h, h->pl, h->pr, h->pocc, nullptr, k, st));
                     R.n_forward += 1;
                 }
         }
-        vmat_master_opts mo = so.master;
-        vmat_status rc = run_master(h, l, r, occ, y, mo, &mr, st, 1, mode);
+        vmat_status rc = run_master(h, so.master, &mr, st, 1, mode);
         if (rc != VMAT_OK && rc != VMAT_ERR_NOT_CONVERGED) return rc;
         if (rc == VMAT_ERR_NOT_CONVERGED) R.not_converged++;
         count(mr);
@@ -443,7 +539,8 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
         costs[0] = c0;
     }
     for (int t = 0; t < iters; ++t) {
-        TRY(launch_price(h, h->g, y, l, r, occ, h->pbeam, h->pscore, nullptr, 1, t, l, r, occ, y, st));
+        TRY(launch_price(h, h->g, h->my, h->pl, h->pr, h->pocc, h->pbeam, h->pscore, nullptr, 1, t, h->pl, h->pr,
+                         h->pocc, h->my, st));
         if (!(ref > 0.0)) {
             double ps[3];
             VMAT_HIP(hipMemcpyAsync(ps, h->pscore, sizeof(ps), hipMemcpyDeviceToHost, st));
@@ -451,12 +548,12 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
             ref = ps[0] != 0.0 && std::isfinite(ps[0]) ? std::fabs(ps[0]) : 1.0;
         }
         if (mode == 1) {
-            TRY(ap_append(h, l, r, occ, h->pbeam, -1, st));
+            TRY(ap_append(h, h->pl, h->pr, h->pocc, h->pbeam, -1, st));
             R.n_forward += 1;
         }
         vmat_master_opts mo = so.master;
         mo.kkt_ref = ref;
-        vmat_status rc = run_master(h, l, r, occ, y, mo, &mr, st, /*fresh=*/0, mode);
+        vmat_status rc = run_master(h, mo, &mr, st, /*fresh=*/0, mode);
         if (rc != VMAT_OK && rc != VMAT_ERR_NOT_CONVERGED) return rc;
         if (rc == VMAT_ERR_NOT_CONVERGED) R.not_converged++;
         count(mr);
@@ -476,6 +573,10 @@ extern "C" vmat_status vmat_solve(vmat_handle h, const vmat_solve_opts* opts, in
         R.gG = mr.gG;
     }
     R.kkt_ref = ref;
+    VMAT_HIP(hipMemcpyAsync(l, h->pl, NR * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(r, h->pr, NR * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(occ, h->pocc, (size_t)N, hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipMemcpyAsync(y, h->my, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (z) TRY(to_float(h->z, z, h->nv, st));
     if (trace) {
         const int n = R.cg_iters;
@@ -510,25 +611,26 @@ extern "C" vmat_status vmat_enforce_rate(vmat_handle h, const vmat_rate_opts* op
     if (mo.ls_max_steps <= 0) mo.ls_max_steps = 50;
     if (!(mo.tol_rel > 0.0)) mo.tol_rel = 1e-5;
     TRY(check_opts(mo));
+    TRY(plan_in(h, y, l, r, occ, st));
     vmat_rate_report R = {};
     const double gamma0 = h->gamma;
     double g_now = gamma0;
     double rate_G[2];
     auto read_rate = [&]() -> vmat_status {
-        TRY(launch_max_rate(h, y, h->cost2, st));
+        TRY(launch_max_rate(h, h->my, h->cost2, st));
         VMAT_HIP(hipMemcpyAsync(rate_G, h->cost2, sizeof(rate_G), hipMemcpyDeviceToHost, st));
         VMAT_HIP(hipStreamSynchronize(st));
         return VMAT_OK;
     };
     // unoccupied beams carry y = 0 (as in the master) before the first check
-    TRY(launch_master_begin(h, y, occ, 1, 1, 1.0, 0.0, 1, st));
+    TRY(launch_master_begin(h, h->my, h->pocc, 1, 1, 1.0, 0.0, 1, st));
     TRY(read_rate());
     vmat_status rc = VMAT_OK;
     while (rate_G[0] > opts->rate_max && R.rounds < opts->max_rounds) {
         g_now *= opts->factor;
-        h->gamma = g_now;
+        if ((rc = set_gamma(h, g_now, st)) != VMAT_OK) break;
         vmat_master_report mr{};
-        rc = run_master(h, l, r, occ, y, mo, &mr, st, R.rounds == 0 ? 1 : 0);
+        rc = run_master(h, mo, &mr, st, R.rounds == 0 ? 1 : 0);
         if (rc != VMAT_OK && rc != VMAT_ERR_NOT_CONVERGED) break;
         if (rc == VMAT_ERR_NOT_CONVERGED) R.not_converged++;
         rc = VMAT_OK;
@@ -538,8 +640,11 @@ extern "C" vmat_status vmat_enforce_rate(vmat_handle h, const vmat_rate_opts* op
         R.gG = mr.gG;
         if ((rc = read_rate()) != VMAT_OK) break;
     }
-    h->gamma = gamma0;
+    const vmat_status rg = set_gamma(h, gamma0, st);
     if (rc != VMAT_OK) return rc;
+    if (rg != VMAT_OK) return rg;
+    VMAT_HIP(hipMemcpyAsync(y, h->my, (size_t)h->N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    VMAT_HIP(hipStreamSynchronize(st));
     R.gamma = g_now;
     R.rate = rate_G[0];
     R.feasible = rate_G[0] <= opts->rate_max ? 1 : 0;

@@ -860,7 +860,7 @@ vmat_status sync_batch(vmat_ctx* h, int B, hipStream_t st) {
 MasterPtrs batch_ptrs(const vmat_ctx* h, double* y, const uint8_t* occ, const int32_t* l, const int32_t* r) {
     const BatchState& b = *h->bs;
     MasterPtrs m;
-    m.N = h->N; m.R = h->R; m.C = h->C; m.circ = h->circular; m.gamma = h->gamma;
+    m.N = h->N; m.R = h->R; m.C = h->C; m.circ = h->circular; m.gamma = h->d_gamma;
     m.th = h->d_theta; m.y = y; m.occ = occ; m.l = l; m.r = r;
     m.grad = b.grad; m.grad_prev = b.grad_prev; m.d = b.d; m.d_prev = b.d_prev;
     m.W = b.W; m.W_prev = b.W_prev; m.gF = b.gF; m.ms = b.ms;
@@ -891,7 +891,7 @@ vmat_status batch_iteration(vmat_ctx* h, const BatchArgs& a, const int32_t* l, c
                           (uint64_t)(uintptr_t)occ, (uint64_t)(uintptr_t)a.label, (uint64_t)(uintptr_t)a.table,
                           (uint64_t)B | ((uint64_t)a.S << 8) | ((uint64_t)(uint32_t)h->tune_fwd[B] << 16) |
                               ((uint64_t)(uint32_t)h->tune_adj[B] << 32),
-                          gamma_bits(h), (uint64_t)(uintptr_t)bs.X};
+                          (uint64_t)(uintptr_t)bs.X};
     auto ls_round = [&](hipStream_t s) -> vmat_status {
         for (int i = 0; i < 3; ++i) {
             k_bls_eval<<<np, BT, 0, s>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.pp, bs.qq,

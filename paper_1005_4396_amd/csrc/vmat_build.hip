@@ -422,11 +422,6 @@ static vmat_status build_layouts(vmat_ctx* h, const vmat_problem* p, hipStream_t
         rc = build_tiled(h, p, st);
         if (rc != VMAT_OK) {
             free_tiled(h);
-    free_batch(h);
-    free_apdose(h);
-    for (auto& g : h->iter_graph)
-        if (g) (void)hipGraphExecDestroy(g);
-    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
             if (h->layout_req == 2 || rc != VMAT_ERR_UNSUPPORTED) return rc;
             set_error("");
         } else {
@@ -448,12 +443,18 @@ static void free_all(vmat_ctx* h) {
     F(h->bm.qptr); F(h->bm.col); F(h->bm.val); F(h->bm.scale);
     F(h->vm.qptr); F(h->vm.col); F(h->vm.val); F(h->vm.scale);
     F(h->abT); F(h->wlab); F(h->wtab); F(h->x); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->bpart); F(h->part); F(h->part_b);
+    F(h->pl); F(h->pr); F(h->pocc); F(h->d_gamma);
     F(h->my); F(h->mgrad); F(h->mgrad_prev); F(h->md); F(h->md_prev); F(h->mgF); F(h->mW); F(h->mW_prev);
     F(h->ms);
     F(h->ms2);
     if (h->ms_host) (void)hipHostFree(h->ms_host);
     if (h->mirror) (void)hipHostFree(h->mirror);
     free_tiled(h);
+    free_batch(h);
+    free_apdose(h);
+    for (auto& g : h->iter_graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     F(h->row_S); F(h->row_l); F(h->row_r); F(h->row_m); F(h->bprice); F(h->pbeam); F(h->pscore); F(h->cost2);
     F(h->tr.beam); F(h->tr.price); F(h->tr.margin); F(h->tr.row_margin); F(h->tr.cost); F(h->tr.miters); F(h->tr.y);
 }
@@ -595,6 +596,10 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     double** vecs[] = {&h->my, &h->mgrad, &h->mgrad_prev, &h->md, &h->md_prev, &h->mgF};
     for (double** v : vecs)
         if ((rc = dalloc(h, v, N)) != VMAT_OK) return bail(rc);
+    if ((rc = dalloc(h, &h->pl, NR)) != VMAT_OK) return bail(rc);
+    if ((rc = dalloc(h, &h->pr, NR)) != VMAT_OK) return bail(rc);
+    if ((rc = dalloc(h, &h->pocc, N)) != VMAT_OK) return bail(rc);
+    if ((rc = dalloc(h, &h->d_gamma, 1)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->mW, N)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->mW_prev, N)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->ms, 1)) != VMAT_OK) return bail(rc);
@@ -624,7 +629,10 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     if (hipMemcpyAsync(h->d_theta, h->theta.data(), N * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return bail(fail(VMAT_ERR_DEVICE, "copy of theta failed"));
+    if ((rc = set_gamma(h, h->gamma, st)) != VMAT_OK) return bail(rc);
     if ((rc = tune_sell(h, st)) != VMAT_OK) return bail(rc);
+    // the streaming master's iteration, captured once on the handle's plan
+    if ((rc = capture_master(h, 0)) != VMAT_OK) return bail(rc);
     *out = h;
     return VMAT_OK;
 }

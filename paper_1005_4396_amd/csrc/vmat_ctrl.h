@@ -29,7 +29,7 @@ __device__ __forceinline__ Pen penalty_at(double z, float4 p) {
 
 struct MasterPtrs {
     int N, R, C, circ;
-    double gamma;
+    const double* gamma;  // device scalar
     const double* th;
     double* y;
     const uint8_t* occ;
@@ -47,7 +47,7 @@ struct MasterPtrs {
 
 inline MasterPtrs master_ptrs(const vmat_ctx* h, double* y, const uint8_t* occ, const int32_t* l, const int32_t* r) {
     MasterPtrs m;
-    m.N = h->N; m.R = h->R; m.C = h->C; m.circ = h->circular; m.gamma = h->gamma;
+    m.N = h->N; m.R = h->R; m.C = h->C; m.circ = h->circular; m.gamma = h->d_gamma;
     m.th = h->d_theta; m.y = y; m.occ = occ; m.l = l; m.r = r;
     m.grad = h->mgrad; m.grad_prev = h->mgrad_prev; m.d = h->md; m.d_prev = h->md_prev;
     m.W = h->mW; m.W_prev = h->mW_prev; m.gF = h->mgF; m.ms = h->ms;
@@ -61,7 +61,7 @@ __device__ inline void ctrl_grad(const MasterPtrs& m, double F, int first, doubl
     double G = smoothing_G_part(m.y, m.th, N, m.circ);
     double ref = 0.0;
     for (int k = threadIdx.x; k < N; k += CTRL) {
-        const double gk = m.gF[k] + m.gamma * dG_at(k, m.y, m.th, N, m.circ);
+        const double gk = m.gF[k] + *m.gamma * dG_at(k, m.y, m.th, N, m.circ);
         m.grad[k] = gk;
         if (m.occ[k]) ref = fmax(ref, fabs(gk));
     }
@@ -70,7 +70,7 @@ __device__ inline void ctrl_grad(const MasterPtrs& m, double F, int first, doubl
     if (threadIdx.x != 0) return;
     MasterState& s = *m.ms;
     s.F = F;
-    s.gG = m.gamma * G;
+    s.gG = *m.gamma * G;
     if (first != 2) s.n_adj += 1;
     if (first) {
         s.it = 0;
@@ -100,7 +100,7 @@ __device__ inline void ctrl_dir(const MasterPtrs& m, double* sh, int* shi, bool 
     const uint8_t* occ = m.occ;
     const double* th = m.th;
     const int circ = m.circ;
-    const double gamma = m.gamma;
+    const double gamma = *m.gamma;
     if (s0.done) return;
     const int have_prev = s0.have_prev;
     double kkt = 0.0;

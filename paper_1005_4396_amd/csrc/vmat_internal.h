@@ -277,11 +277,22 @@ struct vmat_ctx {
     int32_t tune_adj[65] = {};
     vmat::BatchState* bs = nullptr; // batched solves (vmat_reserve_batched)
     vmat::ApDose* ap = nullptr;     // aperture doses (aperture-dose master)
-    // one master iteration's kernels as a replayable graph, per master kind;
-    // captured on cap_stream, keyed by the plan pointers its kernels take
+    // one master iteration's kernels as a replayable graph, per master kind
+    // (captured once on cap_stream: the streaming master's at creation, the
+    // aperture-dose master's by vmat_reserve_solve); the batched sequences are
+    // keyed by the pointers their kernels take
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t iter_graph[4] = {nullptr, nullptr, nullptr, nullptr};
     uint64_t iter_key[4][vmat::GRAPH_KEY_LEN] = {};
+    // the plan the master and column generation work on: the handle's own
+    // copies of the caller's leaf pairs, occupancy and intensities (my), so
+    // that the captured master iterations take fixed pointers
+    int32_t* pl = nullptr;         // [N*R]
+    int32_t* pr = nullptr;         // [N*R]
+    uint8_t* pocc = nullptr;       // [N]
+    // gamma on the device, read by the captured control kernels (so a new
+    // gamma needs no new capture); h->gamma is its host copy
+    double* d_gamma = nullptr;
     // master vectors [N]
     double *my = nullptr, *mgrad = nullptr, *mgrad_prev = nullptr, *md = nullptr, *md_prev = nullptr,
            *mgF = nullptr;

@@ -38,13 +38,14 @@ int beam_parts(const vmat_ctx* h);
 vmat_status launch_adj_beams(const vmat_ctx* h, const float* w, double* g, const int32_t* l, const int32_t* r,
                              const uint8_t* occ, double* bpart, Gate gate, hipStream_t st);
 vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st);
-// Fused master solve over the tiled layout (see vmat_master.hip).
 void free_tiled(vmat_ctx* h);
 void free_batch(vmat_ctx* h);  // batched-solve state (vmat_batch.hip)
 
 // ---- aperture doses (vmat_apdose.hip)
 void free_apdose(vmat_ctx* h);
-// empty store, allocated on first use
+// allocates the store at the size no plan can exceed (kept until destroy)
+vmat_status ap_reserve(vmat_ctx* h);
+// empties the reserved store
 vmat_status ap_reset(vmat_ctx* h, hipStream_t st);
 // stores d_k = D^T 1_{A_k} for beam *beam_dev (device) or beam_h (beam_dev null)
 vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uint8_t* occ,
@@ -95,6 +96,12 @@ vmat_status launch_grad_dir(const vmat_ctx* h, const double* y, const uint8_t* o
 
 // max over eq. 2 pairs of |y_b - y_a| / (theta_b - theta_a) -> out[0]; G(y) -> out[1]
 vmat_status launch_max_rate(const vmat_ctx* h, const double* y, double* out, hipStream_t st);
+
+// the handle's gamma (host copy and the device scalar the control kernels read)
+vmat_status set_gamma(vmat_ctx* h, double gamma, hipStream_t st);
+// captures one master iteration on the handle's plan (mode 0: the master that
+// streams D; mode 1: the aperture-dose master, after ap_reserve)
+vmat_status capture_master(vmat_ctx* h, int mode);
 
 // ---- pricing
 // apply != 0: also occupy the chosen beam in (l, r, occ, y), record the trace

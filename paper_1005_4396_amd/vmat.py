@@ -131,6 +131,7 @@ def lib():
             "vmat_tune_batched": [P, I32, P, P, P, P, I32, P, P, P],
             "vmat_set_batched_tile": [P, I32, I32, I32],
             "vmat_reserve_batched": [P, I32],
+            "vmat_reserve_solve": [P],
             "vmat_read_stream": [P, ctypes.c_int64, P, I32, P],
             "vmat_enforce_rate": [P, ctypes.POINTER(RateOpts), P, P, P, P, ctypes.POINTER(RateReport), P],
             "vmat_solve_batched": [P, ctypes.POINTER(SolveOpts), I32, I32, P, P, P, P, P, P,
@@ -431,7 +432,13 @@ class Problem:
         _check(code, allow=(VMAT_ERR_NOT_CONVERGED,))
         return rep
 
+    def reserve_solve(self):
+        """Aperture-dose store and captured iteration for master_mode 1."""
+        _check(lib().vmat_reserve_solve(self._h))
+
     def solve(self, l, r, occ, y, opts: SolveOpts | None = None, z=None, want_trace=True):
+        if opts is not None and opts.master_mode == 1:
+            self.reserve_solve()
         rep = SolveReport()
         n = self.N
         tr_arrays = None

@@ -1,6 +1,6 @@
 """Column generation with the master over stored aperture doses
 (master_mode 1): resuming a stopped plan, graph replay against direct
-launches, and a store that grows during a plan.  The plans themselves are
+launches, and the store reserved at a size no plan exceeds.  The plans themselves are
 checked against the oracle in lockstep (test_gpu_lockstep.py,
 test_gpu_fullsize.py)."""
 import numpy as np
@@ -82,34 +82,36 @@ def test_graph_replay_matches_direct_launches(mode, name, monkeypatch):
         np.testing.assert_array_equal(r, out[0][3])
 
 
-def test_aperture_store_growth_keeps_results(monkeypatch):
-    """A store that starts at its smallest capacity (one dose vector) has to
-    grow during the plan, each time copying the stored entries to larger
-    arrays; the plan is the same, bit for bit, as with the default capacity."""
-    c = small_case(n_beams=8, n_rows=4, n_cols=6, grid=(12, 12, 8))
-    out = []
-    for small in (False, True):
-        if small:
-            monkeypatch.setenv("VMAT_AP_MIN_CAP", "1")
-        else:
-            monkeypatch.delenv("VMAT_AP_MIN_CAP", raising=False)
-        prob = P.Problem.from_case(c)
-        try:
-            b0 = prob.device_bytes()
-            l, r, occ, y = prob.empty_plan()
-            rep, tr = prob.solve(l, r, occ, y, _opts(1))
-            b1 = prob.device_bytes()
-            out.append((tr, y.cpu().numpy(), l.cpu().numpy(), r.cpu().numpy(), rep.F + rep.gG, b1 - b0))
-        finally:
-            prob.close()
-    (t0, y0, l0, r0, f0, s0), (t1, y1, l1, r1, f1, s1) = out
-    # the smaller store: the hook took effect, so the appends after the first
-    # found it full (one dose vector ahead of the stored entries) and grew it
-    assert s1 < s0
-    assert len(t1["beam"]) == c.n_beams > 1
-    np.testing.assert_array_equal(t1["beam"], t0["beam"])
-    np.testing.assert_array_equal(t1["cost"], t0["cost"])
-    np.testing.assert_array_equal(y1, y0)
-    np.testing.assert_array_equal(l1, l0)
-    np.testing.assert_array_equal(r1, r0)
-    assert f1 == f0
+def _beam_voxel_bound(c):
+    """Sum over beams of the voxels each beam reaches (non-zero D), counted on
+    the host from the case's CSR."""
+    RC = c.n_rows * c.n_cols
+    rows = np.repeat(np.arange(c.row_ptr.size - 1), np.diff(c.row_ptr))
+    keep = c.val != 0
+    key = (rows[keep] // RC).astype(np.int64) * c.n_voxels + c.col[keep]
+    return int(np.unique(key).size)
+
+
+@pytest.mark.parametrize("name", ["small", "hand", "tiny36"])
+def test_reserved_store_holds_every_plan(name):
+    """vmat_reserve_solve sizes the store at U + nv entries (U: voxels each
+    beam reaches, summed over beams; 28 bytes per entry), and a full plan in
+    mode 1 allocates nothing more."""
+    c = dict(CASES)[name]()
+    U = _beam_voxel_bound(c)
+    prob = P.Problem.from_case(c)
+    try:
+        b0 = prob.device_bytes()
+        prob.reserve_solve()
+        b1 = prob.device_bytes()
+        nv, N = c.n_voxels, c.n_beams
+        entries = 28 * (U + nv)
+        assert entries <= b1 - b0 <= entries + 16 * (nv + 1) + 4 * ((nv + 1023) // 1024 + 2) + 24 * (N + 1) + 64
+        prob.reserve_solve()   # once per handle
+        assert prob.device_bytes() == b1
+        l, r, occ, y = prob.empty_plan()
+        rep, _ = prob.solve(l, r, occ, y, _opts(1))
+        assert rep.cg_iters == c.n_beams
+        assert prob.device_bytes() == b1
+    finally:
+        prob.close()
