@@ -113,9 +113,10 @@ vmat_status vmat_device_bytes(vmat_handle h, int64_t* bytes);
 typedef struct vmat_layout_info {
     int32_t tiled;          /* 1: tiled layout (LDS-staged gathers), 0: plain quad CSR   */
     int32_t n_blocks;       /* voxel blocks of the tiled layout                          */
-    int32_t fwd_lanes;      /* lanes per row of the CSR-shaped tiled forward (the sliced  */
-                            /* kernels, used by default, give every row one lane)         */
-    int32_t adj_lanes;      /* lanes per row of the CSR-shaped tiled adjoint              */
+    int32_t fwd_lanes;      /* lanes per row of the forward: 1 in the tiled layout (its   */
+                            /* sliced kernels give every row one lane), else the plain    */
+                            /* layout's lane group                                        */
+    int32_t adj_lanes;      /* lanes per row of the adjoint, likewise                     */
     int64_t fwd_entries;    /* stored entries of the forward layout, padding included     */
     int64_t adj_entries;    /* stored entries of the adjoint layout, padding included     */
     int64_t slots;          /* (block, beamlet) pairs of the tiled layout                 */

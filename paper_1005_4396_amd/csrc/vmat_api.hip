@@ -412,8 +412,8 @@ extern "C" vmat_status vmat_layout(vmat_handle h, vmat_layout_info* out) {
     if (h->tl.on) {
         const Tiled& t = h->tl;
         L.n_blocks = t.nblk;
-        L.fwd_lanes = t.fG;
-        L.adj_lanes = t.aG;
+        L.fwd_lanes = 1;  // the sliced products give every row one lane
+        L.adj_lanes = 1;
         L.adj_entries = t.a_quads * 4;
         L.slots = t.S;
         L.fwd_bytes = L.fwd_entries * (vb + 2) + 4 * (nv + 1) + 4 * t.S + 8 * nb + 8 * nv;

@@ -20,7 +20,6 @@
 #include "vmat_graph.h"
 #include "vmat_internal.h"
 #include "vmat_kernels.h"
-#include "vmat_rows.h"
 
 namespace vmat {
 

@@ -53,10 +53,6 @@ constexpr int TILE_VOXELS = 16384;
 constexpr int TILE_LIST = 8192;
 constexpr int TILE_THREADS = 512;
 constexpr int TILE_ROWS = 2048;   // rows per work item (their starts are staged in LDS)
-// Quads per lane and pass of the tiled forward.  Voxel rows are short (about
-// 27 quads on the prostate case), so wide lane groups with 2 quads each beat
-// narrower groups with 4 (measured: 16 x 2 about 9% faster than 8 x 4).
-constexpr int FWD_U = 2;
 // Quads in flight per lane in the sliced forward.
 constexpr int SELL_U = 4;
 
@@ -73,7 +69,6 @@ struct Tiled {
     int n_fwork = 0;
     int4* fwork_half = nullptr;   // fwork with each item's rows split in two halves (batched forward)
     int n_fwork_half = 0;
-    int fG = 8;
     // forward, sliced: each work item's rows sorted by length (longest first)
     // and cut into slices of 64 rows; a slice stores its quads column-major
     // (quad k of its 64 rows contiguous), padded to its longest row
@@ -96,7 +91,6 @@ struct Tiled {
     int64_t a_quads = 0;
     int4* awork = nullptr;        // (block, first slot, end slot, 0)
     int n_awork = 0;
-    int aG = 4;
     double* part = nullptr;       // [S] slot sums
     uint32_t* red_ptr = nullptr;  // [nb+1]
     uint32_t* red_slot = nullptr; // [S] slots of each beamlet, in block order

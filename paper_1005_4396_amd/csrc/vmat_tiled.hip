@@ -17,7 +17,6 @@
 #include "vmat_formats.h"
 #include "vmat_internal.h"
 #include "vmat_kernels.h"
-#include "vmat_rows.h"
 
 namespace vmat {
 
@@ -31,49 +30,6 @@ namespace vmat {
 // row are issued before the current row is summed (two rows in flight per
 // lane group).  Longer rows finish in extra passes.
 
-// Forward: rows are voxels of the block; x values of the block's beamlets
-// are staged in LDS (FWD_U quads per lane and pass).
-template <int FMT, int G, int U>
-__global__ __launch_bounds__(TILE_THREADS) void k_fwd_tiled(const int4* __restrict__ work,
-                                                          const uint32_t* __restrict__ loff,
-                                                          const uint32_t* __restrict__ list,
-                                                          const uint32_t* __restrict__ qptr,
-                                                          const uint16_t* __restrict__ col16,
-                                                          const void* __restrict__ val,
-                                                          const double* __restrict__ x, double* __restrict__ out,
-                                                          Gate gate) {
-    __shared__ double xs[TILE_LIST];
-    __shared__ uint32_t rq[TILE_ROWS + 1];
-    if (gate.closed()) return;
-    const int4 wk = work[blockIdx.x];
-    if (wk.x < 0) return;
-    const uint32_t l0 = loff[wk.x], ln = loff[wk.x + 1] - l0;
-    const int nrows = wk.z - wk.y;
-    stage_rows(rq, qptr + wk.y, nrows);
-    {
-        constexpr int K = TILE_LIST / TILE_THREADS;
-        uint32_t id[K];
-        double v[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint32_t u = threadIdx.x + k * TILE_THREADS;
-            id[k] = u < ln ? list[l0 + u] : 0u;
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint32_t u = threadIdx.x + k * TILE_THREADS;
-            v[k] = u < ln ? x[id[k]] : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint32_t u = threadIdx.x + k * TILE_THREADS;
-            if (u < ln) xs[u] = v[k];
-        }
-    }
-    __syncthreads();
-    StoreRow epi{out};
-    rows_of_item<FMT, G, U, double>(rq, nrows, wk.y, val, reinterpret_cast<const u16x4*>(col16), xs, epi);
-}
 
 // The slices of one work item: wave w takes slices w, w + 8, ...; lane i owns
 // row i of the slice and walks its quads in order, U quads in flight.
@@ -193,42 +149,6 @@ __global__ __launch_bounds__(64) void k_sell_fill(const uint32_t* __restrict__ s
     }
 }
 
-// Adjoint: rows are the block's slots; the block's slice of w is staged in
-// LDS; each slot row's sum goes to part[slot].
-template <int FMT, int G, int U>
-__global__ __launch_bounds__(TILE_THREADS) void k_adj_tiled(const int4* __restrict__ work,
-                                                          const int32_t* __restrict__ bounds,
-                                                          const uint32_t* __restrict__ aqptr,
-                                                          const uint16_t* __restrict__ col16,
-                                                          const void* __restrict__ val,
-                                                          const float* __restrict__ w, double* __restrict__ part,
-                                                          Gate gate) {
-    __shared__ float ws[TILE_VOXELS];
-    __shared__ uint32_t rq[TILE_ROWS + 1];
-    if (gate.closed()) return;
-    const int4 wk = work[blockIdx.x];
-    if (wk.x < 0) return;
-    const int32_t j0 = bounds[wk.x], jn = bounds[wk.x + 1] - j0;
-    const int nrows = wk.z - wk.y;
-    stage_rows(rq, aqptr + wk.y, nrows);
-    {
-        constexpr int K = TILE_VOXELS / TILE_THREADS;
-        float v[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int u = threadIdx.x + k * TILE_THREADS;
-            v[k] = u < jn ? w[j0 + u] : 0.0f;
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int u = threadIdx.x + k * TILE_THREADS;
-            if (u < jn) ws[u] = v[k];
-        }
-    }
-    __syncthreads();
-    StoreRow epi{part};
-    rows_of_item<FMT, G, U, float>(rq, nrows, wk.y, val, reinterpret_cast<const u16x4*>(col16), ws, epi);
-}
 
 // Adjoint over the sliced layout: rows are the block's slots, the block's
 // slice of w is staged in LDS; each slot row's sum goes to part[slot].
@@ -328,31 +248,15 @@ static vmat_status fwd_fmt(const vmat_ctx* h, const double* x, double* out, Gate
     const Tiled& t = h->tl;
     const unsigned grid = (unsigned)t.n_fwork;
     if (grid == 0) return VMAT_OK;
-    static const bool csr = getenv("VMAT_FWD_CSR") != nullptr;
-    if (t.s_val && !csr) {
-        const int su = sell_u(h, true);
+    const int su = sell_u(h, true);
 #define SELL(UU) k_fwd_sell<FMT, UU><<<grid, TILE_THREADS, 0, st>>>(t.fwork, t.loff, t.list, t.s_off, t.s_len, \
-                                                                  t.s_row, t.s_col, t.s_val, x, out, gate)
-        switch (su) {
-            case 2: SELL(2); break;
-            case 8: SELL(8); break;
-            default: SELL(4); break;
-        }
+                                                              t.s_row, t.s_col, t.s_val, x, out, gate)
+    switch (su) {
+        case 2: SELL(2); break;
+        case 8: SELL(8); break;
+        default: SELL(4); break;
+    }
 #undef SELL
-        VMAT_LAUNCH_CHECK();
-        return VMAT_OK;
-    }
-
-#define FWD(GG) k_fwd_tiled<FMT, GG, FWD_U><<<grid, TILE_THREADS, 0, st>>>(t.fwork, t.loff, t.list, h->vm.qptr, \
-                                                                       t.fcol, h->vm.val, x, out, gate)
-    switch (t.fG) {
-        case 2: FWD(2); break;
-        case 4: FWD(4); break;
-        case 8: FWD(8); break;
-        case 16: FWD(16); break;
-        default: FWD(32); break;
-    }
-#undef FWD
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
 }
@@ -361,8 +265,7 @@ template <int FMT>
 static vmat_status adj_fmt(const vmat_ctx* h, const float* w, double* g, Gate gate, hipStream_t st,
                            bool slots_only = false) {
     const Tiled& t = h->tl;
-    static const bool acsr = getenv("VMAT_ADJ_CSR") != nullptr;
-    if (t.n_awork > 0 && t.as_val && !acsr) {
+    if (t.n_awork > 0) {
         const int su = sell_u(h, false);
 #define ASELL(UU) k_adj_sell<FMT, UU><<<(unsigned)t.n_awork, TILE_THREADS, 0, st>>>( \
     t.awork, t.bounds, t.as_off, t.as_len, t.as_row, t.as_col, t.as_val, w, t.part, gate)
@@ -372,19 +275,6 @@ static vmat_status adj_fmt(const vmat_ctx* h, const float* w, double* g, Gate ga
             default: ASELL(4); break;
         }
 #undef ASELL
-        VMAT_LAUNCH_CHECK();
-    } else if (t.n_awork > 0) {
-#define ADJ(GG) k_adj_tiled<FMT, GG, 4><<<(unsigned)t.n_awork, TILE_THREADS, 0, st>>>(t.awork, t.bounds, \
-                                                                                      t.aqptr, t.acol, t.aval, w, \
-                                                                                      t.part, gate)
-        switch (t.aG) {
-            case 2: ADJ(2); break;
-            case 4: ADJ(4); break;
-            case 8: ADJ(8); break;
-            case 16: ADJ(16); break;
-            default: ADJ(32); break;
-        }
-#undef ADJ
         VMAT_LAUNCH_CHECK();
     }
     if (slots_only) return VMAT_OK;
@@ -664,12 +554,6 @@ hipError_t dmalloc(DevBuf& b, size_t bytes) {
     return hipMalloc(&b.p, std::max<size_t>(bytes, 16));
 }
 
-int pow2_floor_clamp(double v, int lo, int hi) {
-    int g = lo;
-    while (g * 2 <= hi && g * 2 <= v) g *= 2;
-    return g;
-}
-
 // Work items of about `qpw` quads each, never crossing a block; placed so
 // that consecutive items (same block) land on the same XCD (workgroup w runs
 // on XCD w mod 8).
@@ -881,8 +765,7 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     VMAT_HIP(hipMemcpyAsync(vq.data(), h->vm.qptr, (nv + 1) * 4, hipMemcpyDeviceToHost, st));
     VMAT_HIP(hipMemcpyAsync(aq.data(), t.aqptr, (t.S + 1) * 4, hipMemcpyDeviceToHost, st));
     VMAT_HIP(hipStreamSynchronize(st));
-    int64_t target_items = 1024;
-    if (const char* e = getenv("VMAT_WORK_ITEMS")) target_items = std::max(64, atoi(e));
+    const int64_t target_items = 1024;
     const int64_t fq = std::max<int64_t>(1, (int64_t)vq[nv]);
     const int64_t aqn = std::max<int64_t>(1, (int64_t)aq[t.S]);
     std::vector<int64_t> rb(bounds.begin(), bounds.end());
@@ -963,11 +846,6 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
                     t.as_row, t.as_col, t.as_val);
         if (rs != VMAT_OK) return rs;
     }
-    // about one pass of U = 4 quads per lane for a mean row
-    t.fG = pow2_floor_clamp(nv > 0 ? (double)fq / (double)nv / FWD_U * 1.5 : 1.0, 2, 32);
-    t.aG = pow2_floor_clamp(t.S > 0 ? (double)aqn / (double)t.S / 4.0 * 1.5 : 1.0, 2, 32);
-    if (const char* e = getenv("VMAT_FWD_LANES")) t.fG = std::max(2, std::min(32, atoi(e)));
-    if (const char* e = getenv("VMAT_ADJ_LANES")) t.aG = std::max(2, std::min(32, atoi(e)));
     VMAT_HIP(hipStreamSynchronize(st));
 #undef A
     t.on = true;
