@@ -228,6 +228,38 @@ vmat_status vmat_price(vmat_handle h, const double* g, const double* y, const in
                        const int32_t* r, const uint8_t* occ, int32_t* out_beam,
                        double* out_price, double* beam_prices, hipStream_t stream);
 
+/* Pricing without a handle and without allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  The same computation and results, bit
+ * for bit, as vmat_price on a handle built with the same beams, gamma,
+ * circular and max_leaf_step; the beam geometry comes in this struct.
+ * Per-row and per-beam intermediate results live in a static device array
+ * of the library (about 1.6 MB per GPU, held until the process ends), so:
+ *   - n_beams * n_rows <= VMAT_PRICE_NOALLOC_MAX_ROWS and
+ *     n_beams <= VMAT_PRICE_NOALLOC_MAX_BEAMS, else VMAT_ERR_INVALID_ARG
+ *     (nothing launched);
+ *   - calls that overlap on one GPU (two streams, or two threads) race on
+ *     that array: serialise them;
+ *   - nothing needs clearing between calls (each call writes every entry it
+ *     reads first).
+ * theta_deg is DEVICE double [N] here, strictly increasing in [0, 360) (not
+ * checked: the call is asynchronous).  g, y, l, r, occ and the outputs as for
+ * vmat_price.  The first call on a device looks up the array's address there;
+ * no call allocates.                                                          */
+#define VMAT_PRICE_NOALLOC_MAX_ROWS 65536
+#define VMAT_PRICE_NOALLOC_MAX_BEAMS 4096
+typedef struct vmat_beams {
+    int32_t n_beams, n_rows, n_cols;  /* N, R, C (C <= 64)                          */
+    int32_t circular;                 /* as vmat_problem.circular                    */
+    int32_t max_leaf_step;            /* delta, < 0 unconstrained                    */
+    int32_t reserved;
+    double gamma;                     /* finite, >= 0                                */
+    const double* theta_deg;          /* DEVICE [N]                                  */
+} vmat_beams;
+vmat_status vmat_price_noalloc(const vmat_beams* beams, const double* g, const double* y, const int32_t* l,
+                               const int32_t* r, const uint8_t* occ, int32_t* out_beam, double* out_price,
+                               double* beam_prices, hipStream_t stream);
+
 typedef struct vmat_master_opts {
     int32_t max_iter;       /* iteration cap (default 200)                              */
     int32_t ls_max_steps;   /* Newton/bisection steps per line search (default 50)     */

@@ -9,10 +9,13 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "vmat_block.h"
 #include "vmat_internal.h"
 #include "vmat_kernels.h"
+
+#include <string>
 
 namespace vmat {
 
@@ -297,4 +300,79 @@ vmat_status launch_price_variants(const vmat_ctx* h, int B, const double* g, con
     return VMAT_OK;
 }
 
+// ---------------------------------------------------------------- pricing without allocation
+// Scratch of vmat_price_noalloc: the per-row results (S*, margin, l*, r*) of
+// up to PRICE_NA_ROWS leaf rows and the prices of up to PRICE_NA_BEAMS beams,
+// in one file-scope device array.  Every GPU the library runs on holds its own
+// copy until the process ends.  Kernels get its address from
+// hipGetSymbolAddress (per device, at the first call on that device); the
+// array's name is not a device address in host code.
+constexpr int64_t PRICE_NA_ROWS = VMAT_PRICE_NOALLOC_MAX_ROWS;
+constexpr int64_t PRICE_NA_BEAMS = VMAT_PRICE_NOALLOC_MAX_BEAMS;
+constexpr size_t PRICE_NA_BYTES = (size_t)PRICE_NA_ROWS * (8 + 8 + 4 + 4) + (size_t)PRICE_NA_BEAMS * 8;
+static __device__ __align__(256) unsigned char scratch[PRICE_NA_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of this device's scratch array (looked up once).
+vmat_status scratch_address(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(VMAT_ERR_UNSUPPORTED, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(VMAT_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return VMAT_OK;
+}
+}  // namespace
+
 }  // namespace vmat
+
+using namespace vmat;
+
+extern "C" vmat_status vmat_price_noalloc(const vmat_beams* b, const double* g, const double* y, const int32_t* l,
+                                          const int32_t* r, const uint8_t* occ, int32_t* out_beam,
+                                          double* out_price, double* beam_prices, hipStream_t st) {
+    set_error("");
+    if (!b) return fail(VMAT_ERR_INVALID_ARG, "null beam description");
+    if (b->n_beams < 1 || b->n_rows < 1 || b->n_cols < 1)
+        return fail(VMAT_ERR_INVALID_ARG, "n_beams, n_rows and n_cols must be >= 1");
+    if (b->n_cols > 64) return fail(VMAT_ERR_UNSUPPORTED, "n_cols > 64 is not supported");
+    const int64_t NR = (int64_t)b->n_beams * b->n_rows;
+    if (NR > PRICE_NA_ROWS || b->n_beams > PRICE_NA_BEAMS)
+        return fail(VMAT_ERR_INVALID_ARG, "vmat_price_noalloc: n_beams * n_rows exceeds " +
+                                              std::to_string(PRICE_NA_ROWS) + " or n_beams exceeds " +
+                                              std::to_string(PRICE_NA_BEAMS) + " (the size of its static scratch)");
+    if (!std::isfinite(b->gamma) || b->gamma < 0.0) return fail(VMAT_ERR_INVALID_ARG, "gamma must be finite and >= 0");
+    if (!b->theta_deg || !g || !y || !l || !r || !occ || !out_beam || !out_price)
+        return fail(VMAT_ERR_INVALID_ARG, "null array");
+    int dev = -1;
+    VMAT_HIP(hipGetDevice(&dev));
+    unsigned char* base = nullptr;
+    vmat_status rc = scratch_address(dev, &base);
+    if (rc != VMAT_OK) return rc;
+    double* rowS = reinterpret_cast<double*>(base);
+    double* rowm = rowS + PRICE_NA_ROWS;
+    int32_t* rowl = reinterpret_cast<int32_t*>(rowm + PRICE_NA_ROWS);
+    int32_t* rowr = rowl + PRICE_NA_ROWS;
+    double* bprice = reinterpret_cast<double*>(rowr + PRICE_NA_ROWS);
+    // every entry the kernels read is written first in the same call (rows
+    // and beams of this problem): nothing needs clearing
+    k_price_rows<<<dim3((unsigned)((NR + 3) / 4), 1u), 256, 0, st>>>(b->n_beams, b->n_rows, b->n_cols,
+                                                                    b->max_leaf_step, b->circular ? 1 : 0, 1, g, l,
+                                                                    r, occ, rowS, rowl, rowr, rowm, nullptr);
+    VMAT_LAUNCH_CHECK();
+    k_price_beams<<<1u, CTRL, 0, st>>>(b->n_beams, b->n_rows, b->gamma, b->circular ? 1 : 0, b->theta_deg, y, occ,
+                                       rowS, rowl, rowr, rowm, bprice, out_beam, out_price, beam_prices, 0, 0,
+                                       nullptr, nullptr, nullptr, nullptr, SolveTraceDev{}, nullptr, nullptr);
+    VMAT_LAUNCH_CHECK();
+    return VMAT_OK;
+}
+

@@ -49,6 +49,12 @@ class LayoutInfo(ctypes.Structure):
                 ("weight_labels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class Beams(ctypes.Structure):
+    _fields_ = [("n_beams", ctypes.c_int32), ("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32),
+                ("circular", ctypes.c_int32), ("max_leaf_step", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("theta_deg", ctypes.c_void_p)]
+
+
 class MasterOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("ls_max_steps", ctypes.c_int32),
                 ("tol_rel", ctypes.c_double), ("kkt_ref", ctypes.c_double)]
@@ -132,6 +138,7 @@ def lib():
             "vmat_set_batched_tile": [P, I32, I32, I32],
             "vmat_reserve_batched": [P, I32],
             "vmat_reserve_solve": [P],
+            "vmat_price_noalloc": [ctypes.POINTER(Beams), P, P, P, P, P, P, P, P, P],
             "vmat_read_stream": [P, ctypes.c_int64, P, I32, P],
             "vmat_enforce_rate": [P, ctypes.POINTER(RateOpts), P, P, P, P, ctypes.POINTER(RateReport), P],
             "vmat_solve_batched": [P, ctypes.POINTER(SolveOpts), I32, I32, P, P, P, P, P, P,
@@ -174,6 +181,16 @@ def read_stream(buf, partials, grid: int) -> None:
     HBM read ceiling); partials: float32 device tensor of at least grid."""
     assert partials.numel() >= grid and partials.dtype.itemsize == 4
     _check(lib().vmat_read_stream(_ptr(buf), buf.numel() * buf.element_size(), _ptr(partials), grid, _stream()))
+
+
+def price_noalloc(theta, n_rows, n_cols, gamma, circular, max_leaf_step, g, y, l, r, occ, out_beam, out_price,
+                  beam_prices=None) -> int:
+    """vmat_price_noalloc on caller tensors (theta: float64 device [N]);
+    returns the status code (outputs are written on the device)."""
+    b = Beams(int(theta.numel()), int(n_rows), int(n_cols), int(circular), int(max_leaf_step), 0, float(gamma),
+              theta.data_ptr())
+    return lib().vmat_price_noalloc(ctypes.byref(b), _ptr(g), _ptr(y), _ptr(l), _ptr(r), _ptr(occ),
+                                    _ptr(out_beam), _ptr(out_price), _ptr(beam_prices), _stream())
 
 
 def master_opts(max_iter=200, ls_max_steps=50, tol_rel=1e-5, kkt_ref=0.0) -> MasterOpts:
