@@ -189,17 +189,26 @@ vmat_status vmat_adjoint(vmat_handle h, const float* w, double* g, hipStream_t s
  *              (larger labels are read as n_struct-1);
  *       table: DEVICE float [B][n_struct][3] = (alpha, beta, T) per variant
  *              and structure; cost: DEVICE double [B]; dF: DEVICE float [nv*B]
- *   vmat_tune_batched: times every RHS tile width (1, 2, 4, 8, 16, 32, 64;
- *       widths of 2B and more are skipped, their time +inf) for both products on the
- *       given buffers, reps launches each, and keeps the fastest for later
- *       calls with this B.  best: HOST int32 [2] (forward, adjoint tile);
- *       times_ms: HOST float [14] (nullable): forward then adjoint, per width.
- *   vmat_set_batched_tile: sets the tile widths used at B right-hand sides
- *       (0 = default; otherwise 1, 2, 4, ..., 64), e.g. from an earlier tuning.
+ *   vmat_tune_batched: times every product variant for both products on the
+ *       given buffers, reps launches each, and keeps the fastest of each for
+ *       later calls with this B.  A variant is (TB, RPW): TB right-hand sides
+ *       per pass over a row of D and RPW rows per wavefront (64 / RPW lanes
+ *       per row, each with TB * RPW / 64 consecutive right-hand sides), in
+ *       this order: (1,64) (2,32) (4,16) (8,8) (16,4) (16,8) (32,2) (32,4)
+ *       (32,8) (64,1) (64,2) (64,4) (64,8).  Variants with TB >= 2B, or whose
+ *       per-lane count does not divide B, are skipped (time +inf); the plain
+ *       layout has one variant per TB (RPW = 64 / TB).
+ *       best: HOST int32 [4] (forward TB, RPW, adjoint TB, RPW);
+ *       times_ms: HOST float [26] (nullable): forward then adjoint, per variant.
+ *   vmat_set_batched_tile: sets the variants used at B right-hand sides
+ *       ((0, 0) = default; otherwise a listed pair), e.g. from an earlier tuning.
  * 1 <= B <= 64, 1 <= n_struct <= 16, FP64 accumulation, any storage format.
- * Results are deterministic (no atomics).  Tile widths change no result,
- * except that after vmat_reserve_batched the 64-wide adjoint (tiled layout)
- * sums each beamlet per voxel block first: rounding-level differences.     */
+ * Results are deterministic (no atomics).  Variants change no result.  In
+ * the tiled layout the adjoint sums each beamlet per voxel block first, which
+ * needs the state of vmat_reserve_batched (without it the plain beamlet-major
+ * rows are used: rounding-level differences).  Each XCD of the GPU walks its
+ * own range of voxel blocks, so the right-hand sides a block gathers stay in
+ * that XCD's L2.                                                              */
 vmat_status vmat_forward_batched(vmat_handle h, int32_t B, const float* X, double* Z,
                                  hipStream_t stream);
 vmat_status vmat_adjoint_batched(vmat_handle h, int32_t B, const float* W, double* G,
@@ -207,7 +216,8 @@ vmat_status vmat_adjoint_batched(vmat_handle h, int32_t B, const float* W, doubl
 vmat_status vmat_grad_batched(vmat_handle h, int32_t B, int32_t n_struct, const uint8_t* label,
                               const float* table, const float* X, double* Z, double* cost,
                               float* dF, double* G, hipStream_t stream);
-vmat_status vmat_set_batched_tile(vmat_handle h, int32_t B, int32_t fwd_tile, int32_t adj_tile);
+vmat_status vmat_set_batched_tile(vmat_handle h, int32_t B, int32_t fwd_tile, int32_t fwd_rpw, int32_t adj_tile,
+                                  int32_t adj_rpw);
 vmat_status vmat_tune_batched(vmat_handle h, int32_t B, const float* X, double* Z, const float* W,
                               double* G, int32_t reps, int32_t* best, float* times_ms,
                               hipStream_t stream);

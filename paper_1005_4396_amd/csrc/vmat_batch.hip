@@ -35,48 +35,333 @@ __device__ __forceinline__ double xval(const float* __restrict__ X, const float*
     else return v;
 }
 
-// Forward, tiled layout: rows are voxels of the block, the block's beamlet
-// list is staged in LDS and maps the 16-bit indices to beamlets.
-template <int FMT, int TB>
-__global__ __launch_bounds__(SPMM_THREADS) void k_spmm_fwd_tiled(const int4* __restrict__ work,
-                                                                const uint32_t* __restrict__ loff,
-                                                                const uint32_t* __restrict__ list,
-                                                                const uint32_t* __restrict__ qptr,
-                                                                const uint16_t* __restrict__ col16,
-                                                                const void* __restrict__ val,
-                                                                const float* __restrict__ cscale, int B,
-                                                                const float* __restrict__ X, double* __restrict__ Z) {
-    __shared__ uint32_t ls[TILE_LIST];
-    const int4 wk = work[blockIdx.x];
-    if (wk.x < 0) return;
-    const uint32_t l0 = loff[wk.x], ln = loff[wk.x + 1] - l0;
-    for (uint32_t u = threadIdx.x; u < ln; u += SPMM_THREADS) ls[u] = list[l0 + u];
-    __syncthreads();
-    constexpr int RPW = 64 / TB;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int b = blockIdx.y * TB + (lane % TB);
-    const bool col_ok = b < B;
-    const u16x4* c4 = reinterpret_cast<const u16x4*>(col16);
-    for (int row = wk.y + wave * RPW + lane / TB; row < wk.z; row += (SPMM_THREADS / 64) * RPW) {
-        double acc = 0.0;
-        const uint32_t q1 = qptr[row + 1];
-        for (uint32_t q = qptr[row]; q < q1; ++q) {
-            const float4 v = Quad<FMT>::load(val, q);
-            const u16x4 c = c4[q];
-            if (col_ok) {
-                const uint32_t i0 = ls[c.x], i1 = ls[c.y], i2 = ls[c.z], i3 = ls[c.w];
-                acc = fma((double)v.x, xval<FMT>(X, cscale, i0, B, b), acc);
-                acc = fma((double)v.y, xval<FMT>(X, cscale, i1, B, b), acc);
-                acc = fma((double)v.z, xval<FMT>(X, cscale, i2, B, b), acc);
-                acc = fma((double)v.w, xval<FMT>(X, cscale, i3, B, b), acc);
-            }
+// ---- tiled layout: XCD-owned voxel blocks over the sliced layouts
+//
+// A row of D (a voxel of the forward, a slot row of the adjoint) is walked by
+// LPR lanes, each holding V consecutive right-hand sides (TB = LPR * V per
+// pass over the row; RPW = 64 / LPR rows per wave).  Every (row, RHS) sum
+// runs over the row's quads in order, entries in order: the bits do not
+// depend on LPR, V or the schedule.
+//
+// Schedule: workgroup w runs on XCD w % 8.  XCD i walks its own contiguous
+// range of voxel blocks in order, and within a block the right-hand sides in
+// tiles of TB, all its workgroups on one (block, tile) at a time, so the rows
+// a block gathers (at most TILE_LIST beamlets, or the block's voxels, times
+// TB values) stay in that XCD's L2 while its workgroups read them.  Within a
+// (block, tile) the units of work are (slice, group of RPW rows), dealt to
+// the XCD's waves in order.  Gathered rows are addressed by 32-bit element
+// offsets from a uniform base.
+
+// V consecutive floats at p (V-aligned: V | B and the column is a multiple of V).
+template <int V>
+__device__ __forceinline__ void ld_vec(const float* __restrict__ p, float (&o)[V]) {
+    if constexpr (V == 1) {
+        o[0] = *p;
+    } else if constexpr (V == 2) {
+        const f32x2 a = *reinterpret_cast<const f32x2*>(p);
+        o[0] = a.x;
+        o[1] = a.y;
+    } else {
+#pragma unroll
+        for (int h = 0; h < V / 4; ++h) {
+            const f32x4 a = reinterpret_cast<const f32x4*>(p)[h];
+            o[4 * h + 0] = a.x;
+            o[4 * h + 1] = a.y;
+            o[4 * h + 2] = a.z;
+            o[4 * h + 3] = a.w;
         }
-        if (col_ok) Z[(int64_t)row * B + b] = acc;
     }
 }
 
-// Quad-CSR rows with 32-bit column indices: the plain voxel-major copy
-// (forward) or the beamlet-major copy (adjoint, with the FP8 row scale).
+// Blocks of XCD xcd: [xr.b[xcd], xr.b[xcd + 1]).
+struct XcdRanges {
+    int32_t b[9];
+};
+
+// One row's sums over its quads [q, q + 64 len) (column-major slice: the
+// row's next quad is 64 quads on), V right-hand sides.  ROW(c16) gives the
+// element offset of the gathered row's first right-hand side of this lane
+// (from the uniform base Y); SC(c16) its column scale (CS only).  Two quads
+// per step keep eight gathers in flight.
+template <int FMT, int V, bool CS, class ROW, class SCL>
+__device__ __forceinline__ void row_sums(uint32_t q, uint32_t len, const u16x4* __restrict__ col,
+                                         const void* __restrict__ val, const float* __restrict__ Y, ROW rowoff,
+                                         SCL scl, double (&acc)[V]) {
+    uint32_t k = 0;
+    for (; k + 2 <= len; k += 2) {
+        float4 v[2];
+        u16x4 cc[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            v[h] = Quad<FMT>::ld(val, q + (k + h) * 64);
+            cc[h] = col[q + (k + h) * 64];
+        }
+        float y[2][4][V];
+        float sc[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint16_t ce[4] = {cc[h].x, cc[h].y, cc[h].z, cc[h].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                ld_vec<V>(Y + rowoff(ce[e]), y[h][e]);
+                if constexpr (CS) sc[h][e] = scl(ce[e]);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float ve[4] = {v[h].x, v[h].y, v[h].z, v[h].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    double xv = (double)y[h][e][j];
+                    if constexpr (CS) xv *= (double)sc[h][e];
+                    acc[j] = fma((double)ve[e], xv, acc[j]);
+                }
+        }
+    }
+    if (k < len) {
+        const float4 v1 = Quad<FMT>::ld(val, q + k * 64);
+        const u16x4 c1 = col[q + k * 64];
+        const uint16_t ce[4] = {c1.x, c1.y, c1.z, c1.w};
+        const float ve[4] = {v1.x, v1.y, v1.z, v1.w};
+        float y[4][V];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ld_vec<V>(Y + rowoff(ce[e]), y[e]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double s = CS ? (double)scl(ce[e]) : 1.0;
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                double xv = (double)y[e][j];
+                if constexpr (CS) xv *= s;
+                acc[j] = fma((double)ve[e], xv, acc[j]);
+            }
+        }
+    }
+}
+
+constexpr int BFWD_THREADS = 256;
+
+// Forward Z = D^T X on the sliced voxel rows.  The block's beamlet list is
+// staged in LDS as element offsets of the beamlets' rows of X (beamlet * B),
+// with the FP8 column scales beside them; entries past the list's end read as
+// beamlet 0 (padding quads).
+template <int FMT, int LPR, int V>
+__global__ __launch_bounds__(BFWD_THREADS) void k_bfwd(XcdRanges xr, const uint32_t* __restrict__ bptr,
+                                                      const uint32_t* __restrict__ bsl,
+                                                      const uint32_t* __restrict__ loff,
+                                                      const uint32_t* __restrict__ list,
+                                                      const uint32_t* __restrict__ s_off,
+                                                      const uint32_t* __restrict__ s_len,
+                                                      const uint32_t* __restrict__ s_row,
+                                                      const u16x4* __restrict__ s_col, const void* __restrict__ s_val,
+                                                      const float* __restrict__ cscale, int B,
+                                                      const float* __restrict__ X, double* __restrict__ Z) {
+    constexpr int RPW = 64 / LPR, TB = LPR * V, UPS = LPR;  // units (row groups) per slice
+    constexpr int WAVES = BFWD_THREADS / 64;
+    constexpr bool CS = FMT == FMT_FP8;
+    __shared__ uint32_t ls[TILE_LIST];
+    __shared__ float lsc[CS ? TILE_LIST : 1];
+    const int xcd = blockIdx.x & 7, wl = blockIdx.x >> 3, G = gridDim.x >> 3;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rg = lane / LPR, sub = lane % LPR;
+    for (int b = xr.b[xcd]; b < xr.b[xcd + 1]; ++b) {
+        const uint32_t l0 = loff[b], ln = loff[b + 1] - l0;
+        __syncthreads();
+        for (uint32_t u = threadIdx.x; u < TILE_LIST; u += BFWD_THREADS) {
+            const uint32_t i = u < ln ? list[l0 + u] : 0u;
+            ls[u] = i * (uint32_t)B;
+            if constexpr (CS) lsc[u] = cscale[i];
+        }
+        __syncthreads();
+        const uint32_t s0 = bptr[b], nunits = (bptr[b + 1] - s0) * UPS;
+        for (int b0 = 0; b0 < B; b0 += TB) {
+            const int c = min(b0 + sub * V, B - V);
+            auto rowoff = [&](uint32_t c16) { return ls[c16] + (uint32_t)c; };
+            auto scl = [&](uint32_t c16) { return CS ? lsc[c16] : 1.0f; };
+            for (uint32_t unit = (uint32_t)wl * WAVES + wave; unit < nunits; unit += (uint32_t)G * WAVES) {
+                const uint32_t sl = bsl[s0 + unit / UPS];
+                const uint32_t r = (unit % UPS) * RPW + rg;
+                const uint32_t row = s_row[(int64_t)sl * 64 + r];
+                double acc[V];
+#pragma unroll
+                for (int j = 0; j < V; ++j) acc[j] = 0.0;
+                row_sums<FMT, V, CS>(s_off[sl] + r, s_len[sl], s_col, s_val, X, rowoff, scl, acc);
+                if (row != 0xFFFFFFFFu && b0 + sub * V < B)
+#pragma unroll
+                    for (int j = 0; j < V; ++j) Z[(int64_t)row * B + c + j] = acc[j];
+            }
+        }
+    }
+}
+
+// One row per wave, one right-hand side per lane (TB = 64, RPW = 1): the row
+// is the same for every lane, so its quads of D (and, in the forward, the
+// beamlets they name) come through scalar loads, and each gather is one
+// coalesced 256-byte row of the right-hand sides: a uniform row pointer
+// indexed by the lane.  The FP8 column scale folds into the uniform value:
+// fma(d * s, x, acc) rounds the same exact product d * s * x as
+// fma(d, x * s, acc).  ROWP(c16): the uniform pointer to the gathered row.
+template <int FMT, bool CS, class ROWP, class SCL>
+__device__ __forceinline__ double row_sum_w(uint32_t q, uint32_t len, const u16x4* __restrict__ col,
+                                            const void* __restrict__ val, int lane, ROWP rowp, SCL scl) {
+    double acc = 0.0;
+    uint32_t k = 0;
+    for (; k + 2 <= len; k += 2) {
+        float4 v[2];
+        u16x4 cc[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            v[h] = Quad<FMT>::ld(val, q + (k + h) * 64);
+            cc[h] = col[q + (k + h) * 64];
+        }
+        float y[8];
+        double d[8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint16_t ce[4] = {cc[h].x, cc[h].y, cc[h].z, cc[h].w};
+            const float ve[4] = {v[h].x, v[h].y, v[h].z, v[h].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                y[4 * h + e] = rowp(ce[e])[lane];
+                d[4 * h + e] = CS ? (double)ve[e] * (double)scl(ce[e]) : (double)ve[e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc = fma(d[e], (double)y[e], acc);
+    }
+    if (k < len) {
+        const float4 v1 = Quad<FMT>::ld(val, q + k * 64);
+        const u16x4 c1 = col[q + k * 64];
+        const uint16_t ce[4] = {c1.x, c1.y, c1.z, c1.w};
+        const float ve[4] = {v1.x, v1.y, v1.z, v1.w};
+        float y[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) y[e] = rowp(ce[e])[lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double dv = CS ? (double)ve[e] * (double)scl(ce[e]) : (double)ve[e];
+            acc = fma(dv, (double)y[e], acc);
+        }
+    }
+    return acc;
+}
+
+// The uniform wave index (every value derived from it stays scalar).
+__device__ __forceinline__ uint32_t wave_id() {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+template <int FMT>
+__global__ __launch_bounds__(SPMM_THREADS) void k_bfwd_w(XcdRanges xr, const uint32_t* __restrict__ bptr,
+                                                        const uint32_t* __restrict__ bsl,
+                                                        const uint32_t* __restrict__ loff,
+                                                        const uint32_t* __restrict__ list,
+                                                        const uint32_t* __restrict__ s_off,
+                                                        const uint32_t* __restrict__ s_len,
+                                                        const uint32_t* __restrict__ s_row,
+                                                        const u16x4* __restrict__ s_col,
+                                                        const void* __restrict__ s_val,
+                                                        const float* __restrict__ cscale, int B,
+                                                        const float* __restrict__ X, double* __restrict__ Z) {
+    constexpr int WAVES = SPMM_THREADS / 64;
+    constexpr bool CS = FMT == FMT_FP8;
+    const int xcd = blockIdx.x & 7, wl = blockIdx.x >> 3, G = gridDim.x >> 3;
+    const uint32_t wave = wave_id();
+    const int lane = (int)(threadIdx.x & 63);
+    const int cl = min(lane, B - 1);
+    for (int b = xr.b[xcd]; b < xr.b[xcd + 1]; ++b) {
+        const uint32_t* __restrict__ lb = list + loff[b];
+        auto rowp = [&](uint32_t c16) { return X + (size_t)(lb[c16] * (uint32_t)B); };
+        auto scl = [&](uint32_t c16) { return CS ? cscale[lb[c16]] : 1.0f; };
+        const uint32_t s0 = bptr[b], nunits = (bptr[b + 1] - s0) * 64;
+        for (uint32_t unit = (uint32_t)wl * WAVES + wave; unit < nunits; unit += (uint32_t)G * WAVES) {
+            const uint32_t sl = bsl[s0 + unit / 64];
+            const uint32_t r = unit % 64;
+            const uint32_t row = s_row[(int64_t)sl * 64 + r];
+            const double acc = row_sum_w<FMT, CS>(s_off[sl] + r, s_len[sl], s_col, s_val, cl, rowp, scl);
+            if (row != 0xFFFFFFFFu && lane < B) Z[(int64_t)row * B + lane] = acc;
+        }
+    }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(SPMM_THREADS) void k_badj_w(XcdRanges xr, const uint32_t* __restrict__ bptr,
+                                                        const uint32_t* __restrict__ bsl,
+                                                        const int32_t* __restrict__ bounds,
+                                                        const uint32_t* __restrict__ s_off,
+                                                        const uint32_t* __restrict__ s_len,
+                                                        const uint32_t* __restrict__ s_row,
+                                                        const u16x4* __restrict__ s_col,
+                                                        const void* __restrict__ s_val, int B,
+                                                        const float* __restrict__ W, double* __restrict__ part) {
+    constexpr int WAVES = SPMM_THREADS / 64;
+    const int xcd = blockIdx.x & 7, wl = blockIdx.x >> 3, G = gridDim.x >> 3;
+    const uint32_t wave = wave_id();
+    const int lane = (int)(threadIdx.x & 63);
+    const int cl = min(lane, B - 1);
+    for (int b = xr.b[xcd]; b < xr.b[xcd + 1]; ++b) {
+        const float* __restrict__ Wb = W + (int64_t)bounds[b] * B;
+        auto rowp = [&](uint32_t c16) { return Wb + (size_t)(c16 * (uint32_t)B); };
+        auto scl = [](uint32_t) { return 1.0f; };
+        const uint32_t s0 = bptr[b], nunits = (bptr[b + 1] - s0) * 64;
+        for (uint32_t unit = (uint32_t)wl * WAVES + wave; unit < nunits; unit += (uint32_t)G * WAVES) {
+            const uint32_t sl = bsl[s0 + unit / 64];
+            const uint32_t r = unit % 64;
+            const uint32_t row = s_row[(int64_t)sl * 64 + r];
+            const double acc = row_sum_w<FMT, false>(s_off[sl] + r, s_len[sl], s_col, s_val, cl, rowp, scl);
+            if (row != 0xFFFFFFFFu && lane < B) part[(int64_t)row * B + lane] = acc;
+        }
+    }
+}
+
+// Adjoint slot sums part[slot][b] = sum over the slot row's entries of
+// D * W[voxel][b], on the sliced slot rows (16-bit voxel offsets from the
+// block's first voxel); k_spmm_adj_reduce then sums each beamlet's slots.
+template <int FMT, int LPR, int V>
+__global__ __launch_bounds__(SPMM_THREADS) void k_badj(XcdRanges xr, const uint32_t* __restrict__ bptr,
+                                                      const uint32_t* __restrict__ bsl,
+                                                      const int32_t* __restrict__ bounds,
+                                                      const uint32_t* __restrict__ s_off,
+                                                      const uint32_t* __restrict__ s_len,
+                                                      const uint32_t* __restrict__ s_row,
+                                                      const u16x4* __restrict__ s_col, const void* __restrict__ s_val,
+                                                      int B, const float* __restrict__ W, double* __restrict__ part) {
+    constexpr int RPW = 64 / LPR, TB = LPR * V, UPS = LPR;
+    constexpr int WAVES = SPMM_THREADS / 64;
+    const int xcd = blockIdx.x & 7, wl = blockIdx.x >> 3, G = gridDim.x >> 3;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rg = lane / LPR, sub = lane % LPR;
+    for (int b = xr.b[xcd]; b < xr.b[xcd + 1]; ++b) {
+        const float* __restrict__ Wb = W + (int64_t)bounds[b] * B;
+        const uint32_t s0 = bptr[b], nunits = (bptr[b + 1] - s0) * UPS;
+        for (int b0 = 0; b0 < B; b0 += TB) {
+            const int c = min(b0 + sub * V, B - V);
+            auto rowoff = [&](uint32_t c16) { return c16 * (uint32_t)B + (uint32_t)c; };
+            auto scl = [](uint32_t) { return 1.0f; };
+            for (uint32_t unit = (uint32_t)wl * WAVES + wave; unit < nunits; unit += (uint32_t)G * WAVES) {
+                const uint32_t sl = bsl[s0 + unit / UPS];
+                const uint32_t r = (unit % UPS) * RPW + rg;
+                const uint32_t row = s_row[(int64_t)sl * 64 + r];
+                double acc[V];
+#pragma unroll
+                for (int j = 0; j < V; ++j) acc[j] = 0.0;
+                row_sums<FMT, V, false>(s_off[sl] + r, s_len[sl], s_col, s_val, Wb, rowoff, scl, acc);
+                if (row != 0xFFFFFFFFu && b0 + sub * V < B)
+#pragma unroll
+                    for (int j = 0; j < V; ++j) part[(int64_t)row * B + c + j] = acc[j];
+            }
+        }
+    }
+}
+
+// ---- plain layout (quad CSR with 32-bit indices): the untileable fallback,
+// and the adjoint of a handle without the batched state's slot sums
+
+// TB lanes of a wave share a row (its index and value loads are broadcasts)
+// and gather TB consecutive right-hand sides per non-zero; 64/TB rows go
+// through a wave at once.
 template <int FMT, int TB>
 __global__ __launch_bounds__(SPMM_THREADS) void k_spmm_rows(const uint32_t* __restrict__ qptr,
                                                            const int32_t* __restrict__ col,
@@ -110,180 +395,6 @@ __global__ __launch_bounds__(SPMM_THREADS) void k_spmm_rows(const uint32_t* __re
     Z[row * B + b] = rscale ? acc * (double)rscale[row] : acc;
 }
 
-// Full-wave tile (64 right-hand sides): one row per wave at a time.  The
-// wave loads up to 64 quads of the row at once, one per lane (coalesced),
-// then walks them with the quad's indices and values broadcast from the
-// owning lane, so the gathers of several quads are in flight together.
-__device__ __forceinline__ uint32_t bcast(uint32_t v, int lane) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
-}
-__device__ __forceinline__ float bcastf(float v, int lane) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
-// ROWS: 0 = tiled forward (16-bit local indices through the LDS list),
-// 1 = 32-bit indices.  CS: the FP8 column scale applies (forward side).
-template <int FMT, int ROWS, bool CS>
-__device__ __forceinline__ double row_w64(uint32_t q0, uint32_t q1, const void* __restrict__ val,
-                                          const void* __restrict__ colp, const uint32_t* __restrict__ ls,
-                                          const float* __restrict__ cscale, int B, int b,
-                                          const float* __restrict__ X) {
-    const int lane = threadIdx.x & 63;
-    double acc = 0.0;
-    for (uint32_t base = q0; base < q1; base += 64) {
-        const uint32_t n = min(64u, q1 - base);
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-        if ((uint32_t)lane < n) {
-            v = Quad<FMT>::load(val, base + lane);
-            if constexpr (ROWS == 0) {
-                const u16x4 c = reinterpret_cast<const u16x4*>(colp)[base + lane];
-                c0 = ls[c.x];
-                c1 = ls[c.y];
-                c2 = ls[c.z];
-                c3 = ls[c.w];
-            } else {
-                const i32x4 c = reinterpret_cast<const i32x4*>(colp)[base + lane];
-                c0 = (uint32_t)c.x;
-                c1 = (uint32_t)c.y;
-                c2 = (uint32_t)c.z;
-                c3 = (uint32_t)c.w;
-            }
-        }
-        // lanes past the last right-hand side gather a valid column and store
-        // nothing; quads past the row's end (lanes >= n) hold zeros and index 0
-        const int bb = b < B ? b : B - 1;
-        constexpr int XF = CS ? FMT : FMT_F32;
-        for (uint32_t k = 0; k < n; k += 4) {
-            double xs[4][4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                xs[u][0] = xval<XF>(X, cscale, bcast(c0, k + u), B, bb);
-                xs[u][1] = xval<XF>(X, cscale, bcast(c1, k + u), B, bb);
-                xs[u][2] = xval<XF>(X, cscale, bcast(c2, k + u), B, bb);
-                xs[u][3] = xval<XF>(X, cscale, bcast(c3, k + u), B, bb);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                acc = fma((double)bcastf(v.x, k + u), xs[u][0], acc);
-                acc = fma((double)bcastf(v.y, k + u), xs[u][1], acc);
-                acc = fma((double)bcastf(v.z, k + u), xs[u][2], acc);
-                acc = fma((double)bcastf(v.w, k + u), xs[u][3], acc);
-            }
-        }
-    }
-    return acc;
-}
-
-template <int FMT>
-__global__ __launch_bounds__(SPMM_THREADS) void k_spmm_fwd_tiled_w64(const int4* __restrict__ work, int n_items,
-                                                                    const uint32_t* __restrict__ loff,
-                                                                    const uint32_t* __restrict__ list,
-                                                                    const uint32_t* __restrict__ qptr,
-                                                                    const uint16_t* __restrict__ col16,
-                                                                    const void* __restrict__ val,
-                                                                    const float* __restrict__ cscale, int B,
-                                                                    const float* __restrict__ X,
-                                                                    double* __restrict__ Z) {
-    __shared__ uint32_t ls[TILE_LIST];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int b = blockIdx.y * 64 + lane;
-    // persistent: a fixed grid (a multiple of 8 workgroups, so item i keeps
-    // running on XCD i mod 8) walks the work items
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int4 wk = work[it];
-        if (wk.x < 0) continue;
-        const uint32_t l0 = loff[wk.x], ln = loff[wk.x + 1] - l0;
-        for (uint32_t u = threadIdx.x; u < ln; u += SPMM_THREADS) ls[u] = list[l0 + u];
-        __syncthreads();
-        for (int row = wk.y + wave; row < wk.z; row += SPMM_THREADS / 64) {
-            const double acc =
-                row_w64<FMT, 0, FMT == FMT_FP8>(qptr[row], qptr[row + 1], val, col16, ls, cscale, B, b, X);
-            if (b < B) Z[(int64_t)row * B + b] = acc;
-        }
-        __syncthreads();
-    }
-}
-
-template <int FMT, bool CS>
-__global__ __launch_bounds__(SPMM_THREADS) void k_spmm_rows_w64(const uint32_t* __restrict__ qptr,
-                                                               const int32_t* __restrict__ col,
-                                                               const void* __restrict__ val,
-                                                               const float* __restrict__ cscale,
-                                                               const float* __restrict__ rscale, int64_t nrows,
-                                                               int B, const float* __restrict__ X,
-                                                               double* __restrict__ Z) {
-    const int lane = threadIdx.x & 63;
-    // the grid is a multiple of 8 blocks; workgroup w runs on XCD w mod 8, so
-    // XCD x takes the x-th eighth of the rows (neighbouring rows gather
-    // neighbouring right-hand-side rows through the same L2)
-    const int64_t per = gridDim.x / 8;
-    const int64_t blk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-    const int64_t row = (blk * SPMM_THREADS + threadIdx.x) / 64;
-    const int b = blockIdx.y * 64 + lane;
-    if (row >= nrows) return;
-    const double acc = row_w64<FMT, 1, CS>(qptr[row], qptr[row + 1], val, col, nullptr, cscale, B, b, X);
-    if (b < B) Z[row * B + b] = rscale ? acc * (double)rscale[row] : acc;
-}
-
-// Adjoint over the tiled slot rows (one beamlet's entries within one voxel
-// block, 16-bit voxel offsets): the W rows a block gathers belong to its
-// voxel range and stay in the L2 of the XCD its work items run on.  One slot
-// row per wave at a time; sums go to part[slot][b].
-template <int FMT>
-__global__ __launch_bounds__(SPMM_THREADS) void k_spmm_adj_slots_w64(const int4* __restrict__ work, int n_items,
-                                                                    const int32_t* __restrict__ bounds,
-                                                                    const uint32_t* __restrict__ aqptr,
-                                                                    const uint16_t* __restrict__ acol,
-                                                                    const void* __restrict__ aval, int B,
-                                                                    const float* __restrict__ W,
-                                                                    double* __restrict__ part) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int b = lane;
-    const int bb = b < B ? b : B - 1;
-    const u16x4* __restrict__ c4 = reinterpret_cast<const u16x4*>(acol);
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {  // persistent, as the forward
-        const int4 wk = work[it];
-        if (wk.x < 0) continue;
-        const float* __restrict__ Wb = W + (int64_t)bounds[wk.x] * B;
-        for (int row = wk.y + wave; row < wk.z; row += SPMM_THREADS / 64) {
-            const uint32_t q0 = aqptr[row], q1 = aqptr[row + 1];
-            double acc = 0.0;
-            for (uint32_t base = q0; base < q1; base += 64) {
-                const uint32_t n = min(64u, q1 - base);
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-                if ((uint32_t)lane < n) {
-                    v = Quad<FMT>::load(aval, base + lane);
-                    const u16x4 c = c4[base + lane];
-                    c0 = c.x;
-                    c1 = c.y;
-                    c2 = c.z;
-                    c3 = c.w;
-                }
-                for (uint32_t k = 0; k < n; k += 8) {
-                    double xs[8][4];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        xs[u][0] = (double)Wb[(int64_t)bcast(c0, k + u) * B + bb];
-                        xs[u][1] = (double)Wb[(int64_t)bcast(c1, k + u) * B + bb];
-                        xs[u][2] = (double)Wb[(int64_t)bcast(c2, k + u) * B + bb];
-                        xs[u][3] = (double)Wb[(int64_t)bcast(c3, k + u) * B + bb];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        acc = fma((double)bcastf(v.x, k + u), xs[u][0], acc);
-                        acc = fma((double)bcastf(v.y, k + u), xs[u][1], acc);
-                        acc = fma((double)bcastf(v.z, k + u), xs[u][2], acc);
-                        acc = fma((double)bcastf(v.w, k + u), xs[u][3], acc);
-                    }
-                }
-            }
-            if (b < B) part[(int64_t)row * B + b] = acc;
-        }
-    }
-}
-
 // G[i][b] = scale_i * sum of beamlet i's slot sums (block order).
 __global__ __launch_bounds__(256) void k_spmm_adj_reduce(int64_t nb, int B, const uint32_t* __restrict__ red_ptr,
                                                          const uint32_t* __restrict__ red_slot,
@@ -298,102 +409,163 @@ __global__ __launch_bounds__(256) void k_spmm_adj_reduce(int64_t nb, int B, cons
     G[e] = scale ? s * (double)scale[i] : s;
 }
 
-// Workgroups of the persistent 64-wide kernels: at most per_cu per compute
-// unit (256 CUs), a multiple of 8 (work items are placed round-robin on the
-// XCDs).  Measured on the prostate case: the adjoint is fastest with 2 per
-// CU, the forward (whose LDS list limits residency) with 4.
-static unsigned persistent_grid(int n_items, int per_cu) {
-    const int g = std::min(n_items, per_cu * 256);
-    return (unsigned)std::max(8, (g + 7) / 8 * 8);
+// The product variants: TB right-hand sides per pass over a row and RPW rows
+// per wave (LPR = 64 / RPW lanes per row, V = TB / LPR per lane).  The tiled
+// layout runs every listed pair; the plain layout runs k_spmm_rows<TB>
+// (RPW = 64 / TB) whatever RPW is asked.
+struct SpmmCfg {
+    int tb, rpw;
+};
+static const SpmmCfg kCfgs[] = {{1, 64}, {2, 32}, {4, 16}, {8, 8},  {16, 4}, {16, 8}, {32, 2},
+                                {32, 4}, {32, 8}, {64, 1}, {64, 2}, {64, 4}, {64, 8}};
+constexpr int N_CFGS = sizeof(kCfgs) / sizeof(kCfgs[0]);
+
+static bool cfg_known(int tb, int rpw) {
+    for (const SpmmCfg& c : kCfgs)
+        if (c.tb == tb && c.rpw == rpw) return true;
+    return false;
 }
 
-// Blocks for nrows rows at rpb rows per block, rounded up to a multiple of 8.
-static unsigned xcd_grid(int64_t nrows, int64_t rpb) {
-    const int64_t n = (nrows + rpb - 1) / rpb;
-    return (unsigned)((n + 7) / 8 * 8);
+// Untuned: one pass over all right-hand sides (the smallest width >= B),
+// four rows per wave where the width allows.
+static SpmmCfg default_cfg(int B) {
+    int t = 1;
+    while (t < B && t < 64) t <<= 1;
+    return SpmmCfg{t, std::max(4, 64 / t)};
 }
 
-template <int FMT, int TB>
-static void spmm_fwd_t(const vmat_ctx* h, int B, const float* X, double* Z, hipStream_t st) {
-    const unsigned tiles = (unsigned)((B + TB - 1) / TB);
-    if constexpr (TB == 64) {
-        if (h->tl.on) {
-            const Tiled& t = h->tl;
-            k_spmm_fwd_tiled_w64<FMT><<<dim3(persistent_grid(t.n_fwork_half, 8), tiles), SPMM_THREADS, 0, st>>>(
-                t.fwork_half, t.n_fwork_half, t.loff, t.list, h->vm.qptr, t.fcol, h->vm.val, h->bm.scale, B, X, Z);
-        } else {
-            const int64_t rpb = SPMM_THREADS / 64;
-            k_spmm_rows_w64<FMT, FMT == FMT_FP8><<<dim3(xcd_grid(h->nv, rpb), tiles), SPMM_THREADS, 0, st>>>(
-                h->vm.qptr, h->vm.col, h->vm.val, h->bm.scale, nullptr, h->nv, B, X, Z);
-        }
-        return;
+// Persistent grids: as many workgroups as can be resident at once (the
+// occupancy of the kernel, on the 32 compute units of each XCD), a multiple
+// of 8 so that workgroup w stays on XCD w % 8.
+template <class K>
+static unsigned resident_grid(K kernel, int threads) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int cus = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount >= 8)
+            cus = prop.multiProcessorCount;
     }
-    if (h->tl.on) {
-        const Tiled& t = h->tl;
-        k_spmm_fwd_tiled<FMT, TB><<<dim3((unsigned)t.n_fwork, tiles), SPMM_THREADS, 0, st>>>(
-            t.fwork, t.loff, t.list, h->vm.qptr, t.fcol, h->vm.val, h->bm.scale, B, X, Z);
-    } else {
-        const int64_t rows_per_block = (SPMM_THREADS / 64) * (64 / TB);
-        k_spmm_rows<FMT, TB><<<dim3((unsigned)((h->nv + rows_per_block - 1) / rows_per_block), tiles),
-                               SPMM_THREADS, 0, st>>>(h->vm.qptr, h->vm.col, h->vm.val, h->bm.scale, nullptr, h->nv, B, X, Z);
-    }
+    return (unsigned)(cus / 8 * 8 * per_cu);
 }
 
-template <int FMT, int TB>
-static void spmm_adj_t(const vmat_ctx* h, int B, const float* W, double* G, hipStream_t st) {
-    const unsigned tiles = (unsigned)((B + TB - 1) / TB);
-    if constexpr (TB == 64) {
-        const BatchState* bs = h->bs;
-        if (h->tl.on && bs && bs->spart && B <= bs->cap && h->tl.n_awork > 0) {
-            const Tiled& t = h->tl;
-            k_spmm_adj_slots_w64<FMT><<<persistent_grid(t.n_awork, 2), SPMM_THREADS, 0, st>>>(
-                t.awork, t.n_awork, t.bounds, t.aqptr, t.acol, t.aval, B, W, bs->spart);
-            k_spmm_adj_reduce<<<(unsigned)((h->nb * B + 255) / 256), 256, 0, st>>>(h->nb, B, t.red_ptr, t.red_slot,
-                                                                                   bs->spart, h->bm.scale, G);
-            return;
-        }
-        const int64_t rpb = SPMM_THREADS / 64;
-        k_spmm_rows_w64<FMT, false><<<dim3(xcd_grid(h->nb, rpb), tiles), SPMM_THREADS, 0, st>>>(
-            h->bm.qptr, h->bm.col, h->bm.val, nullptr, h->bm.scale, h->nb, B, W, G);
-        return;
-    }
-    const int64_t rows_per_block = (SPMM_THREADS / 64) * (64 / TB);
-    k_spmm_rows<FMT, TB><<<dim3((unsigned)((h->nb + rows_per_block - 1) / rows_per_block), tiles), SPMM_THREADS, 0,
-                           st>>>(h->bm.qptr, h->bm.col, h->bm.val, nullptr, h->bm.scale, h->nb, B, W, G);
+template <int FMT, int LPR, int V>
+static void tiled_fwd(const vmat_ctx* h, int B, const float* X, double* Z, hipStream_t st) {
+    const Tiled& t = h->tl;
+    XcdRanges xr;
+    for (int i = 0; i < 9; ++i) xr.b[i] = t.fx[i];
+    static const unsigned grid = resident_grid(k_bfwd<FMT, LPR, V>, BFWD_THREADS);
+    k_bfwd<FMT, LPR, V><<<grid, BFWD_THREADS, 0, st>>>(
+        xr, t.fb_ptr, t.fb_sl, t.loff, t.list, t.s_off, t.s_len, t.s_row, reinterpret_cast<const u16x4*>(t.s_col),
+        t.s_val, h->bm.scale, B, X, Z);
+}
+
+template <int FMT, int LPR, int V>
+static void tiled_adj(const vmat_ctx* h, int B, const float* W, double* part, hipStream_t st) {
+    const Tiled& t = h->tl;
+    XcdRanges xr;
+    for (int i = 0; i < 9; ++i) xr.b[i] = t.ax[i];
+    static const unsigned grid = resident_grid(k_badj<FMT, LPR, V>, SPMM_THREADS);
+    k_badj<FMT, LPR, V><<<grid, SPMM_THREADS, 0, st>>>(
+        xr, t.ab_ptr, t.ab_sl, t.bounds, t.as_off, t.as_len, t.as_row, reinterpret_cast<const u16x4*>(t.as_col),
+        t.as_val, B, W, part);
 }
 
 template <int FMT>
-static void spmm_dispatch(const vmat_ctx* h, bool fwd, int TB, int B, const float* X, double* Z, hipStream_t st) {
-#define CASE(T)                                          \
-    case T:                                              \
-        if (fwd) spmm_fwd_t<FMT, T>(h, B, X, Z, st);     \
-        else spmm_adj_t<FMT, T>(h, B, X, Z, st);         \
-        break;
-    switch (TB) {
-        CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) default : CASE(64)
+static void tiled_dispatch(const vmat_ctx* h, bool fwd, SpmmCfg c, int B, const float* in, double* out,
+                           hipStream_t st) {
+    const int lpr = 64 / c.rpw, v = c.tb / lpr;
+    if (c.tb == 64 && c.rpw == 1) {
+        const Tiled& t = h->tl;
+        XcdRanges xr;
+        if (fwd) {
+            for (int i = 0; i < 9; ++i) xr.b[i] = t.fx[i];
+            static const unsigned grid = resident_grid(k_bfwd_w<FMT>, SPMM_THREADS);
+            k_bfwd_w<FMT><<<grid, SPMM_THREADS, 0, st>>>(xr, t.fb_ptr, t.fb_sl, t.loff, t.list, t.s_off, t.s_len,
+                                                       t.s_row, reinterpret_cast<const u16x4*>(t.s_col), t.s_val,
+                                                       h->bm.scale, B, in, out);
+        } else {
+            for (int i = 0; i < 9; ++i) xr.b[i] = t.ax[i];
+            static const unsigned grid = resident_grid(k_badj_w<FMT>, SPMM_THREADS);
+            k_badj_w<FMT><<<grid, SPMM_THREADS, 0, st>>>(xr, t.ab_ptr, t.ab_sl, t.bounds, t.as_off, t.as_len,
+                                                       t.as_row, reinterpret_cast<const u16x4*>(t.as_col), t.as_val,
+                                                       B, in, out);
+        }
+        return;
     }
+#define CASE(L, VV)                                                     \
+    if (lpr == L && v == VV) {                                          \
+        if (fwd) tiled_fwd<FMT, L, VV>(h, B, in, out, st);              \
+        else tiled_adj<FMT, L, VV>(h, B, in, out, st);                  \
+        return;                                                         \
+    }
+    CASE(1, 1) CASE(2, 1) CASE(4, 1) CASE(8, 1) CASE(16, 1) CASE(8, 2) CASE(32, 1) CASE(16, 2) CASE(8, 4)
+    CASE(32, 2) CASE(16, 4) CASE(8, 8)
 #undef CASE
 }
 
-static const int kTiles[] = {1, 2, 4, 8, 16, 32, 64};
-
-// Untuned: one tile over all right-hand sides (the smallest width >= B).
-static int default_tile(int B) {
-    int t = 1;
-    while (t < B && t < 64) t <<= 1;
-    return t;
+template <int FMT>
+static void plain_dispatch(const vmat_ctx* h, bool fwd, int TB, int B, const float* in, double* out,
+                           hipStream_t st) {
+    const unsigned tiles = (unsigned)((B + TB - 1) / TB);
+    const int64_t nrows = fwd ? h->nv : h->nb;
+    const QuadCsr& A = fwd ? h->vm : h->bm;
+    const float* cs = fwd && FMT == FMT_FP8 ? h->bm.scale : nullptr;
+    const float* rs = fwd ? nullptr : h->bm.scale;
+    const int64_t rows_per_block = (SPMM_THREADS / 64) * (64 / TB);
+    const dim3 grid((unsigned)((nrows + rows_per_block - 1) / rows_per_block), tiles);
+#define CASE(T) \
+    case T: k_spmm_rows<FMT, T><<<grid, SPMM_THREADS, 0, st>>>(A.qptr, A.col, A.val, cs, rs, nrows, B, in, out); break;
+    switch (TB) { CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) default : CASE(64) }
+#undef CASE
 }
 
-static vmat_status launch_spmm(const vmat_ctx* h, bool fwd, int B, const float* X, double* Z, hipStream_t st, int TB) {
-    if (TB <= 0) {
-        TB = (fwd ? h->tune_fwd : h->tune_adj)[B];
-        if (TB <= 0) TB = default_tile(B);
+// Whether the adjoint runs on the tiled slot rows (their sums need the
+// batched state's buffer of S x B doubles, sized by vmat_reserve_batched).
+static bool tiled_adj_ready(const vmat_ctx* h, int B) {
+    const BatchState* bs = h->bs;
+    return h->tl.on && bs && bs->spart && B <= bs->cap;
+}
+
+static vmat_status launch_spmm(const vmat_ctx* h, bool fwd, int B, const float* X, double* Z, hipStream_t st,
+                               SpmmCfg c = SpmmCfg{0, 0}) {
+    if (c.tb <= 0) {
+        const int32_t packed = (fwd ? h->tune_fwd : h->tune_adj)[B];
+        c = packed > 0 ? SpmmCfg{packed & 0xFF, packed >> 8} : default_cfg(B);
     }
+    // V must divide B, and the gathered rows must be aligned for V-wide loads
+    // (vector gathers stay inside each row of the RHS block): else V = 1
+    const int v = c.tb / (64 / c.rpw);
+    if (B % v != 0 || ((uintptr_t)X & (uintptr_t)(4 * v - 1)) != 0) c.rpw = 64 / c.tb;
+    const bool tiled = h->tl.on && (fwd || tiled_adj_ready(h, B));
+    if (tiled) {
+        if (h->nb * B >= ((int64_t)1 << 32))
+            return fail(VMAT_ERR_UNSUPPORTED, "beamlets x right-hand sides exceed 2^32 elements");
+        double* out = fwd ? Z : h->bs->spart;
+        switch (h->d_store) {
+            case VMAT_F32: tiled_dispatch<FMT_F32>(h, fwd, c, B, X, out, st); break;
+            case VMAT_F16: tiled_dispatch<FMT_F16>(h, fwd, c, B, X, out, st); break;
+            case VMAT_BF16: tiled_dispatch<FMT_BF16>(h, fwd, c, B, X, out, st); break;
+            default: tiled_dispatch<FMT_FP8>(h, fwd, c, B, X, out, st); break;
+        }
+        VMAT_LAUNCH_CHECK();
+        if (!fwd) {
+            const Tiled& t = h->tl;
+            k_spmm_adj_reduce<<<(unsigned)((h->nb * B + 255) / 256), 256, 0, st>>>(h->nb, B, t.red_ptr, t.red_slot,
+                                                                                   h->bs->spart, h->bm.scale, Z);
+            VMAT_LAUNCH_CHECK();
+        }
+        return VMAT_OK;
+    }
+    if (fwd && !h->vm.col) return fail(VMAT_ERR_DEVICE, "no voxel-major copy for the plain batched forward");
     switch (h->d_store) {
-        case VMAT_F32: spmm_dispatch<FMT_F32>(h, fwd, TB, B, X, Z, st); break;
-        case VMAT_F16: spmm_dispatch<FMT_F16>(h, fwd, TB, B, X, Z, st); break;
-        case VMAT_BF16: spmm_dispatch<FMT_BF16>(h, fwd, TB, B, X, Z, st); break;
-        default: spmm_dispatch<FMT_FP8>(h, fwd, TB, B, X, Z, st); break;
+        case VMAT_F32: plain_dispatch<FMT_F32>(h, fwd, c.tb, B, X, Z, st); break;
+        case VMAT_F16: plain_dispatch<FMT_F16>(h, fwd, c.tb, B, X, Z, st); break;
+        case VMAT_BF16: plain_dispatch<FMT_BF16>(h, fwd, c.tb, B, X, Z, st); break;
+        default: plain_dispatch<FMT_FP8>(h, fwd, c.tb, B, X, Z, st); break;
     }
     VMAT_LAUNCH_CHECK();
     return VMAT_OK;
@@ -713,14 +885,14 @@ extern "C" vmat_status vmat_forward_batched(vmat_handle h, int32_t B, const floa
     vmat_status rc = check_batch(h, B);
     if (rc != VMAT_OK) return rc;
     if (!X || !Z) return fail(VMAT_ERR_INVALID_ARG, "null X or Z");
-    return launch_spmm(h, true, B, X, Z, st, 0);
+    return launch_spmm(h, true, B, X, Z, st);
 }
 
 extern "C" vmat_status vmat_adjoint_batched(vmat_handle h, int32_t B, const float* W, double* G, hipStream_t st) {
     vmat_status rc = check_batch(h, B);
     if (rc != VMAT_OK) return rc;
     if (!W || !G) return fail(VMAT_ERR_INVALID_ARG, "null W or G");
-    return launch_spmm(h, false, B, W, G, st, 0);
+    return launch_spmm(h, false, B, W, G, st);
 }
 
 extern "C" vmat_status vmat_grad_batched(vmat_handle h, int32_t B, int32_t n_struct, const uint8_t* label,
@@ -731,17 +903,18 @@ extern "C" vmat_status vmat_grad_batched(vmat_handle h, int32_t B, int32_t n_str
     if (n_struct < 1 || n_struct > 16) return fail(VMAT_ERR_INVALID_ARG, "n_struct must be in [1, 16]");
     if (!label || !table || !X || !Z || !cost || !dF)
         return fail(VMAT_ERR_INVALID_ARG, "null argument");
-    if ((rc = launch_spmm(h, true, B, X, Z, st, 0)) != VMAT_OK) return rc;
+    if ((rc = launch_spmm(h, true, B, X, Z, st)) != VMAT_OK) return rc;
     k_pen_batched<<<h->n_part, 256, 0, st>>>(h->nv, B, n_struct, label, table, Z, dF, h->part_b);
     VMAT_LAUNCH_CHECK();
     k_pen_batched_sum<<<1, 64, 0, st>>>(B, h->n_part, h->part_b, cost);
     VMAT_LAUNCH_CHECK();
-    if (G) return launch_spmm(h, false, B, dF, G, st, 0);
+    if (G) return launch_spmm(h, false, B, dF, G, st);
     return VMAT_OK;
 }
 
-// Times each tile width for both products at B right-hand sides on the
-// caller's buffers and keeps the fastest for later batched calls.
+// Times each product variant (tile width x rows per wave) for both products
+// at B right-hand sides on the caller's buffers and keeps the fastest for
+// later batched calls.
 extern "C" vmat_status vmat_tune_batched(vmat_handle h, int32_t B, const float* X, double* Z, const float* W,
                                          double* G, int32_t reps, int32_t* best, float* times_ms,
                                          hipStream_t st) {
@@ -758,51 +931,56 @@ extern "C" vmat_status vmat_tune_batched(vmat_handle h, int32_t B, const float* 
     } ev;
     VMAT_HIP(hipEventCreate(&ev.e[0]));
     VMAT_HIP(hipEventCreate(&ev.e[1]));
-    int bt[2] = {0, 0};
-    float bm[2] = {INFINITY, INFINITY};
+    SpmmCfg bc[2] = {default_cfg(B), default_cfg(B)};
+    float bms[2] = {INFINITY, INFINITY};
     int idx = 0;
     for (int dir = 0; dir < 2; ++dir) {
-        for (int TB : kTiles) {
+        for (const SpmmCfg& c : kCfgs) {
             float ms = INFINITY;
-            if (TB < 2 * B) {
+            const int v = c.tb / (64 / c.rpw);
+            const bool plain_dup = !h->tl.on && c.rpw != 64 / c.tb;  // the plain layout ignores rpw
+            if (c.tb < 2 * B && B % v == 0 && !plain_dup) {
                 const bool fwd = dir == 0;
                 const float* in = fwd ? X : W;
                 double* out = fwd ? Z : G;
-                if ((rc = launch_spmm(h, fwd, B, in, out, st, TB)) != VMAT_OK) return rc;
+                if ((rc = launch_spmm(h, fwd, B, in, out, st, c)) != VMAT_OK) return rc;
                 VMAT_HIP(hipEventRecord(ev.e[0], st));
                 for (int k = 0; k < reps; ++k)
-                    if ((rc = launch_spmm(h, fwd, B, in, out, st, TB)) != VMAT_OK) return rc;
+                    if ((rc = launch_spmm(h, fwd, B, in, out, st, c)) != VMAT_OK) return rc;
                 VMAT_HIP(hipEventRecord(ev.e[1], st));
                 VMAT_HIP(hipEventSynchronize(ev.e[1]));
                 VMAT_HIP(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
                 ms /= (float)reps;
-                if (ms < bm[dir]) {
-                    bm[dir] = ms;
-                    bt[dir] = TB;
+                if (ms < bms[dir]) {
+                    bms[dir] = ms;
+                    bc[dir] = c;
                 }
             }
             if (times_ms) times_ms[idx] = ms;
             ++idx;
         }
     }
-    if (rc != VMAT_OK) return rc;
-    h->tune_fwd[B] = bt[0];
-    h->tune_adj[B] = bt[1];
+    h->tune_fwd[B] = bc[0].tb | (bc[0].rpw << 8);
+    h->tune_adj[B] = bc[1].tb | (bc[1].rpw << 8);
     if (best) {
-        best[0] = bt[0];
-        best[1] = bt[1];
+        best[0] = bc[0].tb;
+        best[1] = bc[0].rpw;
+        best[2] = bc[1].tb;
+        best[3] = bc[1].rpw;
     }
     return VMAT_OK;
 }
 
-extern "C" vmat_status vmat_set_batched_tile(vmat_handle h, int32_t B, int32_t fwd_tile, int32_t adj_tile) {
+extern "C" vmat_status vmat_set_batched_tile(vmat_handle h, int32_t B, int32_t fwd_tile, int32_t fwd_rpw,
+                                             int32_t adj_tile, int32_t adj_rpw) {
     set_error("");
     if (!h) return fail(VMAT_ERR_INVALID_ARG, "null handle");
     if (B < 1 || B > 64) return fail(VMAT_ERR_INVALID_ARG, "the number of right-hand sides must be in [1, 64]");
-    auto ok = [](int t) { return t == 0 || (t <= 64 && (t & (t - 1)) == 0 && t > 0); };
-    if (!ok(fwd_tile) || !ok(adj_tile)) return fail(VMAT_ERR_INVALID_ARG, "tile widths must be 0 or 1, 2, 4, ..., 64");
-    h->tune_fwd[B] = fwd_tile;
-    h->tune_adj[B] = adj_tile;
+    auto ok = [](int t, int r) { return (t == 0 && r == 0) || cfg_known(t, r); };
+    if (!ok(fwd_tile, fwd_rpw) || !ok(adj_tile, adj_rpw))
+        return fail(VMAT_ERR_INVALID_ARG, "unknown (tile width, rows per wave) pair");
+    h->tune_fwd[B] = fwd_tile | (fwd_rpw << 8);
+    h->tune_adj[B] = adj_tile | (adj_rpw << 8);
     return VMAT_OK;
 }
 
@@ -907,7 +1085,7 @@ vmat_status batch_iteration(vmat_ctx* h, const BatchArgs& a, const int32_t* l, c
         k_bfluence<<<(unsigned)((nbB + BT - 1) / BT), BT, 0, s>>>(h->nb, h->N, h->R, h->C, B, bs.d, l, r, occ,
                                                                   bs.ms, bs.X);
         VMAT_LAUNCH_CHECK();
-        BTRY(launch_spmm(h, true, B, bs.X, bs.dZ, s, 0));
+        BTRY(launch_spmm(h, true, B, bs.X, bs.dZ, s));
         return ls_round(s);
     };
     auto step = [&](hipStream_t s) -> vmat_status {
@@ -915,7 +1093,7 @@ vmat_status batch_iteration(vmat_ctx* h, const BatchArgs& a, const int32_t* l, c
         VMAT_LAUNCH_CHECK();
         k_bupdate<<<np, BT, 0, s>>>(h->nv, B, a.S, a.label, a.table, bs.Z, bs.dZ, bs.ms, bs.RZ, bs.pf);
         VMAT_LAUNCH_CHECK();
-        BTRY(launch_spmm(h, false, B, bs.RZ, bs.G, s, 0));
+        BTRY(launch_spmm(h, false, B, bs.RZ, bs.G, s));
         k_bbeam_sums<<<h->N, BT, 0, s>>>(h->N, h->R, h->C, B, bs.G, l, r, occ, bs.gF);
         VMAT_LAUNCH_CHECK();
         k_bmaster_grad<<<B, CTRL, 0, s>>>(m, bs.pf, np, 0, nullptr);
@@ -1026,7 +1204,7 @@ extern "C" vmat_status vmat_solve_batched(vmat_handle h, const vmat_solve_opts* 
     VMAT_LAUNCH_CHECK();
     k_pen_batched_sum<<<1, 64, 0, st>>>(B, h->n_part, bs.pf, bs.cost);
     VMAT_LAUNCH_CHECK();
-    BTRY(launch_spmm(h, false, B, bs.RZ, bs.G, st, 0));
+    BTRY(launch_spmm(h, false, B, bs.RZ, bs.G, st));
     cnt[1] += 1;
     std::vector<double> cost0(B);
     VMAT_HIP(hipMemcpyAsync(cost0.data(), bs.cost, sizeof(double) * B, hipMemcpyDeviceToHost, st));

@@ -425,11 +425,18 @@ static vmat_status build_layouts(vmat_ctx* h, const vmat_problem* p, hipStream_t
             if (h->layout_req == 2 || rc != VMAT_ERR_UNSUPPORTED) return rc;
             set_error("");
         } else {
-            // the tiled copy replaces the voxel-major column indices; the
-            // beamlet-major copy stays for the many-right-hand-side adjoint
+            // the tiled copy replaces the voxel-major quad CSR; the
+            // beamlet-major copy stays for the aperture-dose bound and the
+            // adjoint with many right-hand sides before its slot sums are
+            // reserved
+            const int64_t vbytes = h->d_store == VMAT_F32 ? 4 : (h->d_store == VMAT_FP8_E4M3 ? 1 : 2);
             (void)hipFree(h->vm.col);
-            h->bytes -= (int64_t)h->vm.n_quads * 16;
+            (void)hipFree(h->vm.val);
+            (void)hipFree(h->vm.qptr);
+            h->bytes -= (int64_t)h->vm.n_quads * 4 * (4 + vbytes) + (nv + 1) * 4;
             h->vm.col = nullptr;
+            h->vm.val = nullptr;
+            h->vm.qptr = nullptr;
         }
     }
     return VMAT_OK;

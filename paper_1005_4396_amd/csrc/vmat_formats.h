@@ -75,39 +75,59 @@ __device__ __forceinline__ uint8_t f64_to_e4m3_rne(double v) {
 }
 
 // ---- 4-value loads for quad CSR
+// load: non-temporal (a stream read once per product); ld: an ordinary load,
+// for data that other waves read again soon (kept in the caches).
 template <int FMT> struct Quad;
 
 template <> struct Quad<FMT_F32> {
+    __device__ __forceinline__ static float4 dec(f32x4 v) { return make_float4(v.x, v.y, v.z, v.w); }
     __device__ __forceinline__ static float4 load(const void* base, int64_t q) {
-        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(base) + q);
-        return make_float4(v.x, v.y, v.z, v.w);
+        return dec(__builtin_nontemporal_load(reinterpret_cast<const f32x4*>(base) + q));
+    }
+    __device__ __forceinline__ static float4 ld(const void* base, int64_t q) {
+        return dec(reinterpret_cast<const f32x4*>(base)[q]);
     }
 };
 
 template <> struct Quad<FMT_BF16> {
-    __device__ __forceinline__ static float4 load(const void* base, int64_t q) {
-        const u32x2 u = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(base) + q);
+    __device__ __forceinline__ static float4 dec(u32x2 u) {
         return make_float4(bf16_to_f32(u.x & 0xFFFFu), bf16_to_f32(u.x >> 16),
                            bf16_to_f32(u.y & 0xFFFFu), bf16_to_f32(u.y >> 16));
+    }
+    __device__ __forceinline__ static float4 load(const void* base, int64_t q) {
+        return dec(__builtin_nontemporal_load(reinterpret_cast<const u32x2*>(base) + q));
+    }
+    __device__ __forceinline__ static float4 ld(const void* base, int64_t q) {
+        return dec(reinterpret_cast<const u32x2*>(base)[q]);
     }
 };
 
 template <> struct Quad<FMT_F16> {
-    __device__ __forceinline__ static float4 load(const void* base, int64_t q) {
-        const u32x2 u = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(base) + q);
+    __device__ __forceinline__ static float4 dec(u32x2 u) {
         return make_float4(f16_to_f32(u.x & 0xFFFFu), f16_to_f32(u.x >> 16),
                            f16_to_f32(u.y & 0xFFFFu), f16_to_f32(u.y >> 16));
+    }
+    __device__ __forceinline__ static float4 load(const void* base, int64_t q) {
+        return dec(__builtin_nontemporal_load(reinterpret_cast<const u32x2*>(base) + q));
+    }
+    __device__ __forceinline__ static float4 ld(const void* base, int64_t q) {
+        return dec(reinterpret_cast<const u32x2*>(base)[q]);
     }
 };
 
 // The hardware conversion (two codes per instruction) gives the same bits as
 // e4m3_to_f32 on every finite code; stored codes never exceed 0x7E.
 template <> struct Quad<FMT_FP8> {
-    __device__ __forceinline__ static float4 load(const void* base, int64_t q) {
-        const uint32_t u = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base) + q);
+    __device__ __forceinline__ static float4 dec(uint32_t u) {
         const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)u, false);
         const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)u, true);
         return make_float4(lo.x, lo.y, hi.x, hi.y);
+    }
+    __device__ __forceinline__ static float4 load(const void* base, int64_t q) {
+        return dec(__builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base) + q));
+    }
+    __device__ __forceinline__ static float4 ld(const void* base, int64_t q) {
+        return dec(reinterpret_cast<const uint32_t*>(base)[q]);
     }
 };
 

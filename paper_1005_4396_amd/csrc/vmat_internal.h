@@ -67,8 +67,6 @@ struct Tiled {
     uint16_t* fcol = nullptr;     // [4 * vm.n_quads]
     int4* fwork = nullptr;        // (block, first row, end row, first slice)
     int n_fwork = 0;
-    int4* fwork_half = nullptr;   // fwork with each item's rows split in two halves (batched forward)
-    int n_fwork_half = 0;
     // forward, sliced: each work item's rows sorted by length (longest first)
     // and cut into slices of 64 rows; a slice stores its quads column-major
     // (quad k of its 64 rows contiguous), padded to its longest row
@@ -94,6 +92,14 @@ struct Tiled {
     double* part = nullptr;       // [S] slot sums
     uint32_t* red_ptr = nullptr;  // [nb+1]
     uint32_t* red_slot = nullptr; // [S] slots of each beamlet, in block order
+    // batched products: the slices of each block (forward and adjoint), and
+    // for each of the 8 XCDs a contiguous range of blocks [x[i], x[i+1])
+    // balanced by stored quads
+    uint32_t* fb_ptr = nullptr;   // [nblk+1]
+    uint32_t* fb_sl = nullptr;    // [n_slices]
+    uint32_t* ab_ptr = nullptr;   // [nblk+1]
+    uint32_t* ab_sl = nullptr;    // [an_slices]
+    int32_t fx[9] = {}, ax[9] = {};
 };
 
 // Launch gate: a kernel given a gate returns at once unless the device-side

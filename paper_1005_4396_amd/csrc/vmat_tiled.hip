@@ -785,28 +785,55 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
         t.an_slices = (int64_t)as_len.size();
         t.as_quads = (int64_t)aq_s;
     }
+    {
+        // slices grouped by block, and XCD block ranges, for the batched products
+        auto group = [&](const std::vector<int4>& items, int64_t n_sl, const std::vector<uint32_t>& slen,
+                         uint32_t*& d_ptr, uint32_t*& d_sl, int32_t* xr) -> vmat_status {
+            std::vector<std::vector<uint32_t>> per(nblk);
+            for (const int4& it : items) {
+                if (it.x < 0) continue;
+                const int ns = (it.z - it.y + 63) / 64;
+                for (int k = 0; k < ns; ++k) per[it.x].push_back((uint32_t)(it.w + k));
+            }
+            std::vector<uint32_t> ptr(nblk + 1, 0), sl;
+            sl.reserve((size_t)n_sl);
+            std::vector<double> load(nblk, 0.0);
+            for (int b = 0; b < nblk; ++b) {
+                for (uint32_t x : per[b]) {
+                    sl.push_back(x);
+                    load[b] += 64.0 * slen[x];
+                }
+                ptr[b + 1] = (uint32_t)sl.size();
+            }
+            double tot = 0.0;
+            for (double v : load) tot += v;
+            // XCD i takes the blocks whose cumulative load starts in its eighth
+            xr[0] = 0;
+            double acc = 0.0;
+            int b = 0;
+            for (int i = 1; i < 8; ++i) {
+                while (b < nblk && acc + 0.5 * load[b] < tot * i / 8.0) acc += load[b++];
+                xr[i] = b;
+            }
+            xr[8] = nblk;
+            A(d_ptr, ptr.size() * 4);
+            A(d_sl, std::max<size_t>(sl.size(), 1) * 4);
+            VMAT_HIP(hipMemcpyAsync(d_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, st));
+            if (!sl.empty()) VMAT_HIP(hipMemcpyAsync(d_sl, sl.data(), sl.size() * 4, hipMemcpyHostToDevice, st));
+            VMAT_HIP(hipStreamSynchronize(st));
+            return VMAT_OK;
+        };
+        vmat_status rg = group(fw, t.n_slices, s_len, t.fb_ptr, t.fb_sl, t.fx);
+        if (rg != VMAT_OK) return rg;
+        rg = group(aw, t.an_slices, as_len, t.ab_ptr, t.ab_sl, t.ax);
+        if (rg != VMAT_OK) return rg;
+    }
     A(t.fwork, fw.size() * sizeof(int4));
     A(t.awork, aw.size() * sizeof(int4));
     VMAT_HIP(hipMemcpyAsync(t.fwork, fw.data(), fw.size() * sizeof(int4), hipMemcpyHostToDevice, st));
     VMAT_HIP(hipMemcpyAsync(t.awork, aw.data(), aw.size() * sizeof(int4), hipMemcpyHostToDevice, st));
     t.n_fwork = (int)fw.size();
     t.n_awork = (int)aw.size();
-    {
-        // entry i = pos * 8 + xcd of fw becomes entries (2 pos + h) * 8 + xcd,
-        // h = 0, 1: both halves stay on the item's XCD
-        std::vector<int4> fh(fw.size() * 2, make_int4(-1, 0, 0, 0));
-        for (size_t i = 0; i < fw.size(); ++i) {
-            const int4 w = fw[i];
-            const size_t pos = i / 8, xcd = i % 8;
-            if (w.x < 0) continue;
-            const int mid = w.y + (w.z - w.y) / 2;
-            fh[(2 * pos) * 8 + xcd] = make_int4(w.x, w.y, mid, w.w);
-            fh[(2 * pos + 1) * 8 + xcd] = make_int4(w.x, mid, w.z, w.w);
-        }
-        A(t.fwork_half, fh.size() * sizeof(int4));
-        VMAT_HIP(hipMemcpyAsync(t.fwork_half, fh.data(), fh.size() * sizeof(int4), hipMemcpyHostToDevice, st));
-        t.n_fwork_half = (int)fh.size();
-    }
     {
         const int vb = h->d_store == VMAT_F32 ? 4 : (h->d_store == VMAT_FP8_E4M3 ? 1 : 2);
         auto sliced = [&](int64_t n_sl, int64_t quads, const std::vector<uint32_t>& so,
@@ -848,15 +875,27 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     }
     VMAT_HIP(hipStreamSynchronize(st));
 #undef A
+    // the CSR-shaped forms were the sources of the sliced ones; every product
+    // runs on the sliced forms
+    auto release = [&](void*& p, int64_t bytes) {
+        if (!p) return;
+        (void)hipFree(p);
+        h->bytes -= bytes;
+        p = nullptr;
+    };
+    release(reinterpret_cast<void*&>(t.fcol), h->vm.n_quads * 4 * 2);
+    release(reinterpret_cast<void*&>(t.aqptr), (t.S + 1) * 4);
+    release(reinterpret_cast<void*&>(t.acol), t.a_quads * 4 * 2);
+    release(t.aval, t.a_quads * 4 * (int64_t)vb);
     t.on = true;
     return VMAT_OK;
 }
 
 void free_tiled(vmat_ctx* h) {
     Tiled& t = h->tl;
-    void* ps[] = {t.bounds, t.loff, t.list, t.fcol, t.fwork, t.fwork_half, t.aqptr, t.acol, t.aval, t.awork, t.part, t.red_ptr,
+    void* ps[] = {t.bounds, t.loff, t.list, t.fcol, t.fwork, t.aqptr, t.acol, t.aval, t.awork, t.part, t.red_ptr,
                   t.red_slot, t.s_off, t.s_len, t.s_row, t.s_col, t.s_val, t.as_off, t.as_len, t.as_row, t.as_col,
-                  t.as_val};
+                  t.as_val, t.fb_ptr, t.fb_sl, t.ab_ptr, t.ab_sl};
     for (void* q : ps)
         if (q) (void)hipFree(q);
     t = Tiled();

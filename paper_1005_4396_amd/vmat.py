@@ -19,6 +19,9 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "vmat.h")
 
 VMAT_OK, VMAT_ERR_INVALID_ARG, VMAT_ERR_DEVICE, VMAT_ERR_ALLOC, VMAT_ERR_NOT_CONVERGED, VMAT_ERR_UNSUPPORTED = range(6)
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
+# (TB, RPW) product variants of the batched products, in the library's order
+SPMM_VARIANTS = ((1, 64), (2, 32), (4, 16), (8, 8), (16, 4), (16, 8), (32, 2), (32, 4), (32, 8), (64, 1), (64, 2),
+                 (64, 4), (64, 8))
 LAYOUTS = {"auto": 0, "plain": 1, "tiled": 2}
 
 _lib = None
@@ -135,7 +138,7 @@ def lib():
             "vmat_adjoint_batched": [P, I32, P, P, P],
             "vmat_grad_batched": [P, I32, I32, P, P, P, P, P, P, P, P],
             "vmat_tune_batched": [P, I32, P, P, P, P, I32, P, P, P],
-            "vmat_set_batched_tile": [P, I32, I32, I32],
+            "vmat_set_batched_tile": [P, I32, I32, I32, I32, I32],
             "vmat_reserve_batched": [P, I32],
             "vmat_reserve_solve": [P],
             "vmat_price_noalloc": [ctypes.POINTER(Beams), P, P, P, P, P, P, P, P, P],
@@ -378,12 +381,16 @@ class Problem:
                    for t, rep in zip(trs, reports)]
         return (l, r, occ, y), reports, trs, (cnt[0], cnt[1])
 
-    def set_batched_tile(self, B, fwd_tile, adj_tile):
-        _check(lib().vmat_set_batched_tile(self._h, B, fwd_tile, adj_tile))
+    def set_batched_tile(self, B, fwd, adj):
+        """Product variants at B right-hand sides: fwd, adj = (TB, RPW) pairs
+        ((0, 0): default)."""
+        _check(lib().vmat_set_batched_tile(self._h, B, fwd[0], fwd[1], adj[0], adj[1]))
 
     def tune_batched(self, B, reps=5, seed=0):
-        """Times every RHS tile width for both products at B right-hand sides
-        and keeps the fastest.  Returns (forward tile, adjoint tile, times)."""
+        """Times every product variant (TB right-hand sides per pass, RPW rows
+        per wave) for both products at B right-hand sides and keeps the
+        fastest.  Returns (forward (TB, RPW), adjoint (TB, RPW), times in ms
+        by variant)."""
         import torch
         dev = self.device
         g = torch.Generator(device="cpu").manual_seed(seed)
@@ -391,12 +398,13 @@ class Problem:
         W = torch.randn(self.nv, B, generator=g).to(dev, torch.float32)
         Z = torch.empty(self.nv, B, dtype=torch.float64, device=dev)
         G = torch.empty(self.nb, B, dtype=torch.float64, device=dev)
-        best = (ctypes.c_int32 * 2)()
-        times = (ctypes.c_float * 14)()
+        best = (ctypes.c_int32 * 4)()
+        n = len(SPMM_VARIANTS)
+        times = (ctypes.c_float * (2 * n))()
         _check(lib().vmat_tune_batched(self._h, B, _ptr(X), _ptr(Z), _ptr(W), _ptr(G), reps, best, times,
                                        _stream()))
-        widths = (1, 2, 4, 8, 16, 32, 64)
-        return best[0], best[1], {"forward": dict(zip(widths, times[:7])), "adjoint": dict(zip(widths, times[7:]))}
+        return ((best[0], best[1]), (best[2], best[3]),
+                {"forward": dict(zip(SPMM_VARIANTS, times[:n])), "adjoint": dict(zip(SPMM_VARIANTS, times[n:]))})
 
     def grad(self, y, l, r, occ, want=("z", "dF", "g", "dfdy")):
         import torch

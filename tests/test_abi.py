@@ -36,7 +36,7 @@ def test_null_handle_rejected():
     assert L.vmat_dose(None, None, None, None, None, None, None) == V.VMAT_ERR_INVALID_ARG
     assert "handle" in V.last_error()
     assert L.vmat_forward_batched(None, 4, None, None, None) == V.VMAT_ERR_INVALID_ARG
-    assert L.vmat_set_batched_tile(None, 4, 8, 8) == V.VMAT_ERR_INVALID_ARG
+    assert L.vmat_set_batched_tile(None, 4, 8, 8, 8, 8) == V.VMAT_ERR_INVALID_ARG
     assert L.vmat_destroy(None) in (V.VMAT_OK, V.VMAT_ERR_INVALID_ARG)
 
 

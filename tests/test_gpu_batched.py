@@ -1,7 +1,8 @@
 """Plan variants sharing one D: products with many right-hand sides and the
 batched cost/gradient, against the FP64 reference applied column by column.
 
-Tile widths change no result: every width gives the same bits.
+Product variants (tile width x rows per wave) change no result: every
+variant gives the same bits.
 """
 import numpy as np
 import pytest
@@ -18,7 +19,7 @@ if not torch.cuda.is_available():
 
 import paper_1005_4396_amd as P  # noqa: E402
 
-WIDTHS = (1, 2, 4, 8, 16, 32, 64)
+VARIANTS = P.vmat.SPMM_VARIANTS
 
 
 def T(a, dtype):
@@ -64,6 +65,8 @@ def test_batched_products_and_cost(name, B, layout):
     Z, dF, cost = _reference(D, c, X, tab)
     prob = P.Problem.from_case(c, layout=layout)
     try:
+        if layout == "tiled":
+            prob.reserve_batched(B)   # the adjoint's slot sums
         out = prob.grad_batched(T(c.label, torch.uint8), T(tab, torch.float32), T(X, torch.float32))
         Zg = out["Z"].cpu().numpy()
         assert rel_inf(Zg, Z) <= 1e-12
@@ -73,18 +76,19 @@ def test_batched_products_and_cost(name, B, layout):
         # adjoint of the library's own dF against the reference product
         G_ref = D @ dFg
         assert rel_inf(out["G"].cpu().numpy(), G_ref) <= 1e-12
-        # every tile width gives the same bits
+        # every variant gives the same bits
         Xt, Wt = T(X, torch.float32), out["dF"]
         ref_z, ref_g = None, None
-        for w in WIDTHS:
-            prob.set_batched_tile(B, w, w)
+        for v in VARIANTS:
+            prob.set_batched_tile(B, v, v)
             z = prob.forward_batched(Xt).cpu().numpy()
             g = prob.adjoint_batched(Wt).cpu().numpy()
             if ref_z is None:
                 ref_z, ref_g = z, g
-            assert np.array_equal(z, ref_z) and np.array_equal(g, ref_g), w
+            assert np.array_equal(z, ref_z) and np.array_equal(g, ref_g), v
         fw, aw, times = prob.tune_batched(B, reps=2)
-        assert fw in WIDTHS and aw in WIDTHS and fw <= max(B, 1) * 2 and aw <= max(B, 1) * 2
+        assert fw in VARIANTS and aw in VARIANTS and fw[0] <= max(B, 1) * 2 and aw[0] <= max(B, 1) * 2
+        assert np.isfinite(times["forward"][fw]) and np.isfinite(times["adjoint"][aw])
         assert np.array_equal(prob.forward_batched(Xt).cpu().numpy(), ref_z)
     finally:
         prob.close()
@@ -122,6 +126,7 @@ def test_batched_prostate_full_size():
     tab = casegen.variant_table(c, B, seed=3)
     prob = P.Problem.from_case(c)
     try:
+        prob.reserve_batched(B)
         prob.tune_batched(B, reps=2)
         out = prob.grad_batched(T(c.label, torch.uint8), T(tab, torch.float32), T(X, torch.float32))
         Zg, dFg = out["Z"].cpu().numpy(), out["dF"].cpu().numpy().astype(np.float64)
@@ -208,8 +213,8 @@ def test_batched_solve_graph_replay_matches_direct_launches(monkeypatch):
 
 @pytest.mark.parametrize("fmt", ["f32", "fp8"])
 def test_batched_tiled_adjoint_after_reserve(fmt):
-    """With the batched state reserved, the 64-wide adjoint runs over the tiled
-    slot rows: same result as the reference product up to rounding."""
+    """With the batched state reserved, the adjoint runs over the tiled slot
+    rows: same result as the reference product up to rounding."""
     c = dict(CASES)["tiny36"]()
     if fmt == "fp8":
         s_, q_ = O.fp8_quantise(c.row_ptr, c.val)
@@ -220,7 +225,7 @@ def test_batched_tiled_adjoint_after_reserve(fmt):
     W = np.random.default_rng(31).standard_normal((c.n_voxels, B)).astype(np.float32)
     prob = P.Problem.from_case(c, d_store=fmt)
     try:
-        prob.set_batched_tile(B, 64, 64)
+        prob.set_batched_tile(B, (64, 4), (64, 4))
         G_plain = prob.adjoint_batched(T(W, torch.float32)).cpu().numpy()
         prob.reserve_batched(B)
         G_tiled = prob.adjoint_batched(T(W, torch.float32)).cpu().numpy()
