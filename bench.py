@@ -13,8 +13,14 @@ reported beside it (`aperture_master`).
 value = algorithmic bytes of all D.x (forward) and D^T.r (adjoint) products
 run during the timed plans / wall time of those plans (GB/s).  The roofline
 object reports the dominant product kernel alone, timed with HIP events on the
-stream it runs on, against the 8 TB/s HBM peak.  The CPU baseline is the FP64
-reference running the first column-generation iterations of the same plan.
+stream it runs on, against the 8 TB/s HBM peak.  Its algorithmic bytes per
+launch are those of a plain CSR product with int32 indices: nnz (v + 4) +
+8 (rows + 1) + 4 (gathered vector) + 4 (output) (v = value bytes, +4 per
+beamlet for FP8 scales); the fractions on the layout's own bytes (16-bit
+local indices) and on the rocprofv3 HBM counters are reported beside it.  The
+CPU baseline is the FP64 reference running the first column-generation
+iterations of the same plan, with per-call reference times on the three cases
+and an all-cores row-parallel product beside it.
 
 Prints one JSON line.
 """
@@ -33,10 +39,14 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 
+PEAK_FP64_TFLOPS = 78.6
+VALUE_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "fp8": 1}
+
 # HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.0, calibrated on a
-# 512 MiB copy) + WRITE_SIZE, for the product kernels as they stand; see
-# profiles/fwd_adj_sell_prostate180_hbm_counters.md.  Used only when the
-# layout matches the one measured (same workload, storage and byte counts).
+# 512 MiB copy) + WRITE_SIZE, for the product kernels as they stand
+# (k_fwd_sell, k_adj_sell + k_adj_reduce).  Used only when the layout matches
+# the one measured (same workload, storage and byte counts).
+TRAFFIC_SOURCE = "profiles/fwd_adj_sell_prostate180_hbm_counters.md"
 MEASURED_TRAFFIC = {
     ("prostate180", "f32", 676890628, 676191240): {
         "forward": (343236.75 * 2 + 8397.84375) * 1024,
@@ -56,6 +66,96 @@ def time_kernel(fn, reps, torch):
     e.record()
     torch.cuda.synchronize()
     return s.elapsed_time(e) / reps  # ms
+
+
+def algorithmic_bytes(case, d_store, B=1):
+    """Bytes one product has to move with a plain CSR layout (int32 indices,
+    int64 row pointers, FP32 vectors): D once, the gathered vector read once
+    and the output written once, each B times for B right-hand sides (FP64
+    outputs of the batched products).  FP8 adds the per-beamlet scales."""
+    v = VALUE_BYTES[d_store]
+    nnz, nb, nv = case.nnz, case.n_beamlets, case.n_voxels
+    sc = 4 * nb if d_store == "fp8" else 0
+    out_b = 4 if B == 1 else 8
+    fwd = nnz * (v + 4) + 8 * (nv + 1) + B * (4 * nb + out_b * nv) + sc
+    adj = nnz * (v + 4) + 8 * (nb + 1) + B * (4 * nv + out_b * nb) + sc
+    return fwd, adj
+
+
+def host_info():
+    """Host cores and CPU model (os.cpu_count, the affinity mask, lscpu)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    if model is None:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return {"nproc": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def median_time(fn, n=3):
+    ts = []
+    for _ in range(n):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def cpu_per_call(workloads, log, hn_iters=1):
+    """The FP64 reference, one host core, per call on each case: forward and
+    adjoint products, one pricing of the empty plan, the first
+    column-generation iterations (pricing + master), and the full plan on the
+    tiny case; plus the two products row-parallel on all host cores
+    (oracle/rowpar.c).  Medians of 3 for the single calls."""
+    import casegen
+    import oracle as O
+    from oracle import rowpar
+    from threadpoolctl import threadpool_limits
+    res = {}
+    for wl in workloads:
+        c = casegen.make_case(casegen.preset(wl))
+        D = O.dose_matrix(c.row_ptr, c.col, c.val, c.n_voxels)
+        Dt = D.T.tocsr()
+        rng = np.random.default_rng(0)
+        x = rng.random(c.n_beamlets)
+        w = rng.standard_normal(c.n_voxels)
+        N, R, C = c.n_beams, c.n_rows, c.n_cols
+        l0 = np.zeros(N * R, np.int32)
+        occ0 = np.zeros(N, np.uint8)
+        r_ = {"nnz": c.nnz}
+        with threadpool_limits(limits=1):
+            r_["forward_s"] = round(median_time(lambda: O.dose(D, x)), 4)
+            r_["adjoint_s"] = round(median_time(lambda: D @ w), 4)
+            g = D @ w
+            r_["pricing_s"] = round(median_time(lambda: O.price(g, np.zeros(N), l0, l0, occ0, c.theta_deg, c.gamma,
+                                                                  R, C, c.max_leaf_step, c.circular)), 4)
+            iters = N if wl == "tiny36" else (hn_iters if wl == "headneck180" else 1)
+            t0 = time.perf_counter()
+            sol = O.solve(D, c.alpha, c.beta, c.T, c.theta_deg, c.gamma, c.circular, R, C, c.max_leaf_step,
+                          max_cg_iter=iters, with_margins=False)
+            key = "full_plan_s" if iters == N else f"first_{iters}_cg_iterations_s"
+            r_[key] = round(time.perf_counter() - t0, 3)
+            r_["master_iters"] = int(sum(sol.master_iters))
+        r_["rowpar_forward_s"] = round(median_time(lambda: rowpar.spmv(Dt, x)), 4)
+        r_["rowpar_adjoint_s"] = round(median_time(lambda: rowpar.spmv(D, w)), 4)
+        r_["rowpar_threads"] = rowpar.threads()
+        res[wl] = r_
+        log(f"[bench] cpu reference {wl}: {r_}")
+        del D, Dt, c
+    return res
 
 
 def cpu_baseline(case, n_iter):
@@ -87,6 +187,9 @@ def main():
     ap.add_argument("--d-store", default="f32", choices=["f32", "bf16", "f16", "fp8"])
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=16)
+    ap.add_argument("--cpu-hn-iters", type=int, default=1,
+                    help="column-generation iterations of the reference on the head-and-neck case")
+    ap.add_argument("--no-cpu-per-call", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--precision-workload", default="headneck180")
@@ -98,8 +201,14 @@ def main():
     ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--products-only", action="store_true",
                     help="no plans and no side studies: only the per-kernel product timing (for profiling)")
-    ap.add_argument("--sequential-variants", type=int, default=64,
-                    help="variants solved one at a time for the batched-solve comparison")
+    ap.add_argument("--sequential-variants", type=int, default=4,
+                    help="variants solved one at a time (master streaming D) for the batched-solve comparison")
+    ap.add_argument("--sequential-apdose-variants", type=int, default=8,
+                    help="variants solved one at a time with the aperture-dose master")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the tuned batched products at --variants right-hand sides (for profiling)")
+    ap.add_argument("--apmaster-only", action="store_true",
+                    help="only plans with the aperture-dose master (for profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -128,6 +237,24 @@ def main():
         rep, tr = prob.solve(l, r, occ, y, want_trace=True)
         return rep, tr
 
+    if args.batched_only:
+        res = batched_study(case, prob, torch, args.variants, max(3, args.kernel_reps // 10), log, args.d_store)
+        log(f"[bench] batched only: {res}")
+        prob.close()
+        return
+    if args.apmaster_only:
+        o = P.vmat.SolveOpts()
+        o.max_cg_iter = 0
+        o.master_mode = 1
+        o.master = P.master_opts()
+        for i in range(max(1, args.steps)):
+            l, r, occ, y = prob.empty_plan()
+            t0 = time.perf_counter()
+            rep, _ = prob.solve(l, r, occ, y, o, want_trace=False)
+            torch.cuda.synchronize()
+            log(f"[bench] aperture-dose plan {i}: {time.perf_counter() - t0:.3f} s, cost {rep.F + rep.gG:.9g}")
+        prob.close()
+        return
     if args.products_only:
         args.steps = args.warmup = 0
         args.no_precision = args.no_batched = args.no_batched_solve = args.no_cpu_baseline = True
@@ -167,9 +294,13 @@ def main():
     adj_ms = time_kernel(lambda: prob.adjoint(w, gbuf), args.kernel_reps, torch)
     fwd_gbs = fwd_b / fwd_ms / 1e6
     adj_gbs = adj_b / adj_ms / 1e6
+    fwd_alg, adj_alg = algorithmic_bytes(case, args.d_store)
     dom = "forward" if fwd_ms * n_fwd >= adj_ms * n_adj else "adjoint"
-    dom_gbs, dom_bytes = (fwd_gbs, fwd_b) if dom == "forward" else (adj_gbs, adj_b)
-    log(f"[bench] forward {fwd_ms:.4f} ms ({fwd_gbs:.0f} GB/s), adjoint {adj_ms:.4f} ms ({adj_gbs:.0f} GB/s)")
+    dom_ms = fwd_ms if dom == "forward" else adj_ms
+    dom_alg, dom_lay = (fwd_alg, fwd_b) if dom == "forward" else (adj_alg, adj_b)
+    dom_gbs = dom_alg / dom_ms / 1e6
+    log(f"[bench] forward {fwd_ms:.4f} ms ({fwd_alg / fwd_ms / 1e6:.0f} GB/s algorithmic, {fwd_gbs:.0f} layout), "
+        f"adjoint {adj_ms:.4f} ms ({adj_alg / adj_ms / 1e6:.0f} GB/s algorithmic, {adj_gbs:.0f} layout)")
 
     meas = MEASURED_TRAFFIC.get((args.workload, args.d_store, fwd_b, adj_b))
     traffic = round(meas[dom]) if meas else None
@@ -215,8 +346,16 @@ def main():
                  "n_ls_evals": reps[-1].n_ls_evals, "cost": reps[-1].F + reps[-1].gG} if reps else None,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(dom_gbs, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(dom_gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "bytes_per_launch": dom_bytes},
+                     "frac_basis": "algorithmic bytes of a plain CSR product: nnz*(v+4) + 8*(rows+1) + "
+                                   "4*(gathered vector) + 4*(output)",
+                     "bytes_per_launch": dom_alg, "duration_ms": round(dom_ms, 5),
+                     "layout_bytes_per_launch": dom_lay,
+                     "frac_layout_bytes": round(dom_lay / dom_ms / 1e6 / PEAK_HBM_GBS, 4),
+                     "frac_counter_bytes": round(traffic / dom_ms / 1e6 / PEAK_HBM_GBS, 4) if traffic else None,
+                     "traffic_source": TRAFFIC_SOURCE if traffic else None},
         "products": {"forward_ms": round(fwd_ms, 5), "forward_GBs": round(fwd_gbs, 1), "forward_bytes": fwd_b,
+                     "forward_alg_bytes": fwd_alg, "forward_alg_GBs": round(fwd_alg / fwd_ms / 1e6, 1),
+                     "adjoint_alg_bytes": adj_alg, "adjoint_alg_GBs": round(adj_alg / adj_ms / 1e6, 1),
                      "adjoint_ms": round(adj_ms, 5), "adjoint_GBs": round(adj_gbs, 1), "adjoint_bytes": adj_b,
                      "nnz_per_s_fwd": round(case.nnz / fwd_ms / 1e6, 1), "nnz_per_s_adj": round(case.nnz / adj_ms / 1e6, 1),
                      "csr_fp32_equiv_GBs_fwd": round(8 * case.nnz / fwd_ms / 1e6, 1),
@@ -238,10 +377,11 @@ def main():
         out["autograd"] = autograd_study(case, prob, P, torch, args.kernel_reps, log)
 
     if not args.no_batched:
-        out["batched"] = batched_study(case, prob, torch, args.variants, max(3, args.kernel_reps // 10), log)
+        out["batched"] = batched_study(case, prob, torch, args.variants, max(3, args.kernel_reps // 10), log,
+                                       args.d_store)
     if not args.no_batched_solve:
         out["batched_solve"] = batched_solve_study(case, prob, torch, P, args.variants, args.sequential_variants,
-                                                   log)
+                                                   args.sequential_apdose_variants, log)
 
     if not args.no_cpu_baseline:
         nf, na, n_it, dt = cpu_baseline(case, args.cpu_iters)
@@ -249,29 +389,49 @@ def main():
         out["cpu_baseline"] = {"value": round(cpu_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"first {n_it} column-generation iterations of the same plan "
-                                         f"({nf} forward + {na} adjoint products, {dt:.1f} s)"}
+                                         f"({nf} forward + {na} adjoint products, {dt:.1f} s)",
+                               "host": host_info()}
+        if reps:
+            # the reference makes the same iterations as the GPU plan: scale
+            # its time by master iterations (labelled as an extrapolation)
+            gpu_mi = [int(v) for v in tr["master_iters"]]
+            part = sum(gpu_mi[:n_it])
+            if part > 0:
+                out["cpu_baseline"]["full_plan_s_extrapolated"] = round(dt * sum(gpu_mi) / part, 1)
+        if not args.no_cpu_per_call:
+            out["cpu_baseline"]["per_call"] = cpu_per_call(("tiny36", args.workload, args.precision_workload), log,
+                                                           args.cpu_hn_iters)
         log(f"[bench] cpu baseline {out['cpu_baseline']}")
 
     prob.close()
     print(json.dumps(out), flush=True)
 
 
-def batched_study(case, prob, torch, B, reps, log):
+def batched_study(case, prob, torch, B, reps, log, d_store="f32"):
     """B objective variants (alpha, beta ~ U[0.5, 2] x base per structure,
-    target T ~ U[0.95, 1.05] x base) sharing D: one batched cost + gradient
-    (forward SpMM, eq. 1 per variant, adjoint SpMM) against B sequential
-    single-variant evaluations (forward SpMV, eq. 1, adjoint SpMV)."""
+    target T ~ U[0.95, 1.05] x base) sharing D: the tuned forward and adjoint
+    SpMM timed alone against their HBM and FP64-VALU rooflines, and one
+    batched cost + gradient (forward SpMM, eq. 1 per variant, adjoint SpMM)
+    against B sequential single-variant evaluations (forward SpMV, eq. 1,
+    adjoint SpMV)."""
     import casegen
     tab = casegen.variant_table(case, B, seed=1)
     rng = np.random.default_rng(5)
     X = rng.random((case.n_beamlets, B)).astype(np.float32)
-    prob.reserve_batched(B)            # enables the tiled 64-wide adjoint
+    prob.reserve_batched(B)            # the tiled adjoint's slot sums
     t0 = time.perf_counter()
     fw, aw, times = prob.tune_batched(B, reps=3)
-    log(f"[bench] tuned B={B}: forward tile {fw}, adjoint tile {aw} ({time.perf_counter() - t0:.1f}s) {times}")
+    log(f"[bench] tuned B={B}: forward {fw}, adjoint {aw} ({time.perf_counter() - t0:.1f}s) {times}")
     lab = torch.as_tensor(case.label, device="cuda")
     tabt = torch.as_tensor(tab, device="cuda")
     Xt = torch.as_tensor(X, device="cuda")
+    Wt = torch.as_tensor(rng.standard_normal((case.n_voxels, B)).astype(np.float32), device="cuda")
+    Zb = torch.empty(case.n_voxels, B, dtype=torch.float64, device="cuda")
+    Gb = torch.empty(case.n_beamlets, B, dtype=torch.float64, device="cuda")
+    f_ms = time_kernel(lambda: prob.forward_batched(Xt, Zb), reps, torch)
+    a_ms = time_kernel(lambda: prob.adjoint_batched(Wt, Gb), reps, torch)
+    fb, ab = algorithmic_bytes(case, d_store, B)
+    flops = 2.0 * case.nnz * B
     b_ms = time_kernel(lambda: prob.grad_batched(lab, tabt, Xt), reps, torch)
     # sequential: the same work one variant at a time through the single-RHS path
     xs = [Xt[:, b].double().contiguous() for b in range(B)]
@@ -283,12 +443,20 @@ def batched_study(case, prob, torch, B, reps, log):
     s_ms = time_kernel(seq, max(1, reps // 3), torch)
     lay = prob.layout()
     seq_bytes = B * (lay["fwd_bytes"] + lay["adj_bytes"])
-    res = {"variants": B, "forward_tile": fw, "adjoint_tile": aw,
-           "tune_ms": {k: {str(w): (round(v, 4) if v != float("inf") else None) for w, v in d.items()}
+
+    def roof(ms, nbytes):
+        return {"ms": round(ms, 4), "alg_bytes": nbytes, "GBs": round(nbytes / ms / 1e6, 1),
+                "hbm_frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 4),
+                "fp64_TFLOPs": round(flops / ms / 1e9, 2),
+                "valu_fp64_frac": round(flops / ms / 1e9 / PEAK_FP64_TFLOPS, 4)}
+    res = {"variants": B, "forward_variant": list(fw), "adjoint_variant": list(aw),
+           "forward": roof(f_ms, fb), "adjoint": roof(a_ms, ab),
+           "tune_ms": {k: {f"{v[0]}x{v[1]}": (round(t, 4) if t != float("inf") else None) for v, t in d.items()}
                        for k, d in times.items()},
            "batched_ms": round(b_ms, 3), "sequential_ms": round(s_ms, 3), "speedup": round(s_ms / b_ms, 2),
            "spmv_equiv_GBs": round(seq_bytes / b_ms / 1e6, 1)}
-    log(f"[bench] batched {B} variants: {b_ms:.2f} ms vs sequential {s_ms:.2f} ms ({s_ms / b_ms:.1f}x)")
+    log(f"[bench] batched {B} variants: forward {f_ms:.3f} ms, adjoint {a_ms:.3f} ms; cost + gradient "
+        f"{b_ms:.2f} ms vs sequential {s_ms:.2f} ms ({s_ms / b_ms:.1f}x)")
     return res
 
 
@@ -301,7 +469,7 @@ def aperture_master_study(prob, P, torch, steps, ms_stream, rep_stream, log):
     o.master_mode = 1
     o.master = P.master_opts()
     l, r, occ, y = prob.empty_plan()
-    prob.solve(l, r, occ, y, o, want_trace=False)  # warm-up (allocates the aperture-dose store)
+    prob.solve(l, r, occ, y, o, want_trace=False)  # warm-up (reserves the aperture-dose store)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -379,10 +547,12 @@ def mixed_resolution_study(case, prob_full, P, torch, log):
             "cost_ratio": float((cm[0] + cm[1]) / full)}
 
 
-def batched_solve_study(case, prob, torch, P, B, n_seq, log):
+def batched_solve_study(case, prob, torch, P, B, n_seq, n_seq_ap, log):
     """B plan variants solved by one lockstep column-generation run (every
-    product an SpMM over the variants) against n_seq of them solved one after
-    another by the single-plan solver (scaled to B if n_seq < B)."""
+    product an SpMM over the variants) against some of them solved one after
+    another by the single-plan solver, with the master streaming D (n_seq
+    variants) and with the aperture-dose master (n_seq_ap variants), each
+    scaled to B."""
     import dataclasses
 
     import casegen
@@ -396,25 +566,36 @@ def batched_solve_study(case, prob, torch, P, B, n_seq, log):
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
     log(f"[bench] batched solve of {B} variants: {t_b:.2f}s, {cnt[0]} forward + {cnt[1]} adjoint SpMM")
-    t_seq = 0.0
-    seq_iters = []
-    n_seq = min(n_seq, B)
-    for b in range(n_seq):
-        w = tab[b][np.minimum(case.label, tab.shape[1] - 1)]
-        cb = dataclasses.replace(case, alpha=w[:, 0].copy(), beta=w[:, 1].copy(), T=w[:, 2].copy())
-        pb = P.Problem.from_case(cb)
-        l, r, occ, y = pb.empty_plan()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rep, _ = pb.solve(l, r, occ, y, want_trace=False)
-        torch.cuda.synchronize()
-        t_seq += time.perf_counter() - t0
-        seq_iters.append(rep.master_iters)
-        pb.close()
-    t_seq_B = t_seq * B / n_seq
-    log(f"[bench] {n_seq} sequential single-variant plans: {t_seq:.2f}s (x{B / n_seq:.2f} -> {t_seq_B:.2f}s)")
+
+    def sequential(n, mode):
+        o = P.vmat.SolveOpts()
+        o.max_cg_iter = 0
+        o.master_mode = mode
+        o.master = P.master_opts()
+        t = 0.0
+        for b in range(n):
+            w = tab[b][np.minimum(case.label, tab.shape[1] - 1)]
+            cb = dataclasses.replace(case, alpha=w[:, 0].copy(), beta=w[:, 1].copy(), T=w[:, 2].copy())
+            pb = P.Problem.from_case(cb)
+            if mode == 1:
+                pb.reserve_solve()
+            l, r, occ, y = pb.empty_plan()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pb.solve(l, r, occ, y, o, want_trace=False)
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            pb.close()
+        return t * B / max(n, 1)
+    n_seq, n_seq_ap = min(n_seq, B), min(n_seq_ap, B)
+    t_seq_B = sequential(n_seq, 0)
+    t_ap_B = sequential(n_seq_ap, 1)
+    log(f"[bench] sequential single-variant plans scaled to {B}: streaming master {t_seq_B:.2f}s "
+        f"({n_seq} measured), aperture-dose master {t_ap_B:.2f}s ({n_seq_ap} measured)")
     return {"variants": B, "batched_s": round(t_b, 3), "sequential_s": round(t_seq_B, 3),
             "sequential_measured": n_seq, "speedup": round(t_seq_B / t_b, 2),
+            "sequential_apdose_s": round(t_ap_B, 3), "sequential_apdose_measured": n_seq_ap,
+            "speedup_vs_apdose": round(t_ap_B / t_b, 2),
             "plans_per_s": round(B / t_b, 2), "spmm_forward": int(cnt[0]), "spmm_adjoint": int(cnt[1]),
             "master_iters_mean": round(float(np.mean([r.master_iters for r in reps])), 1),
             "costs_first": [round(r.F + r.gG, 3) for r in reps[:4]]}
