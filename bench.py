@@ -196,6 +196,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--variants", type=int, default=64)
     ap.add_argument("--no-batched-solve", action="store_true")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="skip the variant plans run K at a time on K handles")
     ap.add_argument("--no-aperture-master", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autograd", action="store_true")
@@ -258,6 +260,7 @@ def main():
     if args.products_only:
         args.steps = args.warmup = 0
         args.no_precision = args.no_batched = args.no_batched_solve = args.no_cpu_baseline = True
+        args.no_concurrent = True
     for w in range(args.warmup):
         rep, tr = one_plan()
         torch.cuda.synchronize()
@@ -382,6 +385,9 @@ def main():
     if not args.no_batched_solve:
         out["batched_solve"] = batched_solve_study(case, prob, torch, P, args.variants, args.sequential_variants,
                                                    args.sequential_apdose_variants, log)
+
+    if not args.no_concurrent:
+        out["concurrent_variants"] = concurrent_study(case, torch, P, args.variants, (4, 8), log)
 
     if not args.no_cpu_baseline:
         nf, na, n_it, dt = cpu_baseline(case, args.cpu_iters)
@@ -599,6 +605,53 @@ def batched_solve_study(case, prob, torch, P, B, n_seq, n_seq_ap, log):
             "plans_per_s": round(B / t_b, 2), "spmm_forward": int(cnt[0]), "spmm_adjoint": int(cnt[1]),
             "master_iters_mean": round(float(np.mean([r.master_iters for r in reps])), 1),
             "costs_first": [round(r.F + r.gG, 3) for r in reps[:4]]}
+
+
+def concurrent_study(case, torch, P, B, ks, log):
+    """The same B plan variants with the aperture-dose master, K at a time:
+    K handles (one per thread and stream), each taking its next variant with
+    vmat_set_weights (D, beams and the captured iterations stay).  A plan
+    with that master is bound by launch latency, so plans on K streams
+    overlap."""
+    import concurrent.futures as cf
+
+    import casegen
+    tab = casegen.variant_table(case, B, seed=1)
+    lab = np.minimum(case.label, tab.shape[1] - 1)
+    W = [[torch.as_tensor(np.ascontiguousarray(tab[b][lab][:, q], dtype=np.float32), device="cuda")
+          for q in range(3)] for b in range(B)]
+    o = P.vmat.SolveOpts()
+    o.max_cg_iter = 0
+    o.master_mode = 1
+    o.master = P.master_opts()
+    res = {"variants": B}
+    for K in ks:
+        probs = [P.Problem.from_case(case) for _ in range(K)]
+        streams = [torch.cuda.Stream() for _ in range(K)]
+        for p in probs:
+            p.reserve_solve()
+        costs = [None] * B
+
+        def work(t):
+            with torch.cuda.stream(streams[t]):
+                for b in range(t, B, K):
+                    probs[t].set_weights(*W[b])
+                    l, r, occ, y = probs[t].empty_plan()
+                    rep, _ = probs[t].solve(l, r, occ, y, o, want_trace=False)
+                    costs[b] = rep.F + rep.gG
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(K) as ex:
+            list(ex.map(work, range(K)))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        for p in probs:
+            p.close()
+        res[f"k{K}_s"] = round(dt, 3)
+        res[f"k{K}_plans_per_s"] = round(B / dt, 2)
+        log(f"[bench] {B} variant plans, aperture-dose master, {K} at a time: {dt:.2f}s")
+    res["costs_first"] = [round(c, 3) for c in costs[:4]]
+    return res
 
 
 def precision_study(workload, torch, P, reps, log):

@@ -105,6 +105,18 @@ const char* vmat_last_error(void);
 /* Device bytes held by the handle (all layouts and work buffers). */
 vmat_status vmat_device_bytes(vmat_handle h, int64_t* bytes);
 
+/* Plan variants on one handle: replaces the voxel weights and thresholds of
+ * eq. 1 (alpha, beta, T: DEVICE float [nv], the same rules as in
+ * vmat_problem).  D, the beams and gamma stay.  The weights are checked before
+ * anything changes (VMAT_ERR_INVALID_ARG leaves the handle as it was).  A
+ * handle whose weights were held as one-byte labels (at most 256 distinct
+ * (alpha, beta, T), see vmat_layout_info.weight_labels) keeps that form and
+ * returns VMAT_ERR_UNSUPPORTED, unchanged, for weights with more distinct
+ * triples.  Allocates nothing; the captured master iterations stay valid.
+ * Synchronises the stream.                                                    */
+vmat_status vmat_set_weights(vmat_handle h, const float* alpha, const float* beta, const float* T,
+                             hipStream_t stream);
+
 /* The device layout of D chosen by vmat_create and the bytes one product has to
  * move through HBM with it (the figure the achieved bandwidth is quoted on):
  * stored entries x (value + index bytes), row pointers, the gathered vector

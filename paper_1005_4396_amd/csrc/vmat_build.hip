@@ -450,7 +450,7 @@ static void free_all(vmat_ctx* h) {
     F(h->bm.qptr); F(h->bm.col); F(h->bm.val); F(h->bm.scale);
     F(h->vm.qptr); F(h->vm.col); F(h->vm.val); F(h->vm.scale);
     F(h->abT); F(h->wlab); F(h->wtab); F(h->x); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->bpart); F(h->part); F(h->part_b);
-    F(h->pl); F(h->pr); F(h->pocc); F(h->d_gamma);
+    F(h->pl); F(h->pr); F(h->pocc); F(h->d_gamma); F(h->vflag);
     F(h->my); F(h->mgrad); F(h->mgrad_prev); F(h->md); F(h->md_prev); F(h->mgF); F(h->mW); F(h->mW_prev);
     F(h->ms);
     F(h->ms2);
@@ -467,42 +467,77 @@ static void free_all(vmat_ctx* h) {
 }
 
 // Labels of the voxel weights: the distinct (alpha, beta, T) triples, compared
-// bit for bit, in order of first appearance.  More than 256 of them: no labels
-// (the kernels read abT).  VMAT_NO_WEIGHT_LABELS in the environment at
-// creation also keeps abT only.
-static vmat_status build_weight_labels(vmat_ctx* h, hipStream_t st) {
-    if (getenv("VMAT_NO_WEIGHT_LABELS")) return VMAT_OK;
-    const int64_t nv = h->nv;
-    std::vector<float4> w((size_t)nv);
-    if (hipMemcpyAsync(w.data(), h->abT, (size_t)nv * sizeof(float4), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return fail(VMAT_ERR_DEVICE, "copy of the voxel weights failed");
-    auto same = [](const float4& a, const float4& b) { return std::memcmp(&a, &b, 3 * sizeof(float)) == 0; };
-    std::vector<float4> tab;
-    std::vector<uint8_t> lab((size_t)nv);
+// bit for bit, in order of first appearance.  Returns false when there are
+// more than WTAB_CAP of them.
+static bool label_weights(const float* a, const float* b, const float* t, int64_t nv, std::vector<float4>& tab,
+                          std::vector<uint8_t>& lab) {
+    auto same = [](const float4& u, const float4& v) { return std::memcmp(&u, &v, 3 * sizeof(float)) == 0; };
+    tab.clear();
+    lab.assign((size_t)nv, 0);
     int last = -1;
     for (int64_t j = 0; j < nv; ++j) {
-        if (last < 0 || !same(w[j], tab[last])) {
+        const float4 w = make_float4(a[j], b[j], t[j], 0.0f);
+        if (last < 0 || !same(w, tab[last])) {
             last = -1;
             for (int q = 0; q < (int)tab.size(); ++q)
-                if (same(w[j], tab[q])) { last = q; break; }
+                if (same(w, tab[q])) {
+                    last = q;
+                    break;
+                }
             if (last < 0) {
-                if (tab.size() == 256) return VMAT_OK;
-                tab.push_back(make_float4(w[j].x, w[j].y, w[j].z, 0.0f));
+                if ((int)tab.size() == WTAB_CAP) return false;
+                tab.push_back(w);
                 last = (int)tab.size() - 1;
             }
         }
         lab[j] = (uint8_t)last;
     }
-    vmat_status rc;
-    if ((rc = dalloc(h, &h->wlab, nv)) != VMAT_OK) return rc;
-    if ((rc = dalloc(h, &h->wtab, (int64_t)tab.size())) != VMAT_OK) return rc;
-    if (hipMemcpyAsync(h->wlab, lab.data(), (size_t)nv, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(h->wtab, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice, st) != hipSuccess ||
+    return true;
+}
+
+// Uploads labels and table (the table padded with zeros to WTAB_CAP).
+static vmat_status upload_labels(vmat_ctx* h, const std::vector<float4>& tab, const std::vector<uint8_t>& lab,
+                                 hipStream_t st) {
+    std::vector<float4> full(WTAB_CAP, make_float4(0.f, 0.f, 0.f, 0.f));
+    std::copy(tab.begin(), tab.end(), full.begin());
+    if (hipMemcpyAsync(h->wlab, lab.data(), (size_t)h->nv, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h->wtab, full.data(), WTAB_CAP * sizeof(float4), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return fail(VMAT_ERR_DEVICE, "upload of the weight labels failed");
     h->n_wtab = (int)tab.size();
     return VMAT_OK;
+}
+
+// Host copies of the caller's device weights.
+static vmat_status weights_to_host(const float* a, const float* b, const float* t, int64_t nv,
+                                   std::vector<float>& ha, std::vector<float>& hb, std::vector<float>& ht,
+                                   hipStream_t st) {
+    ha.resize((size_t)nv);
+    hb.resize((size_t)nv);
+    ht.resize((size_t)nv);
+    if (hipMemcpyAsync(ha.data(), a, (size_t)nv * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(hb.data(), b, (size_t)nv * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(ht.data(), t, (size_t)nv * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(VMAT_ERR_DEVICE, "copy of the voxel weights failed");
+    return VMAT_OK;
+}
+
+// The voxel weights as one-byte labels when there are at most WTAB_CAP
+// distinct triples (one per structure in the usual case); else the kernels
+// read abT.  VMAT_NO_WEIGHT_LABELS in the environment at creation also keeps
+// abT only.  The label mode chosen here stays with the handle.
+static vmat_status build_weight_labels(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
+    if (getenv("VMAT_NO_WEIGHT_LABELS")) return VMAT_OK;
+    std::vector<float> a, b, t;
+    vmat_status rc = weights_to_host(p->alpha, p->beta, p->T, h->nv, a, b, t, st);
+    if (rc != VMAT_OK) return rc;
+    std::vector<float4> tab;
+    std::vector<uint8_t> lab;
+    if (!label_weights(a.data(), b.data(), t.data(), h->nv, tab, lab)) return VMAT_OK;
+    if ((rc = dalloc(h, &h->wlab, h->nv)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->wtab, (int64_t)WTAB_CAP)) != VMAT_OK) return rc;
+    return upload_labels(h, tab, lab, st);
 }
 
 }  // namespace vmat
@@ -573,7 +608,7 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
         if (flag & BAD_T) m += " T";
         return bail(fail(VMAT_ERR_INVALID_ARG, m));
     }
-    if ((rc = build_weight_labels(h, st)) != VMAT_OK) return bail(rc);
+    if ((rc = build_weight_labels(h, p, st)) != VMAT_OK) return bail(rc);
     switch (h->d_store) {
         case VMAT_F32: rc = build_layouts<FMT_F32>(h, p, st, dflag); break;
         case VMAT_F16: rc = build_layouts<FMT_F16>(h, p, st, dflag); break;
@@ -607,6 +642,7 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     if ((rc = dalloc(h, &h->pr, NR)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->pocc, N)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->d_gamma, 1)) != VMAT_OK) return bail(rc);
+    if ((rc = dalloc(h, &h->vflag, 1)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->mW, N)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->mW_prev, N)) != VMAT_OK) return bail(rc);
     if ((rc = dalloc(h, &h->ms, 1)) != VMAT_OK) return bail(rc);
@@ -641,6 +677,57 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     // the streaming master's iteration, captured once on the handle's plan
     if ((rc = capture_master(h, 0)) != VMAT_OK) return bail(rc);
     *out = h;
+    return VMAT_OK;
+}
+
+// Checks the voxel weights without writing anything.
+__global__ void k_check_voxels(const float* __restrict__ alpha, const float* __restrict__ beta,
+                               const float* __restrict__ T, int64_t nv, int* __restrict__ flag) {
+    int bad = 0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nv; j += (int64_t)gridDim.x * blockDim.x) {
+        const float a = alpha[j], b = beta[j], t = T[j];
+        if (!(a >= 0.0f) || !isfinite(a)) bad |= BAD_ALPHA;
+        if (!(b >= 0.0f) || !isfinite(b)) bad |= BAD_BETA;
+        if (!isfinite(t)) bad |= BAD_T;
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+extern "C" vmat_status vmat_set_weights(vmat_handle h, const float* alpha, const float* beta, const float* T,
+                                        hipStream_t st) {
+    set_error("");
+    if (!h) return fail(VMAT_ERR_INVALID_ARG, "null handle");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != h->device)
+        return fail(VMAT_ERR_INVALID_ARG, "the handle belongs to another device than the current one");
+    if (!alpha || !beta || !T) return fail(VMAT_ERR_INVALID_ARG, "null alpha, beta or T");
+    VMAT_HIP(hipMemsetAsync(h->vflag, 0, sizeof(int), st));
+    k_check_voxels<<<1024, 256, 0, st>>>(alpha, beta, T, h->nv, h->vflag);
+    VMAT_LAUNCH_CHECK();
+    int flag = 0;
+    VMAT_HIP(hipMemcpyAsync(&flag, h->vflag, sizeof(int), hipMemcpyDeviceToHost, st));
+    VMAT_HIP(hipStreamSynchronize(st));
+    if (flag) {
+        std::string m = "invalid voxel weights:";
+        if (flag & BAD_ALPHA) m += " alpha";
+        if (flag & BAD_BETA) m += " beta";
+        if (flag & BAD_T) m += " T";
+        return fail(VMAT_ERR_INVALID_ARG, m);
+    }
+    std::vector<float4> tab;
+    std::vector<uint8_t> lab;
+    if (h->n_wtab > 0) {
+        std::vector<float> a, b, t;
+        vmat_status rc = weights_to_host(alpha, beta, T, h->nv, a, b, t, st);
+        if (rc != VMAT_OK) return rc;
+        if (!label_weights(a.data(), b.data(), t.data(), h->nv, tab, lab))
+            return fail(VMAT_ERR_UNSUPPORTED, "more than 256 distinct (alpha, beta, T) on a handle created with "
+                                              "labelled weights");
+    }
+    k_validate_voxels<<<1024, 256, 0, st>>>(alpha, beta, T, h->nv, h->abT, h->vflag);
+    VMAT_LAUNCH_CHECK();
+    if (h->n_wtab > 0) return upload_labels(h, tab, lab, st);
+    VMAT_HIP(hipStreamSynchronize(st));
     return VMAT_OK;
 }
 

@@ -49,6 +49,7 @@ struct QuadCsr {
 //            the block, with 16-bit voxel offsets from the block start; the
 //            block's slice of the gathered vector is staged in LDS (FP32); the
 //            slot results are summed per beamlet over its blocks in block order.
+constexpr int WTAB_CAP = 256;     // distinct (alpha, beta, T) held as voxel labels
 constexpr int TILE_VOXELS = 16384;
 constexpr int TILE_LIST = 8192;
 constexpr int TILE_THREADS = 512;
@@ -260,8 +261,9 @@ struct vmat_ctx {
     // distinct (alpha, beta, T), kept when there are at most 256 of them (one
     // per structure in the usual case); n_wtab == 0: none
     uint8_t* wlab = nullptr;       // [nv]
-    float4* wtab = nullptr;        // [n_wtab]
+    float4* wtab = nullptr;        // [WTAB_CAP], entries past n_wtab zero
     int n_wtab = 0;
+    int* vflag = nullptr;          // [1] validation flags of vmat_set_weights
 
     // work buffers
     double* x = nullptr;           // [nb] fluence

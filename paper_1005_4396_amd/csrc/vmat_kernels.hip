@@ -382,12 +382,15 @@ __device__ __forceinline__ void reduce_parts(const double* part, int n, double* 
 }
 
 // Penalty weights of the voxels: abT per voxel, or (LAB) a one-byte label per
-// voxel into a table staged in LDS.  Both give the same float4.
+// voxel into a table staged in LDS.  Both give the same float4.  The table is
+// staged at its full capacity (WTAB_CAP entries, unused ones zero), so a
+// captured kernel stays valid when vmat_set_weights changes the number of
+// distinct triples.
 struct VoxW {
     const float4* abT;
     const uint8_t* lab;
     const float4* tab;
-    int n_tab;
+    int n_tab;  // > 0: labels in use
 };
 
 inline VoxW voxw(const vmat_ctx* h) { return VoxW{h->abT, h->wlab, h->wtab, h->n_wtab}; }
@@ -395,7 +398,7 @@ inline VoxW voxw(const vmat_ctx* h) { return VoxW{h->abT, h->wlab, h->wtab, h->n
 template <bool LAB>
 __device__ __forceinline__ void stage_tab(const VoxW& vw, float4* stab) {
     if (LAB)
-        for (int i = threadIdx.x; i < vw.n_tab; i += BLOCK) stab[i] = vw.tab[i];
+        for (int i = threadIdx.x; i < WTAB_CAP; i += BLOCK) stab[i] = vw.tab[i];
 }
 
 // U voxels a grid stride apart, loaded before any arithmetic so that a grid

@@ -141,6 +141,7 @@ def lib():
             "vmat_set_batched_tile": [P, I32, I32, I32, I32, I32],
             "vmat_reserve_batched": [P, I32],
             "vmat_reserve_solve": [P],
+            "vmat_set_weights": [P, P, P, P, P],
             "vmat_price_noalloc": [ctypes.POINTER(Beams), P, P, P, P, P, P, P, P, P],
             "vmat_read_stream": [P, ctypes.c_int64, P, I32, P],
             "vmat_enforce_rate": [P, ctypes.POINTER(RateOpts), P, P, P, P, ctypes.POINTER(RateReport), P],
@@ -456,6 +457,14 @@ class Problem:
                                  ctypes.byref(opts) if opts is not None else None, ctypes.byref(rep), _stream())
         _check(code, allow=(VMAT_ERR_NOT_CONVERGED,))
         return rep
+
+    def set_weights(self, alpha, beta, T):
+        """New voxel weights and thresholds of eq. 1 (float32 device tensors [nv])
+        on this handle: a plan variant with the same D."""
+        for t in (alpha, beta, T):
+            if t.dtype.itemsize != 4 or not t.is_cuda or not t.is_contiguous() or t.numel() != self.nv:
+                raise ValueError("alpha, beta, T must be contiguous float32 CUDA tensors of n_voxels")
+        _check(lib().vmat_set_weights(self._h, _ptr(alpha), _ptr(beta), _ptr(T), _stream()))
 
     def reserve_solve(self):
         """Aperture-dose store and captured iteration for master_mode 1."""
