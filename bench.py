@@ -158,7 +158,7 @@ def cpu_per_call(workloads, log, hn_iters=1):
     return res
 
 
-def cpu_baseline(case, n_iter):
+def cpu_baseline(case, n_iter, log=None):
     """The FP64 reference, unmodified, on the first column-generation iterations
     of the same plan.  Returns (bytes-weighted product counts, seconds, result)."""
     import oracle as O
@@ -169,7 +169,9 @@ def cpu_baseline(case, n_iter):
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         res = O.solve(D, case.alpha, case.beta, case.T, case.theta_deg, case.gamma, case.circular,
-                      case.n_rows, case.n_cols, case.max_leaf_step, max_cg_iter=n_iter, with_margins=False)
+                      case.n_rows, case.n_cols, case.max_leaf_step, max_cg_iter=n_iter, with_margins=False,
+                      on_iter=(lambda t, k, c: log(f"[bench] reference iteration {t}: beam {k}, cost {c:.6g}"))
+                      if log and n_iter is None else None)
         dt = time.perf_counter() - t0
     n_it = len(res.order)
     # one adjoint for the empty plan, then one forward + one adjoint per master iteration
@@ -190,6 +192,8 @@ def main():
     ap.add_argument("--cpu-hn-iters", type=int, default=1,
                     help="column-generation iterations of the reference on the head-and-neck case")
     ap.add_argument("--no-cpu-per-call", action="store_true")
+    ap.add_argument("--cpu-full-plan", action="store_true",
+                    help="also run the reference's whole plan on the timed case (minutes on one core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--precision-workload", default="headneck180")
@@ -404,6 +408,11 @@ def main():
             part = sum(gpu_mi[:n_it])
             if part > 0:
                 out["cpu_baseline"]["full_plan_s_extrapolated"] = round(dt * sum(gpu_mi) / part, 1)
+        if args.cpu_full_plan:
+            nf2, na2, n_it2, dt2 = cpu_baseline(case, None, log)
+            out["cpu_baseline"]["full_plan_s"] = round(dt2, 1)
+            out["cpu_baseline"]["full_plan_value"] = round((nf2 * fwd_b + na2 * adj_b) / dt2 / 1e9, 4)
+            log(f"[bench] reference full plan: {n_it2} iterations, {dt2:.1f} s")
         if not args.no_cpu_per_call:
             out["cpu_baseline"]["per_call"] = cpu_per_call(("tiny36", args.workload, args.precision_workload), log,
                                                            args.cpu_hn_iters)

@@ -501,11 +501,13 @@ class SolveResult:
 
 
 def solve(D, alpha, beta, T, theta_deg, gamma, circular, R, C, delta, max_cg_iter=None,
-          master_opts=MasterOpts(), with_margins=True):
+          master_opts=MasterOpts(), with_margins=True, on_iter=None):
     """Column generation: price one aperture over the unoccupied beams, add it,
     re-solve the master, until every beam has an aperture (Sec. 2.2; abstract).
     The dose and prices of the current plan carry over from one master solve to
-    the next: the new aperture starts at intensity 0."""
+    the next: the new aperture starts at intensity 0.  on_iter (optional) is
+    called after every iteration with (iteration, beam, cost), for progress
+    reports; it takes no part in the computation."""
     N = len(theta_deg)
     occ = np.zeros(N, dtype=np.uint8)
     l = np.zeros(N * R, dtype=np.int64)
@@ -539,6 +541,8 @@ def solve(D, alpha, beta, T, theta_deg, gamma, circular, R, C, delta, max_cg_ite
         out.costs.append(m.F + m.gG)
         out.master_iters.append(m.iters)
         out.apertures.append((pr.l.copy(), pr.r.copy()))
+        if on_iter is not None:
+            on_iter(len(out.order), k, m.F + m.gG)
     out.y, out.l, out.r, out.occ, out.z = y, l, r, occ, z
     return out
 

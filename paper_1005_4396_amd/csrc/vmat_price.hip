@@ -3,9 +3,11 @@
 // and the chosen beam.
 //
 // One wavefront per (beam, row): lane c holds the prefix sum P[c] (summed in
-// column order, as a sequential pass would), lane r evaluates right end r
-// against the running best left end inside the leaf-speed window, and a
-// shuffle tree picks the least key (S, r-l, l).  C <= 64 columns fit one wave.
+// column order, as a sequential pass would); an inclusive max-scan of (P[l], l)
+// across the lanes gives every right end r its best left end inside the
+// leaf-speed window (the running best of a left-to-right pass); lane r forms
+// the candidate for right end r, and a shuffle tree picks the least key
+// (S, r-l, l).  C <= 64 columns fit one wave.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -93,23 +95,41 @@ __global__ __launch_bounds__(256) void k_price_rows(int N, int R, int C, int del
     }
     __syncthreads();
 
+    // Best left end for every right end r: the largest P[l] over
+    // Llo <= l <= min(r, Lhi), ties to the larger l.  The upper end grows
+    // with r, so this is a prefix maximum of the key (P[l], l) from Llo on:
+    // an inclusive max-scan across the wave's lanes (positions 0..63), with
+    // position 64 (C = 64 only) folded in for r = 64.  Maxima are exact, so
+    // the choice is that of a sequential left-to-right pass.
+    double kp = -INFINITY;
+    int kl = -1;
+    if (active && lane >= Llo && lane <= min(Lhi, C)) {
+        kp = P[w][lane];
+        kl = lane;
+    }
+    for (int off = 1; off < 64; off <<= 1) {
+        const double op = __shfl_up(kp, off, 64);
+        const int ol = __shfl_up(kl, off, 64);
+        if (lane >= off && ol >= 0 && (kl < 0 || op > kp)) {
+            kp = op;
+            kl = ol;
+        }
+    }
     // lane t evaluates the right ends t and t+64 (C <= 64, so at most r = 64)
     Cand best;
     best.S = INFINITY;
     best.len = 1 << 30;
     best.l = -1;
     best.r = -1;
-    for (int rr = lane; active && rr <= C; rr += 64) {
-        if (rr < Rlo || rr > Rhi) continue;
-        const int lmax = min(Lhi, rr);
-        double bp = -INFINITY;
-        int bl = -1;
-        for (int ll = Llo; ll <= lmax; ++ll) {
-            const double pl = P[w][ll];
-            if (pl >= bp) {
-                bp = pl;
-                bl = ll;
-            }
+    for (int rr = lane, pass = 0; pass < 2; rr += 64, ++pass) {
+        // the prefix maximum at position min(rr, Lhi) (every lane takes part in the shuffle)
+        const int src = min(min(rr, Lhi), 63);
+        double bp = __shfl(kp, src < 0 ? 0 : src, 64);
+        int bl = __shfl(kl, src < 0 ? 0 : src, 64);
+        if (!active || rr > C || rr < Rlo || rr > Rhi || min(rr, Lhi) < Llo) continue;
+        if (min(rr, Lhi) == 64 && P[w][64] >= bp) {
+            bp = P[w][64];
+            bl = 64;
         }
         if (bl >= 0) {
             Cand c;
