@@ -618,10 +618,11 @@ def batched_solve_study(case, prob, torch, P, B, n_seq, n_seq_ap, log):
 
 def concurrent_study(case, torch, P, B, ks, log):
     """The same B plan variants with the aperture-dose master, K at a time:
-    K handles (one per thread and stream), each taking its next variant with
-    vmat_set_weights (D, beams and the captured iterations stay).  A plan
-    with that master is bound by launch latency, so plans on K streams
-    overlap."""
+    one handle that owns D and K - 1 plan contexts reading it
+    (vmat_create_plan), one per thread and stream, each taking its next
+    variant with vmat_set_weights (D, beams and the captured iterations
+    stay).  A plan with that master is bound by launch latency, so plans on
+    K streams overlap."""
     import concurrent.futures as cf
 
     import casegen
@@ -635,7 +636,8 @@ def concurrent_study(case, torch, P, B, ks, log):
     o.master = P.master_opts()
     res = {"variants": B}
     for K in ks:
-        probs = [P.Problem.from_case(case) for _ in range(K)]
+        owner = P.Problem.from_case(case)
+        probs = [owner] + [owner.new_plan() for _ in range(K - 1)]
         streams = [torch.cuda.Stream() for _ in range(K)]
         for p in probs:
             p.reserve_solve()
@@ -654,11 +656,13 @@ def concurrent_study(case, torch, P, B, ks, log):
             list(ex.map(work, range(K)))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        for p in probs:
+        res[f"k{K}_device_bytes"] = int(sum(p.device_bytes() for p in probs))
+        for p in probs[::-1]:       # the contexts before the owner of D
             p.close()
         res[f"k{K}_s"] = round(dt, 3)
         res[f"k{K}_plans_per_s"] = round(B / dt, 2)
-        log(f"[bench] {B} variant plans, aperture-dose master, {K} at a time: {dt:.2f}s")
+        log(f"[bench] {B} variant plans, aperture-dose master, {K} at a time on one D: {dt:.2f}s, "
+            f"{res[f'k{K}_device_bytes'] / 2**30:.2f} GiB on the device")
     res["costs_first"] = [round(c, 3) for c in costs[:4]]
     return res
 

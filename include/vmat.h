@@ -27,7 +27,8 @@
  *     calling thread.
  *   - A handle is not thread-safe; distinct handles are independent.  Device
  *     memory is allocated by vmat_create (D's layouts, work buffers and the
- *     captured iteration of the master that streams D), by vmat_reserve_solve
+ *     captured iteration of the master that streams D), by vmat_create_plan
+ *     (the same without D, which it reads from its source), by vmat_reserve_solve
  *     (the aperture-dose store at the size no plan exceeds, and the captured
  *     iteration of the aperture-dose master) and by vmat_reserve_batched
  *     (batched state); vmat_destroy releases all of it.  The dose, gradient,
@@ -116,6 +117,21 @@ vmat_status vmat_device_bytes(vmat_handle h, int64_t* bytes);
  * Synchronises the stream.                                                    */
 vmat_status vmat_set_weights(vmat_handle h, const float* alpha, const float* beta, const float* T,
                              hipStream_t stream);
+
+/* Plan variants sharing one D: a second handle (a plan context) that reads
+ * src's device layouts of D and owns everything else a plan needs: a copy of
+ * src's current voxel weights (vmat_set_weights changes only this context's),
+ * gamma, the work buffers, the plan, the master state and its captured
+ * iteration, and what vmat_reserve_solve / vmat_reserve_batched add to it.
+ * Every call that takes a handle takes a context, with the same results as on
+ * src; contexts on different streams run concurrently (each is, like any
+ * handle, used from one thread at a time).  Allocates the context's state
+ * (about 37 bytes per voxel, 16 per beamlet and 8 per slot of the tiled
+ * adjoint), not D; vmat_device_bytes counts that state only.  A context made
+ * from a context reads the same owner's D.  The owner outlives its contexts:
+ * vmat_destroy on a handle whose layouts a live context reads returns
+ * VMAT_ERR_INVALID_ARG and frees nothing.  Synchronises the stream.         */
+vmat_status vmat_create_plan(vmat_handle src, hipStream_t stream, vmat_handle* out);
 
 /* The device layout of D chosen by vmat_create and the bytes one product has to
  * move through HBM with it (the figure the achieved bandwidth is quoted on):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <iterator>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -447,8 +448,14 @@ static vmat_status build_layouts(vmat_ctx* h, const vmat_problem* p, hipStream_t
 static void free_all(vmat_ctx* h) {
     auto F = [](void* p) { if (p) (void)hipFree(p); };
     F(h->d_theta);
-    F(h->bm.qptr); F(h->bm.col); F(h->bm.val); F(h->bm.scale);
-    F(h->vm.qptr); F(h->vm.col); F(h->vm.val); F(h->vm.scale);
+    if (h->d_owner) {
+        // the layouts of D belong to the owner; only the slot sums are ours
+        F(h->tl.part);
+    } else {
+        F(h->bm.qptr); F(h->bm.col); F(h->bm.val); F(h->bm.scale);
+        F(h->vm.qptr); F(h->vm.col); F(h->vm.val); F(h->vm.scale);
+        free_tiled(h);
+    }
     F(h->abT); F(h->wlab); F(h->wtab); F(h->x); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->bpart); F(h->part); F(h->part_b);
     F(h->pl); F(h->pr); F(h->pocc); F(h->d_gamma); F(h->vflag);
     F(h->my); F(h->mgrad); F(h->mgrad_prev); F(h->md); F(h->md_prev); F(h->mgF); F(h->mW); F(h->mW_prev);
@@ -456,7 +463,6 @@ static void free_all(vmat_ctx* h) {
     F(h->ms2);
     if (h->ms_host) (void)hipHostFree(h->ms_host);
     if (h->mirror) (void)hipHostFree(h->mirror);
-    free_tiled(h);
     free_batch(h);
     free_apdose(h);
     for (auto& g : h->iter_graph)
@@ -546,6 +552,66 @@ using namespace vmat;
 
 extern "C" const char* vmat_last_error(void) { return vmat::last_error(); }
 
+// The state of one plan on a handle: work buffers, the plan copy, the master
+// state and its pinned mirror, pricing results and the trace; theta and gamma
+// on the device.  Everything that is not a layout of D.
+static vmat_status alloc_plan_state(vmat_ctx* h, hipStream_t st) {
+    vmat_status rc = VMAT_OK;
+    const int64_t N = h->N, NR = (int64_t)h->N * h->R;
+    // partial-sum workgroups of the voxel passes: one per 2048 voxels, at
+    // least 256 (a small grid leaves CUs idle on these latency-bound passes)
+    // and at most 1024 (every pass reduces all partials of the previous one)
+    h->n_part = (int)std::min<int64_t>(1024, std::max<int64_t>(256, (h->nv + 2047) / 2048));
+    if ((rc = dalloc(h, &h->d_theta, N)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->x, h->nb)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->z, h->nv)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->dz, h->nv)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->rz, h->nv)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->g, h->nb)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->bpart, (size_t)N * std::max(AP_GRAD_PARTS, (h->R * h->C + 255) / 256))) != VMAT_OK)
+        return rc;
+    if ((rc = dalloc(h, &h->part, (size_t)h->n_part * 8)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->part_b, (size_t)h->n_part * 64)) != VMAT_OK) return rc;
+    double** vecs[] = {&h->my, &h->mgrad, &h->mgrad_prev, &h->md, &h->md_prev, &h->mgF};
+    for (double** v : vecs)
+        if ((rc = dalloc(h, v, N)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->pl, NR)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->pr, NR)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->pocc, N)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->d_gamma, 1)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->vflag, 1)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->mW, N)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->mW_prev, N)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->ms, 1)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->ms2, 1)) != VMAT_OK) return rc;
+    if (hipHostMalloc((void**)&h->ms_host, sizeof(MasterState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->mirror, sizeof(MasterMirror), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess)
+        return fail(VMAT_ERR_ALLOC, "hipHostMalloc failed");
+    std::memset((void*)h->mirror, 0, sizeof(MasterMirror));
+    if (hipHostGetDevicePointer((void**)&h->mirror_dev, h->mirror, 0) != hipSuccess)
+        return fail(VMAT_ERR_DEVICE, "hipHostGetDevicePointer failed");
+    if ((rc = dalloc(h, &h->row_S, NR)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->row_l, NR)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->row_r, NR)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->row_m, NR)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->bprice, N)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->pbeam, 1 + 2 * (int64_t)h->R)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->pscore, 3)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->cost2, 2)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->tr.beam, N)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->tr.price, N)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->tr.margin, N)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->tr.row_margin, N)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->tr.cost, N + 1)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->tr.miters, N)) != VMAT_OK) return rc;
+    if ((rc = dalloc(h, &h->tr.y, N * N)) != VMAT_OK) return rc;
+    if (hipMemcpyAsync(h->d_theta, h->theta.data(), N * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(VMAT_ERR_DEVICE, "copy of theta failed");
+    return set_gamma(h, h->gamma, st);
+}
+
 extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_handle* out) {
     set_error("");
     if (!p || !out) return fail(VMAT_ERR_INVALID_ARG, "null problem or output pointer");
@@ -619,63 +685,65 @@ extern "C" vmat_status vmat_create(const vmat_problem* p, hipStream_t st, vmat_h
     (void)hipFree(dflag);
     dflag = nullptr;
 
-    // work buffers
-    const int64_t N = h->N, NR = (int64_t)h->N * h->R;
-    // partial-sum workgroups of the voxel passes: one per 2048 voxels, at
-    // least 256 (a small grid leaves CUs idle on these latency-bound passes)
-    // and at most 1024 (every pass reduces all partials of the previous one)
-    h->n_part = (int)std::min<int64_t>(1024, std::max<int64_t>(256, (h->nv + 2047) / 2048));
-    if ((rc = dalloc(h, &h->d_theta, N)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->x, h->nb)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->z, h->nv)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->dz, h->nv)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->rz, h->nv)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->g, h->nb)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->bpart, (size_t)N * std::max(AP_GRAD_PARTS, (h->R * h->C + 255) / 256))) != VMAT_OK)
-        return bail(rc);
-    if ((rc = dalloc(h, &h->part, (size_t)h->n_part * 8)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->part_b, (size_t)h->n_part * 64)) != VMAT_OK) return bail(rc);
-    double** vecs[] = {&h->my, &h->mgrad, &h->mgrad_prev, &h->md, &h->md_prev, &h->mgF};
-    for (double** v : vecs)
-        if ((rc = dalloc(h, v, N)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->pl, NR)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->pr, NR)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->pocc, N)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->d_gamma, 1)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->vflag, 1)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->mW, N)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->mW_prev, N)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->ms, 1)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->ms2, 1)) != VMAT_OK) return bail(rc);
-    if (hipHostMalloc((void**)&h->ms_host, sizeof(MasterState), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&h->mirror, sizeof(MasterMirror), hipHostMallocMapped | hipHostMallocCoherent) !=
-            hipSuccess)
-        return bail(fail(VMAT_ERR_ALLOC, "hipHostMalloc failed"));
-    std::memset((void*)h->mirror, 0, sizeof(MasterMirror));
-    if (hipHostGetDevicePointer((void**)&h->mirror_dev, h->mirror, 0) != hipSuccess)
-        return bail(fail(VMAT_ERR_DEVICE, "hipHostGetDevicePointer failed"));
-    if ((rc = dalloc(h, &h->row_S, NR)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->row_l, NR)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->row_r, NR)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->row_m, NR)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->bprice, N)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->pbeam, 1 + 2 * (int64_t)h->R)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->pscore, 3)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->cost2, 2)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->tr.beam, N)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->tr.price, N)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->tr.margin, N)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->tr.row_margin, N)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->tr.cost, N + 1)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->tr.miters, N)) != VMAT_OK) return bail(rc);
-    if ((rc = dalloc(h, &h->tr.y, N * N)) != VMAT_OK) return bail(rc);
-    if (hipMemcpyAsync(h->d_theta, h->theta.data(), N * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return bail(fail(VMAT_ERR_DEVICE, "copy of theta failed"));
-    if ((rc = set_gamma(h, h->gamma, st)) != VMAT_OK) return bail(rc);
+    // work buffers and the plan state
+    if ((rc = alloc_plan_state(h, st)) != VMAT_OK) return bail(rc);
     if ((rc = tune_sell(h, st)) != VMAT_OK) return bail(rc);
     // the streaming master's iteration, captured once on the handle's plan
     if ((rc = capture_master(h, 0)) != VMAT_OK) return bail(rc);
+    *out = h;
+    return VMAT_OK;
+}
+
+extern "C" vmat_status vmat_create_plan(vmat_handle src, hipStream_t st, vmat_handle* out) {
+    set_error("");
+    if (out) *out = nullptr;
+    if (!src || !out) return fail(VMAT_ERR_INVALID_ARG, "null handle or output pointer");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != src->device)
+        return fail(VMAT_ERR_INVALID_ARG, "the handle belongs to another device than the current one");
+    vmat_ctx* o = src->d_owner ? src->d_owner : src;
+    vmat_ctx* h = new (std::nothrow) vmat_ctx();
+    if (!h) return fail(VMAT_ERR_ALLOC, "host allocation failed");
+    h->N = src->N; h->R = src->R; h->C = src->C;
+    h->nb = src->nb; h->nv = src->nv; h->nnz = src->nnz;
+    h->d_store = src->d_store; h->gamma = src->gamma;
+    h->circular = src->circular; h->delta = src->delta;
+    h->device = src->device;
+    h->theta = src->theta;
+    h->layout_req = src->layout_req;
+    h->sell_u_fwd = o->sell_u_fwd; h->sell_u_adj = o->sell_u_adj;
+    std::copy(std::begin(src->tune_fwd), std::end(src->tune_fwd), std::begin(h->tune_fwd));
+    std::copy(std::begin(src->tune_adj), std::end(src->tune_adj), std::begin(h->tune_adj));
+    // the layouts of D, read-only from here on; the slot sums the tiled
+    // adjoint writes are this context's own
+    h->bm = o->bm;
+    h->vm = o->vm;
+    h->tl = o->tl;
+    h->tl.part = nullptr;
+    h->d_owner = o;
+    auto bail = [&](vmat_status code) {
+        free_all(h);
+        delete h;
+        return code;
+    };
+    vmat_status rc = VMAT_OK;
+    if (h->tl.on && (rc = dalloc(h, &h->tl.part, (size_t)h->tl.S)) != VMAT_OK) return bail(rc);
+    // the source's current weights, in its form (labels or per-voxel)
+    if ((rc = dalloc(h, &h->abT, h->nv)) != VMAT_OK) return bail(rc);
+    if (hipMemcpyAsync(h->abT, src->abT, (size_t)h->nv * sizeof(float4), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return bail(fail(VMAT_ERR_DEVICE, "copy of the voxel weights failed"));
+    if (src->n_wtab > 0) {
+        if ((rc = dalloc(h, &h->wlab, h->nv)) != VMAT_OK) return bail(rc);
+        if ((rc = dalloc(h, &h->wtab, (int64_t)WTAB_CAP)) != VMAT_OK) return bail(rc);
+        if (hipMemcpyAsync(h->wlab, src->wlab, (size_t)h->nv, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(h->wtab, src->wtab, WTAB_CAP * sizeof(float4), hipMemcpyDeviceToDevice, st) !=
+                hipSuccess)
+            return bail(fail(VMAT_ERR_DEVICE, "copy of the weight labels failed"));
+        h->n_wtab = src->n_wtab;
+    }
+    if ((rc = alloc_plan_state(h, st)) != VMAT_OK) return bail(rc);
+    if ((rc = capture_master(h, 0)) != VMAT_OK) return bail(rc);
+    o->n_plans.fetch_add(1);
     *out = h;
     return VMAT_OK;
 }
@@ -733,12 +801,15 @@ extern "C" vmat_status vmat_set_weights(vmat_handle h, const float* alpha, const
 
 extern "C" vmat_status vmat_destroy(vmat_handle h) {
     if (!h) return fail(VMAT_ERR_INVALID_ARG, "null handle");
+    if (h->n_plans.load() > 0)
+        return fail(VMAT_ERR_INVALID_ARG, "plan contexts made from this handle still read its layouts of D");
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
     free_all(h);
     (void)hipSetDevice(cur);
+    if (h->d_owner) h->d_owner->n_plans.fetch_sub(1);
     delete h;
     return VMAT_OK;
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -320,4 +321,9 @@ struct vmat_ctx {
     double* cost2 = nullptr;       // [2]
     vmat::SolveTraceDev tr{};
     int64_t bytes = 0;
+    // plan contexts (vmat_create_plan): d_owner is the handle whose layouts
+    // of D this one reads (null: it built its own); n_plans counts the live
+    // contexts reading this handle's layouts
+    vmat_ctx* d_owner = nullptr;
+    std::atomic<int> n_plans{0};
 };

@@ -142,6 +142,7 @@ def lib():
             "vmat_reserve_batched": [P, I32],
             "vmat_reserve_solve": [P],
             "vmat_set_weights": [P, P, P, P, P],
+            "vmat_create_plan": [P, P, ctypes.POINTER(P)],
             "vmat_price_noalloc": [ctypes.POINTER(Beams), P, P, P, P, P, P, P, P, P],
             "vmat_read_stream": [P, ctypes.c_int64, P, I32, P],
             "vmat_enforce_rate": [P, ctypes.POINTER(RateOpts), P, P, P, P, ctypes.POINTER(RateReport), P],
@@ -247,11 +248,25 @@ class Problem:
         torch.cuda.synchronize()
         return prob
 
+    def new_plan(self) -> "Problem":
+        """A plan context on this problem's D (vmat_create_plan): its own
+        weights (a copy of the current ones), plan, master state and stores;
+        D is read from this handle, which must stay open while the context
+        lives (closing it first raises)."""
+        h = ctypes.c_void_p()
+        _check(lib().vmat_create_plan(self._h, _stream(), ctypes.byref(h)))
+        ctx = Problem.__new__(Problem)
+        ctx.__dict__.update({k: v for k, v in self.__dict__.items() if k not in ("_h", "_src")})
+        ctx._h = h
+        ctx._src = self            # keeps the owner of D alive
+        return ctx
+
     # ------------------------------------------------------------ lifecycle
     def close(self):
         if getattr(self, "_h", None):
-            lib().vmat_destroy(self._h)
+            _check(lib().vmat_destroy(self._h))
             self._h = None
+            self._src = None
 
     def __del__(self):
         try:

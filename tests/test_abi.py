@@ -37,6 +37,9 @@ def test_null_handle_rejected():
     assert "handle" in V.last_error()
     assert L.vmat_forward_batched(None, 4, None, None, None) == V.VMAT_ERR_INVALID_ARG
     assert L.vmat_set_batched_tile(None, 4, 8, 8, 8, 8) == V.VMAT_ERR_INVALID_ARG
+    h = ctypes.c_void_p(1)
+    assert L.vmat_create_plan(None, None, ctypes.byref(h)) == V.VMAT_ERR_INVALID_ARG
+    assert h.value is None            # the output is cleared on every path out
     assert L.vmat_destroy(None) in (V.VMAT_OK, V.VMAT_ERR_INVALID_ARG)
 
 
