@@ -10,8 +10,11 @@ and one adjoint per master iteration), the configuration whose products the
 metric counts; the plan time of the master over stored aperture doses is
 reported beside it (`aperture_master`).
 
-value = algorithmic bytes of all D.x (forward) and D^T.r (adjoint) products
-run during the timed plans / wall time of those plans (GB/s).  The roofline
+value = the bytes all D.x (forward) and D^T.r (adjoint) products run during
+the timed plans move with the handle's layout (vmat_layout fwd_bytes and
+adj_bytes: stored entries with their 16-bit local indices, row and slot
+pointers, the gathered vector and the output) / wall time of those plans
+(GB/s).  The roofline
 object reports the dominant product kernel alone, timed with HIP events on the
 stream it runs on, against the 8 TB/s HBM peak.  Its algorithmic bytes per
 launch are those of a plain CSR product with int32 indices: nnz (v + 4) +
@@ -281,7 +284,7 @@ def main():
     wall = time.perf_counter() - t_start
     ms_per_step = wall * 1e3 / args.steps if args.steps else None
 
-    # algorithmic bytes of the products run during the timed plans
+    # the layout's bytes of the products run during the timed plans
     lay = prob.layout()
     fwd_b, adj_b = lay["fwd_bytes"], lay["adj_bytes"]
     n_fwd = sum(r.n_forward for r in reps)

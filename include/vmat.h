@@ -148,8 +148,8 @@ typedef struct vmat_layout_info {
     int64_t fwd_entries;    /* stored entries of the forward layout, padding included     */
     int64_t adj_entries;    /* stored entries of the adjoint layout, padding included     */
     int64_t slots;          /* (block, beamlet) pairs of the tiled layout                 */
-    int64_t fwd_bytes;      /* algorithmic HBM bytes of one vmat_forward                  */
-    int64_t adj_bytes;      /* algorithmic HBM bytes of one vmat_adjoint                  */
+    int64_t fwd_bytes;      /* HBM bytes one vmat_forward moves with this layout          */
+    int64_t adj_bytes;      /* HBM bytes one vmat_adjoint moves with this layout          */
     int32_t weight_labels;  /* distinct (alpha, beta, T) held as one-byte voxel labels    */
                             /* for the master's voxel passes (at most 256); 0: per-voxel  */
                             /* weights (more than 256 distinct, or VMAT_NO_WEIGHT_LABELS  */
