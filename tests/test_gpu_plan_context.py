@@ -49,13 +49,15 @@ def _same(a, b):
         np.testing.assert_array_equal(u, v)
 
 
+@pytest.mark.parametrize("layout", ["tiled", "plain"])
 @pytest.mark.parametrize("mode", [0, 1])
-def test_context_plan_matches_owner(mode):
+def test_context_plan_matches_owner(mode, layout):
     """A context with a second objective gives the bits the owner gives with
     that objective; the owner's own plan afterwards is unchanged."""
     c = small_case(n_beams=8, n_rows=4, n_cols=6, grid=(12, 12, 8))
-    src = P.Problem.from_case(c)
+    src = P.Problem.from_case(c, layout=layout)
     ctx = src.new_plan()
+    assert ctx.layout() == src.layout() and src.layout()["tiled"] == (layout == "tiled")
     try:
         base = _plan(src, mode)
         w = _weights(c, 11)
