@@ -621,52 +621,36 @@ def batched_solve_study(case, prob, torch, P, B, n_seq, n_seq_ap, log):
 
 def concurrent_study(case, torch, P, B, ks, log):
     """The same B plan variants with the aperture-dose master, K at a time:
-    one handle that owns D and K - 1 plan contexts reading it
-    (vmat_create_plan), one per thread and stream, each taking its next
-    variant with vmat_set_weights (D, beams and the captured iterations
-    stay).  A plan with that master is bound by launch latency, so plans on
-    K streams overlap."""
-    import concurrent.futures as cf
-
+    vmat_solve_variants, which makes K plan contexts over one handle's D, one
+    host thread and stream each (each context takes its next variant with
+    vmat_set_weights).  A plan with that master is bound by launch latency,
+    so plans on K streams overlap.  The time includes making the contexts and
+    their aperture-dose stores."""
     import casegen
-    tab = casegen.variant_table(case, B, seed=1)
-    lab = np.minimum(case.label, tab.shape[1] - 1)
-    W = [[torch.as_tensor(np.ascontiguousarray(tab[b][lab][:, q], dtype=np.float32), device="cuda")
-          for q in range(3)] for b in range(B)]
+    tab = torch.as_tensor(casegen.variant_table(case, B, seed=1), device="cuda")
+    label = torch.as_tensor(case.label, device="cuda")
     o = P.vmat.SolveOpts()
     o.max_cg_iter = 0
     o.master_mode = 1
     o.master = P.master_opts()
     res = {"variants": B}
-    for K in ks:
-        owner = P.Problem.from_case(case)
-        probs = [owner] + [owner.new_plan() for _ in range(K - 1)]
-        streams = [torch.cuda.Stream() for _ in range(K)]
-        for p in probs:
-            p.reserve_solve()
-        costs = [None] * B
-
-        def work(t):
-            with torch.cuda.stream(streams[t]):
-                for b in range(t, B, K):
-                    probs[t].set_weights(*W[b])
-                    l, r, occ, y = probs[t].empty_plan()
-                    rep, _ = probs[t].solve(l, r, occ, y, o, want_trace=False)
-                    costs[b] = rep.F + rep.gG
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        with cf.ThreadPoolExecutor(K) as ex:
-            list(ex.map(work, range(K)))
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        res[f"k{K}_device_bytes"] = int(sum(p.device_bytes() for p in probs))
-        for p in probs[::-1]:       # the contexts before the owner of D
-            p.close()
-        res[f"k{K}_s"] = round(dt, 3)
-        res[f"k{K}_plans_per_s"] = round(B / dt, 2)
-        log(f"[bench] {B} variant plans, aperture-dose master, {K} at a time on one D: {dt:.2f}s, "
-            f"{res[f'k{K}_device_bytes'] / 2**30:.2f} GiB on the device")
-    res["costs_first"] = [round(c, 3) for c in costs[:4]]
+    owner = P.Problem.from_case(case)
+    try:
+        res["owner_device_bytes"] = owner.device_bytes()
+        for K in ks:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps, l, r, occ, y = owner.solve_variants(label, tab, K=K, opts=o)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res[f"k{K}_s"] = round(dt, 3)
+            res[f"k{K}_plans_per_s"] = round(B / dt, 2)
+            log(f"[bench] {B} variant plans, aperture-dose master, {K} at a time on one D "
+                f"(vmat_solve_variants): {dt:.2f}s")
+            res["costs_first"] = [round(rp.F + rp.gG, 3) for rp in reps[:4]]
+            del l, r, occ, y
+    finally:
+        owner.close()
     return res
 
 

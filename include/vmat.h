@@ -28,7 +28,8 @@
  *   - A handle is not thread-safe; distinct handles are independent.  Device
  *     memory is allocated by vmat_create (D's layouts, work buffers and the
  *     captured iteration of the master that streams D), by vmat_create_plan
- *     (the same without D, which it reads from its source), by vmat_reserve_solve
+ *     (the same without D, which it reads from its source), by
+ *     vmat_solve_variants (its worker contexts, for the call), by vmat_reserve_solve
  *     (the aperture-dose store at the size no plan exceeds, and the captured
  *     iteration of the aperture-dose master) and by vmat_reserve_batched
  *     (batched state); vmat_destroy releases all of it.  The dose, gradient,
@@ -441,6 +442,28 @@ vmat_status vmat_solve_batched(vmat_handle h, const vmat_solve_opts* opts, int32
                                const uint8_t* label, const float* table, int32_t* l, int32_t* r,
                                uint8_t* occ, double* y, vmat_solve_report* rep,
                                vmat_solve_trace* trace, int64_t* n_spmm, hipStream_t stream);
+
+/* Plan variants sharing one D, K at a time: B plans, variant b with the
+ * weights and thresholds table[b] (label/table as in vmat_grad_batched;
+ * n_struct in [1, 256]), each a full vmat_solve from an empty plan.  The call
+ * makes K plan contexts from h (vmat_create_plan), one host thread and one
+ * stream each; worker t takes variants t, t + K, ... in turn, sets their
+ * weights (vmat_set_weights) and solves.  Every plan is bit for bit the plan
+ * vmat_solve gives on h with that variant's weights; h itself is not changed.
+ * The plans of one worker follow each other; the workers' plans overlap on
+ * the device (a plan with the aperture-dose master is bound by the latency of
+ * its small launches).  opts: as in vmat_solve (nullable: defaults); with
+ * master_mode 1 each context reserves its aperture-dose store.  K in
+ * [1, 16] (more workers than the device's hardware queues add nothing).
+ * l, r: DEVICE int32 [B][N*R]; occ: DEVICE uint8 [B][N]; y: DEVICE double
+ * [B][N] (outputs: the plans); rep: HOST [B] reports.  Synchronises `stream`
+ * before it starts; returns when every plan is done.  Allocates the K
+ * contexts (their plan state and, in mode 1, their stores), K streams and
+ * 12 nv bytes per worker, and releases all of it before it returns.         */
+vmat_status vmat_solve_variants(vmat_handle h, const vmat_solve_opts* opts, int32_t B, int32_t n_struct,
+                                const uint8_t* label, const float* table, int32_t K, int32_t* l,
+                                int32_t* r, uint8_t* occ, double* y, vmat_solve_report* rep,
+                                hipStream_t stream);
 
 /* Measurement aid, not a step of the method: one streaming read of a device
  * buffer (non-temporal 16-byte loads, eight in flight per lane), timed by the

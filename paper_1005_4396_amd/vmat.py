@@ -143,6 +143,8 @@ def lib():
             "vmat_reserve_solve": [P],
             "vmat_set_weights": [P, P, P, P, P],
             "vmat_create_plan": [P, P, ctypes.POINTER(P)],
+            "vmat_solve_variants": [P, ctypes.POINTER(SolveOpts), I32, I32, P, P, I32, P, P, P, P,
+                                    ctypes.POINTER(SolveReport), P],
             "vmat_price_noalloc": [ctypes.POINTER(Beams), P, P, P, P, P, P, P, P, P],
             "vmat_read_stream": [P, ctypes.c_int64, P, I32, P],
             "vmat_enforce_rate": [P, ctypes.POINTER(RateOpts), P, P, P, P, ctypes.POINTER(RateReport), P],
@@ -247,6 +249,24 @@ class Problem:
                    case.gamma, case.circular, case.max_leaf_step, d_store, layout)
         torch.cuda.synchronize()
         return prob
+
+    def solve_variants(self, label, table, K=4, opts: SolveOpts | None = None):
+        """B full plans, variant b with weights table[b] (float [B, S, 3] of
+        (alpha, beta, T) per structure; label uint8 [nv]), K at a time on K
+        plan contexts over this problem's D (vmat_solve_variants).  Returns
+        (reports, l [B, N*R], r, occ [B, N], y [B, N])."""
+        import torch
+        dev = self.device
+        B, S = int(table.shape[0]), int(table.shape[1])
+        l = torch.zeros(B, self.N * self.R, dtype=torch.int32, device=dev)
+        r = torch.zeros_like(l)
+        occ = torch.zeros(B, self.N, dtype=torch.uint8, device=dev)
+        y = torch.zeros(B, self.N, dtype=torch.float64, device=dev)
+        reps = (SolveReport * B)()
+        _check(lib().vmat_solve_variants(self._h, ctypes.byref(opts) if opts else None, B, S, _ptr(label),
+                                         _ptr(table), int(K), _ptr(l), _ptr(r), _ptr(occ), _ptr(y), reps,
+                                         _stream()))
+        return list(reps), l, r, occ, y
 
     def new_plan(self) -> "Problem":
         """A plan context on this problem's D (vmat_create_plan): its own

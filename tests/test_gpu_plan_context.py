@@ -176,3 +176,45 @@ def test_contexts_run_plans_concurrently():
         for p in ctxs:
             p.close()
         src.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_solve_variants_matches_plans_one_by_one(mode):
+    """vmat_solve_variants (five variants, three workers) gives each variant
+    the plan vmat_solve gives on the owner with that variant's weights, and
+    leaves the owner's own weights as they were."""
+    c = preset_case("tiny36")
+    B = 5
+    tab = casegen.variant_table(c, B, seed=7)
+    lab = np.minimum(c.label, tab.shape[1] - 1)
+    src = P.Problem.from_case(c)
+    try:
+        before = _plan(src, mode)
+        reps, l, r, occ, y = src.solve_variants(torch.as_tensor(c.label, device="cuda"),
+                                                torch.as_tensor(tab, device="cuda"), K=3, opts=_opts(mode))
+        _same(_plan(src, mode), before)
+        for b in range(B):
+            src.set_weights(*[torch.as_tensor(np.ascontiguousarray(tab[b][lab][:, q]), device="cuda")
+                              for q in range(3)])
+            one = _plan(src, mode)
+            np.testing.assert_array_equal(l[b].cpu().numpy(), one[0])
+            np.testing.assert_array_equal(r[b].cpu().numpy(), one[1])
+            np.testing.assert_array_equal(y[b].cpu().numpy(), one[2])
+            assert occ[b].cpu().numpy().all()
+            assert [reps[b].F, reps[b].gG, reps[b].master_iters] == list(one[5])
+    finally:
+        src.close()
+
+
+def test_solve_variants_rejects_bad_worker_counts():
+    c = small_case(n_beams=6, n_rows=3, n_cols=5, grid=(10, 10, 6))
+    tab = torch.as_tensor(casegen.variant_table(c, 2, seed=1), device="cuda")
+    label = torch.as_tensor(c.label, device="cuda")
+    src = P.Problem.from_case(c)
+    try:
+        for K in (0, 17):
+            with pytest.raises(P.vmat.VmatError) as e:
+                src.solve_variants(label, tab, K=K)
+            assert e.value.code == P.vmat.VMAT_ERR_INVALID_ARG
+    finally:
+        src.close()
