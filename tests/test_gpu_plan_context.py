@@ -206,15 +206,26 @@ def test_solve_variants_matches_plans_one_by_one(mode):
         src.close()
 
 
-def test_solve_variants_rejects_bad_worker_counts():
+def test_solve_variants_worker_counts():
+    """K outside [1, 16] is rejected; more workers than variants run one
+    variant each (default options: the master that streams D)."""
     c = small_case(n_beams=6, n_rows=3, n_cols=5, grid=(10, 10, 6))
-    tab = torch.as_tensor(casegen.variant_table(c, 2, seed=1), device="cuda")
+    tabn = casegen.variant_table(c, 2, seed=1)
+    tab = torch.as_tensor(tabn, device="cuda")
     label = torch.as_tensor(c.label, device="cuda")
+    lab = np.minimum(c.label, tabn.shape[1] - 1)
     src = P.Problem.from_case(c)
     try:
         for K in (0, 17):
             with pytest.raises(P.vmat.VmatError) as e:
                 src.solve_variants(label, tab, K=K)
             assert e.value.code == P.vmat.VMAT_ERR_INVALID_ARG
+        reps, l, r, occ, y = src.solve_variants(label, tab, K=4)
+        for b in range(2):
+            src.set_weights(*[torch.as_tensor(np.ascontiguousarray(tabn[b][lab][:, q]), device="cuda")
+                              for q in range(3)])
+            one = _plan(src, 0)
+            np.testing.assert_array_equal(y[b].cpu().numpy(), one[2])
+            assert reps[b].cg_iters == c.n_beams
     finally:
         src.close()
