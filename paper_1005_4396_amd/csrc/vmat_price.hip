@@ -42,6 +42,8 @@ __global__ __launch_bounds__(256) void k_price_rows(int N, int R, int C, int del
                                                     int32_t* __restrict__ rowr, double* __restrict__ rowm,
                                                     const uint8_t* __restrict__ vmask) {
     __shared__ double P[4][65];
+    __shared__ double gs[4][64];   // the wave's row of prices
+    __shared__ uint8_t socc[4096]; // occupancy (N <= 4096), for the neighbour search
     if (vmask && !vmask[blockIdx.y]) return;
     {
         const int b = blockIdx.y;
@@ -60,21 +62,35 @@ __global__ __launch_bounds__(256) void k_price_rows(int N, int R, int C, int del
     const bool valid = kr < (int64_t)N * R;
     const int k = valid ? (int)(kr / R) : 0;
     const int rho = valid ? (int)(kr - (int64_t)k * R) : 0;
-    const bool active = valid && !occ[k];
+    for (int i = threadIdx.x; i < N; i += 256) socc[i] = occ[i];
+    if (valid && lane < C) gs[w][lane] = g[(kr * C + lane) * B];
+    __syncthreads();
+    const bool active = valid && !socc[k];
 
-    // leaf windows from the nearest occupied beam on each side
+    // leaf windows from the nearest occupied beam on each side: the wave
+    // tests 64 index distances at once (lane t: distance base + t, wrapping
+    // round the circle when circular, else ending at the first or last beam)
+    // and the lowest lane with an occupied beam gives the nearest
     int Llo = 0, Lhi = C, Rlo = 0, Rhi = C;
     if (active && delta >= 0) {
         for (int side = 0; side < 2; ++side) {
-            for (int dist = 1; dist < N; ++dist) {
+            for (int base = 1; base < N; base += 64) {
+                const int dist = base + lane;
                 int kk = side == 0 ? k - dist : k + dist;
-                if (kk < 0 || kk >= N) {
-                    if (!circ) break;
-                    kk = kk < 0 ? kk + N : kk - N;
+                bool hit = false;
+                if (dist < N) {
+                    if (kk < 0 || kk >= N) {
+                        if (circ) kk = kk < 0 ? kk + N : kk - N;
+                    }
+                    hit = kk >= 0 && kk < N && socc[kk];
                 }
-                if (occ[kk]) {
-                    const int reach = (int)min((int64_t)delta * dist, (int64_t)(1 << 20));
-                    const int64_t a = (int64_t)kk * R + rho;
+                const uint64_t m = __ballot(hit);
+                if (m) {
+                    const int first = __ffsll((unsigned long long)m) - 1;
+                    const int d = base + first;
+                    const int kn = __shfl(kk, first, 64);
+                    const int reach = (int)min((int64_t)delta * d, (int64_t)(1 << 20));
+                    const int64_t a = (int64_t)kn * R + rho;
                     Llo = max(Llo, l[a] - reach);
                     Lhi = min(Lhi, l[a] + reach);
                     Rlo = max(Rlo, r[a] - reach);
@@ -85,11 +101,10 @@ __global__ __launch_bounds__(256) void k_price_rows(int N, int R, int C, int del
         }
     }
     // prefix sums P[0..C] in column order; lane t holds P[t] and P[t+64]
-    const double* gr = g + kr * C * B;
     if (active) {
         for (int pos = lane; pos <= C; pos += 64) {
             double acc = 0.0;
-            for (int c = 0; c < pos; ++c) acc = acc + gr[(int64_t)c * B];
+            for (int c = 0; c < pos; ++c) acc = acc + gs[w][c];
             P[w][pos] = acc;
         }
     }
