@@ -45,7 +45,9 @@ __device__ __forceinline__ double xval(const float* __restrict__ X, const float*
 // runs over the row's quads in order, entries in order: the bits do not
 // depend on LPR, V or the schedule.
 //
-// Schedule: workgroup w runs on XCD w % 8.  XCD i walks its own contiguous
+// Schedule: workgroups are dealt to the XCDs in turn, so those with the
+// same w % 8 share an XCD (measured on MI355X: XCD (w + 7) mod 8); group i of
+// them (one XCD) walks its own contiguous
 // range of voxel blocks in order, and within a block the right-hand sides in
 // tiles of TB, all its workgroups on one (block, tile) at a time, so the rows
 // a block gathers (at most TILE_LIST beamlets, or the block's voxels, times
@@ -596,7 +598,7 @@ static SpmmCfg default_cfg(int B) {
 
 // Persistent grids: as many workgroups as can be resident at once (the
 // occupancy of the kernel, on the 32 compute units of each XCD), a multiple
-// of 8 so that workgroup w stays on XCD w % 8.
+// of 8 so that the workgroups with one value of w % 8 are one XCD's.
 template <class K>
 static unsigned resident_grid(K kernel, int threads) {
     int per_cu = 0;

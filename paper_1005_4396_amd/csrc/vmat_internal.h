@@ -54,7 +54,10 @@ constexpr int WTAB_CAP = 256;     // distinct (alpha, beta, T) held as voxel lab
 constexpr int TILE_VOXELS = 16384;
 constexpr int TILE_LIST = 8192;
 constexpr int TILE_THREADS = 512;
-constexpr int TILE_ROWS = 2048;   // rows per work item (their starts are staged in LDS)
+// Most rows of one work item (32 slices); their sums are staged in LDS, and
+// 64 KB of staged values + TILE_ROWS doubles + a counter fit two 512-thread
+// workgroups in a compute unit's 160 KB.
+constexpr int TILE_ROWS = 2040;
 // Quads in flight per lane in the sliced forward.
 constexpr int SELL_U = 4;
 

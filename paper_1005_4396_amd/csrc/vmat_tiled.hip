@@ -23,25 +23,32 @@ namespace vmat {
 
 // ---------------------------------------------------------------- kernels
 //
-// A work item is (block, rows [r0, r1)) with at most TILE_ROWS rows.  Its row
-// starts are staged in LDS with the gathered values, so no global load sits
-// between one row and the next.  G lanes share a row; each lane issues the
-// loads of up to U quads of a row at once, and the loads of the group's next
-// row are issued before the current row is summed (two rows in flight per
-// lane group).  Longer rows finish in extra passes.
+// A work item is (block, rows [r0, r1)) with at most TILE_ROWS rows, cut into
+// 64-row slices (rows sorted longest first).  One workgroup takes one item:
+// it stages the block's gathered values in LDS, then its waves sum the
+// item's slices, one lane per row.
 
 
-// The slices of one work item: wave w takes slices w, w + 8, ...; lane i owns
-// row i of the slice and walks its quads in order, U quads in flight.
+// The slices of one work item.  Wave w starts with slice w; a wave that
+// finishes a slice takes the next one nobody has taken (counter *qnext in
+// LDS, starting at the number of waves), so a long slice does not hold the
+// workgroup while the other waves idle.  Lane i owns row i of the slice and
+// walks its quads in order, U quads in flight; the last len mod U quads are
+// loaded together too.  The order of the sums within a row does not depend
+// on which wave takes the slice.  Row sums go to os[row - first row of the
+// item] in LDS: the rows of a slice are scattered over the item (sorted by
+// length), and 64 scattered 8-byte global stores cost the memory pipeline
+// about as much as several of the slice's streaming loads.
 template <int FMT, int U, typename ST>
 __device__ __forceinline__ void sell_rows(const int4 wk, const uint32_t* __restrict__ s_off,
                                           const uint32_t* __restrict__ s_len, const uint32_t* __restrict__ s_row,
                                           const uint16_t* __restrict__ s_col, const void* __restrict__ s_val,
-                                          const ST* __restrict__ xs, double* __restrict__ out) {
+                                          const ST* __restrict__ xs, double* __restrict__ os,
+                                          uint32_t* qnext) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nsl = (wk.z - wk.y + 63) / 64;
     const u16x4* __restrict__ c4 = reinterpret_cast<const u16x4*>(s_col);
-    for (int j = wave; j < nsl; j += TILE_THREADS / 64) {
+    for (int j = wave; j < nsl;) {
         const int64_t sl = (int64_t)wk.w + j;
         const uint32_t base = s_off[sl] + lane, len = s_len[sl];
         const uint32_t row = s_row[sl * 64 + lane];
@@ -63,22 +70,47 @@ __device__ __forceinline__ void sell_rows(const int4 wk, const uint32_t* __restr
                 acc = fma((double)v[u].w, (double)xs[c[u].w], acc);
             }
         }
-        for (; k < len; ++k) {
-            const float4 v = Quad<FMT>::load(s_val, base + k * 64);
-            const u16x4 c = __builtin_nontemporal_load(c4 + base + k * 64);
-            acc = fma((double)v.x, (double)xs[c.x], acc);
-            acc = fma((double)v.y, (double)xs[c.y], acc);
-            acc = fma((double)v.z, (double)xs[c.z], acc);
-            acc = fma((double)v.w, (double)xs[c.w], acc);
+        if (k < len) {
+            // the last rem < U quads; addresses past the row's end re-read
+            // its last quad and are not summed
+            const uint32_t rem = len - k;
+            float4 v[U - 1];
+            u16x4 c[U - 1];
+#pragma unroll
+            for (int u = 0; u < U - 1; ++u) {
+                const uint32_t kk = k + min((uint32_t)u, rem - 1);
+                v[u] = Quad<FMT>::load(s_val, base + kk * 64);
+                c[u] = __builtin_nontemporal_load(c4 + base + kk * 64);
+            }
+#pragma unroll
+            for (int u = 0; u < U - 1; ++u) {
+                if ((uint32_t)u < rem) {
+                    acc = fma((double)v[u].x, (double)xs[c[u].x], acc);
+                    acc = fma((double)v[u].y, (double)xs[c[u].y], acc);
+                    acc = fma((double)v[u].z, (double)xs[c[u].z], acc);
+                    acc = fma((double)v[u].w, (double)xs[c[u].w], acc);
+                }
+            }
         }
-        if (row != 0xFFFFFFFFu) out[row] = acc;
+        if (row != 0xFFFFFFFFu) os[row - (uint32_t)wk.y] = acc;
+        uint32_t nj = 0;
+        if (lane == 0) nj = atomicAdd(qnext, 1u);
+        j = (int)__builtin_amdgcn_readlane(nj, 0);
     }
 }
 
+// Writes the item's row sums (rows wk.y .. wk.z - 1, staged in os) to
+// out[wk.y ...] with coalesced stores, once every wave has finished.
+__device__ __forceinline__ void flush_rows(const int4 wk, const double* os, double* __restrict__ out) {
+    __syncthreads();
+    const int n = wk.z - wk.y;
+    for (int i = threadIdx.x; i < n; i += TILE_THREADS) out[(int64_t)wk.y + i] = os[i];
+}
+
 // Forward over the sliced layout: after the block's x values are staged in
-// LDS, wave w takes the item's slices w, w + 8, ...; lane i owns row i of the
-// slice and walks its quads in order (quad k of the 64 rows is one contiguous
-// 1-KB load for FP32 values), U quads in flight per lane, no cross-lane sums.
+// LDS, the waves take the item's slices as sell_rows describes; lane i owns
+// row i of the slice and walks its quads in order (quad k of the 64 rows is
+// one contiguous 1-KB load for FP32 values), no cross-lane sums.
 template <int FMT, int U>
 __global__ __launch_bounds__(TILE_THREADS) void k_fwd_sell(const int4* __restrict__ work,
                                                          const uint32_t* __restrict__ loff,
@@ -91,7 +123,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_fwd_sell(const int4* __restric
                                                          const double* __restrict__ x, double* __restrict__ out,
                                                          Gate gate) {
     __shared__ double xs[TILE_LIST];
+    __shared__ double os[TILE_ROWS];
+    __shared__ uint32_t qn;
     if (gate.closed()) return;
+    if (threadIdx.x == 0) qn = TILE_THREADS / 64;
     const int4 wk = work[blockIdx.x];
     if (wk.x < 0) return;
     const uint32_t l0 = loff[wk.x], ln = loff[wk.x + 1] - l0;
@@ -116,7 +151,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_fwd_sell(const int4* __restric
         }
     }
     __syncthreads();
-    sell_rows<FMT, U>(wk, s_off, s_len, s_row, s_col, s_val, xs, out);
+    sell_rows<FMT, U>(wk, s_off, s_len, s_row, s_col, s_val, xs, os, &qn);
+    flush_rows(wk, os, out);
 }
 
 // Builder of the sliced layout: one wave per slice copies each row's quads
@@ -163,7 +199,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_adj_sell(const int4* __restric
                                                          const float* __restrict__ w, double* __restrict__ part,
                                                          Gate gate) {
     __shared__ float ws[TILE_VOXELS];
+    __shared__ double os[TILE_ROWS];
+    __shared__ uint32_t qn;
     if (gate.closed()) return;
+    if (threadIdx.x == 0) qn = TILE_THREADS / 64;
     const int4 wk = work[blockIdx.x];
     if (wk.x < 0) return;
     const int32_t j0 = bounds[wk.x], jn = bounds[wk.x + 1] - j0;
@@ -182,7 +221,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_adj_sell(const int4* __restric
         }
     }
     __syncthreads();
-    sell_rows<FMT, U>(wk, s_off, s_len, s_row, s_col, s_val, ws, part);
+    sell_rows<FMT, U>(wk, s_off, s_len, s_row, s_col, s_val, ws, os, &qn);
+    flush_rows(wk, os, part);
 }
 
 // g_i = scale_i * sum of beamlet i's slot sums, in block order.
@@ -554,9 +594,15 @@ hipError_t dmalloc(DevBuf& b, size_t bytes) {
     return hipMalloc(&b.p, std::max<size_t>(bytes, 16));
 }
 
-// Work items of about `qpw` quads each, never crossing a block; placed so
-// that consecutive items (same block) land on the same XCD (workgroup w runs
-// on XCD w mod 8).
+// Work items of about `qpw` quads each (at most max_rows rows), never
+// crossing a block, placed for the XCDs.  Workgroups are dealt to the eight
+// XCDs in turn (w and w + 8 on the same XCD; measured on MI355X: XCD
+// (w + 7) mod 8), so slot x of each group of eight is one XCD's sequence.
+// The items, in block order, are cut into eight runs of about equal quads;
+// run x becomes sequence x, so an XCD's items share their blocks' staged
+// values in its L2.  Each sequence is ordered by quads, largest first: a
+// compute unit that frees a slot late in the launch takes a small item, so
+// the launch ends with short items (longest-processing-time order).
 std::vector<int4> make_work(const std::vector<int64_t>& row_begin_of_block, const std::vector<uint32_t>& rowq,
                             int nblk, int64_t qpw, int64_t max_rows) {
     std::vector<int4> items;
@@ -574,13 +620,25 @@ std::vector<int4> make_work(const std::vector<int64_t>& row_begin_of_block, cons
         }
         if (start < r1) items.push_back(make_int4(b, (int)start, (int)r1, 0));
     }
-    const int n = (int)items.size();
-    const int per = (n + 7) / 8;
-    std::vector<int4> out((size_t)per * 8, make_int4(-1, 0, 0, 0));
-    for (int p = 0; p < n; ++p) {
-        const int xcd = p / per, pos = p % per;
-        out[(size_t)pos * 8 + xcd] = items[p];
+    auto quads = [&](const int4& it) { return (uint64_t)(rowq[it.z] - rowq[it.y]); };
+    uint64_t total = 0;
+    for (const int4& it : items) total += quads(it);
+    std::vector<std::vector<int4>> seq(8);
+    uint64_t before = 0;
+    for (const int4& it : items) {
+        // the run holding the item's midpoint
+        const uint64_t mid = before + quads(it) / 2;
+        seq[(size_t)std::min<uint64_t>(7, mid * 8 / std::max<uint64_t>(1, total))].push_back(it);
+        before += quads(it);
     }
+    size_t per = 0;
+    for (std::vector<int4>& q : seq) {
+        std::stable_sort(q.begin(), q.end(), [&](const int4& a, const int4& b) { return quads(a) > quads(b); });
+        per = std::max(per, q.size());
+    }
+    std::vector<int4> out(per * 8, make_int4(-1, 0, 0, 0));
+    for (int x = 0; x < 8; ++x)
+        for (size_t k = 0; k < seq[(size_t)x].size(); ++k) out[k * 8 + (size_t)x] = seq[(size_t)x][k];
     return out;
 }
 
@@ -774,6 +832,11 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     const int64_t mrows = TILE_ROWS;
     std::vector<int4> fw = make_work(rb, vq, nblk, std::max<int64_t>(256, fq / target_items), mrows);
     std::vector<int4> aw = make_work(sb, aq, nblk, std::max<int64_t>(256, aqn / target_items), mrows);
+    // the products stage an item's row sums in LDS (TILE_ROWS of them)
+    for (const std::vector<int4>* items : {&fw, &aw})
+        for (const int4& it : *items)
+            if (it.x >= 0 && (it.z < it.y || it.z - it.y > TILE_ROWS))
+                return fail(VMAT_ERR_UNSUPPORTED, "work item longer than TILE_ROWS rows");
     // sliced layouts: rows of each work item sorted by length, 64 per slice
     std::vector<uint32_t> s_off, s_len, s_row, as_off, as_len, as_row;
     {
