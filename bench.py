@@ -320,15 +320,22 @@ def main():
     big2 = torch.empty_like(big)
     cp_ms = time_kernel(lambda: big2.copy_(big), 20, torch)
     copy_gbs = 2 * big.numel() * 4 / cp_ms / 1e6
-    # streaming-read ceiling (context): 1 GiB read by the library's read kernel
+    # streaming-read ceiling (context): 1 GiB read by the library's read
+    # kernel, the best over a few grid sizes (the rate depends on the grid:
+    # one workgroup per compute unit reads fastest on MI355X)
     del big2
     big = torch.empty(1024 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
     big.zero_()
-    rs_part = torch.empty(8192, dtype=torch.float32, device="cuda")
-    rd_ms = time_kernel(lambda: P.vmat.read_stream(big, rs_part, 8192), 20, torch)
-    read_gbs = big.numel() * 4 / rd_ms / 1e6
+    rs_part = torch.empty(65536, dtype=torch.float32, device="cuda")
+    read_by_grid = {}
+    for grid in (256, 512, 1024, 8192, 65536):
+        rd_ms = time_kernel(lambda: P.vmat.read_stream(big, rs_part, grid), 20, torch)
+        read_by_grid[grid] = big.numel() * 4 / rd_ms / 1e6
+    read_grid = max(read_by_grid, key=read_by_grid.get)
+    read_gbs = read_by_grid[read_grid]
     del big, rs_part
-    log(f"[bench] device copy {copy_gbs:.0f} GB/s, streaming read {read_gbs:.0f} GB/s")
+    log(f"[bench] device copy {copy_gbs:.0f} GB/s, streaming read {read_gbs:.0f} GB/s (grid {read_grid}; "
+        + ", ".join(f"{g}: {v:.0f}" for g, v in read_by_grid.items()) + ")")
 
     out = {
         "metric": METRIC,
@@ -370,6 +377,7 @@ def main():
                      "nnz_per_s_fwd": round(case.nnz / fwd_ms / 1e6, 1), "nnz_per_s_adj": round(case.nnz / adj_ms / 1e6, 1),
                      "csr_fp32_equiv_GBs_fwd": round(8 * case.nnz / fwd_ms / 1e6, 1),
                      "device_copy_GBs": round(copy_gbs, 1), "read_stream_GBs": round(read_gbs, 1),
+                     "read_stream_grid": read_grid,
                      "fwd_frac_of_read_stream": round(fwd_gbs / read_gbs, 3),
                      "adj_frac_of_read_stream": round(adj_gbs / read_gbs, 3), "layout": lay},
     }
