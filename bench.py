@@ -52,8 +52,8 @@ VALUE_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "fp8": 1}
 TRAFFIC_SOURCE = "profiles/fwd_adj_sell_prostate180_hbm_counters.md"
 MEASURED_TRAFFIC = {
     ("prostate180", "f32", 676890628, 676191240): {
-        "forward": (343236.75 * 2 + 8397.84375) * 1024,
-        "adjoint": (352312.25 * 2 + 3621.40625 + 3748.3125 * 2 + 2250.0) * 1024,
+        "forward": (344953.94 * 2 + 8228.22) * 1024,
+        "adjoint": (352822.25 * 2 + 3625.22 + 3742.31 * 2 + 2250.0) * 1024,
     },
 }
 METRIC = "D·x + Dᵀr HBM GB/s vs peak; plan s; bf16/fp8-D vs fp32 at stated dose error"
