@@ -52,8 +52,8 @@ VALUE_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "fp8": 1}
 TRAFFIC_SOURCE = "profiles/fwd_adj_sell_prostate180_hbm_counters.md"
 MEASURED_TRAFFIC = {
     ("prostate180", "f32", 676890628, 676191240): {
-        "forward": (344953.94 * 2 + 8228.22) * 1024,
-        "adjoint": (352822.25 * 2 + 3625.22 + 3742.31 * 2 + 2250.0) * 1024,
+        "forward": (344971.25 * 2 + 8293.88) * 1024,
+        "adjoint": (352700.69 * 2 + 3624.22 + 3742.31 * 2 + 2250.0) * 1024,
     },
 }
 METRIC = "D·x + Dᵀr HBM GB/s vs peak; plan s; bf16/fp8-D vs fp32 at stated dose error"
@@ -333,9 +333,23 @@ def main():
         read_by_grid[grid] = big.numel() * 4 / rd_ms / 1e6
     read_grid = max(read_by_grid, key=read_by_grid.get)
     read_gbs = read_by_grid[read_grid]
+    # the same read with each product's share of writes mixed in (the
+    # products write their outputs while they stream D): bytes read and
+    # written over the time, as the layout byte counts are
+    nv, nb = case.n_voxels, case.n_beamlets
+    write_share = {"forward": 8 * nv / fwd_b, "adjoint": (8 * lay["slots"] + 8 * nb) / adj_b} if lay["tiled"] \
+        else {"forward": 8 * nv / fwd_b, "adjoint": 8 * nb / adj_b}
+    rw_gbs = {}
+    for prod, f in write_share.items():
+        wb = int(round(big.numel() * 4 * f / (1 - f) / 512)) * 512
+        wbuf = torch.empty(wb // 8, dtype=torch.float64, device="cuda")
+        rw_ms = time_kernel(lambda: P.vmat.read_write_stream(big, wbuf, rs_part, read_grid), 20, torch)
+        rw_gbs[prod] = (big.numel() * 4 + wb) / rw_ms / 1e6
+        del wbuf
     del big, rs_part
     log(f"[bench] device copy {copy_gbs:.0f} GB/s, streaming read {read_gbs:.0f} GB/s (grid {read_grid}; "
-        + ", ".join(f"{g}: {v:.0f}" for g, v in read_by_grid.items()) + ")")
+        + ", ".join(f"{g}: {v:.0f}" for g, v in read_by_grid.items()) + "); with the products' write shares "
+        + ", ".join(f"{k} {100 * write_share[k]:.2f}%: {v:.0f} GB/s" for k, v in rw_gbs.items()))
 
     out = {
         "metric": METRIC,
@@ -379,7 +393,11 @@ def main():
                      "device_copy_GBs": round(copy_gbs, 1), "read_stream_GBs": round(read_gbs, 1),
                      "read_stream_grid": read_grid,
                      "fwd_frac_of_read_stream": round(fwd_gbs / read_gbs, 3),
-                     "adj_frac_of_read_stream": round(adj_gbs / read_gbs, 3), "layout": lay},
+                     "adj_frac_of_read_stream": round(adj_gbs / read_gbs, 3),
+                     "write_share": {k: round(v, 5) for k, v in write_share.items()},
+                     "read_write_stream_GBs": {k: round(v, 1) for k, v in rw_gbs.items()},
+                     "fwd_frac_of_read_write_stream": round(fwd_gbs / rw_gbs["forward"], 3),
+                     "adj_frac_of_read_write_stream": round(adj_gbs / rw_gbs["adjoint"], 3), "layout": lay},
     }
 
     if not args.no_precision and args.d_store == "f32":

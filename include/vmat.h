@@ -473,6 +473,17 @@ vmat_status vmat_solve_variants(vmat_handle h, const vmat_solve_opts* opts, int3
  * [1, 65536] blocks of 256 lanes.  Asynchronous; allocates nothing.        */
 vmat_status vmat_read_stream(const void* buf, int64_t bytes, float* partials, int32_t grid, hipStream_t stream);
 
+/* Measurement aid, not a step of the method: the read of vmat_read_stream
+ * with wbytes of writes mixed in, spread evenly over the read (512-byte
+ * chunks, 64 lanes x 8 bytes, each wave writing its share as it goes): the
+ * ceiling of a kernel that streams its input and writes a given share of
+ * its traffic, as the products write their outputs.  wbuf: DEVICE double
+ * [wbytes / 8] (out: overwritten with running sums), may be NULL when
+ * wbytes is 0; wbytes a non-negative multiple of 512; other arguments as
+ * vmat_read_stream.  Asynchronous; allocates nothing.                      */
+vmat_status vmat_read_write_stream(const void* buf, int64_t bytes, double* wbuf, int64_t wbytes, float* partials,
+                                   int32_t grid, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

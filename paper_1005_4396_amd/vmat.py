@@ -147,6 +147,7 @@ def lib():
                                     ctypes.POINTER(SolveReport), P],
             "vmat_price_noalloc": [ctypes.POINTER(Beams), P, P, P, P, P, P, P, P, P],
             "vmat_read_stream": [P, ctypes.c_int64, P, I32, P],
+            "vmat_read_write_stream": [P, ctypes.c_int64, P, ctypes.c_int64, P, I32, P],
             "vmat_enforce_rate": [P, ctypes.POINTER(RateOpts), P, P, P, P, ctypes.POINTER(RateReport), P],
             "vmat_solve_batched": [P, ctypes.POINTER(SolveOpts), I32, I32, P, P, P, P, P, P,
                                    ctypes.POINTER(SolveReport), ctypes.POINTER(SolveTrace), P, P],
@@ -188,6 +189,15 @@ def read_stream(buf, partials, grid: int) -> None:
     HBM read ceiling); partials: float32 device tensor of at least grid."""
     assert partials.numel() >= grid and partials.dtype.itemsize == 4
     _check(lib().vmat_read_stream(_ptr(buf), buf.numel() * buf.element_size(), _ptr(partials), grid, _stream()))
+
+
+def read_write_stream(buf, wbuf, partials, grid: int) -> None:
+    """The read of read_stream with all of the float64 device tensor wbuf
+    written while it runs (a measurement aid: the ceiling of a stream with
+    that share of writes); wbuf's byte size must be a multiple of 512."""
+    assert partials.numel() >= grid and partials.dtype.itemsize == 4 and wbuf.dtype.itemsize == 8
+    _check(lib().vmat_read_write_stream(_ptr(buf), buf.numel() * buf.element_size(), _ptr(wbuf),
+                                        wbuf.numel() * 8, _ptr(partials), grid, _stream()))
 
 
 def price_noalloc(theta, n_rows, n_cols, gamma, circular, max_leaf_step, g, y, l, r, occ, out_beam, out_price,

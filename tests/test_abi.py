@@ -110,3 +110,22 @@ def test_read_stream_rejects_bad_arguments_before_launch():
     assert L.vmat_read_stream(fake, 1024, fake, 0, None) == V.VMAT_ERR_INVALID_ARG
     assert L.vmat_read_stream(fake, 1024, fake, 65537, None) == V.VMAT_ERR_INVALID_ARG
     assert "grid" in V.last_error()
+
+
+def test_read_write_stream_rejects_bad_arguments_before_launch():
+    """The read-with-writes aid checks its arguments on the host: a null read
+    buffer or partials, a read size that is not a positive multiple of 16, a
+    write size that is negative or not a multiple of 512, a null write buffer
+    with writes asked for, a grid outside [1, 65536]."""
+    L = _lib()
+    fake = ctypes.c_void_p(0x1000)
+    rw = L.vmat_read_write_stream
+    assert rw(None, 1024, fake, 512, fake, 8, None) == V.VMAT_ERR_INVALID_ARG
+    assert rw(fake, 1024, fake, 512, None, 8, None) == V.VMAT_ERR_INVALID_ARG
+    assert rw(fake, 1000, fake, 512, fake, 8, None) == V.VMAT_ERR_INVALID_ARG
+    assert rw(fake, 1024, fake, -512, fake, 8, None) == V.VMAT_ERR_INVALID_ARG
+    assert rw(fake, 1024, fake, 100, fake, 8, None) == V.VMAT_ERR_INVALID_ARG
+    assert "512" in V.last_error()
+    assert rw(fake, 1024, None, 512, fake, 8, None) == V.VMAT_ERR_INVALID_ARG
+    assert rw(fake, 1024, fake, 512, fake, 0, None) == V.VMAT_ERR_INVALID_ARG
+    assert rw(fake, 1024, fake, 512, fake, 65537, None) == V.VMAT_ERR_INVALID_ARG
