@@ -369,22 +369,27 @@ vmat_status tune_sell(vmat_ctx* h, hipStream_t st) {
     } ev;
     VMAT_HIP(hipEventCreate(&ev.e[0]));
     VMAT_HIP(hipEventCreate(&ev.e[1]));
-    constexpr int reps = 3;
-    float best[2][2];
+    // three rounds, the two variants in alternating order, the best round of
+    // each kept: the two often differ by 2-3%, less than one timing's spread
+    constexpr int reps = 3, rounds = 3;
+    float best[2][2] = {{1e30f, 1e30f}, {1e30f, 1e30f}};
     for (int fwd = 0; fwd < 2; ++fwd)
-        for (int ui = 0; ui < 2; ++ui) {
-            const int u = ui ? 8 : 4;
-            (fwd ? h->sell_u_fwd : h->sell_u_adj) = u;
-            for (int r = -1; r < reps; ++r) {
-                if (r == 0) VMAT_HIP(hipEventRecord(ev.e[0], st));
-                const vmat_status rc = fwd ? launch_fwd(h, h->x, h->dz, Gate{}, st)
-                                           : launch_adj(h, h->rz, h->g, Gate{}, st);
-                if (rc != VMAT_OK) return rc;
+        for (int round = 0; round < rounds; ++round)
+            for (int k = 0; k < 2; ++k) {
+                const int ui = (round & 1) ? 1 - k : k;
+                (fwd ? h->sell_u_fwd : h->sell_u_adj) = ui ? 8 : 4;
+                for (int r = -1; r < reps; ++r) {
+                    if (r == 0) VMAT_HIP(hipEventRecord(ev.e[0], st));
+                    const vmat_status rc = fwd ? launch_fwd(h, h->x, h->dz, Gate{}, st)
+                                               : launch_adj(h, h->rz, h->g, Gate{}, st);
+                    if (rc != VMAT_OK) return rc;
+                }
+                VMAT_HIP(hipEventRecord(ev.e[1], st));
+                VMAT_HIP(hipEventSynchronize(ev.e[1]));
+                float ms = 0.f;
+                VMAT_HIP(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+                best[fwd][ui] = std::min(best[fwd][ui], ms);
             }
-            VMAT_HIP(hipEventRecord(ev.e[1], st));
-            VMAT_HIP(hipEventSynchronize(ev.e[1]));
-            VMAT_HIP(hipEventElapsedTime(&best[fwd][ui], ev.e[0], ev.e[1]));
-        }
     h->sell_u_adj = best[0][1] < best[0][0] ? 8 : 4;
     h->sell_u_fwd = best[1][1] < best[1][0] ? 8 : 4;
     return VMAT_OK;
