@@ -59,11 +59,18 @@ MEASURED_TRAFFIC = {
 METRIC = "D·x + Dᵀr HBM GB/s vs peak; plan s; bf16/fp8-D vs fp32 at stated dose error"
 
 
-def time_kernel(fn, reps, torch, warm=1):
+def time_kernel(fn, reps, torch, warm=1, warm_s=0.0):
+    """Average ms of fn over reps launches, after warm launches and then
+    more until warm_s seconds have passed."""
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for _ in range(warm):
         fn()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < warm_s:
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
     s.record()
     for _ in range(reps):
         fn()
@@ -301,10 +308,10 @@ def main():
     w = torch.from_numpy(rng.standard_normal(case.n_voxels).astype(np.float32)).cuda()
     zbuf = torch.empty(case.n_voxels, dtype=torch.float64, device="cuda")
     gbuf = torch.empty(case.n_beamlets, dtype=torch.float64, device="cuda")
-    # 20 launches first: right after the handle's creation the device runs
-    # the products about 3% slower for the first tens of milliseconds
-    fwd_ms = time_kernel(lambda: prob.forward(x, zbuf), args.kernel_reps, torch, warm=20)
-    adj_ms = time_kernel(lambda: prob.adjoint(w, gbuf), args.kernel_reps, torch, warm=20)
+    # 0.2 s of launches first: right after a handle's creation the device
+    # runs the products about 3% slower for a while
+    fwd_ms = time_kernel(lambda: prob.forward(x, zbuf), args.kernel_reps, torch, warm_s=0.2)
+    adj_ms = time_kernel(lambda: prob.adjoint(w, gbuf), args.kernel_reps, torch, warm_s=0.2)
     fwd_gbs = fwd_b / fwd_ms / 1e6
     adj_gbs = adj_b / adj_ms / 1e6
     fwd_alg, adj_alg = algorithmic_bytes(case, args.d_store)
@@ -718,8 +725,8 @@ def precision_study(workload, torch, P, reps, log):
         zg = prob.dose(yt, lt, rt, ot).cpu().numpy().astype(np.float64)
         err_l2 = float(np.linalg.norm(zg - zo) / np.linalg.norm(zo))
         err_inf = float(np.abs(zg - zo).max() / np.abs(zo).max())
-        f_ms = time_kernel(lambda: prob.forward(x, zb), reps, torch, warm=20)
-        a_ms = time_kernel(lambda: prob.adjoint(w, gb), reps, torch, warm=20)
+        f_ms = time_kernel(lambda: prob.forward(x, zb), reps, torch, warm_s=0.2)
+        a_ms = time_kernel(lambda: prob.adjoint(w, gb), reps, torch, warm_s=0.2)
         lay = prob.layout()
         res[fmt] = {"forward_ms": round(f_ms, 5), "adjoint_ms": round(a_ms, 5),
                     "forward_GBs": round(lay["fwd_bytes"] / f_ms / 1e6, 1),
