@@ -479,8 +479,7 @@ vmat_status ap_append(vmat_ctx* h, const int32_t* l, const int32_t* r, const uin
     int32_t* kb = reinterpret_cast<int32_t*>(a->unit + h->N);
     k_ap_unit<<<1, AP_T, 0, st>>>(h->N, beam_dev, beam_h, a->unit, kb);
     VMAT_LAUNCH_CHECK();
-    if ((rc = launch_fluence(h, a->unit, l, r, occ, h->bm.scale, h->x, Gate{}, st)) != VMAT_OK) return rc;
-    if ((rc = launch_fwd(h, h->x, h->dz, Gate{}, st)) != VMAT_OK) return rc;
+    if ((rc = launch_fwd_plan(h, a->unit, l, r, occ, h->dz, Gate{}, st)) != VMAT_OK) return rc;
     const int nch = n_chunks_of(h->nv);
     k_ap_count<<<nch, AP_T, 0, st>>>(h->nv, h->dz, a->chunk);
     VMAT_LAUNCH_CHECK();

@@ -73,8 +73,7 @@ vmat_status forward_from_fluence(vmat_ctx* h, const double* x, hipStream_t st) {
 
 vmat_status forward_from_plan(vmat_ctx* h, const double* y, const int32_t* l, const int32_t* r,
                               const uint8_t* occ, double* zout, Gate gate, hipStream_t st) {
-    TRY(launch_fluence(h, y, l, r, occ, h->bm.scale, h->x, gate, st));
-    return launch_fwd(h, h->x, zout, gate, st);
+    return launch_fwd_plan(h, y, l, r, occ, zout, gate, st);
 }
 
 vmat_master_opts defaults(const vmat_master_opts* o) {
@@ -141,8 +140,7 @@ vmat_status search(vmat_ctx* h, int mode, hipStream_t s) {
     if (mode == 1) {
         TRY(ap_dose(h, h->md, h->dz, done, s));
     } else {
-        TRY(launch_fluence(h, h->md, h->pl, h->pr, h->pocc, h->bm.scale, h->x, done, s));
-        TRY(launch_fwd(h, h->x, h->dz, done, s));
+        TRY(launch_fwd_plan(h, h->md, h->pl, h->pr, h->pocc, h->dz, done, s));
     }
     return launch_ls_passes(h, s);
 }

@@ -456,7 +456,7 @@ static void free_all(vmat_ctx* h) {
         F(h->vm.qptr); F(h->vm.col); F(h->vm.val); F(h->vm.scale);
         free_tiled(h);
     }
-    F(h->abT); F(h->wlab); F(h->wtab); F(h->x); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->bpart); F(h->part); F(h->part_b);
+    F(h->abT); F(h->wlab); F(h->wtab); F(h->x); F(h->xl); F(h->z); F(h->dz); F(h->rz); F(h->g); F(h->bpart); F(h->part); F(h->part_b);
     F(h->pl); F(h->pr); F(h->pocc); F(h->d_gamma); F(h->vflag);
     F(h->my); F(h->mgrad); F(h->mgrad_prev); F(h->md); F(h->md_prev); F(h->mgF); F(h->mW); F(h->mW_prev);
     F(h->ms);
@@ -564,6 +564,7 @@ static vmat_status alloc_plan_state(vmat_ctx* h, hipStream_t st) {
     h->n_part = (int)std::min<int64_t>(1024, std::max<int64_t>(256, (h->nv + 2047) / 2048));
     if ((rc = dalloc(h, &h->d_theta, N)) != VMAT_OK) return rc;
     if ((rc = dalloc(h, &h->x, h->nb)) != VMAT_OK) return rc;
+    if (h->tl.on && h->tl.S > 0 && (rc = dalloc(h, &h->xl, h->tl.S)) != VMAT_OK) return rc;
     if ((rc = dalloc(h, &h->z, h->nv)) != VMAT_OK) return rc;
     if ((rc = dalloc(h, &h->dz, h->nv)) != VMAT_OK) return rc;
     if ((rc = dalloc(h, &h->rz, h->nv)) != VMAT_OK) return rc;

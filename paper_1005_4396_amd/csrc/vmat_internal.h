@@ -271,6 +271,7 @@ struct vmat_ctx {
 
     // work buffers
     double* x = nullptr;           // [nb] fluence
+    double* xl = nullptr;          // [tl.S] fluence in block-list order (tiled layout)
     double* z = nullptr;           // [nv] dose (FP64)
     double* dz = nullptr;          // [nv] dose of the search direction
     float* rz = nullptr;           // [nv] F'(z) for the adjoint gather

@@ -24,6 +24,9 @@ vmat_status launch_spmv(const vmat_ctx* h, const QuadCsr& A, const float* x, dou
 // Dispatch to the tiled or the plain layout.
 // forward: out = D^T x (x: fluence, FP8 scale already folded in); adjoint: g = D w.
 vmat_status launch_fwd(const vmat_ctx* h, const double* x, double* out, Gate gate, hipStream_t st);
+// fluence of the plan (v, l, r, occ) and its dose into out, in two launches
+vmat_status launch_fwd_plan(const vmat_ctx* h, const double* v, const int32_t* l, const int32_t* r,
+                            const uint8_t* occ, double* out, Gate gate, hipStream_t st);
 // picks the quads in flight of the sliced products by timing (at creation)
 vmat_status tune_sell(vmat_ctx* h, hipStream_t st);
 vmat_status launch_adj(const vmat_ctx* h, const float* w, double* g, Gate gate, hipStream_t st);

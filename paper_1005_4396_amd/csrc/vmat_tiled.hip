@@ -118,8 +118,10 @@ __device__ __forceinline__ void flush_rows(const int4 wk, const double* os, doub
 // Forward over the sliced layout: after the block's x values are staged in
 // LDS, the waves take the item's slices as sell_rows describes; lane i owns
 // row i of the slice and walks its quads in order (quad k of the 64 rows is
-// one contiguous 1-KB load for FP32 values), no cross-lane sums.
-template <int FMT, int U>
+// one contiguous 1-KB load for FP32 values), no cross-lane sums.  XL: x is
+// given in block-list order (xl[e] = x[list[e]], as k_fluence_list writes
+// it), so staging is one contiguous read instead of the list and a gather.
+template <int FMT, int U, bool XL>
 __global__ __launch_bounds__(TILE_THREADS) void k_fwd_sell(const int4* __restrict__ work,
                                                          const uint32_t* __restrict__ loff,
                                                          const uint32_t* __restrict__ list,
@@ -140,17 +142,25 @@ __global__ __launch_bounds__(TILE_THREADS) void k_fwd_sell(const int4* __restric
     const uint32_t l0 = loff[wk.x], ln = loff[wk.x + 1] - l0;
     {
         constexpr int K = TILE_LIST / TILE_THREADS;
-        uint32_t id[K];
         double v[K];
+        if constexpr (XL) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint32_t u = threadIdx.x + k * TILE_THREADS;
-            id[k] = u < ln ? list[l0 + u] : 0u;
-        }
+            for (int k = 0; k < K; ++k) {
+                const uint32_t u = threadIdx.x + k * TILE_THREADS;
+                v[k] = u < ln ? x[l0 + u] : 0.0;
+            }
+        } else {
+            uint32_t id[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint32_t u = threadIdx.x + k * TILE_THREADS;
-            v[k] = u < ln ? x[id[k]] : 0.0;
+            for (int k = 0; k < K; ++k) {
+                const uint32_t u = threadIdx.x + k * TILE_THREADS;
+                id[k] = u < ln ? list[l0 + u] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t u = threadIdx.x + k * TILE_THREADS;
+                v[k] = u < ln ? x[id[k]] : 0.0;
+            }
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -280,6 +290,26 @@ __global__ __launch_bounds__(256) void k_adj_reduce_beams(int R, int C, int Q, c
     if (threadIdx.x == 0) bpart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
+// The fluence of a plan (as k_fluence) at each entry of the blocks' beamlet
+// lists: xl[e] = x_i for i = list[e], the forward's staging order.
+__global__ __launch_bounds__(256) void k_fluence_list(int64_t S, const uint32_t* __restrict__ list, int R, int C,
+                                                      const double* __restrict__ v, const int32_t* __restrict__ l,
+                                                      const int32_t* __restrict__ r, const uint8_t* __restrict__ occ,
+                                                      const float* __restrict__ scale, double* __restrict__ xl,
+                                                      Gate gate) {
+    if (gate.closed()) return;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= S) return;
+    const int64_t i = list[e];
+    const int64_t kr = i / C;
+    const int c = (int)(i - kr * C);
+    const int64_t k = kr / R;
+    double xi = 0.0;
+    if (occ[k] && c >= l[kr] && c < r[kr]) xi = v[k];
+    if (scale) xi *= (double)scale[i];
+    xl[e] = xi;
+}
+
 // ---------------------------------------------------------------- launchers
 
 // Quads in flight per lane of the sliced products: VMAT_SELL_U (2, 4 or 8)
@@ -291,14 +321,14 @@ static int sell_u(const vmat_ctx* h, bool fwd) {
     return fwd ? h->sell_u_fwd : h->sell_u_adj;
 }
 
-template <int FMT>
+template <int FMT, bool XL>
 static vmat_status fwd_fmt(const vmat_ctx* h, const double* x, double* out, Gate gate, hipStream_t st) {
     const Tiled& t = h->tl;
     const unsigned grid = (unsigned)t.n_fwork;
     if (grid == 0) return VMAT_OK;
     const int su = sell_u(h, true);
-#define SELL(UU) k_fwd_sell<FMT, UU><<<grid, TILE_THREADS, 0, st>>>(t.fwork, t.loff, t.list, t.s_off, t.s_len, \
-                                                              t.s_row, t.s_col, t.s_val, x, out, gate)
+#define SELL(UU) k_fwd_sell<FMT, UU, XL><<<grid, TILE_THREADS, 0, st>>>(t.fwork, t.loff, t.list, t.s_off, t.s_len, \
+                                                                  t.s_row, t.s_col, t.s_val, x, out, gate)
     switch (su) {
         case 2: SELL(2); break;
         case 8: SELL(8); break;
@@ -335,10 +365,32 @@ static vmat_status adj_fmt(const vmat_ctx* h, const float* w, double* g, Gate ga
 vmat_status launch_fwd(const vmat_ctx* h, const double* x, double* out, Gate gate, hipStream_t st) {
     if (!h->tl.on) return launch_spmv(h, h->vm, x, out, gate, st);
     switch (h->d_store) {
-        case VMAT_F32: return fwd_fmt<FMT_F32>(h, x, out, gate, st);
-        case VMAT_F16: return fwd_fmt<FMT_F16>(h, x, out, gate, st);
-        case VMAT_BF16: return fwd_fmt<FMT_BF16>(h, x, out, gate, st);
-        default: return fwd_fmt<FMT_FP8>(h, x, out, gate, st);
+        case VMAT_F32: return fwd_fmt<FMT_F32, false>(h, x, out, gate, st);
+        case VMAT_F16: return fwd_fmt<FMT_F16, false>(h, x, out, gate, st);
+        case VMAT_BF16: return fwd_fmt<FMT_BF16, false>(h, x, out, gate, st);
+        default: return fwd_fmt<FMT_FP8, false>(h, x, out, gate, st);
+    }
+}
+
+// The dose of a plan's fluence: with the tiled layout the fluence is formed
+// in block-list order (h->xl) and staged from there; otherwise in beamlet
+// order (h->x) for the plain product.  Same bits either way.
+vmat_status launch_fwd_plan(const vmat_ctx* h, const double* v, const int32_t* l, const int32_t* r,
+                            const uint8_t* occ, double* out, Gate gate, hipStream_t st) {
+    if (!h->tl.on || !h->xl) {
+        vmat_status rc = launch_fluence(h, v, l, r, occ, h->bm.scale, h->x, gate, st);
+        if (rc != VMAT_OK) return rc;
+        return launch_fwd(h, h->x, out, gate, st);
+    }
+    const Tiled& t = h->tl;
+    k_fluence_list<<<(unsigned)((t.S + 255) / 256), 256, 0, st>>>(t.S, t.list, h->R, h->C, v, l, r, occ,
+                                                                    h->bm.scale, h->xl, gate);
+    VMAT_LAUNCH_CHECK();
+    switch (h->d_store) {
+        case VMAT_F32: return fwd_fmt<FMT_F32, true>(h, h->xl, out, gate, st);
+        case VMAT_F16: return fwd_fmt<FMT_F16, true>(h, h->xl, out, gate, st);
+        case VMAT_BF16: return fwd_fmt<FMT_BF16, true>(h, h->xl, out, gate, st);
+        default: return fwd_fmt<FMT_FP8, true>(h, h->xl, out, gate, st);
     }
 }
 
