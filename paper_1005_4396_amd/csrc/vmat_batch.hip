@@ -566,8 +566,7 @@ __global__ __launch_bounds__(256) void k_spmm_adj_reduce(int64_t nb, int B, cons
     if (e >= nb * B) return;
     const int64_t i = e / B;
     const int b = (int)(e - i * B);
-    double s = 0.0;
-    for (uint32_t k = red_ptr[i]; k < red_ptr[i + 1]; ++k) s += part[(int64_t)red_slot[k] * B + b];
+    const double s = slot_sum(red_ptr[i], red_ptr[i + 1], red_slot, part, B, b);
     G[e] = scale ? s * (double)scale[i] : s;
 }
 

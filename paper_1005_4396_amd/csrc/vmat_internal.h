@@ -116,6 +116,27 @@ struct Gate {
     __host__ __device__ bool closed() const { return p && !((1u << *p) & mask); }
 };
 
+// The sum of part[red_slot[k] * stride + b] over k in [k0, k1), added in k
+// order: a beamlet's slot sums.  The slot indices of up to four slots are
+// loaded at once, then their sums, so a beamlet with up to four slots costs
+// two dependent loads after its range instead of two per slot.
+__device__ __forceinline__ double slot_sum(uint32_t k0, uint32_t k1, const uint32_t* __restrict__ red_slot,
+                                           const double* __restrict__ part, int64_t stride, int b) {
+    double s = 0.0;
+    for (uint32_t k = k0; k < k1; k += 4) {
+        uint32_t sl[4];
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sl[j] = k + j < k1 ? red_slot[k + j] : 0u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = k + j < k1 ? part[(int64_t)sl[j] * stride + b] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (k + j < k1) s += v[j];
+    }
+    return s;
+}
+
 // Scalars and small vectors of the master iteration, resident on the device.
 struct MasterState {
     // line search

@@ -252,8 +252,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce(int64_t nb, const uint32_t* 
     if (gate.closed()) return;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= nb) return;
-    double s = 0.0;
-    for (uint32_t k = red_ptr[i]; k < red_ptr[i + 1]; ++k) s += part[red_slot[k]];
+    const double s = slot_sum(red_ptr[i], red_ptr[i + 1], red_slot, part, 1, 0);
     g[i] = scale ? s * (double)scale[i] : s;
 }
 
@@ -275,8 +274,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce_beams(int R, int C, int Q, c
     double ex = 0.0;
     if (e < RC) {
         const int64_t i = (int64_t)k * RC + e;
-        double s = 0.0;
-        for (uint32_t p = red_ptr[i]; p < red_ptr[i + 1]; ++p) s += part[red_slot[p]];
+        const double s = slot_sum(red_ptr[i], red_ptr[i + 1], red_slot, part, 1, 0);
         const double gi = scale ? s * (double)scale[i] : s;
         g[i] = gi;
         const int rho = e / C, c = e - rho * C;
