@@ -80,6 +80,10 @@ __device__ __forceinline__ uint8_t f64_to_e4m3_rne(double v) {
 template <int FMT> struct Quad;
 
 template <> struct Quad<FMT_F32> {
+    using raw_t = f32x4;
+    __device__ __forceinline__ static raw_t raw(const void* base, int64_t q) {
+        return __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(base) + q);
+    }
     __device__ __forceinline__ static float4 dec(f32x4 v) { return make_float4(v.x, v.y, v.z, v.w); }
     __device__ __forceinline__ static float4 load(const void* base, int64_t q) {
         return dec(__builtin_nontemporal_load(reinterpret_cast<const f32x4*>(base) + q));
@@ -90,6 +94,10 @@ template <> struct Quad<FMT_F32> {
 };
 
 template <> struct Quad<FMT_BF16> {
+    using raw_t = u32x2;
+    __device__ __forceinline__ static raw_t raw(const void* base, int64_t q) {
+        return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(base) + q);
+    }
     __device__ __forceinline__ static float4 dec(u32x2 u) {
         return make_float4(bf16_to_f32(u.x & 0xFFFFu), bf16_to_f32(u.x >> 16),
                            bf16_to_f32(u.y & 0xFFFFu), bf16_to_f32(u.y >> 16));
@@ -103,6 +111,10 @@ template <> struct Quad<FMT_BF16> {
 };
 
 template <> struct Quad<FMT_F16> {
+    using raw_t = u32x2;
+    __device__ __forceinline__ static raw_t raw(const void* base, int64_t q) {
+        return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(base) + q);
+    }
     __device__ __forceinline__ static float4 dec(u32x2 u) {
         return make_float4(f16_to_f32(u.x & 0xFFFFu), f16_to_f32(u.x >> 16),
                            f16_to_f32(u.y & 0xFFFFu), f16_to_f32(u.y >> 16));
@@ -118,6 +130,10 @@ template <> struct Quad<FMT_F16> {
 // The hardware conversion (two codes per instruction) gives the same bits as
 // e4m3_to_f32 on every finite code; stored codes never exceed 0x7E.
 template <> struct Quad<FMT_FP8> {
+    using raw_t = uint32_t;
+    __device__ __forceinline__ static raw_t raw(const void* base, int64_t q) {
+        return __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base) + q);
+    }
     __device__ __forceinline__ static float4 dec(uint32_t u) {
         const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)u, false);
         const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)u, true);

@@ -55,40 +55,45 @@ __device__ __forceinline__ void sell_rows(const int4 wk, const uint32_t* __restr
         double acc = 0.0;
         uint32_t k = 0;
         for (; k + U <= len; k += U) {
-            float4 v[U];
+            // the stored words first, decoded only when summed: decoding at
+            // the load let the compiler reuse one register for every FP8
+            // load and wait for each in turn
+            typename Quad<FMT>::raw_t rv[U];
             u16x4 c[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                v[u] = Quad<FMT>::load(s_val, base + (k + u) * 64);
+                rv[u] = Quad<FMT>::raw(s_val, base + (k + u) * 64);
                 c[u] = __builtin_nontemporal_load(c4 + base + (k + u) * 64);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                acc = fma((double)v[u].x, (double)xs[c[u].x], acc);
-                acc = fma((double)v[u].y, (double)xs[c[u].y], acc);
-                acc = fma((double)v[u].z, (double)xs[c[u].z], acc);
-                acc = fma((double)v[u].w, (double)xs[c[u].w], acc);
+                const float4 vu = Quad<FMT>::dec(rv[u]);
+                acc = fma((double)vu.x, (double)xs[c[u].x], acc);
+                acc = fma((double)vu.y, (double)xs[c[u].y], acc);
+                acc = fma((double)vu.z, (double)xs[c[u].z], acc);
+                acc = fma((double)vu.w, (double)xs[c[u].w], acc);
             }
         }
         if (k < len) {
             // the last rem < U quads; addresses past the row's end re-read
             // its last quad and are not summed
             const uint32_t rem = len - k;
-            float4 v[U - 1];
+            typename Quad<FMT>::raw_t rv[U - 1];
             u16x4 c[U - 1];
 #pragma unroll
             for (int u = 0; u < U - 1; ++u) {
                 const uint32_t kk = k + min((uint32_t)u, rem - 1);
-                v[u] = Quad<FMT>::load(s_val, base + kk * 64);
+                rv[u] = Quad<FMT>::raw(s_val, base + kk * 64);
                 c[u] = __builtin_nontemporal_load(c4 + base + kk * 64);
             }
 #pragma unroll
             for (int u = 0; u < U - 1; ++u) {
                 if ((uint32_t)u < rem) {
-                    acc = fma((double)v[u].x, (double)xs[c[u].x], acc);
-                    acc = fma((double)v[u].y, (double)xs[c[u].y], acc);
-                    acc = fma((double)v[u].z, (double)xs[c[u].z], acc);
-                    acc = fma((double)v[u].w, (double)xs[c[u].w], acc);
+                    const float4 vu = Quad<FMT>::dec(rv[u]);
+                    acc = fma((double)vu.x, (double)xs[c[u].x], acc);
+                    acc = fma((double)vu.y, (double)xs[c[u].y], acc);
+                    acc = fma((double)vu.z, (double)xs[c[u].z], acc);
+                    acc = fma((double)vu.w, (double)xs[c[u].w], acc);
                 }
             }
         }
