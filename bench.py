@@ -52,8 +52,8 @@ VALUE_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "fp8": 1}
 TRAFFIC_SOURCE = "profiles/fwd_adj_sell_prostate180_hbm_counters.md"
 MEASURED_TRAFFIC = {
     ("prostate180", "f32", 676890628, 676191240): {
-        "forward": (344736.56 * 2 + 8293.94) * 1024,
-        "adjoint": (347072.44 * 2 + 3601.88 + 3750.31 * 2 + 2250.0) * 1024,
+        "forward": (344731.94 * 2 + 8308.53) * 1024,
+        "adjoint": (347202.12 * 2 + 3601.91 + 3750.31 * 2 + 2250.0) * 1024,
     },
 }
 METRIC = "D·x + Dᵀr HBM GB/s vs peak; plan s; bf16/fp8-D vs fp32 at stated dose error"

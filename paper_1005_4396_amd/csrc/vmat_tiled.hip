@@ -903,8 +903,8 @@ vmat_status build_tiled(vmat_ctx* h, const vmat_problem* p, hipStream_t st) {
     // slices per item at 1,024 items, fewer than a workgroup's 8 waves);
     // 512 items, one per resident workgroup, measured best on prostate
     // (3.4% faster than 1,024) and 1.6-1.9% faster on head-and-neck FP32 and
-    // BF16, 1.6% slower with FP8
-    const int64_t adj_items = 512;
+    // BF16; FP8 keeps 1,024 (1.6% faster than 512 on head-and-neck)
+    const int64_t adj_items = h->d_store == VMAT_FP8_E4M3 ? 1024 : 512;
     std::vector<int4> aw = make_work(sb, aq, nblk, std::max<int64_t>(256, aqn / adj_items), mrows);
     // the products stage an item's row sums in LDS (TILE_ROWS of them)
     for (const std::vector<int4>* items : {&fw, &aw})
